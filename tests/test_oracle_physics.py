@@ -1,0 +1,184 @@
+"""Pins of the oracle against what the paper and closed forms fix.
+
+P4/P5  mass of each species and total momentum conserved on a lattice run.
+P6     solvent shear-wave decay at nu = c_s^2 tau1 (Sec. IV: viscosity is
+       proportional to tau1), second-order convergence in L.
+P7     polymer density diffusion with D = c_s^2 tau2_P in the dilute limit
+       (App. A, density diffusion equation).
+P8     homogeneous Hookean conformation relaxation C - I ~ exp(-t/lambda)
+       (App. A, homogeneous Smoluchowski equation), converging with NQ.
+P9     forced laminar Kolmogorov state with Hookean dumbbells against the
+       Oldroyd-B closed form (Sec. VII forcing; Sec. III elastic stress).
+P12    x-invariance: with no perturbation the amplitude stays at round-off.
+P14    the parameter mapping gives the paper's Schmidt-number range (Sec. VII).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests import inputs
+
+CS2 = 1.0 / 3.0
+
+
+def _sin_amp(f, k, x):
+    return 2.0 / len(x) * np.sum(f * np.sin(k * x))
+
+
+def _cos_amp(f, k, x):
+    return 2.0 / len(x) * np.sum(f * np.cos(k * x))
+
+
+def _abs_momentum(sim):
+    st = sim.get_state()
+    t = sim.tables()
+    cS = t["cS"].astype(float); v = t["cP"][:, :2].astype(float)
+    J = np.einsum("ia,iyx->ayx", cS, st["XS"]) + np.einsum("ka,kqyx->ayx", v, st["XP"])
+    return np.sqrt((J ** 2).sum(0)).sum()
+
+
+@pytest.mark.parametrize("spring", [0, 1])
+def test_conservation_on_lattice(spring):
+    sim = oracle.OracleSim(16, 16, nq=6, spring=spring)
+    sim.base_state(300)
+    sim.perturb(seed=3, amp=0.05, multimode=True)
+    d0 = sim.diagnostics()
+    pabs = _abs_momentum(sim)
+    sim.step(200)
+    d1 = sim.diagnostics()
+    assert abs(d1["mass_S"] / d0["mass_S"] - 1) < 1e-13
+    assert abs(d1["mass_P"] / d0["mass_P"] - 1) < 1e-13
+    for c in ("mom_x", "mom_y"):
+        assert abs(d1[c] - d0[c]) < 1e-12 * pabs
+
+
+def _shear_wave_error(L, nu=0.05, A=1e-4, n1=100, n2=600):
+    l = L / (2 * np.pi)
+    sim = oracle.OracleSim(1, L, nq=4, phi=0.0, Wi=0.0, Re=0.05 * l / nu, force_scale=0.0)
+    d = sim.derived()
+    y = np.arange(L)
+    u = A * np.sin(2 * np.pi * y / L)
+    XS = np.stack([oracle.OracleSim.solvent_eq(1.0, uj, 0.0) for uj in u], axis=1)[:, :, None]
+    U = np.zeros((2, L, 1)); U[0, :, 0] = u
+    sim.set_state(XS=XS, XP=np.zeros((25, sim.nqd, L, 1)),
+                  psi=np.zeros((sim.nqd, L, 1)), U=U)
+    k = 2 * np.pi / L
+    sim.step(n1); a1 = _sin_amp(sim.get_state()["U"][0, :, 0], k, y)
+    sim.step(n2 - n1); a2 = _sin_amp(sim.get_state()["U"][0, :, 0], k, y)
+    rate = -np.log(a2 / a1) / (n2 - n1)
+    return rate / (d["nuS"] * k * k) - 1.0
+
+
+def test_shear_wave_viscosity():
+    e = {L: _shear_wave_error(L) for L in (32, 64, 128)}
+    assert abs(e[64]) < 1e-3
+    # second-order lattice error
+    assert 3.5 < e[32] / e[64] < 4.5 and 3.5 < e[64] / e[128] < 4.5
+
+
+def _polymer_diffusion_error(L, tau2=0.25, eps=1e-3, n1=50, n2=1050):
+    sig2 = oracle.OracleSim(1, 1, nq=4, spring=1).derived()["sigma"] ** 2
+    sim = oracle.OracleSim(L, 1, nq=4, spring=1, Wi=0.0, phi=1e-6, force_scale=0.0,
+                           lambda_set=3 * sig2 / (2 * tau2), ny_param=64)
+    d = sim.derived(); t = sim.tables()
+    x = np.arange(L)
+    psi = d["rhoP0"] * t["peq"][:, None, None] * (1 + eps * np.sin(2 * np.pi * x / L))[None, None, :]
+    XS = np.broadcast_to(oracle.OracleSim.solvent_eq(d["rhoS0"], 0, 0)[:, None, None], (9, 1, L))
+    sim.set_state(XS=XS, XP=t["wP"][:, None, None, None] * psi[None], psi=psi,
+                  U=np.zeros((2, 1, L)))
+    k = 2 * np.pi / L
+    sim.step(n1); a1 = _sin_amp(sim.observables()[3, 0, :], k, x)
+    sim.step(n2 - n1); a2 = _sin_amp(sim.observables()[3, 0, :], k, x)
+    rate = -np.log(a2 / a1) / (n2 - n1)
+    return rate / (CS2 * d["tau2P"] * k * k) - 1.0
+
+
+def test_polymer_density_diffusion():
+    e32, e64 = _polymer_diffusion_error(32), _polymer_diffusion_error(64)
+    assert abs(e64) < 1e-3
+    assert 3.5 < e32 / e64 < 4.5
+
+
+def _conformation_relaxation_error(nq, tau2=0.0768):
+    sig2 = oracle.OracleSim(1, 1, nq=nq, spring=1).derived()["sigma"] ** 2
+    lam = 3 * sig2 / (2 * tau2)
+    sim = oracle.OracleSim(1, 1, nq=nq, spring=1, Wi=0.0, force_scale=0.0,
+                           lambda_set=lam, ny_param=64)
+    d = sim.derived(); t = sim.tables(); Q = t["Q"]
+    # anisotropic Gaussian with C(0) = diag(1.5, 0.75)
+    p = np.exp(-Q[:, 0] ** 2 / (2 * 1.5 * sig2) - Q[:, 1] ** 2 / (2 * 0.75 * sig2))
+    psi = d["rhoP0"] * (p / p.sum())[:, None, None]
+    XS = oracle.OracleSim.solvent_eq(d["rhoS0"], 0, 0)[:, None, None]
+    sim.set_state(XS=XS, XP=t["wP"][:, None, None, None] * psi[None], psi=psi,
+                  U=np.zeros((2, 1, 1)))
+
+    def aniso():
+        o = sim.observables()
+        return o[4, 0, 0] - o[6, 0, 0]
+    n1, n2 = int(0.4 * lam), int(4 * lam)
+    sim.step(n1); a1 = aniso()
+    sim.step(n2 - n1); a2 = aniso()
+    return -np.log(a2 / a1) / (n2 - n1) * d["lambda"] - 1.0
+
+
+def test_conformation_relaxation_time():
+    e = [abs(_conformation_relaxation_error(nq)) for nq in (8, 12, 16)]
+    assert e[2] < 1e-2
+    assert e[0] > e[1] > e[2]
+
+
+def test_laminar_oldroyd_b_profile():
+    """Hookean laminar state: U = U_L sin ky with
+    U_L = F0 / (k^2 [eta_s + eta_pk + G lambda / (1 + lambda D k^2)]),
+    C_xy = lambda U_L k cos(ky) / (1 + lambda D k^2),
+    C_xx - C_yy = lambda^2 U_L^2 k^2 / (1 + lambda D k^2) [1 + cos 2ky / (1 + 4 lambda D k^2)].
+    eta_s = rho_S c_s^2 tau1_S, eta_pk = rho_P c_s^2 tau1_P (kinetic part of the
+    polymer populations), D = c_s^2 tau2_P (r-diffusion)."""
+    ny = 64
+    sim = oracle.OracleSim(1, ny, nq=16, spring=1, Re=5.0, Wi=0.5, beta=0.8, periods=1)
+    d = sim.derived()
+    sim.rest()
+    sim.step(int(12 * max(d["l"] ** 2 / d["nu"], d["lambda"])))
+    o = sim.observables()
+    y = np.arange(ny); k = d["kf"]; lam = d["lambda"]
+    Dk = lam * CS2 * d["tau2P"] * k * k
+    eta = d["rhoS0"] * CS2 * d["tau1S"] + d["rhoP0"] * CS2 * d["tau1P"] + d["G"] * lam / (1 + Dk)
+    UL_c = d["F0"] / (k * k * eta)
+    UL = _sin_amp(o[1, :, 0], k, y)
+    assert abs(UL / UL_c - 1) < 2e-3
+    Cxy = _cos_amp(o[5, :, 0], k, y)
+    assert abs(Cxy / (lam * UL * k / (1 + Dk)) - 1) < 2e-3
+    dxx = o[4, :, 0] - o[6, :, 0]
+    m0 = lam ** 2 * UL ** 2 * k * k / (1 + Dk)
+    assert abs(dxx.mean() / m0 - 1) < 3e-3
+    assert abs(_cos_amp(dxx, 2 * k, y) / (m0 / (1 + 4 * Dk)) - 1) < 6e-3
+    # cross-stream velocity: only the slow acoustic relaxation of the tiny
+    # y-force of the non-uniform conformation remains
+    assert np.abs(o[2]).max() < 1e-9 * d["F0"] / (k * k * eta)
+
+
+def test_unperturbed_state_stays_x_invariant():
+    sim = oracle.OracleSim(16, 16, nq=6, ny_param=64)
+    sim.base_state(200)
+    sim.step(100)
+    assert sim.amplitude() < 1e-14
+
+
+@pytest.mark.parametrize("Wi", [0.1, 2.5, 5.0])
+def test_schmidt_number_at_paper_parameters(Wi):
+    """72^2 cell, 32 Q points, 4 periods, Re = 3.5, beta = 0.5 (Sec. VII);
+    the paper quotes Sc between 0.05 and 4 for its runs."""
+    d = oracle.OracleSim(1, 1, nq=32, periods=4, Re=3.5, beta=0.5, Wi=Wi,
+                         ny_param=72).derived()
+    assert 0.01 < d["Sc"] < 10.0
+
+
+def test_perturbation_amplitude():
+    sim = oracle.OracleSim(32, 32, nq=4, ny_param=64)
+    sim.base_state(50)
+    sim.perturb(seed=5, amp=1e-3, multimode=True)
+    assert abs(sim.amplitude() / 1e-3 - 1) < 1e-12
+    sim2 = oracle.OracleSim(32, 32, nq=4, ny_param=64)
+    sim2.base_state(50)
+    sim2.perturb(seed=5, amp=1e-3, multimode=False)
+    assert abs(sim2.amplitude() / (1e-3 / np.sqrt(2)) - 1) < 1e-12
