@@ -1,0 +1,198 @@
+/*
+ * tpl.h -- C ABI of the MI355X implementation of the two-fluid kinetic scheme
+ * for dilute polymer solutions of Singh, Subramanian & Ansumali,
+ * "Two-fluid kinetic theory for dilute polymer solutions" (arXiv:2201.10132).
+ *
+ * One time step advances two populations on one 2-D periodic lattice:
+ *   - solvent: D2Q9 populations (Sec. VI.A);
+ *   - polymer: D4Q25 populations over (r, Q) (Sec. VI.B, Table I), i.e. at
+ *     every r-node a disk of Q-nodes (|Q| < NQ/2, bounce-back on the circle,
+ *     Sec. VI.C) with 25 populations each;
+ * coupled through the mixture velocity and the dumbbell spring term
+ * (imposed fluxes of Sec. V), relaxed by the component-momentum
+ * quasi-equilibrium model (Sec. IV-V) with the trapezoidal time
+ * discretisation made explicit (Sec. VI.C), and driven by the Kolmogorov
+ * body force of Sec. VII.
+ *
+ * Conventions
+ *   - Lattice units dx = dt = dQ = 1, c_s^2 = 1/3.
+ *   - Every call returns 0 (TPL_OK) or a negative TPL_E* code; no C++
+ *     exception crosses this boundary.  tpl_last_error() returns a
+ *     thread-local message describing the last failure of the calling thread.
+ *   - A context is used by one host thread at a time.
+ *   - Host buffers passed in are owned by the caller and only read/written
+ *     during the call.  Device buffers are owned by the context (or by the
+ *     caller after tpl_adopt_buffers).
+ *   - Canonical array layouts (row index y, column index x, r = y*nx + x):
+ *       solvent populations  XS[9][ny][nx]
+ *       polymer populations  XP[25][nqd][ny][nx]
+ *       polymer density      psi[nqd][ny][nx]      (psi = sum_k XP_k)
+ *       mixture velocity     U[2][ny][nx]
+ *     D2Q9 order: (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1).
+ *     D4Q25 order: k = 0 rest; k = 1 + 4p + s for coordinate pairs
+ *     p = (vx,vy) (vx,Qx) (vx,Qy) (vy,Qx) (vy,Qy) (Qx,Qy) and sign pairs
+ *     s = (+,+) (+,-) (-,+) (-,-).  Q-disk nodes Q = (a + 1/2 - NQ/2,
+ *     b + 1/2 - NQ/2) with |Q| < NQ/2, numbered row by row (b outer).
+ */
+#ifndef TPL_H
+#define TPL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TPL_OK = 0,
+  TPL_EINVAL = -1,    /* invalid argument or parameter combination */
+  TPL_ENOMEM = -2,    /* device or host allocation failed */
+  TPL_EHIP = -3,      /* a HIP runtime call failed */
+  TPL_ESTATE = -4,    /* call not allowed in the context's current state */
+  TPL_EUNSTABLE = -5, /* the state holds NaN/Inf: the run diverged */
+  TPL_EREJECTED = -6  /* a learned correction was rejected by its drift gate */
+};
+
+enum { TPL_FP64 = 0, TPL_FP32 = 1 };
+enum { TPL_SOLVENT = 0, TPL_POLYMER = 1 };
+
+#define TPL_NFIELDS 10
+#define TPL_NDIAG 9
+
+typedef struct tpl_ctx tpl_ctx;
+
+/* Kolmogorov forcing (Sec. VII): body force F0 sin(2 pi periods y / ny) on the
+ * solvent, F0 = nu u0 k^2 (F = eta U / l^2 with rho = 1). */
+typedef struct {
+  int periods;
+  double u0; /* lattice velocity scale, <= 0.1 */
+} tpl_forcing;
+
+typedef struct {
+  double step;      /* completed time steps since tpl_init */
+  double mass_S;    /* sum of solvent populations */
+  double mass_P;    /* sum of polymer populations */
+  double mom_x;     /* sum of population momenta, both species */
+  double mom_y;
+  double amplitude; /* tpl_perturbation_amplitude() */
+  double enstrophy; /* (1/2) sum omega^2, omega = dUy/dx - dUx/dy (central) */
+  double qrms;      /* sqrt(sum psi |Q|^2 / sum psi) / (NQ/2) */
+  double min_psi;   /* smallest psi over all (r, Q) nodes */
+} tpl_diag;
+
+/* Create a context for an nx x ny periodic lattice (nx = 1 is the x-invariant
+ * column).  Parameters (Sec. VII): Re = u0 l / nu with l = ny / (2 pi periods)
+ * and nu the solution viscosity; beta = eta_s / (eta_s + eta_p);
+ * Wi = u0 lambda / l (Wi = 0: Newtonian limit, no elastic stress).  Derives
+ * every lattice parameter and builds the Q-disk tables on the host; no device
+ * memory is touched until tpl_init.  Returns NULL on error (tpl_last_error):
+ * nx < 1, ny < 4 periods, nx ny >= 2^29, Re <= 0, Wi < 0, beta outside (0, 1], u0 outside
+ * (0, 0.1], or tau1 > tau2 for either species (H-theorem ordering, Sec. IV). */
+tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
+                    tpl_forcing forcing);
+
+/* Set a parameter before tpl_init (TPL_ESTATE afterwards, except for the
+ * launch/timing knobs qsplit and time_kernels, which may be set at any time;
+ * TPL_EINVAL for an unknown key or a value out of range).  Keys and defaults:
+ *   nq 16         Q points per axis (even, 4..48)
+ *   spring 0      0 = FENE (Warner), 1 = Hookean
+ *   b 25          FENE extensibility; sigma = (nq/2) / sqrt(b)
+ *   phi 0.01      polymer mass fraction
+ *   tau_drag 1    solvent tau2 (drag time)
+ *   tau_ratio_p 1 polymer tau1 / tau2
+ *   force_scale 1 multiplies F0
+ *   lambda 0      > 0: polymer relaxation time in steps instead of Wi l / u0
+ *   drift_cap 0.1 cap on the Q-drift D_Q |F/kT| per step (0 = none)
+ *   precision 0   TPL_FP64 or TPL_FP32 population storage
+ *   pert_modes 1  0 = single x-mode, 1 = multimode perturbation
+ *   pre_steps -1  base-state column steps (-1 = 5 max(l^2/nu, lambda))
+ *   qsplit 0      Q-slices per r-tile in the step kernel: 0 (automatic),
+ *                 1, 2, 4 or 8 (other values round down)
+ *   time_kernels 0  1 = time every step-kernel launch with HIP events
+ * Any parameter also fixes the derived values read by tpl_query. */
+int tpl_set_param(tpl_ctx *ctx, const char *key, double value);
+
+/* Read a parameter, a derived value or a size.  Keys: every tpl_set_param key
+ * and nx ny nqd Re Wi beta u0 periods kf l nu nuS G tau1S tau2S tau1P tau2P
+ * lambda_eff sigma R DQ F0 kappa meq Sc rhoS0 rhoP0 step bytes_XS bytes_XP
+ * bytes_PSI bytes_FLD bytes_state bytes_per_step
+ * kernel_ms kernel_launches qsplit_used.  Host only; TPL_EINVAL for an
+ * unknown key. */
+int tpl_query(const tpl_ctx *ctx, const char *key, double *out);
+
+/* Bind a hipStream_t (NULL = the null stream).  All device work of the
+ * context is enqueued on it. */
+int tpl_set_stream(tpl_ctx *ctx, void *hip_stream);
+
+/* Use caller-owned device memory for the state instead of allocating it.
+ * Call before tpl_init.  dptrs[i] must be a device pointer of at least
+ * bytes[i] bytes, 256-byte aligned, for i = 0..3 in the order returned by
+ * tpl_query keys bytes_XS, bytes_XP, bytes_PSI, bytes_FLD (each holds the
+ * double-buffered array).  The caller keeps ownership. */
+int tpl_adopt_buffers(tpl_ctx *ctx, void *const *dptrs, const size_t *bytes,
+                      int n);
+
+/* Allocate the state (TPL_ENOMEM if it does not fit), set the rest state,
+ * run the forced x-invariant base state on a one-column lattice, copy it to
+ * every column and add a seeded perturbation of RMS amplitude
+ * perturbation * u0 (single mode: du_y = perturbation u0 sin(2 pi x/nx + phi0)).
+ * Random numbers: SplitMix64 (Steele, Lea & Flood 2014) seeded by seed.
+ * Synchronises before returning.  May be called again to restart. */
+int tpl_init(tpl_ctx *ctx, uint64_t seed, double perturbation);
+
+/* Advance n >= 0 time steps.  Enqueued on the bound stream; synchronises
+ * before returning.  Returns TPL_EUNSTABLE if the mixture velocity holds a
+ * NaN or Inf afterwards. */
+int tpl_step(tpl_ctx *ctx, int64_t n);
+
+/* Observables of the last completed step (step 0 = the initial state), SoA
+ * [TPL_NFIELDS][ny][nx] doubles: rho, Ux, Uy, rho_P, Cxx, Cxy, Cyy, tau_xx,
+ * tau_xy, tau_yy with C = sum psi Q Q^T / (sigma^2 sum psi) and
+ * tau = G (M / (rho_P0 m_eq) - I), M = sum psi Q F^T / kT.  len counts
+ * doubles; TPL_EINVAL if len < TPL_NFIELDS nx ny. */
+int tpl_moments(tpl_ctx *ctx, double *out, size_t len);
+/* Same into a device buffer of at least len doubles (no synchronisation). */
+int tpl_moments_device(tpl_ctx *ctx, void *dptr, size_t len);
+
+/* A(n) = sqrt(mean over the lattice of |U - <U>_x(y)|^2) / u0, reduced in
+ * FP64 on the device.  NaN on error. */
+double tpl_perturbation_amplitude(tpl_ctx *ctx);
+
+/* FP64 totals and extremes of the current state (see tpl_diag). */
+int tpl_diagnostics(tpl_ctx *ctx, tpl_diag *out);
+
+/* Whole-lattice state exchange in the canonical layouts, as doubles.  Any
+ * pointer may be NULL (that array is skipped).  tpl_set_state requires a
+ * context after tpl_init; it replaces populations, the lagged psi and U and
+ * recomputes every derived per-node field from them. */
+int tpl_get_state(tpl_ctx *ctx, double *XS, double *XP, double *psi,
+                  double *U);
+int tpl_set_state(tpl_ctx *ctx, const double *XS, const double *XP,
+                  const double *psi, const double *U);
+/* A w x h window with periodic wrap starting at (x0, y0), canonical layouts
+ * with nx, ny replaced by w, h. */
+int tpl_get_window(tpl_ctx *ctx, int x0, int y0, int w, int h, double *XS,
+                   double *XP, double *psi, double *U);
+/* One species' populations (TPL_SOLVENT or TPL_POLYMER) as doubles;
+ * bytes must equal the array size. */
+int tpl_get_populations(tpl_ctx *ctx, int species, void *host, size_t bytes);
+int tpl_set_populations(tpl_ctx *ctx, int species, const void *host,
+                        size_t bytes);
+
+/* Checkpoint: parameters, step counter and the full state in storage
+ * precision.  tpl_load requires a context created with the same lattice
+ * size and parameters and resumes bitwise. */
+int tpl_save(tpl_ctx *ctx, const char *path);
+int tpl_load(tpl_ctx *ctx, const char *path);
+
+/* Release everything the context owns.  NULL is ignored. */
+void tpl_destroy(tpl_ctx *ctx);
+
+/* Thread-local description of the last error ("" if none). */
+const char *tpl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,721 @@
+// Device kernels of libtpl for gfx950 (MI355X): the fused stream +
+// quasi-equilibrium step of the two-fluid polymer scheme (arXiv:2201.10132,
+// Sec. VI) and its FP64 initialisation and reduction kernels.
+//
+// Layout (structure of arrays, r = y*nx + x innermost, so a wave's 64 lanes
+// touch 64 consecutive doubles of one plane):
+//   XS[9][N], XP[25][nqd][N], PSI[nqd][N], FLD[NF][N]      (one half)
+#include "tpl_internal.h"
+
+namespace tplk {
+
+// ---------------------------------------------------------------------------
+// Velocity sets.
+// D2Q9 (Sec. VI.A; the standard set, the only one matching the weights
+// 4/9, 1/9, 1/36).
+constexpr int C9X[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int C9Y[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr double W9[9] = {4.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9, 1.0 / 9,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+// D4Q25 (Sec. VI.B, Table I) as (v_x, v_y, Qdot_x, Qdot_y): the rest vector,
+// then for the coordinate pairs (vx,vy) (vx,Qx) (vx,Qy) (vy,Qx) (vy,Qy)
+// (Qx,Qy) the sign pairs (+,+) (+,-) (-,+) (-,-).
+constexpr int PV[25][4] = {
+    {0, 0, 0, 0},                                                    //
+    {1, 1, 0, 0},  {1, -1, 0, 0},  {-1, 1, 0, 0},  {-1, -1, 0, 0},   //
+    {1, 0, 1, 0},  {1, 0, -1, 0},  {-1, 0, 1, 0},  {-1, 0, -1, 0},   //
+    {1, 0, 0, 1},  {1, 0, 0, -1},  {-1, 0, 0, 1},  {-1, 0, 0, -1},   //
+    {0, 1, 1, 0},  {0, 1, -1, 0},  {0, -1, 1, 0},  {0, -1, -1, 0},   //
+    {0, 1, 0, 1},  {0, 1, 0, -1},  {0, -1, 0, 1},  {0, -1, 0, -1},   //
+    {0, 0, 1, 1},  {0, 0, 1, -1},  {0, 0, -1, 1},  {0, 0, -1, -1}};  //
+
+// D2Q9 direction of a D4Q25 velocity's r-part.
+__host__ __device__ constexpr int dir9(int vx, int vy) {
+  return (vx == 0 && vy == 0)    ? 0
+         : (vx == 1 && vy == 0)  ? 1
+         : (vx == 0 && vy == 1)  ? 2
+         : (vx == -1 && vy == 0) ? 3
+         : (vx == 0 && vy == -1) ? 4
+         : (vx == 1 && vy == 1)  ? 5
+         : (vx == -1 && vy == 1) ? 6
+         : (vx == -1 && vy == -1) ? 7
+                                  : 8;
+}
+__host__ __device__ constexpr int pdir(int k) { return dir9(PV[k][0], PV[k][1]); }
+// The velocity with the same r-part and reversed Q-part (Q bounce-back).
+__host__ __device__ constexpr int kstar(int k) {
+  int j = 0;
+  for (int i = 0; i < 25; ++i)
+    if (PV[i][0] == PV[k][0] && PV[i][1] == PV[k][1] &&
+        PV[i][2] == -PV[k][2] && PV[i][3] == -PV[k][3])
+      j = i;
+  return j;
+}
+static_assert(kstar(5) == 6 && kstar(21) == 24 && kstar(22) == 23 &&
+                  kstar(1) == 1 && pdir(9) == 1 && pdir(16) == 4,
+              "D4Q25 table");
+
+__device__ __forceinline__ int xcd_tile(int bid, int tiles_per_xcd) {
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous range of tiles so that stencil neighbours share its L2.
+  return tiles_per_xcd > 0 ? (bid & 7) * tiles_per_xcd + (bid >> 3) : bid;
+}
+
+// ---------------------------------------------------------------------------
+// The fused step.  One lane per r-node; the Q-disk of that node is split over
+// qs waves (slices) of the workgroup, each walking its Q-nodes in order.  All
+// Q-dependent addressing (source Q-node, bounce-back) is wave-uniform.
+//
+// Per r-node, before any Q-node: solvent pull (9), polymer density and
+// momentum from the 9 streamed Q-marginals of the previous step, lagged
+// velocity gradient and spring-stress divergence from the 4 neighbours, the
+// body force, the mixture velocity, the solvent collision.
+// Per (r, Q)-node: pull 25 populations (bounce-back at the disk edge), their
+// moments, the spring term from the lagged psi of the 4 neighbours, the
+// imposed fluxes, the moment inversion, the blended equilibrium and the
+// relaxation; write 25 populations and psi; accumulate the new marginals and
+// M.  The slices' partial marginals are summed in LDS in a fixed order.
+// Loads and stores at a wave-uniform plane base plus a 32-bit byte offset
+// (global_load/store with an SGPR base; every offset is < 8 N < 2^32).  The
+// base goes through readfirstlane so that the compiler cannot fold the
+// per-lane offset into hoisted 64-bit per-lane pointers.
+template <typename T>
+__device__ __forceinline__ T *uni(T *p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double ldo(const double *base, uint32_t off) {
+  return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + off);
+}
+__device__ __forceinline__ void sto(double *base, uint32_t off, double v) {
+  *reinterpret_cast<double *>(reinterpret_cast<char *>(base) + off) = v;
+}
+
+template <int MAXT>
+__global__ void __launch_bounds__(MAXT)
+    k_step_f64(StepParams p, StateView a, StateView b,
+               const QNode *__restrict__ qtab) {
+  extern __shared__ double red[];  // [qs][12][64]
+  const int tile = xcd_tile(blockIdx.x, p.tiles_per_xcd);
+  if (tile >= p.ntiles) return;  // whole workgroup leaves together
+  const int lane = threadIdx.x & 63;
+  const int slice = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long long N = p.N;
+  const long long rr = (long long)tile * 64 + lane;
+  const bool active = rr < N;
+  const int r = (int)(active ? rr : N - 1);
+  const int nx = p.nx, ny = p.ny;
+  const int y = r / nx, x = r - y * nx;
+  const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+  const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
+  const uint32_t oR = 8u * (uint32_t)r;
+  const uint32_t oE = 8u * (uint32_t)(y * nx + xp), oW = 8u * (uint32_t)(y * nx + xm);
+  const uint32_t oN = 8u * (uint32_t)(yp * nx + x), oS = 8u * (uint32_t)(ym * nx + x);
+  uint32_t osrc[9];  // byte offset of the pull source r - c_d
+#pragma unroll
+  for (int d = 0; d < 9; ++d) {
+    const int sx = C9X[d] == 1 ? xm : (C9X[d] == -1 ? xp : x);
+    const int sy = C9Y[d] == 1 ? ym : (C9Y[d] == -1 ? yp : y);
+    osrc[d] = 8u * (uint32_t)(sy * nx + sx);
+  }
+  auto plane = [&](const double *arr, long long i) { return uni(arr + (size_t)i * N); };
+  auto wplane = [&](double *arr, long long i) { return uni(arr + (size_t)i * N); };
+
+  // ---- solvent pull and moments
+  double gS[9], rhoS = 0.0, JSx = 0.0, JSy = 0.0;
+#pragma unroll
+  for (int d = 0; d < 9; ++d) {
+    gS[d] = ldo(plane(a.XS, d), osrc[d]);
+    rhoS += gS[d];
+    if (C9X[d]) JSx += C9X[d] * gS[d];
+    if (C9Y[d]) JSy += C9Y[d] * gS[d];
+  }
+  // ---- polymer density and r-momentum: the streamed Q-marginals
+  double rhoP = 0.0, JPx = 0.0, JPy = 0.0;
+#pragma unroll
+  for (int d = 0; d < 9; ++d) {
+    const double m = ldo(plane(a.FLD, F_M0 + d), osrc[d]);
+    rhoP += m;
+    if (C9X[d]) JPx += C9X[d] * m;
+    if (C9Y[d]) JPy += C9Y[d] * m;
+  }
+  // ---- lagged non-local terms (central differences)
+  auto dX = [&](int f) { return 0.5 * (ldo(plane(a.FLD, f), oE) - ldo(plane(a.FLD, f), oW)); };
+  auto dY = [&](int f) { return 0.5 * (ldo(plane(a.FLD, f), oN) - ldo(plane(a.FLD, f), oS)); };
+  const double Kxx = dX(F_UX), Kxy = dY(F_UX), Kyx = dX(F_UY), Kyy = dY(F_UY);
+  const double Sx = p.kappa * (dX(F_MXX) + dY(F_MXY));
+  const double Sy = p.kappa * (dX(F_MXY) + dY(F_MYY));
+  const double Fbx = p.F0 * sin(p.kf * (double)(y + p.y0));
+  // ---- mixture velocity: exchange of the two species cancels
+  const double den = rhoS * p.aS + rhoP * p.aP;
+  const double Ux = ((JSx + 0.5 * Fbx) * p.aS + (JPx + Sx / (2.0 * p.tau2P)) * p.aP) / den;
+  const double Uy = (JSy * p.aS + (JPy + Sy / (2.0 * p.tau2P)) * p.aP) / den;
+  const bool writer = (slice == 0) && active;
+
+  // ---- solvent collision (slice 0 writes)
+  {
+    const double JfX = (2.0 * p.tau2S * JSx + rhoS * Ux + p.tau2S * Fbx) * p.aS;
+    const double JfY = (2.0 * p.tau2S * JSy + rhoS * Uy) * p.aS;
+    const double usx = JfX / rhoS, usy = JfY / rhoS;
+    const double vx = Ux + p.tau2S * Fbx / rhoS, vy = Uy;
+    const double us2 = usx * usx + usy * usy, v2 = vx * vx + vy * vy;
+    double jx = 0.0, jy = 0.0;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+      const double cu = C9X[d] * usx + C9Y[d] * usy;
+      const double cv = C9X[d] * vx + C9Y[d] * vy;
+      const double fs = W9[d] * rhoS * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * us2);
+      const double fe = W9[d] * rhoS * (1.0 + 3.0 * cv + 4.5 * cv * cv - 1.5 * v2);
+      const double o = p.c1S * gS[d] + p.c2S * ((1.0 - p.rS) * fs + p.rS * fe);
+      if (C9X[d]) jx += C9X[d] * o;
+      if (C9Y[d]) jy += C9Y[d] * o;
+      if (writer) sto(wplane(b.XS, d), oR, o);
+    }
+    if (writer) {
+      sto(wplane(b.FLD, F_JSX), oR, jx);
+      sto(wplane(b.FLD, F_JSY), oR, jy);
+    }
+  }
+
+  // ---- polymer, Q-node by Q-node
+  double mg[9];
+#pragma unroll
+  for (int d = 0; d < 9; ++d) mg[d] = 0.0;
+  double Mxx = 0.0, Mxy = 0.0, Myy = 0.0;
+  const int nqd = p.nqd;
+  const double c2w0 = p.c2P * (1.0 / 3.0), c2w1 = p.c2P * (1.0 / 36.0);
+  const double one_r = 1.0 - p.rP;
+  for (int q = slice; q < nqd; q += p.qs) {
+    const QNode &qn = qtab[q];
+    double g[25];
+#pragma unroll
+    for (int k = 0; k < 25; ++k) g[k] = ldo(plane(a.XP, qn.plane[k]), osrc[pdir(k)]);
+    double psi = 0.0, Jrx = 0.0, Jry = 0.0, JQx = 0.0, JQy = 0.0;
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+      psi += g[k];
+      if (PV[k][0]) Jrx += PV[k][0] * g[k];
+      if (PV[k][1]) Jry += PV[k][1] * g[k];
+      if (PV[k][2]) JQx += PV[k][2] * g[k];
+      if (PV[k][3]) JQy += PV[k][3] * g[k];
+    }
+    // spring term: kappa Fhat (Q . grad psi^{n-1})
+    const double *P = plane(a.PSI, q);
+    const double gx = 0.5 * (ldo(P, oE) - ldo(P, oW));
+    const double gy = 0.5 * (ldo(P, oN) - ldo(P, oS));
+    const double qg = qn.qx * gx + qn.qy * gy;
+    const double sx = p.kappa * qn.fx * qg, sy = p.kappa * qn.fy * qg;
+    // imposed fluxes and moment inversion
+    const double Erx = psi * Ux + sx, Ery = psi * Uy + sy;
+    const double EQx = psi * (Kxx * qn.qx + Kxy * qn.qy - p.DQ * qn.fx);
+    const double EQy = psi * (Kyx * qn.qx + Kyy * qn.qy - p.DQ * qn.fy);
+    const double Frx = (2.0 * p.tau2P * Jrx + Erx) * p.aP;
+    const double Fry = (2.0 * p.tau2P * Jry + Ery) * p.aP;
+    const double FQx = (2.0 * p.tau2P * JQx + EQx) * p.aP;
+    const double FQy = (2.0 * p.tau2P * JQy + EQy) * p.aP;
+    // (1 - r) f* + r f_eq is the linear equilibrium of the blended fluxes
+    double A[4];
+    A[0] = 3.0 * c2w1 * (one_r * Frx + p.rP * Erx);
+    A[1] = 3.0 * c2w1 * (one_r * Fry + p.rP * Ery);
+    A[2] = 3.0 * c2w1 * (one_r * FQx + p.rP * EQx);
+    A[3] = 3.0 * c2w1 * (one_r * FQy + p.rP * EQy);
+    const double h = c2w1 * psi;
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+      double t = (k == 0) ? c2w0 * psi : h;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (PV[k][c]) t += PV[k][c] * A[c];
+      g[k] = p.c1P * g[k] + t;  // post-collision population
+      mg[pdir(k)] += g[k];
+    }
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < 25; ++k) sto(wplane(b.XP, (long long)k * nqd + q), oR, g[k]);
+      sto(wplane(b.PSI, q), oR, psi);
+    }
+    Mxx += psi * qn.qx * qn.fx;
+    Mxy += psi * qn.qx * qn.fy;
+    Myy += psi * qn.qy * qn.fy;
+  }
+
+  // ---- combine the slices' partial sums
+  if (p.qs > 1) {
+    double *mine = red + (size_t)slice * 12 * 64;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) mine[d * 64 + lane] = mg[d];
+    mine[9 * 64 + lane] = Mxx;
+    mine[10 * 64 + lane] = Mxy;
+    mine[11 * 64 + lane] = Myy;
+    __syncthreads();
+    if (slice == 0) {
+      for (int s = 1; s < p.qs; ++s) {
+        const double *o = red + (size_t)s * 12 * 64;
+#pragma unroll
+        for (int d = 0; d < 9; ++d) mg[d] += o[d * 64 + lane];
+        Mxx += o[9 * 64 + lane];
+        Mxy += o[10 * 64 + lane];
+        Myy += o[11 * 64 + lane];
+      }
+    }
+  }
+  if (writer) {
+    sto(wplane(b.FLD, F_RHOS), oR, rhoS);
+    sto(wplane(b.FLD, F_RHOP), oR, rhoP);
+    sto(wplane(b.FLD, F_UX), oR, Ux);
+    sto(wplane(b.FLD, F_UY), oR, Uy);
+    sto(wplane(b.FLD, F_MXX), oR, Mxx);
+    sto(wplane(b.FLD, F_MXY), oR, Mxy);
+    sto(wplane(b.FLD, F_MYY), oR, Myy);
+#pragma unroll
+    for (int d = 0; d < 9; ++d) sto(wplane(b.FLD, F_M0 + d), oR, mg[d]);
+  }
+}
+
+hipError_t launch_step_f64(const StepParams &p, StateView a, StateView b,
+                           const QNode *qtab, hipStream_t s) {
+  const int grid = p.tiles_per_xcd > 0 ? 8 * p.tiles_per_xcd : p.ntiles;
+  const size_t lds = p.qs > 1 ? (size_t)p.qs * 12 * 64 * sizeof(double) : 0;
+  if (p.qs <= 4)
+    hipLaunchKernelGGL(k_step_f64<256>, dim3(grid), dim3(64 * p.qs), lds, s, p,
+                       a, b, qtab);
+  else
+    hipLaunchKernelGGL(k_step_f64<512>, dim3(grid), dim3(64 * p.qs), lds, s,
+                       p, a, b, qtab);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Initial-state kernels.
+
+// Rest: solvent equilibrium at zero velocity; polymer rest distribution.
+__global__ void k_rest(int nqd, long long N, double rhoS0, double rhoP0,
+                       const double *__restrict__ peq, StateView a) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int plane = blockIdx.y;  // 0..8 solvent, then 25*nqd polymer, then psi
+  if (r >= N) return;
+  if (plane < 9) {
+    a.XS[(size_t)plane * N + r] = W9[plane] * rhoS0;
+  } else if (plane < 9 + 25 * nqd) {
+    const int kq = plane - 9, k = kq / nqd, q = kq - k * nqd;
+    a.XP[(size_t)kq * N + r] = (k == 0 ? 1.0 / 3.0 : 1.0 / 36.0) * rhoP0 * peq[q];
+  } else {
+    const int q = plane - 9 - 25 * nqd;
+    a.PSI[(size_t)q * N + r] = rhoP0 * peq[q];
+    if (q == 0) {
+      a.FLD[(size_t)F_UX * N + r] = 0.0;
+      a.FLD[(size_t)F_UY * N + r] = 0.0;
+    }
+  }
+}
+
+hipError_t launch_rest(int nqd, long long N, double rhoS0, double rhoP0,
+                       const double *peq, StateView a, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), 9 + 26 * nqd);
+  hipLaunchKernelGGL(k_rest, grid, dim3(256), 0, s, nqd, N, rhoS0, rhoP0, peq,
+                     a);
+  return hipGetLastError();
+}
+
+// Recompute every per-node field except U from the populations and psi of
+// the same half (used after any direct change of the state).
+__global__ void k_refresh(int nqd, long long N, const QNode *__restrict__ qtab,
+                          StateView a) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  double rs = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+  for (int d = 0; d < 9; ++d) {
+    const double v = a.XS[(size_t)d * N + r];
+    rs += v;
+    jx += C9X[d] * v;
+    jy += C9Y[d] * v;
+  }
+  double mg[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double Mxx = 0.0, Mxy = 0.0, Myy = 0.0;
+  for (int q = 0; q < nqd; ++q) {
+#pragma unroll
+    for (int k = 0; k < 25; ++k) mg[pdir(k)] += a.XP[((size_t)k * nqd + q) * N + r];
+    const double ps = a.PSI[(size_t)q * N + r];
+    Mxx += ps * qtab[q].qx * qtab[q].fx;
+    Mxy += ps * qtab[q].qx * qtab[q].fy;
+    Myy += ps * qtab[q].qy * qtab[q].fy;
+  }
+  double rp = 0.0;
+#pragma unroll
+  for (int d = 0; d < 9; ++d) rp += mg[d];
+  double *G = a.FLD;
+  G[(size_t)F_RHOS * N + r] = rs;
+  G[(size_t)F_RHOP * N + r] = rp;
+  G[(size_t)F_JSX * N + r] = jx;
+  G[(size_t)F_JSY * N + r] = jy;
+  G[(size_t)F_MXX * N + r] = Mxx;
+  G[(size_t)F_MXY * N + r] = Mxy;
+  G[(size_t)F_MYY * N + r] = Myy;
+#pragma unroll
+  for (int d = 0; d < 9; ++d) G[(size_t)(F_M0 + d) * N + r] = mg[d];
+}
+
+hipError_t launch_refresh(int nqd, long long N, const QNode *qtab,
+                          StateView a, hipStream_t s) {
+  hipLaunchKernelGGL(k_refresh, dim3((unsigned)((N + 255) / 256)), dim3(256),
+                     0, s, nqd, N, qtab, a);
+  return hipGetLastError();
+}
+
+// Copy an x-invariant column (nx = 1 lattice) to every column.
+__global__ void k_tile(int nx, int ny, const double *__restrict__ col,
+                       double *__restrict__ dst) {
+  const long long N = (long long)nx * ny;
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t plane = blockIdx.y;
+  if (r >= N) return;
+  const int y = (int)(r / nx);
+  dst[plane * N + r] = col[plane * ny + y];
+}
+
+hipError_t launch_tile(int nqd, int nx, int ny, StateView col, StateView a,
+                       hipStream_t s) {
+  const long long N = (long long)nx * ny;
+  const unsigned gx = (unsigned)((N + 255) / 256);
+  hipLaunchKernelGGL(k_tile, dim3(gx, 9), dim3(256), 0, s, nx, ny, col.XS, a.XS);
+  hipLaunchKernelGGL(k_tile, dim3(gx, 25 * nqd), dim3(256), 0, s, nx, ny,
+                     col.XP, a.XP);
+  hipLaunchKernelGGL(k_tile, dim3(gx, nqd), dim3(256), 0, s, nx, ny, col.PSI,
+                     a.PSI);
+  hipLaunchKernelGGL(k_tile, dim3(gx, NF), dim3(256), 0, s, nx, ny, col.FLD,
+                     a.FLD);
+  return hipGetLastError();
+}
+
+// Block-wide sum of one double (256 threads), fixed order.
+__device__ double block_sum256(double v, double *sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double out = sh[0];
+  __syncthreads();
+  return out;
+}
+__device__ double block_min256(double v, double *sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double out = sh[0];
+  __syncthreads();
+  return out;
+}
+
+// Divergence-free perturbation velocity.  modes[m] = (kx, ky, a, phase).
+// Multimode: du = (d psi/dy, -d psi/dx) of psi = sum a cos(th),
+// th = 2 pi (kx X/NX + ky Y/NY) + phase.  Single mode: du_y = amp_u0
+// sin(2 pi X/NX + phase of mode 0).  partial[block] = sum |du|^2.
+__global__ void k_perturb_field(int nx, int ny, int x0, int y0, int NX, int NY,
+                                int nmodes, const double *__restrict__ modes,
+                                double amp_u0, int multimode,
+                                double *__restrict__ du,
+                                double *__restrict__ partial) {
+  __shared__ double sh[256];
+  const long long N = (long long)nx * ny;
+  const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+  double ux = 0.0, uy = 0.0;
+  if (r < N) {
+    const int y = (int)(r / nx), x = (int)(r - (long long)y * nx);
+    const double X = x + x0, Y = y + y0;
+    const double twopi = 6.283185307179586476925286766559;
+    if (multimode) {
+      for (int m = 0; m < nmodes; ++m) {
+        const double kx = modes[4 * m], ky = modes[4 * m + 1];
+        const double th = twopi * (kx * X / NX + ky * Y / NY) + modes[4 * m + 3];
+        const double sa = modes[4 * m + 2] * sin(th);
+        ux += -sa * (twopi * ky / NY);
+        uy += sa * (twopi * kx / NX);
+      }
+    } else {
+      uy = amp_u0 * sin(twopi * X / NX + modes[3]);
+    }
+    du[r] = ux;
+    du[N + r] = uy;
+  }
+  const double tot = block_sum256(ux * ux + uy * uy, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+hipError_t launch_perturb_field(int nx, int ny, int x0, int y0, int NX, int NY,
+                                int nmodes, const double *modes, double amp_u0,
+                                int multimode, double *du, double *partial,
+                                hipStream_t s) {
+  const long long N = (long long)nx * ny;
+  hipLaunchKernelGGL(k_perturb_field, dim3((unsigned)((N + 255) / 256)),
+                     dim3(256), 0, s, nx, ny, x0, y0, NX, NY, nmodes, modes,
+                     amp_u0, multimode, du, partial);
+  return hipGetLastError();
+}
+
+// Add scale*du at first order to both species and to the lagged U.
+__global__ void k_perturb_apply(int nqd, long long N,
+                                const double *__restrict__ du,
+                                const double *__restrict__ scale,
+                                StateView a) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  const double f = scale[0];
+  const double dx = f * du[r], dy = f * du[N + r];
+  double rs = 0.0;
+#pragma unroll
+  for (int d = 0; d < 9; ++d) rs += a.XS[(size_t)d * N + r];
+#pragma unroll
+  for (int d = 0; d < 9; ++d)
+    a.XS[(size_t)d * N + r] += 3.0 * W9[d] * rs * (C9X[d] * dx + C9Y[d] * dy);
+  for (int q = 0; q < nqd; ++q) {
+    double ps = 0.0;
+#pragma unroll
+    for (int k = 0; k < 25; ++k) ps += a.XP[((size_t)k * nqd + q) * N + r];
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+      if (PV[k][0] == 0 && PV[k][1] == 0) continue;
+      const double w = (k == 0) ? 1.0 / 3.0 : 1.0 / 36.0;
+      a.XP[((size_t)k * nqd + q) * N + r] += 3.0 * w * ps * (PV[k][0] * dx + PV[k][1] * dy);
+    }
+  }
+  a.FLD[(size_t)F_UX * N + r] += dx;
+  a.FLD[(size_t)F_UY * N + r] += dy;
+}
+
+hipError_t launch_perturb_apply(int nqd, long long N, const double *du,
+                                const double *scale, StateView a,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_perturb_apply, dim3((unsigned)((N + 255) / 256)),
+                     dim3(256), 0, s, nqd, N, du, scale, a);
+  return hipGetLastError();
+}
+
+// out[c] = sum_i partial[i*ncomp + c] (one workgroup, fixed order).
+__global__ void k_sum(const double *__restrict__ partial, int n, int ncomp,
+                      double *__restrict__ out) {
+  __shared__ double sh[256];
+  for (int c = 0; c < ncomp; ++c) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) v += partial[(size_t)i * ncomp + c];
+    const double t = block_sum256(v, sh);
+    if (threadIdx.x == 0) out[c] = t;
+  }
+}
+
+hipError_t launch_sum(const double *partial, int n, int ncomp, double *out,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, partial, n, ncomp, out);
+  return hipGetLastError();
+}
+
+// partial[y] = sum_x |U - <U>_x(y)|^2, one workgroup per row.
+__global__ void k_amplitude_rows(int nx, int ny, const double *__restrict__ FLD,
+                                 double *__restrict__ partial) {
+  __shared__ double sh[256];
+  const long long N = (long long)nx * ny;
+  const int y = blockIdx.x;
+  const double *ux = FLD + (size_t)F_UX * N + (size_t)y * nx;
+  const double *uy = FLD + (size_t)F_UY * N + (size_t)y * nx;
+  double sx = 0.0, sy = 0.0;
+  for (int x = threadIdx.x; x < nx; x += 256) {
+    sx += ux[x];
+    sy += uy[x];
+  }
+  const double mx = block_sum256(sx, sh) / nx;
+  const double my = block_sum256(sy, sh) / nx;
+  double acc = 0.0;
+  for (int x = threadIdx.x; x < nx; x += 256) {
+    const double dx = ux[x] - mx, dy = uy[x] - my;
+    acc += dx * dx + dy * dy;
+  }
+  const double t = block_sum256(acc, sh);
+  if (threadIdx.x == 0) partial[y] = t;
+}
+
+hipError_t launch_amplitude_rows(int nx, int ny, const double *FLD,
+                                 double *partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_amplitude_rows, dim3(ny), dim3(256), 0, s, nx, ny, FLD,
+                     partial);
+  return hipGetLastError();
+}
+
+// Diagnostics, one partial per workgroup: masses, population momentum,
+// enstrophy, sum psi |Q|^2, sum psi, min psi.
+__global__ void k_diag(int nx, int ny, int nqd, const QNode *__restrict__ qtab,
+                       StateView a, double *__restrict__ partial) {
+  __shared__ double sh[256];
+  const long long N = (long long)nx * ny;
+  double v[kDiagComp] = {0, 0, 0, 0, 0, 0, 0, 1e300};
+  for (long long r = (long long)blockIdx.x * 256 + threadIdx.x; r < N;
+       r += (long long)gridDim.x * 256) {
+    const double *G = a.FLD;
+    v[0] += G[(size_t)F_RHOS * N + r];
+    v[1] += G[(size_t)F_RHOP * N + r];
+    double px = G[(size_t)F_JSX * N + r], py = G[(size_t)F_JSY * N + r];
+#pragma unroll
+    for (int d = 1; d < 9; ++d) {
+      const double m = G[(size_t)(F_M0 + d) * N + r];
+      px += C9X[d] * m;
+      py += C9Y[d] * m;
+    }
+    v[2] += px;
+    v[3] += py;
+    const int y = (int)(r / nx), x = (int)(r - (long long)y * nx);
+    const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
+    const double *ux = G + (size_t)F_UX * N, *uy = G + (size_t)F_UY * N;
+    const double w = 0.5 * (uy[(size_t)y * nx + xp] - uy[(size_t)y * nx + xm]) -
+                     0.5 * (ux[(size_t)yp * nx + x] - ux[(size_t)ym * nx + x]);
+    v[4] += 0.5 * w * w;
+    for (int q = 0; q < nqd; ++q) {
+      const double ps = a.PSI[(size_t)q * N + r];
+      v[5] += ps * (qtab[q].qx * qtab[q].qx + qtab[q].qy * qtab[q].qy);
+      v[6] += ps;
+      v[7] = fmin(v[7], ps);
+    }
+  }
+  for (int c = 0; c < kDiagComp - 1; ++c) {
+    const double t = block_sum256(v[c], sh);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kDiagComp + c] = t;
+  }
+  const double mn = block_min256(v[7], sh);
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kDiagComp + 7] = mn;
+}
+
+hipError_t launch_diag(int nx, int ny, int nqd, const QNode *qtab,
+                       StateView a, double *partial, int *nblocks,
+                       hipStream_t s) {
+  const long long N = (long long)nx * ny;
+  long long nb = (N + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  *nblocks = (int)nb;
+  hipLaunchKernelGGL(k_diag, dim3((unsigned)nb), dim3(256), 0, s, nx, ny, nqd,
+                     qtab, a, partial);
+  return hipGetLastError();
+}
+
+__global__ void k_diag_final(const double *__restrict__ partial, int n,
+                             double *__restrict__ out) {
+  __shared__ double sh[256];
+  for (int c = 0; c < kDiagComp; ++c) {
+    double v = (c == kDiagComp - 1) ? 1e300 : 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+      const double p = partial[(size_t)i * kDiagComp + c];
+      v = (c == kDiagComp - 1) ? fmin(v, p) : v + p;
+    }
+    const double t = (c == kDiagComp - 1) ? block_min256(v, sh) : block_sum256(v, sh);
+    if (threadIdx.x == 0) out[c] = t;
+  }
+}
+
+hipError_t launch_diag_final(const double *partial, int nblocks, double *out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, partial, nblocks,
+                     out);
+  return hipGetLastError();
+}
+
+// Observables: rho, Ux, Uy, rhoP, C (3), tau_p (3).
+__global__ void k_observables(int nqd, long long N,
+                              const QNode *__restrict__ qtab, double inv_s2,
+                              double G, double mref, StateView a,
+                              double *__restrict__ out) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  double ps = 0.0, cxx = 0.0, cxy = 0.0, cyy = 0.0;
+  for (int q = 0; q < nqd; ++q) {
+    const double v = a.PSI[(size_t)q * N + r];
+    ps += v;
+    cxx += v * qtab[q].qx * qtab[q].qx;
+    cxy += v * qtab[q].qx * qtab[q].qy;
+    cyy += v * qtab[q].qy * qtab[q].qy;
+  }
+  const double *F = a.FLD;
+  const double cn = ps > 0.0 ? inv_s2 / ps : 0.0;
+  out[0 * N + r] = F[(size_t)F_RHOS * N + r] + F[(size_t)F_RHOP * N + r];
+  out[1 * N + r] = F[(size_t)F_UX * N + r];
+  out[2 * N + r] = F[(size_t)F_UY * N + r];
+  out[3 * N + r] = F[(size_t)F_RHOP * N + r];
+  out[4 * N + r] = cxx * cn;
+  out[5 * N + r] = cxy * cn;
+  out[6 * N + r] = cyy * cn;
+  const double g = mref > 0.0 ? G / mref : 0.0;
+  out[7 * N + r] = mref > 0.0 ? g * F[(size_t)F_MXX * N + r] - G : 0.0;
+  out[8 * N + r] = mref > 0.0 ? g * F[(size_t)F_MXY * N + r] : 0.0;
+  out[9 * N + r] = mref > 0.0 ? g * F[(size_t)F_MYY * N + r] - G : 0.0;
+}
+
+hipError_t launch_observables(int nqd, long long N, const QNode *qtab,
+                              double inv_s2, double G, double mref,
+                              StateView a, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_observables, dim3((unsigned)((N + 255) / 256)),
+                     dim3(256), 0, s, nqd, N, qtab, inv_s2, G, mref, a, out);
+  return hipGetLastError();
+}
+
+// Count non-finite mixture-velocity entries per workgroup into partial[], as
+// doubles, so that the generic sum kernel can reduce them.
+__global__ void k_nan_check(long long N, const double *__restrict__ FLD,
+                            double *__restrict__ partial) {
+  __shared__ double sh[256];
+  double bad = 0.0;
+  for (long long r = (long long)blockIdx.x * 256 + threadIdx.x; r < N;
+       r += (long long)gridDim.x * 256) {
+    const double ux = FLD[(size_t)F_UX * N + r], uy = FLD[(size_t)F_UY * N + r];
+    if (!isfinite(ux) || !isfinite(uy)) bad += 1.0;
+  }
+  const double t = block_sum256(bad, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+hipError_t launch_nan_check(long long N, const double *FLD, double *partial,
+                            int *nblocks, hipStream_t s) {
+  long long nb = (N + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  *nblocks = (int)nb;
+  hipLaunchKernelGGL(k_nan_check, dim3((unsigned)nb), dim3(256), 0, s, N, FLD,
+                     partial);
+  return hipGetLastError();
+}
+
+// Gather a w x h window (periodic wrap) of XS, XP, PSI and U into
+// dst[plane][h][w] with planes 9 | 25 nqd | nqd | 2.
+__global__ void k_window(int nx, int ny, int nqd, int x0, int y0, int w,
+                         int h, StateView a, double *__restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int plane = blockIdx.y;
+  if (i >= w * h) return;
+  const int wy = i / w, wx = i - wy * w;
+  const int x = ((x0 + wx) % nx + nx) % nx, y = ((y0 + wy) % ny + ny) % ny;
+  const long long N = (long long)nx * ny;
+  const size_t r = (size_t)y * nx + x;
+  double v;
+  if (plane < 9)
+    v = a.XS[(size_t)plane * N + r];
+  else if (plane < 9 + 25 * nqd)
+    v = a.XP[(size_t)(plane - 9) * N + r];
+  else if (plane < 9 + 26 * nqd)
+    v = a.PSI[(size_t)(plane - 9 - 25 * nqd) * N + r];
+  else
+    v = a.FLD[(size_t)(F_UX + plane - 9 - 26 * nqd) * N + r];
+  dst[(size_t)plane * w * h + i] = v;
+}
+
+hipError_t launch_window(int nx, int ny, int nqd, int x0, int y0, int w, int h,
+                         StateView a, double *dst, hipStream_t s) {
+  dim3 grid((unsigned)((w * h + 255) / 256), 9 + 26 * nqd + 2);
+  hipLaunchKernelGGL(k_window, grid, dim3(256), 0, s, nx, ny, nqd, x0, y0, w,
+                     h, a, dst);
+  return hipGetLastError();
+}
+
+}  // namespace tplk

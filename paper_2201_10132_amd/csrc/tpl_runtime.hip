@@ -1,0 +1,868 @@
+// Host runtime of libtpl: parameter derivation, Q-disk tables, device state,
+// initialisation sequence, time stepping and the C ABI of include/tpl.h.
+#include "../../include/tpl.h"
+#include "tpl_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace tplk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                       \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return fail(TPL_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kCs2 = 1.0 / 3.0;
+
+// Configuration (inputs) and everything derived from it (step 0 of the
+// scheme: Sec. VII parameter definitions; Sec. IV viscosity ~ tau1; App. A
+// Q-diffusivity 2 kT / zeta).
+struct Config {
+  int nx = 0, ny = 0, periods = 1;
+  double Re = 0, Wi = 0, beta = 1, u0 = 0.05;
+  int nq = 16, spring = 0, precision = TPL_FP64, pert_modes = 1;
+  double b = 25.0, phi = 0.01, tau_drag = 1.0, tau_ratio_p = 1.0;
+  double force_scale = 1.0, lambda_set = 0.0, drift_cap = 0.1;
+  long long pre_steps = -1;
+  int qsplit = 0, time_kernels = 0;
+};
+
+struct Derived {
+  double kf, l, nu, nuS, lambda, G, tau1S, tau2S, tau1P, tau2P;
+  double R, sigma, DQ, F0, kappa, meq, rhoS0, rhoP0, Sc;
+  int nqd;
+  std::vector<QNode> qtab;
+  std::vector<double> peq;
+};
+
+int derive(const Config &c, Derived &d) {
+  if (c.nx < 1 || c.ny < 1) return fail(TPL_EINVAL, "nx, ny must be >= 1");
+  if (c.periods < 1 || c.ny < 4 * c.periods)
+    return fail(TPL_EINVAL, "need periods >= 1 and ny >= 4 periods");
+  if (!(c.Re > 0)) return fail(TPL_EINVAL, "Re must be > 0");
+  if (!(c.Wi >= 0)) return fail(TPL_EINVAL, "Wi must be >= 0");
+  if (!(c.beta > 0 && c.beta <= 1)) return fail(TPL_EINVAL, "beta must be in (0,1]");
+  if (!(c.u0 > 0 && c.u0 <= 0.1)) return fail(TPL_EINVAL, "u0 must be in (0,0.1]");
+  if (c.nq < 4 || c.nq > 48 || (c.nq & 1)) return fail(TPL_EINVAL, "nq must be even in [4,48]");
+  if (!(c.phi >= 0 && c.phi < 1)) return fail(TPL_EINVAL, "phi must be in [0,1)");
+  if (!(c.b > 1)) return fail(TPL_EINVAL, "b must be > 1");
+  if (!(c.tau_ratio_p > 0 && c.tau_ratio_p <= 1))
+    return fail(TPL_EINVAL, "tau_ratio_p must be in (0,1] (tau1 <= tau2)");
+  // the step kernel addresses a plane with 32-bit byte offsets: 8 N < 2^32
+  if ((long long)c.nx * c.ny >= (1LL << 29)) return fail(TPL_EINVAL, "lattice too large");
+
+  d.kf = 2.0 * kPi * c.periods / c.ny;
+  d.l = 1.0 / d.kf;
+  d.nu = c.u0 * d.l / c.Re;
+  d.rhoS0 = 1.0 - c.phi;
+  d.rhoP0 = c.phi;
+  d.R = 0.5 * c.nq;
+  d.sigma = d.R / std::sqrt(c.b);
+  if (c.Wi > 0) {
+    d.lambda = c.Wi * d.l / c.u0;
+    d.nuS = c.beta * d.nu;
+    d.G = (1.0 - c.beta) * d.nu / d.lambda;  // eta_p = G lambda, rho = 1
+  } else {  // Newtonian limit: passive polymer, no elastic stress
+    d.lambda = d.l / c.u0;
+    d.nuS = d.nu;
+    d.G = 0.0;
+  }
+  if (c.lambda_set > 0) {
+    d.G *= d.lambda / c.lambda_set;
+    d.lambda = c.lambda_set;
+  }
+  d.tau1S = d.nuS / kCs2;
+  d.tau2S = c.tau_drag;
+  d.tau2P = d.sigma * d.sigma / (2.0 * kCs2 * d.lambda);
+  d.tau1P = c.tau_ratio_p * d.tau2P;
+  d.DQ = kCs2 * d.tau2P;
+  d.F0 = c.force_scale * d.nu * c.u0 * d.kf * d.kf;
+  d.Sc = d.nuS / (kCs2 * d.tau2P);
+  if (d.tau1S > d.tau2S * (1.0 + 1e-12))
+    return fail(TPL_EINVAL, "solvent tau1 = " + std::to_string(d.tau1S) +
+                                " exceeds tau2 = tau_drag (H-theorem ordering)");
+
+  // Q-disk: half-integer nodes strictly inside |Q| < R, row by row.
+  const int nq = c.nq;
+  std::vector<int> idx(nq * nq, -1);
+  std::vector<int> ia, ib;
+  for (int bq = 0; bq < nq; ++bq)
+    for (int aq = 0; aq < nq; ++aq) {
+      const double qx = aq + 0.5 - d.R, qy = bq + 0.5 - d.R;
+      if (qx * qx + qy * qy < d.R * d.R) {
+        idx[bq * nq + aq] = (int)ia.size();
+        ia.push_back(aq);
+        ib.push_back(bq);
+      }
+    }
+  d.nqd = (int)ia.size();
+  d.qtab.assign(d.nqd, QNode{});
+  d.peq.assign(d.nqd, 0.0);
+  static const int PVh[25][4] = {
+      {0, 0, 0, 0},   {1, 1, 0, 0},   {1, -1, 0, 0},  {-1, 1, 0, 0},
+      {-1, -1, 0, 0}, {1, 0, 1, 0},   {1, 0, -1, 0},  {-1, 0, 1, 0},
+      {-1, 0, -1, 0}, {1, 0, 0, 1},   {1, 0, 0, -1},  {-1, 0, 0, 1},
+      {-1, 0, 0, -1}, {0, 1, 1, 0},   {0, 1, -1, 0},  {0, -1, 1, 0},
+      {0, -1, -1, 0}, {0, 1, 0, 1},   {0, 1, 0, -1},  {0, -1, 0, 1},
+      {0, -1, 0, -1}, {0, 0, 1, 1},   {0, 0, 1, -1},  {0, 0, -1, 1},
+      {0, 0, -1, -1}};
+  const double s2 = d.sigma * d.sigma, bs2 = c.b * s2;
+  double wsum = 0.0;
+  for (int q = 0; q < d.nqd; ++q) {
+    QNode &n = d.qtab[q];
+    n.qx = ia[q] + 0.5 - d.R;
+    n.qy = ib[q] + 0.5 - d.R;
+    const double q2 = n.qx * n.qx + n.qy * n.qy;
+    // spring force / kT: Hookean Q/sigma^2 or Warner FENE
+    // Q / (sigma^2 (1 - Q^2/(b sigma^2))), capped so that the Q-drift
+    // D_Q |F/kT| stays <= drift_cap per step
+    double f = 1.0 / s2;
+    if (c.spring == 0) f /= (1.0 - q2 / bs2);
+    const double drift = d.DQ * f * std::sqrt(q2);
+    if (c.drift_cap > 0 && drift > c.drift_cap) f *= c.drift_cap / drift;
+    n.fx = f * n.qx;
+    n.fy = f * n.qy;
+    for (int k = 0; k < 25; ++k) {
+      const int sa = ia[q] - PVh[k][2], sb = ib[q] - PVh[k][3];
+      const int src = (sa >= 0 && sb >= 0 && sa < nq && sb < nq) ? idx[sb * nq + sa] : -1;
+      int ks = k;  // same r-velocity, reversed Q-velocity
+      for (int j = 0; j < 25; ++j)
+        if (PVh[j][0] == PVh[k][0] && PVh[j][1] == PVh[k][1] && PVh[j][2] == -PVh[k][2] &&
+            PVh[j][3] == -PVh[k][3])
+          ks = j;
+      n.plane[k] = src >= 0 ? k * d.nqd + src : ks * d.nqd + q;
+    }
+    n.pad[0] = n.pad[1] = n.pad[2] = 0;
+    const double w = c.spring == 0 ? std::pow(1.0 - q2 / bs2, 0.5 * c.b)
+                                   : std::exp(-0.5 * q2 / s2);
+    d.peq[q] = w;
+    wsum += w;
+  }
+  double m = 0.0;
+  for (int q = 0; q < d.nqd; ++q) {
+    d.peq[q] /= wsum;
+    m += d.peq[q] * (d.qtab[q].qx * d.qtab[q].fx + d.qtab[q].qy * d.qtab[q].fy);
+  }
+  d.meq = 0.5 * m;
+  d.kappa = d.rhoP0 > 0 ? d.G * d.tau2P / (d.rhoP0 * d.meq) : 0.0;
+  return TPL_OK;
+}
+
+struct Buffers {  // double-buffered state: element offsets of each half
+  double *XS = nullptr, *XP = nullptr, *PSI = nullptr, *FLD = nullptr;
+  size_t nXS = 0, nXP = 0, nPSI = 0, nFLD = 0;  // elements per half
+  StateView half(int h) const {
+    return StateView{XS + h * nXS, XP + h * nXP, PSI + h * nPSI, FLD + h * nFLD};
+  }
+};
+
+}  // namespace
+
+struct tpl_ctx {
+  Config c;
+  Derived d;
+  hipStream_t stream = nullptr;
+  bool inited = false, owned = true;
+  Buffers buf;
+  int cur = 0;
+  long long step = 0;
+  QNode *qtab_d = nullptr;
+  double *peq_d = nullptr;
+  double *scratch = nullptr;  // reductions, perturbation field, windows
+  size_t scratch_n = 0;
+  double kernel_ms = 0.0;
+  long long kernel_launches = 0;
+  int qs_used = 0;
+};
+
+namespace {
+
+size_t state_elems(const tpl_ctx *x, int which) {
+  const size_t N = (size_t)x->c.nx * x->c.ny, nqd = x->d.nqd;
+  switch (which) {
+    case 0: return 9 * N;
+    case 1: return 25 * nqd * N;
+    case 2: return nqd * N;
+    default: return (size_t)NF * N;
+  }
+}
+
+StepParams make_step_params(const tpl_ctx *x, int nx, int ny, int qs_req) {
+  StepParams p{};
+  const Derived &d = x->d;
+  p.nx = nx;
+  p.ny = ny;
+  p.N = (long long)nx * ny;
+  p.nqd = d.nqd;
+  p.ntiles = (int)((p.N + 63) / 64);
+  int qs = qs_req;
+  if (qs <= 0) {  // aim at >= 2048 waves in flight, at most 8 slices
+    qs = 1;
+    while (qs < 8 && (long long)p.ntiles * qs < 2048) qs *= 2;
+  }
+  // 1, 2, 4 or 8 slices (the slice reduction uses qs * 6 KB of LDS)
+  qs = qs >= 8 ? 8 : qs >= 4 ? 4 : qs >= 2 ? 2 : 1;
+  p.qs = qs;
+  p.tiles_per_xcd = p.ntiles >= 64 ? (p.ntiles + 7) / 8 : 0;
+  p.y0 = 0;
+  p.aS = 1.0 / (2.0 * d.tau2S + 1.0);
+  p.aP = 1.0 / (2.0 * d.tau2P + 1.0);
+  p.tau2S = d.tau2S;
+  p.tau2P = d.tau2P;
+  const double bS = 1.0 / (2.0 * d.tau1S + 1.0), bP = 1.0 / (2.0 * d.tau1P + 1.0);
+  p.c1S = 1.0 - 2.0 * bS;
+  p.c2S = 2.0 * bS;
+  p.rS = d.tau1S / d.tau2S;
+  p.c1P = 1.0 - 2.0 * bP;
+  p.c2P = 2.0 * bP;
+  p.rP = d.tau1P / d.tau2P;
+  p.kappa = d.kappa;
+  p.DQ = d.DQ;
+  p.F0 = d.F0;
+  p.kf = d.kf;
+  return p;
+}
+
+int ensure_scratch(tpl_ctx *x, size_t n) {
+  if (x->scratch_n >= n) return TPL_OK;
+  if (x->scratch) HIPCHK(hipFree(x->scratch));
+  x->scratch = nullptr;
+  x->scratch_n = 0;
+  if (hipMalloc(&x->scratch, n * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TPL_ENOMEM, "scratch allocation failed");
+  }
+  x->scratch_n = n;
+  return TPL_OK;
+}
+
+int alloc_state(tpl_ctx *x) {
+  if (x->buf.XS) return TPL_OK;
+  Buffers &B = x->buf;
+  B.nXS = state_elems(x, 0);
+  B.nXP = state_elems(x, 1);
+  B.nPSI = state_elems(x, 2);
+  B.nFLD = state_elems(x, 3);
+  double **ptrs[4] = {&B.XS, &B.XP, &B.PSI, &B.FLD};
+  size_t n[4] = {B.nXS, B.nXP, B.nPSI, B.nFLD};
+  for (int i = 0; i < 4; ++i) {
+    if (hipMalloc(ptrs[i], 2 * n[i] * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      for (int j = 0; j < i; ++j) {
+        (void)hipFree(*ptrs[j]);
+        *ptrs[j] = nullptr;
+      }
+      B.XS = B.XP = B.PSI = B.FLD = nullptr;
+      char msg[160];
+      snprintf(msg, sizeof msg, "device allocation of %.2f GB failed",
+               2.0 * n[i] * sizeof(double) / 1e9);
+      return fail(TPL_ENOMEM, msg);
+    }
+  }
+  x->owned = true;
+  return TPL_OK;
+}
+
+int upload_tables(tpl_ctx *x) {
+  if (x->qtab_d) HIPCHK(hipFree(x->qtab_d));
+  if (x->peq_d) HIPCHK(hipFree(x->peq_d));
+  x->qtab_d = nullptr;
+  x->peq_d = nullptr;
+  HIPCHK(hipMalloc(&x->qtab_d, sizeof(QNode) * x->d.nqd));
+  HIPCHK(hipMalloc(&x->peq_d, sizeof(double) * x->d.nqd));
+  HIPCHK(hipMemcpyAsync(x->qtab_d, x->d.qtab.data(), sizeof(QNode) * x->d.nqd,
+                        hipMemcpyHostToDevice, x->stream));
+  HIPCHK(hipMemcpyAsync(x->peq_d, x->d.peq.data(), sizeof(double) * x->d.nqd,
+                        hipMemcpyHostToDevice, x->stream));
+  return TPL_OK;
+}
+
+// Enqueue n steps of an nx x ny lattice held in B (halves *cur and 1-*cur).
+int run_steps(tpl_ctx *x, const Buffers &B, int nx, int ny, int *cur,
+              long long n, bool timed) {
+  StepParams p = make_step_params(x, nx, ny, x->c.qsplit);
+  x->qs_used = p.qs;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+  }
+  for (long long i = 0; i < n; ++i) {
+    if (timed) HIPCHK(hipEventRecord(e0, x->stream));
+    HIPCHK(launch_step_f64(p, B.half(*cur), B.half(1 - *cur), x->qtab_d, x->stream));
+    if (timed) {
+      HIPCHK(hipEventRecord(e1, x->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      x->kernel_ms += ms;
+      x->kernel_launches++;
+    }
+    *cur = 1 - *cur;
+  }
+  if (timed) {
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+  }
+  return TPL_OK;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014) and the uniform double it yields.
+struct SplitMix64 {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return (double)(next() >> 11) * 0x1.0p-53; }
+};
+
+int perturb(tpl_ctx *x, uint64_t seed, double amp) {
+  const int nx = x->c.nx, ny = x->c.ny;
+  const long long N = (long long)nx * ny;
+  const int multimode = x->c.pert_modes ? 1 : 0;
+  // mode table: (kx, ky, a, phase); a ~ N(0,1) by Box-Muller, phase ~ U[0,2pi)
+  std::vector<double> modes;
+  SplitMix64 rng{seed};
+  if (multimode) {
+    for (int kx = -8; kx <= 8; ++kx) {
+      if (kx == 0) continue;
+      for (int ky = -8; ky <= 8; ++ky) {
+        const double u1 = rng.uniform(), u2 = rng.uniform(), u3 = rng.uniform();
+        modes.push_back(kx);
+        modes.push_back(ky);
+        modes.push_back(std::sqrt(-2.0 * std::log(1.0 - u1)) * std::cos(2.0 * kPi * u2));
+        modes.push_back(2.0 * kPi * u3);
+      }
+    }
+  } else {
+    const double ph = 2.0 * kPi * rng.uniform();
+    modes = {1.0, 0.0, 1.0, ph};
+  }
+  const int nmodes = (int)modes.size() / 4;
+  const long long nb = (N + 255) / 256;
+  // scratch: modes | du[2N] | partial[nb] | sum[1] | scale[1]
+  const size_t need = modes.size() + 2 * N + nb + 2;
+  int rc = ensure_scratch(x, need);
+  if (rc) return rc;
+  double *d_modes = x->scratch, *du = d_modes + modes.size(), *part = du + 2 * N;
+  double *sum = part + nb, *scale = sum + 1;
+  HIPCHK(hipMemcpyAsync(d_modes, modes.data(), modes.size() * sizeof(double),
+                        hipMemcpyHostToDevice, x->stream));
+  HIPCHK(launch_perturb_field(nx, ny, 0, 0, nx, ny, nmodes, d_modes,
+                              amp * x->c.u0, multimode, du, part, x->stream));
+  double h_scale = 1.0;
+  if (multimode) {
+    HIPCHK(launch_sum(part, (int)nb, 1, sum, x->stream));
+    double tot = 0.0;
+    HIPCHK(hipMemcpyAsync(&tot, sum, sizeof(double), hipMemcpyDeviceToHost, x->stream));
+    HIPCHK(hipStreamSynchronize(x->stream));
+    const double rms = std::sqrt(tot / (double)N);
+    h_scale = rms > 0 ? amp * x->c.u0 / rms : 0.0;
+  }
+  HIPCHK(hipMemcpyAsync(scale, &h_scale, sizeof(double), hipMemcpyHostToDevice,
+                        x->stream));
+  HIPCHK(launch_perturb_apply(x->d.nqd, N, du, scale, x->buf.half(x->cur), x->stream));
+  HIPCHK(launch_refresh(x->d.nqd, N, x->qtab_d, x->buf.half(x->cur), x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  return TPL_OK;
+}
+
+int check_ready(const tpl_ctx *x) {
+  if (!x) return fail(TPL_EINVAL, "null context");
+  if (!x->inited) return fail(TPL_ESTATE, "context not initialised (call tpl_init)");
+  return TPL_OK;
+}
+
+struct Key {
+  const char *name;
+  double Config::*dbl;
+  int Config::*in;
+  long long Config::*ll;
+};
+
+const Key kKeys[] = {
+    {"nq", nullptr, &Config::nq, nullptr},
+    {"spring", nullptr, &Config::spring, nullptr},
+    {"b", &Config::b, nullptr, nullptr},
+    {"phi", &Config::phi, nullptr, nullptr},
+    {"tau_drag", &Config::tau_drag, nullptr, nullptr},
+    {"tau_ratio_p", &Config::tau_ratio_p, nullptr, nullptr},
+    {"force_scale", &Config::force_scale, nullptr, nullptr},
+    {"lambda", &Config::lambda_set, nullptr, nullptr},
+    {"drift_cap", &Config::drift_cap, nullptr, nullptr},
+    {"precision", nullptr, &Config::precision, nullptr},
+    {"pert_modes", nullptr, &Config::pert_modes, nullptr},
+    {"pre_steps", nullptr, nullptr, &Config::pre_steps},
+    {"qsplit", nullptr, &Config::qsplit, nullptr},
+    {"time_kernels", nullptr, &Config::time_kernels, nullptr},
+    {"u0", &Config::u0, nullptr, nullptr},
+    {"periods", nullptr, &Config::periods, nullptr},
+};
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+extern "C" {
+
+const char *tpl_last_error(void) { return g_err.c_str(); }
+
+tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
+                    tpl_forcing forcing) {
+  g_err.clear();
+  tpl_ctx *x = new (std::nothrow) tpl_ctx();
+  if (!x) {
+    fail(TPL_ENOMEM, "host allocation failed");
+    return nullptr;
+  }
+  x->c.nx = nx;
+  x->c.ny = ny;
+  x->c.Re = Re;
+  x->c.Wi = Wi;
+  x->c.beta = beta;
+  x->c.periods = forcing.periods;
+  x->c.u0 = forcing.u0;
+  if (derive(x->c, x->d) != TPL_OK) {
+    delete x;
+    return nullptr;
+  }
+  return x;
+}
+
+int tpl_set_param(tpl_ctx *x, const char *key, double v) {
+  if (!x || !key) return fail(TPL_EINVAL, "null argument");
+  // launch and timing knobs change no state and may be set at any time
+  const bool runtime_knob = !std::strcmp(key, "qsplit") || !std::strcmp(key, "time_kernels");
+  if (x->inited && !runtime_knob)
+    return fail(TPL_ESTATE, "parameters are fixed after tpl_init");
+  Config c = x->c;
+  bool found = false;
+  for (const Key &k : kKeys) {
+    if (std::strcmp(k.name, key) != 0) continue;
+    found = true;
+    if (k.dbl) c.*(k.dbl) = v;
+    if (k.in) {
+      if (v != std::floor(v)) return fail(TPL_EINVAL, std::string(key) + " must be an integer");
+      c.*(k.in) = (int)v;
+    }
+    if (k.ll) c.*(k.ll) = (long long)v;
+  }
+  if (!found) return fail(TPL_EINVAL, std::string("unknown parameter ") + key);
+  if (c.spring != 0 && c.spring != 1) return fail(TPL_EINVAL, "spring must be 0 or 1");
+  if (c.precision != TPL_FP64)
+    return fail(TPL_EINVAL, "precision: only TPL_FP64 is built in this library");
+  if (c.qsplit < 0 || c.qsplit > 8) return fail(TPL_EINVAL, "qsplit must be in [0,8]");
+  if (!(c.drift_cap >= 0)) return fail(TPL_EINVAL, "drift_cap must be >= 0");
+  if (runtime_knob) {
+    x->c = c;
+    return TPL_OK;
+  }
+  Derived d;
+  int rc = derive(c, d);
+  if (rc) return rc;
+  x->c = c;
+  x->d = std::move(d);
+  return TPL_OK;
+}
+
+int tpl_query(const tpl_ctx *x, const char *key, double *out) {
+  if (!x || !key || !out) return fail(TPL_EINVAL, "null argument");
+  for (const Key &k : kKeys)
+    if (std::strcmp(k.name, key) == 0) {
+      *out = k.dbl ? x->c.*(k.dbl) : k.in ? (double)(x->c.*(k.in)) : (double)(x->c.*(k.ll));
+      return TPL_OK;
+    }
+  const Derived &d = x->d;
+  const double N = (double)x->c.nx * x->c.ny;
+  struct {
+    const char *n;
+    double v;
+  } vals[] = {
+      {"nx", (double)x->c.nx}, {"ny", (double)x->c.ny}, {"nqd", (double)d.nqd},
+      {"Re", x->c.Re}, {"Wi", x->c.Wi}, {"beta", x->c.beta},
+      {"kf", d.kf}, {"l", d.l}, {"nu", d.nu}, {"nuS", d.nuS}, {"G", d.G},
+      {"tau1S", d.tau1S}, {"tau2S", d.tau2S}, {"tau1P", d.tau1P},
+      {"tau2P", d.tau2P}, {"lambda_eff", d.lambda}, {"sigma", d.sigma},
+      {"R", d.R}, {"DQ", d.DQ}, {"F0", d.F0}, {"kappa", d.kappa},
+      {"meq", d.meq}, {"Sc", d.Sc}, {"rhoS0", d.rhoS0}, {"rhoP0", d.rhoP0},
+      {"step", (double)x->step},
+      {"bytes_XS", 16.0 * 9 * N}, {"bytes_XP", 16.0 * 25 * d.nqd * N},
+      {"bytes_PSI", 16.0 * d.nqd * N}, {"bytes_FLD", 16.0 * NF * N},
+      {"bytes_state", 16.0 * N * (9 + 26.0 * d.nqd + NF)},
+      // algorithmic HBM bytes of one step: populations read + written,
+      // lagged psi written + read, lagged per-node fields written + read
+      {"bytes_per_step", 8.0 * N * (2.0 * (9 + 25.0 * d.nqd) + 2.0 * d.nqd + 2.0 * NF)},
+      {"kernel_ms", x->kernel_ms}, {"kernel_launches", (double)x->kernel_launches},
+      {"qsplit_used", (double)x->qs_used},
+  };
+  for (auto &kv : vals)
+    if (std::strcmp(kv.n, key) == 0) {
+      *out = kv.v;
+      return TPL_OK;
+    }
+  return fail(TPL_EINVAL, std::string("unknown query key ") + key);
+}
+
+int tpl_set_stream(tpl_ctx *x, void *s) {
+  if (!x) return fail(TPL_EINVAL, "null context");
+  x->stream = (hipStream_t)s;
+  return TPL_OK;
+}
+
+int tpl_adopt_buffers(tpl_ctx *x, void *const *dptrs, const size_t *bytes, int n) {
+  if (!x || !dptrs || !bytes) return fail(TPL_EINVAL, "null argument");
+  if (x->inited || x->buf.XS) return fail(TPL_ESTATE, "buffers already allocated");
+  if (n != 4) return fail(TPL_EINVAL, "expected 4 buffers (XS, XP, PSI, FLD)");
+  Buffers B;
+  B.nXS = state_elems(x, 0);
+  B.nXP = state_elems(x, 1);
+  B.nPSI = state_elems(x, 2);
+  B.nFLD = state_elems(x, 3);
+  size_t need[4] = {B.nXS, B.nXP, B.nPSI, B.nFLD};
+  for (int i = 0; i < 4; ++i) {
+    if (!dptrs[i] || bytes[i] < 2 * need[i] * sizeof(double))
+      return fail(TPL_EINVAL, "adopted buffer " + std::to_string(i) + " too small");
+    if (((uintptr_t)dptrs[i]) & 255) return fail(TPL_EINVAL, "adopted buffer not 256-byte aligned");
+  }
+  B.XS = (double *)dptrs[0];
+  B.XP = (double *)dptrs[1];
+  B.PSI = (double *)dptrs[2];
+  B.FLD = (double *)dptrs[3];
+  x->buf = B;
+  x->owned = false;
+  return TPL_OK;
+}
+
+int tpl_init(tpl_ctx *x, uint64_t seed, double perturbation) {
+  if (!x) return fail(TPL_EINVAL, "null context");
+  if (!(perturbation >= 0)) return fail(TPL_EINVAL, "perturbation must be >= 0");
+  int rc = alloc_state(x);
+  if (rc) return rc;
+  if (!x->inited || !x->qtab_d) {
+    rc = upload_tables(x);
+    if (rc) return rc;
+  }
+  const Derived &d = x->d;
+  const int nx = x->c.nx, ny = x->c.ny;
+  x->cur = 0;
+  x->step = 0;
+  long long npre = x->c.pre_steps;
+  if (npre < 0) npre = (long long)std::ceil(5.0 * std::max(d.l * d.l / d.nu, d.lambda));
+  // base state on one column, then copied to every column
+  {
+    Buffers C;
+    C.nXS = 9 * (size_t)ny;
+    C.nXP = 25 * (size_t)d.nqd * ny;
+    C.nPSI = (size_t)d.nqd * ny;
+    C.nFLD = (size_t)NF * ny;
+    double *col = nullptr;
+    const size_t tot = 2 * (C.nXS + C.nXP + C.nPSI + C.nFLD);
+    if (hipMalloc(&col, tot * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(TPL_ENOMEM, "column allocation failed");
+    }
+    C.XS = col;
+    C.XP = C.XS + 2 * C.nXS;
+    C.PSI = C.XP + 2 * C.nXP;
+    C.FLD = C.PSI + 2 * C.nPSI;
+    int ccur = 0;
+    int e = TPL_OK;
+    auto run = [&]() -> int {
+      HIPCHK(launch_rest(d.nqd, ny, d.rhoS0, d.rhoP0, x->peq_d, C.half(0), x->stream));
+      HIPCHK(launch_refresh(d.nqd, ny, x->qtab_d, C.half(0), x->stream));
+      int r2 = run_steps(x, C, 1, ny, &ccur, npre, false);
+      if (r2) return r2;
+      HIPCHK(launch_tile(d.nqd, nx, ny, C.half(ccur), x->buf.half(0), x->stream));
+      HIPCHK(hipStreamSynchronize(x->stream));
+      return TPL_OK;
+    };
+    e = run();
+    (void)hipFree(col);
+    if (e) return e;
+  }
+  x->inited = true;
+  if (perturbation > 0) {
+    rc = perturb(x, seed, perturbation);
+    if (rc) return rc;
+  }
+  x->kernel_ms = 0.0;
+  x->kernel_launches = 0;
+  return TPL_OK;
+}
+
+int tpl_step(tpl_ctx *x, int64_t n) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  if (n < 0) return fail(TPL_EINVAL, "n must be >= 0");
+  rc = run_steps(x, x->buf, x->c.nx, x->c.ny, &x->cur, n, x->c.time_kernels != 0);
+  if (rc) return rc;
+  x->step += n;
+  // divergence check on the mixture velocity
+  const long long N = (long long)x->c.nx * x->c.ny;
+  rc = ensure_scratch(x, 1024 + 1);
+  if (rc) return rc;
+  int nb = 0;
+  HIPCHK(launch_nan_check(N, x->buf.half(x->cur).FLD, x->scratch, &nb, x->stream));
+  HIPCHK(launch_sum(x->scratch, nb, 1, x->scratch + 1024, x->stream));
+  double bad = 0.0;
+  HIPCHK(hipMemcpyAsync(&bad, x->scratch + 1024, sizeof(double), hipMemcpyDeviceToHost,
+                        x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  if (bad != 0.0)
+    return fail(TPL_EUNSTABLE, "mixture velocity is not finite at " +
+                                   std::to_string((long long)bad) + " nodes");
+  return TPL_OK;
+}
+
+int tpl_moments_device(tpl_ctx *x, void *dptr, size_t len) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  const long long N = (long long)x->c.nx * x->c.ny;
+  if (!dptr || len < (size_t)TPL_NFIELDS * N) return fail(TPL_EINVAL, "output too small");
+  const double s2 = x->d.sigma * x->d.sigma;
+  HIPCHK(launch_observables(x->d.nqd, N, x->qtab_d, 1.0 / s2, x->d.G,
+                            x->d.rhoP0 * x->d.meq, x->buf.half(x->cur),
+                            (double *)dptr, x->stream));
+  return TPL_OK;
+}
+
+int tpl_moments(tpl_ctx *x, double *out, size_t len) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  const long long N = (long long)x->c.nx * x->c.ny;
+  if (!out || len < (size_t)TPL_NFIELDS * N) return fail(TPL_EINVAL, "output too small");
+  rc = ensure_scratch(x, (size_t)TPL_NFIELDS * N);
+  if (rc) return rc;
+  rc = tpl_moments_device(x, x->scratch, (size_t)TPL_NFIELDS * N);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(out, x->scratch, sizeof(double) * TPL_NFIELDS * N,
+                        hipMemcpyDeviceToHost, x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  return TPL_OK;
+}
+
+double tpl_perturbation_amplitude(tpl_ctx *x) {
+  if (check_ready(x)) return NAN;
+  const int nx = x->c.nx, ny = x->c.ny;
+  if (ensure_scratch(x, (size_t)ny + 1)) return NAN;
+  if (launch_amplitude_rows(nx, ny, x->buf.half(x->cur).FLD, x->scratch, x->stream) != hipSuccess ||
+      launch_sum(x->scratch, ny, 1, x->scratch + ny, x->stream) != hipSuccess) {
+    fail(TPL_EHIP, "amplitude kernels failed");
+    return NAN;
+  }
+  double tot = 0.0;
+  if (hipMemcpyAsync(&tot, x->scratch + ny, sizeof(double), hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
+      hipStreamSynchronize(x->stream) != hipSuccess) {
+    fail(TPL_EHIP, "amplitude copy failed");
+    return NAN;
+  }
+  return std::sqrt(tot / ((double)nx * ny)) / x->c.u0;
+}
+
+int tpl_diagnostics(tpl_ctx *x, tpl_diag *out) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  if (!out) return fail(TPL_EINVAL, "null output");
+  rc = ensure_scratch(x, (size_t)1024 * kDiagComp + kDiagComp);
+  if (rc) return rc;
+  int nb = 0;
+  HIPCHK(launch_diag(x->c.nx, x->c.ny, x->d.nqd, x->qtab_d, x->buf.half(x->cur),
+                     x->scratch, &nb, x->stream));
+  double *res = x->scratch + (size_t)1024 * kDiagComp;
+  HIPCHK(launch_diag_final(x->scratch, nb, res, x->stream));
+  double h[kDiagComp];
+  HIPCHK(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  const double amp = tpl_perturbation_amplitude(x);
+  out->step = (double)x->step;
+  out->mass_S = h[0];
+  out->mass_P = h[1];
+  out->mom_x = h[2];
+  out->mom_y = h[3];
+  out->amplitude = amp;
+  out->enstrophy = h[4];
+  out->qrms = h[6] > 0 ? std::sqrt(h[5] / h[6]) / x->d.R : 0.0;
+  out->min_psi = h[7];
+  return TPL_OK;
+}
+
+int tpl_get_window(tpl_ctx *x, int x0, int y0, int w, int h, double *XS,
+                   double *XP, double *psi, double *U) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  if (w < 1 || h < 1) return fail(TPL_EINVAL, "window must be non-empty");
+  const size_t nqd = x->d.nqd, wh = (size_t)w * h;
+  const size_t planes = 9 + 26 * nqd + 2;
+  rc = ensure_scratch(x, planes * wh);
+  if (rc) return rc;
+  HIPCHK(launch_window(x->c.nx, x->c.ny, (int)nqd, x0, y0, w, h, x->buf.half(x->cur),
+                       x->scratch, x->stream));
+  const double *s = x->scratch;
+  auto cp = [&](double *dst, size_t off, size_t n) -> int {
+    if (dst)
+      HIPCHK(hipMemcpyAsync(dst, s + off * wh, n * wh * sizeof(double),
+                            hipMemcpyDeviceToHost, x->stream));
+    return TPL_OK;
+  };
+  if ((rc = cp(XS, 0, 9)) || (rc = cp(XP, 9, 25 * nqd)) || (rc = cp(psi, 9 + 25 * nqd, nqd)) ||
+      (rc = cp(U, 9 + 26 * nqd, 2)))
+    return rc;
+  HIPCHK(hipStreamSynchronize(x->stream));
+  return TPL_OK;
+}
+
+int tpl_get_state(tpl_ctx *x, double *XS, double *XP, double *psi, double *U) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  const size_t N = (size_t)x->c.nx * x->c.ny;
+  StateView v = x->buf.half(x->cur);
+  if (XS) HIPCHK(hipMemcpyAsync(XS, v.XS, 9 * N * 8, hipMemcpyDeviceToHost, x->stream));
+  if (XP)
+    HIPCHK(hipMemcpyAsync(XP, v.XP, 25 * x->d.nqd * N * 8, hipMemcpyDeviceToHost, x->stream));
+  if (psi)
+    HIPCHK(hipMemcpyAsync(psi, v.PSI, x->d.nqd * N * 8, hipMemcpyDeviceToHost, x->stream));
+  if (U)
+    HIPCHK(hipMemcpyAsync(U, v.FLD + (size_t)F_UX * N, 2 * N * 8, hipMemcpyDeviceToHost,
+                          x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  return TPL_OK;
+}
+
+int tpl_set_state(tpl_ctx *x, const double *XS, const double *XP,
+                  const double *psi, const double *U) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  const size_t N = (size_t)x->c.nx * x->c.ny;
+  StateView v = x->buf.half(x->cur);
+  if (XS) HIPCHK(hipMemcpyAsync(v.XS, XS, 9 * N * 8, hipMemcpyHostToDevice, x->stream));
+  if (XP)
+    HIPCHK(hipMemcpyAsync(v.XP, XP, 25 * x->d.nqd * N * 8, hipMemcpyHostToDevice, x->stream));
+  if (psi)
+    HIPCHK(hipMemcpyAsync(v.PSI, psi, x->d.nqd * N * 8, hipMemcpyHostToDevice, x->stream));
+  if (U)
+    HIPCHK(hipMemcpyAsync(v.FLD + (size_t)F_UX * N, U, 2 * N * 8, hipMemcpyHostToDevice,
+                          x->stream));
+  HIPCHK(launch_refresh(x->d.nqd, (long long)N, x->qtab_d, v, x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  return TPL_OK;
+}
+
+int tpl_get_populations(tpl_ctx *x, int species, void *host, size_t bytes) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  const size_t N = (size_t)x->c.nx * x->c.ny;
+  const size_t need = (species == TPL_SOLVENT ? 9 : 25 * (size_t)x->d.nqd) * N * 8;
+  if (species != TPL_SOLVENT && species != TPL_POLYMER) return fail(TPL_EINVAL, "bad species");
+  if (!host || bytes != need) return fail(TPL_EINVAL, "buffer size mismatch");
+  return species == TPL_SOLVENT ? tpl_get_state(x, (double *)host, nullptr, nullptr, nullptr)
+                                : tpl_get_state(x, nullptr, (double *)host, nullptr, nullptr);
+}
+
+int tpl_set_populations(tpl_ctx *x, int species, const void *host, size_t bytes) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  const size_t N = (size_t)x->c.nx * x->c.ny;
+  const size_t need = (species == TPL_SOLVENT ? 9 : 25 * (size_t)x->d.nqd) * N * 8;
+  if (species != TPL_SOLVENT && species != TPL_POLYMER) return fail(TPL_EINVAL, "bad species");
+  if (!host || bytes != need) return fail(TPL_EINVAL, "buffer size mismatch");
+  return species == TPL_SOLVENT
+             ? tpl_set_state(x, (const double *)host, nullptr, nullptr, nullptr)
+             : tpl_set_state(x, nullptr, (const double *)host, nullptr, nullptr);
+}
+
+static const char kMagic[8] = {'T', 'P', 'L', 'C', 'K', 'P', 'T', '1'};
+
+int tpl_save(tpl_ctx *x, const char *path) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  if (!path) return fail(TPL_EINVAL, "null path");
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(TPL_EINVAL, std::string("cannot open ") + path);
+  HIPCHK(hipStreamSynchronize(x->stream));
+  StateView v = x->buf.half(x->cur);
+  const size_t n[4] = {x->buf.nXS, x->buf.nXP, x->buf.nPSI, x->buf.nFLD};
+  const double *src[4] = {v.XS, v.XP, v.PSI, v.FLD};
+  bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(&x->c, sizeof(Config), 1, f) == 1 &&
+            std::fwrite(&x->step, sizeof x->step, 1, f) == 1;
+  std::vector<double> h;
+  for (int i = 0; i < 4 && ok; ++i) {
+    h.resize(n[i]);
+    if (hipMemcpy(h.data(), src[i], n[i] * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+      std::fclose(f);
+      return fail(TPL_EHIP, "checkpoint copy failed");
+    }
+    ok = std::fwrite(h.data(), 8, n[i], f) == n[i];
+  }
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? TPL_OK : fail(TPL_EINVAL, "checkpoint write failed");
+}
+
+int tpl_load(tpl_ctx *x, const char *path) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  if (!path) return fail(TPL_EINVAL, "null path");
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(TPL_EINVAL, std::string("cannot open ") + path);
+  char magic[8];
+  Config c;
+  long long step = 0;
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
+            std::fread(&c, sizeof c, 1, f) == 1 && std::fread(&step, sizeof step, 1, f) == 1;
+  if (!ok || std::memcmp(&c, &x->c, sizeof c) != 0) {
+    std::fclose(f);
+    return fail(TPL_EINVAL, "checkpoint does not match this context");
+  }
+  StateView v = x->buf.half(x->cur);
+  const size_t n[4] = {x->buf.nXS, x->buf.nXP, x->buf.nPSI, x->buf.nFLD};
+  double *dst[4] = {v.XS, v.XP, v.PSI, v.FLD};
+  std::vector<double> h;
+  HIPCHK(hipStreamSynchronize(x->stream));
+  for (int i = 0; i < 4 && ok; ++i) {
+    h.resize(n[i]);
+    ok = std::fread(h.data(), 8, n[i], f) == n[i];
+    if (ok && hipMemcpy(dst[i], h.data(), n[i] * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      std::fclose(f);
+      return fail(TPL_EHIP, "checkpoint upload failed");
+    }
+  }
+  std::fclose(f);
+  if (!ok) return fail(TPL_EINVAL, "checkpoint truncated");
+  x->step = step;
+  return TPL_OK;
+}
+
+void tpl_destroy(tpl_ctx *x) {
+  if (!x) return;
+  if (x->owned) {
+    (void)hipFree(x->buf.XS);
+    (void)hipFree(x->buf.XP);
+    (void)hipFree(x->buf.PSI);
+    (void)hipFree(x->buf.FLD);
+  }
+  (void)hipFree(x->qtab_d);
+  (void)hipFree(x->peq_d);
+  (void)hipFree(x->scratch);
+  delete x;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol,
+and its host-side logic (parameter derivation, validation, errors) agrees
+with the oracle.  No compute calls are made (no GPU here)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2201_10132_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpl_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared("tpl.h")
+    assert len(names) >= 20
+    L = P.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+CASES = [
+    dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8, periods=1),
+    dict(nx=1024, ny=1024, Re=60.0, Wi=1.0, beta=0.7, periods=4),
+    dict(nx=1024, ny=1024, Re=60.0, Wi=0.0, beta=0.7, periods=4),
+    dict(nx=256, ny=256, Re=20.0, Wi=0.5, beta=0.7, periods=4, nq=8, spring=1),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_derived_parameters_match_oracle(case):
+    c = dict(case)
+    nq = c.pop("nq", 16)
+    spring = c.pop("spring", 0)
+    t = P.Tpl(c["nx"], c["ny"], c["Re"], c["Wi"], c["beta"], periods=c["periods"], nq=nq,
+              spring=spring)
+    o = oracle.OracleSim(1, c["ny"], nq=nq, spring=spring, Re=c["Re"], Wi=c["Wi"],
+                         beta=c["beta"], periods=c["periods"]).derived()
+    assert t.nqd == oracle.OracleSim(1, 1, nq=nq).nqd
+    pairs = dict(kf="kf", l="l", nu="nu", nuS="nuS", G="G", tau1S="tau1S", tau2S="tau2S",
+                 tau1P="tau1P", tau2P="tau2P", lambda_eff="lambda", sigma="sigma", R="R",
+                 DQ="DQ", F0="F0", kappa="kappa", meq="meq", Sc="Sc")
+    for lk, ok in pairs.items():
+        assert abs(t.query(lk) - o[ok]) <= 1e-13 * max(1.0, abs(o[ok])), lk
+
+
+def test_validation_errors():
+    with pytest.raises(P.TplError) as e:
+        P.Tpl(64, 64, -1.0, 0.5, 0.8)
+    assert e.value.code == P.tpl.TPL_EINVAL
+    with pytest.raises(P.TplError):
+        P.Tpl(64, 64, 20.0, 0.5, 1.5)
+    # tau1_S > tau2_S violates the H-theorem ordering
+    with pytest.raises(P.TplError) as e:
+        P.Tpl(64, 64, 0.01, 0.0, 0.8)
+    assert "ordering" in str(e.value)
+    t = P.Tpl(64, 64, 20.0, 0.5, 0.8)
+    with pytest.raises(P.TplError):
+        t.set_param("nq", 7)
+    with pytest.raises(P.TplError):
+        t.set_param("tau_ratio_p", 1.5)
+    with pytest.raises(P.TplError):
+        t.set_param("no_such_key", 1)
+    with pytest.raises(P.TplError) as e:
+        t.step(1)
+    assert e.value.code == P.tpl.TPL_ESTATE
+    assert P.tpl_last_error()
+
+
+def test_algorithmic_bytes_formula():
+    t = P.Tpl(1024, 1024, 60.0, 1.0, 0.7, periods=4)
+    nqd = t.nqd
+    N = 1024 * 1024
+    # populations read + written, lagged psi written + read, per-node fields
+    want = 8 * N * (2 * (9 + 25 * nqd) + 2 * nqd + 2 * 18)
+    assert t.query("bytes_per_step") == want
