@@ -59,7 +59,8 @@ def main():
     ap.add_argument("--pre-steps", type=int, default=-1,
                     help="base-state column steps (-1: 5 max(l^2/nu, lambda))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_step_f64_1024x1024_nq16.json"))
+    ap.add_argument("--traffic-file", default=os.path.join(
+        ROOT, "profiles", "k_step_f64_kolmogorov1024_nq16_traffic.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -79,9 +80,9 @@ def main():
     t.init(seed=w["seed"], perturbation=w["perturbation"])
     init_s = time.perf_counter() - t0
     d0 = t.diagnostics()
-    print(f"# init {init_s:.1f} s  nqd={t.nqd}  qsplit={t.query('qsplit_used') if t.query('qsplit_used') else 'auto'}",
-          file=sys.stderr, flush=True)
     t.step(args.warmup)
+    print(f"# init {init_s:.1f} s  nqd={t.nqd}  qsplit={t.query('qsplit_used'):.0f}",
+          file=sys.stderr, flush=True)
 
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -99,13 +100,12 @@ def main():
     bytes_step = t.query("bytes_per_step")
     mlups = N * args.steps / wall / 1e6
     achieved = bytes_step / (kernel_ms * 1e-3) / 1e9
-    traffic = None
+    traffic = None  # HBM bytes per launch from the committed counter runs
     try:
-        with open(args.traffic_json) as f:
-            tj = json.load(f)
-        if tj.get("kernel_source_sha") == kernel_source_sha():
-            traffic = tj.get("bytes_per_launch")
-    except (OSError, ValueError):
+        rec = dict(l.split(None, 1) for l in open(args.traffic_file).read().splitlines() if l)
+        if rec.get("kernel_source_sha", "").strip() == kernel_source_sha():
+            traffic = float(rec["bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
         pass
     out = {
         "metric": "MLUPS + % HBM roofline, FP64 vs FP32/batched/learned at stated growth-rate error",
@@ -129,6 +129,7 @@ def main():
                      "traffic": traffic},
         "mqlups": round(mlups * nqd, 1),
         "kernel_ms": round(kernel_ms, 4),
+        "init_s": round(init_s, 2),
         "conservation": {"mass_S": abs(d1["mass_S"] / d0["mass_S"] - 1),
                          "mass_P": abs(d1["mass_P"] / d0["mass_P"] - 1)},
         "amplitude": d1["amplitude"],
