@@ -51,45 +51,92 @@ struct StepParams {
   double kappa, DQ, F0, kf;
 };
 
-struct StateView {  // one half of the double-buffered state
-  double *XS, *XP, *PSI, *FLD;
+// One half of the double-buffered state.  Populations and the lagged psi are
+// stored as T (double, or float for the FP32 form); per-node fields are FP64.
+template <typename T>
+struct StateT {
+  T *XS, *XP, *PSI;
+  double *FLD;
+};
+using StateView = StateT<double>;
+using StateView32 = StateT<float>;
+
+// FP32 form: populations and psi are stored as float deviations from an
+// x-invariant reference state (the base state rounded to FP32, so that
+// ref + deviation is exact in FP64), laid out [plane][ny].  Unused (null) for
+// FP64 storage.
+struct RefView {
+  const float *XS, *XP, *PSI;
+  int ny;
+};
+// The same reference values regrouped for the step kernel so that one
+// Q-node's values are contiguous and wave-uniform (scalar loads):
+//   pull[y][q][k]  reference of the population pulled into (k, q) at row y
+//   store[y][q][k] reference of (k, q) at row y
+//   psi[y][q], spull[y][d], sstore[y][d] likewise for psi and the solvent.
+struct StepRef {
+  const float *pull, *store, *psi, *spull, *sstore;
 };
 
 // Launchers (tpl_kernels.hip).  All enqueue on stream and return the launch
-// status.
-hipError_t launch_step_f64(const StepParams &p, StateView a, StateView b,
-                           const QNode *qtab, hipStream_t s);
+// status.  T = double or float.
+template <typename T>
+hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
+                       StepRef ref, const QNode *qtab, hipStream_t s);
+// Build the FP32 form's reference from the FP64 column state (ref = the
+// column rounded to FP32) and the step kernel's regrouped tables.
+hipError_t launch_make_ref(int nqd, int ny, StateView col, float *ref,
+                           hipStream_t s);
+hipError_t launch_step_ref(int nqd, int ny, const QNode *qtab, RefView ref,
+                           float *pull, float *store, float *psi, float *spull,
+                           float *sstore, hipStream_t s);
+// dst[plane][N] = (float)(col[plane][y] - ref[plane][y]) for every x.
+hipError_t launch_tile_dev(int planes, int nx, int ny, const double *col,
+                           const float *ref, float *dst, hipStream_t s);
 hipError_t launch_rest(int nqd, long long N, double rhoS0, double rhoP0,
                        const double *peq, StateView a, hipStream_t s);
-hipError_t launch_refresh(int nqd, long long N, const QNode *qtab,
-                          StateView a, hipStream_t s);
+template <typename T>
+hipError_t launch_refresh(int nqd, int nx, int ny, const QNode *qtab,
+                          StateT<T> a, RefView ref, hipStream_t s);
 hipError_t launch_tile(int nqd, int nx, int ny, StateView col, StateView a,
                        hipStream_t s);
+hipError_t launch_tile_fields(int nx, int ny, const double *colFLD,
+                              double *FLD, hipStream_t s);
 hipError_t launch_perturb_field(int nx, int ny, int x0, int y0, int NX, int NY,
                                 int nmodes, const double *modes, double amp_u0,
                                 int multimode, double *du, double *partial,
                                 hipStream_t s);
-hipError_t launch_perturb_apply(int nqd, long long N, const double *du,
-                                const double *scale, StateView a,
+template <typename T>
+hipError_t launch_perturb_apply(int nqd, int nx, int ny, const double *du,
+                                const double *scale, StateT<T> a, RefView ref,
                                 hipStream_t s);
 hipError_t launch_sum(const double *partial, int n, int ncomp, double *out,
                       hipStream_t s);
 hipError_t launch_amplitude_rows(int nx, int ny, const double *FLD,
                                  double *partial, hipStream_t s);
+template <typename T>
 hipError_t launch_diag(int nx, int ny, int nqd, const QNode *qtab,
-                       StateView a, double *partial, int *nblocks,
+                       StateT<T> a, RefView ref, double *partial, int *nblocks,
                        hipStream_t s);
 hipError_t launch_diag_final(const double *partial, int nblocks, double *out,
                              hipStream_t s);
-hipError_t launch_observables(int nqd, long long N, const QNode *qtab,
+template <typename T>
+hipError_t launch_observables(int nqd, int nx, int ny, const QNode *qtab,
                               double inv_s2, double G, double mref,
-                              StateView a, double *out, hipStream_t s);
+                              StateT<T> a, RefView ref, double *out,
+                              hipStream_t s);
 hipError_t launch_nan_check(long long N, const double *FLD, double *partial,
                             int *nblocks, hipStream_t s);
+template <typename T>
 hipError_t launch_window(int nx, int ny, int nqd, int x0, int y0, int w, int h,
-                         StateView a, double *dst, hipStream_t s);
+                         StateT<T> a, RefView ref, double *dst, hipStream_t s);
+// Whole-array conversion between stored deviations and full FP64 values:
+// dst[plane][N] = ref[plane][y] + src[plane][N] (to64) or the inverse.
+hipError_t launch_to_f64(int nx, int ny, int planes, const float *src,
+                         const float *ref, double *dst, hipStream_t s);
+hipError_t launch_from_f64(int nx, int ny, int planes, const double *src,
+                           const float *ref, float *dst, hipStream_t s);
 
 constexpr int kDiagComp = 8;  // massS massP momx momy enstrophy psiQ2 psi minpsi
-constexpr int kDiagBlock = 256;
 
 }  // namespace tplk

@@ -1,11 +1,16 @@
 // Device kernels of libtpl for gfx950 (MI355X): the fused stream +
 // quasi-equilibrium step of the two-fluid polymer scheme (arXiv:2201.10132,
-// Sec. VI) and its FP64 initialisation and reduction kernels.
+// Sec. VI) and its initialisation and FP64 reduction kernels.
 //
 // Layout (structure of arrays, r = y*nx + x innermost, so a wave's 64 lanes
-// touch 64 consecutive doubles of one plane):
-//   XS[9][N], XP[25][nqd][N], PSI[nqd][N], FLD[NF][N]      (one half)
+// touch 64 consecutive values of one plane):
+//   XS[9][N], XP[25][nqd][N], PSI[nqd][N] (storage type T), FLD[NF][N] (FP64)
+// T = double stores values; T = float stores deviations from an x-invariant
+// FP64 reference (the base state) and every kernel works on the full FP64
+// value ref + deviation.
 #include "tpl_internal.h"
+
+#include <type_traits>
 
 namespace tplk {
 
@@ -63,6 +68,38 @@ __device__ __forceinline__ int xcd_tile(int bid, int tiles_per_xcd) {
 }
 
 // ---------------------------------------------------------------------------
+// Storage access.  Loads and stores at a wave-uniform plane base plus a 32-bit
+// byte offset (global_load/store with an SGPR base; every offset is
+// < sizeof(T) N < 2^32).  The base goes through readfirstlane so that the
+// compiler cannot fold the per-lane offset into hoisted 64-bit per-lane
+// pointers.
+template <typename T>
+__device__ __forceinline__ T *uni(T *p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T ldo(const T *base, uint32_t off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T *base, uint32_t off, T v) {
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
+}
+// Full value from a stored one: identity for FP64, reference + deviation for
+// the FP32 form (ref = the plane's reference value at this row).
+__device__ __forceinline__ double full(double v, double) { return v; }
+__device__ __forceinline__ double full(float v, double ref) { return ref + (double)v; }
+template <typename T>
+__device__ __forceinline__ T stored(double v, double ref);
+template <>
+__device__ __forceinline__ double stored<double>(double v, double) { return v; }
+template <>
+__device__ __forceinline__ float stored<float>(double v, double ref) { return (float)(v - ref); }
+
+// ---------------------------------------------------------------------------
 // The fused step.  One lane per r-node; the Q-disk of that node is split over
 // qs waves (slices) of the workgroup, each walking its Q-nodes in order.  All
 // Q-dependent addressing (source Q-node, bounce-back) is wave-uniform.
@@ -76,28 +113,17 @@ __device__ __forceinline__ int xcd_tile(int bid, int tiles_per_xcd) {
 // imposed fluxes, the moment inversion, the blended equilibrium and the
 // relaxation; write 25 populations and psi; accumulate the new marginals and
 // M.  The slices' partial marginals are summed in LDS in a fixed order.
-// Loads and stores at a wave-uniform plane base plus a 32-bit byte offset
-// (global_load/store with an SGPR base; every offset is < 8 N < 2^32).  The
-// base goes through readfirstlane so that the compiler cannot fold the
-// per-lane offset into hoisted 64-bit per-lane pointers.
-template <typename T>
-__device__ __forceinline__ T *uni(T *p) {
-  const uint64_t v = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ double ldo(const double *base, uint32_t off) {
-  return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + off);
-}
-__device__ __forceinline__ void sto(double *base, uint32_t off, double v) {
-  *reinterpret_cast<double *>(reinterpret_cast<char *>(base) + off) = v;
-}
-
-template <int MAXT>
+// Arithmetic is FP64 for both storage types.  ROWTILE: every 64-node tile
+// lies in one lattice row (nx % 64 == 0), so the FP32 form's reference values
+// are wave-uniform (scalar loads).
+template <typename T, int MAXT, bool ROWTILE>
 __global__ void __launch_bounds__(MAXT)
-    k_step_f64(StepParams p, StateView a, StateView b,
-               const QNode *__restrict__ qtab) {
+    k_step(StepParams p, StateT<T> a, StateT<T> b, const float *__restrict__ rpull,
+           const float *__restrict__ rstore, const float *__restrict__ rpsi,
+           const float *__restrict__ rspull, const float *__restrict__ rsstore,
+           const QNode *__restrict__ qtab) {
+  constexpr bool F32 = std::is_same<T, float>::value;
+  constexpr uint32_t SZ = sizeof(T);
   extern __shared__ double red[];  // [qs][12][64]
   const int tile = xcd_tile(blockIdx.x, p.tiles_per_xcd);
   if (tile >= p.ntiles) return;  // whole workgroup leaves together
@@ -108,27 +134,45 @@ __global__ void __launch_bounds__(MAXT)
   const bool active = rr < N;
   const int r = (int)(active ? rr : N - 1);
   const int nx = p.nx, ny = p.ny;
-  const int y = r / nx, x = r - y * nx;
+  int y = r / nx;
+  const int x = r - y * nx;
+  if (ROWTILE) y = __builtin_amdgcn_readfirstlane(y);
   const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
   const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
-  const uint32_t oR = 8u * (uint32_t)r;
-  const uint32_t oE = 8u * (uint32_t)(y * nx + xp), oW = 8u * (uint32_t)(y * nx + xm);
-  const uint32_t oN = 8u * (uint32_t)(yp * nx + x), oS = 8u * (uint32_t)(ym * nx + x);
-  uint32_t osrc[9];  // byte offset of the pull source r - c_d
+  const uint32_t oR = SZ * (uint32_t)r;
+  const uint32_t oE = SZ * (uint32_t)(y * nx + xp), oW = SZ * (uint32_t)(y * nx + xm);
+  const uint32_t oN = SZ * (uint32_t)(yp * nx + x), oS = SZ * (uint32_t)(ym * nx + x);
+  const uint32_t fR = 8u * (uint32_t)r;
+  const uint32_t fE = 8u * (uint32_t)(y * nx + xp), fW = 8u * (uint32_t)(y * nx + xm);
+  const uint32_t fN = 8u * (uint32_t)(yp * nx + x), fS = 8u * (uint32_t)(ym * nx + x);
+  uint32_t osrc[9], fsrc[9];  // byte offsets of the pull source r - c_d
 #pragma unroll
   for (int d = 0; d < 9; ++d) {
     const int sx = C9X[d] == 1 ? xm : (C9X[d] == -1 ? xp : x);
     const int sy = C9Y[d] == 1 ? ym : (C9Y[d] == -1 ? yp : y);
-    osrc[d] = 8u * (uint32_t)(sy * nx + sx);
+    osrc[d] = SZ * (uint32_t)(sy * nx + sx);
+    fsrc[d] = 8u * (uint32_t)(sy * nx + sx);
   }
-  auto plane = [&](const double *arr, long long i) { return uni(arr + (size_t)i * N); };
-  auto wplane = [&](double *arr, long long i) { return uni(arr + (size_t)i * N); };
+  auto plane = [&](const T *arr, long long i) { return uni(arr + (size_t)i * N); };
+  auto wplane = [&](T *arr, long long i) { return uni(arr + (size_t)i * N); };
+  auto fplane = [&](const double *arr, long long i) { return uni(arr + (size_t)i * N); };
+  auto wfplane = [&](double *arr, long long i) { return uni(arr + (size_t)i * N); };
+  // FP32 form: reference values, [row][q][k] / [row][q] / [row][d]
+  auto rq = [&](const float *tab, int row, int q, int k) -> double {
+    return F32 ? (double)tab[((size_t)row * p.nqd + q) * 25 + k] : 0.0;
+  };
+  auto rpq = [&](int row, int q) -> double {
+    return F32 ? (double)rpsi[(size_t)row * p.nqd + q] : 0.0;
+  };
+  auto rsd = [&](const float *tab, int d) -> double {
+    return F32 ? (double)tab[(size_t)y * 9 + d] : 0.0;
+  };
 
   // ---- solvent pull and moments
   double gS[9], rhoS = 0.0, JSx = 0.0, JSy = 0.0;
 #pragma unroll
   for (int d = 0; d < 9; ++d) {
-    gS[d] = ldo(plane(a.XS, d), osrc[d]);
+    gS[d] = full(ldo(plane(a.XS, d), osrc[d]), rsd(rspull, d));
     rhoS += gS[d];
     if (C9X[d]) JSx += C9X[d] * gS[d];
     if (C9Y[d]) JSy += C9Y[d] * gS[d];
@@ -137,14 +181,14 @@ __global__ void __launch_bounds__(MAXT)
   double rhoP = 0.0, JPx = 0.0, JPy = 0.0;
 #pragma unroll
   for (int d = 0; d < 9; ++d) {
-    const double m = ldo(plane(a.FLD, F_M0 + d), osrc[d]);
+    const double m = ldo(fplane(a.FLD, F_M0 + d), fsrc[d]);
     rhoP += m;
     if (C9X[d]) JPx += C9X[d] * m;
     if (C9Y[d]) JPy += C9Y[d] * m;
   }
   // ---- lagged non-local terms (central differences)
-  auto dX = [&](int f) { return 0.5 * (ldo(plane(a.FLD, f), oE) - ldo(plane(a.FLD, f), oW)); };
-  auto dY = [&](int f) { return 0.5 * (ldo(plane(a.FLD, f), oN) - ldo(plane(a.FLD, f), oS)); };
+  auto dX = [&](int f) { return 0.5 * (ldo(fplane(a.FLD, f), fE) - ldo(fplane(a.FLD, f), fW)); };
+  auto dY = [&](int f) { return 0.5 * (ldo(fplane(a.FLD, f), fN) - ldo(fplane(a.FLD, f), fS)); };
   const double Kxx = dX(F_UX), Kxy = dY(F_UX), Kyx = dX(F_UY), Kyy = dY(F_UY);
   const double Sx = p.kappa * (dX(F_MXX) + dY(F_MXY));
   const double Sy = p.kappa * (dX(F_MXY) + dY(F_MYY));
@@ -172,11 +216,11 @@ __global__ void __launch_bounds__(MAXT)
       const double o = p.c1S * gS[d] + p.c2S * ((1.0 - p.rS) * fs + p.rS * fe);
       if (C9X[d]) jx += C9X[d] * o;
       if (C9Y[d]) jy += C9Y[d] * o;
-      if (writer) sto(wplane(b.XS, d), oR, o);
+      if (writer) sto(wplane(b.XS, d), oR, stored<T>(o, rsd(rsstore, d)));
     }
     if (writer) {
-      sto(wplane(b.FLD, F_JSX), oR, jx);
-      sto(wplane(b.FLD, F_JSY), oR, jy);
+      sto(wfplane(b.FLD, F_JSX), fR, jx);
+      sto(wfplane(b.FLD, F_JSY), fR, jy);
     }
   }
 
@@ -192,7 +236,8 @@ __global__ void __launch_bounds__(MAXT)
     const QNode &qn = qtab[q];
     double g[25];
 #pragma unroll
-    for (int k = 0; k < 25; ++k) g[k] = ldo(plane(a.XP, qn.plane[k]), osrc[pdir(k)]);
+    for (int k = 0; k < 25; ++k)
+      g[k] = full(ldo(plane(a.XP, qn.plane[k]), osrc[pdir(k)]), rq(rpull, y, q, k));
     double psi = 0.0, Jrx = 0.0, Jry = 0.0, JQx = 0.0, JQy = 0.0;
 #pragma unroll
     for (int k = 0; k < 25; ++k) {
@@ -203,9 +248,10 @@ __global__ void __launch_bounds__(MAXT)
       if (PV[k][3]) JQy += PV[k][3] * g[k];
     }
     // spring term: kappa Fhat (Q . grad psi^{n-1})
-    const double *P = plane(a.PSI, q);
-    const double gx = 0.5 * (ldo(P, oE) - ldo(P, oW));
-    const double gy = 0.5 * (ldo(P, oN) - ldo(P, oS));
+    const T *P = plane(a.PSI, q);
+    const double pE = full(ldo(P, oE), rpq(y, q)), pW = full(ldo(P, oW), rpq(y, q));
+    const double pN = full(ldo(P, oN), rpq(yp, q)), pS = full(ldo(P, oS), rpq(ym, q));
+    const double gx = 0.5 * (pE - pW), gy = 0.5 * (pN - pS);
     const double qg = qn.qx * gx + qn.qy * gy;
     const double sx = p.kappa * qn.fx * qg, sy = p.kappa * qn.fy * qg;
     // imposed fluxes and moment inversion
@@ -234,8 +280,9 @@ __global__ void __launch_bounds__(MAXT)
     }
     if (active) {
 #pragma unroll
-      for (int k = 0; k < 25; ++k) sto(wplane(b.XP, (long long)k * nqd + q), oR, g[k]);
-      sto(wplane(b.PSI, q), oR, psi);
+      for (int k = 0; k < 25; ++k)
+        sto(wplane(b.XP, (long long)k * nqd + q), oR, stored<T>(g[k], rq(rstore, y, q, k)));
+      sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
     }
     Mxx += psi * qn.qx * qn.fx;
     Mxy += psi * qn.qx * qn.fy;
@@ -263,35 +310,119 @@ __global__ void __launch_bounds__(MAXT)
     }
   }
   if (writer) {
-    sto(wplane(b.FLD, F_RHOS), oR, rhoS);
-    sto(wplane(b.FLD, F_RHOP), oR, rhoP);
-    sto(wplane(b.FLD, F_UX), oR, Ux);
-    sto(wplane(b.FLD, F_UY), oR, Uy);
-    sto(wplane(b.FLD, F_MXX), oR, Mxx);
-    sto(wplane(b.FLD, F_MXY), oR, Mxy);
-    sto(wplane(b.FLD, F_MYY), oR, Myy);
+    sto(wfplane(b.FLD, F_RHOS), fR, rhoS);
+    sto(wfplane(b.FLD, F_RHOP), fR, rhoP);
+    sto(wfplane(b.FLD, F_UX), fR, Ux);
+    sto(wfplane(b.FLD, F_UY), fR, Uy);
+    sto(wfplane(b.FLD, F_MXX), fR, Mxx);
+    sto(wfplane(b.FLD, F_MXY), fR, Mxy);
+    sto(wfplane(b.FLD, F_MYY), fR, Myy);
 #pragma unroll
-    for (int d = 0; d < 9; ++d) sto(wplane(b.FLD, F_M0 + d), oR, mg[d]);
+    for (int d = 0; d < 9; ++d) sto(wfplane(b.FLD, F_M0 + d), fR, mg[d]);
   }
 }
 
-hipError_t launch_step_f64(const StepParams &p, StateView a, StateView b,
-                           const QNode *qtab, hipStream_t s) {
+template <typename T>
+hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
+                       StepRef r, const QNode *qtab, hipStream_t s) {
   const int grid = p.tiles_per_xcd > 0 ? 8 * p.tiles_per_xcd : p.ntiles;
   const size_t lds = p.qs > 1 ? (size_t)p.qs * 12 * 64 * sizeof(double) : 0;
-  if (p.qs <= 4)
-    hipLaunchKernelGGL(k_step_f64<256>, dim3(grid), dim3(64 * p.qs), lds, s, p,
-                       a, b, qtab);
+  const bool rowtile = (p.nx % 64) == 0;
+  const dim3 g(grid), blk(64 * p.qs);
+#define TPL_STEP_ARGS p, a, b, r.pull, r.store, r.psi, r.spull, r.sstore, qtab
+  if (p.qs <= 4) {
+    if (rowtile)
+      hipLaunchKernelGGL((k_step<T, 256, true>), g, blk, lds, s, TPL_STEP_ARGS);
+    else
+      hipLaunchKernelGGL((k_step<T, 256, false>), g, blk, lds, s, TPL_STEP_ARGS);
+  } else {
+    if (rowtile)
+      hipLaunchKernelGGL((k_step<T, 512, true>), g, blk, lds, s, TPL_STEP_ARGS);
+    else
+      hipLaunchKernelGGL((k_step<T, 512, false>), g, blk, lds, s, TPL_STEP_ARGS);
+  }
+#undef TPL_STEP_ARGS
+  return hipGetLastError();
+}
+template hipError_t launch_step<double>(const StepParams &, StateT<double>, StateT<double>,
+                                        StepRef, const QNode *, hipStream_t);
+template hipError_t launch_step<float>(const StepParams &, StateT<float>, StateT<float>,
+                                       StepRef, const QNode *, hipStream_t);
+
+// FP32 form reference: ref[plane][y] = (float) column[plane][y] for the 9
+// solvent, 25 nqd polymer and nqd psi planes.
+__global__ void k_make_ref(int nqd, int ny, StateView col, float *__restrict__ ref) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  const int plane = blockIdx.y;
+  if (y >= ny) return;
+  double v;
+  if (plane < 9)
+    v = col.XS[(size_t)plane * ny + y];
+  else if (plane < 9 + 25 * nqd)
+    v = col.XP[(size_t)(plane - 9) * ny + y];
   else
-    hipLaunchKernelGGL(k_step_f64<512>, dim3(grid), dim3(64 * p.qs), lds, s,
-                       p, a, b, qtab);
+    v = col.PSI[(size_t)(plane - 9 - 25 * nqd) * ny + y];
+  ref[(size_t)plane * ny + y] = (float)v;
+}
+hipError_t launch_make_ref(int nqd, int ny, StateView col, float *ref, hipStream_t s) {
+  hipLaunchKernelGGL(k_make_ref, dim3((ny + 255) / 256, 9 + 26 * nqd), dim3(256), 0, s, nqd,
+                     ny, col, ref);
+  return hipGetLastError();
+}
+
+// Regroup the reference for the step kernel (one thread per (y, q)).
+__global__ void k_step_ref(int nqd, int ny, const QNode *__restrict__ qtab, RefView ref,
+                           float *__restrict__ pull, float *__restrict__ store,
+                           float *__restrict__ psi, float *__restrict__ spull,
+                           float *__restrict__ sstore) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ny * nqd) return;
+  const int y = i / nqd, q = i - y * nqd;
+  for (int k = 0; k < 25; ++k) {
+    const int sy = ((y - PV[k][1]) % ny + ny) % ny;
+    pull[(size_t)i * 25 + k] = ref.XP[(size_t)qtab[q].plane[k] * ny + sy];
+    store[(size_t)i * 25 + k] = ref.XP[((size_t)k * nqd + q) * ny + y];
+  }
+  psi[i] = ref.PSI[(size_t)q * ny + y];
+  if (q == 0) {
+    for (int d = 0; d < 9; ++d) {
+      const int sy = ((y - C9Y[d]) % ny + ny) % ny;
+      spull[(size_t)y * 9 + d] = ref.XS[(size_t)d * ny + sy];
+      sstore[(size_t)y * 9 + d] = ref.XS[(size_t)d * ny + y];
+    }
+  }
+}
+hipError_t launch_step_ref(int nqd, int ny, const QNode *qtab, RefView ref, float *pull,
+                           float *store, float *psi, float *spull, float *sstore,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_step_ref, dim3((ny * nqd + 255) / 256), dim3(256), 0, s, nqd, ny, qtab,
+                     ref, pull, store, psi, spull, sstore);
+  return hipGetLastError();
+}
+
+// Deviation of the column from the reference, copied to every x.
+__global__ void k_tile_dev(int nx, int ny, const double *__restrict__ col,
+                           const float *__restrict__ ref, float *__restrict__ dst) {
+  const long long N = (long long)nx * ny;
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t plane = blockIdx.y;
+  if (r >= N) return;
+  const int y = (int)(r / nx);
+  dst[plane * N + r] = (float)(col[plane * ny + y] - (double)ref[plane * ny + y]);
+}
+hipError_t launch_tile_dev(int planes, int nx, int ny, const double *col, const float *ref,
+                           float *dst, hipStream_t s) {
+  const long long N = (long long)nx * ny;
+  hipLaunchKernelGGL(k_tile_dev, dim3((unsigned)((N + 255) / 256), planes), dim3(256), 0, s,
+                     nx, ny, col, ref, dst);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Initial-state kernels.
 
-// Rest: solvent equilibrium at zero velocity; polymer rest distribution.
+// Rest (FP64 column): solvent equilibrium at zero velocity; polymer rest
+// distribution; zero lagged velocity.
 __global__ void k_rest(int nqd, long long N, double rhoS0, double rhoP0,
                        const double *__restrict__ peq, StateView a) {
   const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -322,14 +453,19 @@ hipError_t launch_rest(int nqd, long long N, double rhoS0, double rhoP0,
 
 // Recompute every per-node field except U from the populations and psi of
 // the same half (used after any direct change of the state).
-__global__ void k_refresh(int nqd, long long N, const QNode *__restrict__ qtab,
-                          StateView a) {
+template <typename T>
+__global__ void k_refresh(int nqd, int nx, int ny, const QNode *__restrict__ qtab,
+                          StateT<T> a, RefView ref) {
+  const long long N = (long long)nx * ny;
   const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= N) return;
+  const int y = (int)(r / nx);
+  constexpr bool F32 = std::is_same<T, float>::value;
+  auto rv = [&](const float *tab, long long pl) { return F32 ? (double)tab[(size_t)pl * ny + y] : 0.0; };
   double rs = 0.0, jx = 0.0, jy = 0.0;
 #pragma unroll
   for (int d = 0; d < 9; ++d) {
-    const double v = a.XS[(size_t)d * N + r];
+    const double v = full(a.XS[(size_t)d * N + r], rv(ref.XS, d));
     rs += v;
     jx += C9X[d] * v;
     jy += C9Y[d] * v;
@@ -338,8 +474,11 @@ __global__ void k_refresh(int nqd, long long N, const QNode *__restrict__ qtab,
   double Mxx = 0.0, Mxy = 0.0, Myy = 0.0;
   for (int q = 0; q < nqd; ++q) {
 #pragma unroll
-    for (int k = 0; k < 25; ++k) mg[pdir(k)] += a.XP[((size_t)k * nqd + q) * N + r];
-    const double ps = a.PSI[(size_t)q * N + r];
+    for (int k = 0; k < 25; ++k) {
+      const long long pl = (long long)k * nqd + q;
+      mg[pdir(k)] += full(a.XP[(size_t)pl * N + r], rv(ref.XP, pl));
+    }
+    const double ps = full(a.PSI[(size_t)q * N + r], rv(ref.PSI, q));
     Mxx += ps * qtab[q].qx * qtab[q].fx;
     Mxy += ps * qtab[q].qx * qtab[q].fy;
     Myy += ps * qtab[q].qy * qtab[q].fy;
@@ -359,12 +498,18 @@ __global__ void k_refresh(int nqd, long long N, const QNode *__restrict__ qtab,
   for (int d = 0; d < 9; ++d) G[(size_t)(F_M0 + d) * N + r] = mg[d];
 }
 
-hipError_t launch_refresh(int nqd, long long N, const QNode *qtab,
-                          StateView a, hipStream_t s) {
-  hipLaunchKernelGGL(k_refresh, dim3((unsigned)((N + 255) / 256)), dim3(256),
-                     0, s, nqd, N, qtab, a);
+template <typename T>
+hipError_t launch_refresh(int nqd, int nx, int ny, const QNode *qtab,
+                          StateT<T> a, RefView ref, hipStream_t s) {
+  const long long N = (long long)nx * ny;
+  hipLaunchKernelGGL(k_refresh<T>, dim3((unsigned)((N + 255) / 256)), dim3(256),
+                     0, s, nqd, nx, ny, qtab, a, ref);
   return hipGetLastError();
 }
+template hipError_t launch_refresh<double>(int, int, int, const QNode *, StateT<double>,
+                                           RefView, hipStream_t);
+template hipError_t launch_refresh<float>(int, int, int, const QNode *, StateT<float>,
+                                          RefView, hipStream_t);
 
 // Copy an x-invariant column (nx = 1 lattice) to every column.
 __global__ void k_tile(int nx, int ny, const double *__restrict__ col,
@@ -388,6 +533,46 @@ hipError_t launch_tile(int nqd, int nx, int ny, StateView col, StateView a,
                      a.PSI);
   hipLaunchKernelGGL(k_tile, dim3(gx, NF), dim3(256), 0, s, nx, ny, col.FLD,
                      a.FLD);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_fields(int nx, int ny, const double *colFLD,
+                              double *FLD, hipStream_t s) {
+  const long long N = (long long)nx * ny;
+  hipLaunchKernelGGL(k_tile, dim3((unsigned)((N + 255) / 256), NF), dim3(256), 0,
+                     s, nx, ny, colFLD, FLD);
+  return hipGetLastError();
+}
+
+// Whole-array conversions for the FP32 form.
+__global__ void k_to_f64(int nx, int ny, const float *__restrict__ src,
+                         const float *__restrict__ ref, double *__restrict__ dst) {
+  const long long N = (long long)nx * ny;
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t plane = blockIdx.y;
+  if (r >= N) return;
+  dst[plane * N + r] = (double)ref[plane * ny + r / nx] + (double)src[plane * N + r];
+}
+__global__ void k_from_f64(int nx, int ny, const double *__restrict__ src,
+                           const float *__restrict__ ref, float *__restrict__ dst) {
+  const long long N = (long long)nx * ny;
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t plane = blockIdx.y;
+  if (r >= N) return;
+  dst[plane * N + r] = (float)(src[plane * N + r] - (double)ref[plane * ny + r / nx]);
+}
+hipError_t launch_to_f64(int nx, int ny, int planes, const float *src,
+                         const float *ref, double *dst, hipStream_t s) {
+  const long long N = (long long)nx * ny;
+  hipLaunchKernelGGL(k_to_f64, dim3((unsigned)((N + 255) / 256), planes), dim3(256),
+                     0, s, nx, ny, src, ref, dst);
+  return hipGetLastError();
+}
+hipError_t launch_from_f64(int nx, int ny, int planes, const double *src,
+                           const float *ref, float *dst, hipStream_t s) {
+  const long long N = (long long)nx * ny;
+  hipLaunchKernelGGL(k_from_f64, dim3((unsigned)((N + 255) / 256), planes), dim3(256),
+                     0, s, nx, ny, src, ref, dst);
   return hipGetLastError();
 }
 
@@ -462,42 +647,63 @@ hipError_t launch_perturb_field(int nx, int ny, int x0, int y0, int NX, int NY,
 }
 
 // Add scale*du at first order to both species and to the lagged U.
-__global__ void k_perturb_apply(int nqd, long long N,
-                                const double *__restrict__ du,
-                                const double *__restrict__ scale,
-                                StateView a) {
+template <typename T>
+__global__ void k_perturb_apply(int nqd, int nx, int ny, const double *__restrict__ du,
+                                const double *__restrict__ scale, StateT<T> a,
+                                RefView ref) {
+  const long long N = (long long)nx * ny;
   const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= N) return;
+  const int y = (int)(r / nx);
+  constexpr bool F32 = std::is_same<T, float>::value;
+  auto rv = [&](const float *tab, long long pl) { return F32 ? (double)tab[(size_t)pl * ny + y] : 0.0; };
   const double f = scale[0];
   const double dx = f * du[r], dy = f * du[N + r];
   double rs = 0.0;
 #pragma unroll
-  for (int d = 0; d < 9; ++d) rs += a.XS[(size_t)d * N + r];
+  for (int d = 0; d < 9; ++d) rs += full(a.XS[(size_t)d * N + r], rv(ref.XS, d));
 #pragma unroll
-  for (int d = 0; d < 9; ++d)
-    a.XS[(size_t)d * N + r] += 3.0 * W9[d] * rs * (C9X[d] * dx + C9Y[d] * dy);
+  for (int d = 0; d < 9; ++d) {
+    T &v = a.XS[(size_t)d * N + r];
+    v = stored<T>(full(v, rv(ref.XS, d)) + 3.0 * W9[d] * rs * (C9X[d] * dx + C9Y[d] * dy),
+                  rv(ref.XS, d));
+  }
   for (int q = 0; q < nqd; ++q) {
     double ps = 0.0;
 #pragma unroll
-    for (int k = 0; k < 25; ++k) ps += a.XP[((size_t)k * nqd + q) * N + r];
+    for (int k = 0; k < 25; ++k) {
+      const long long pl = (long long)k * nqd + q;
+      ps += full(a.XP[(size_t)pl * N + r], rv(ref.XP, pl));
+    }
 #pragma unroll
     for (int k = 0; k < 25; ++k) {
       if (PV[k][0] == 0 && PV[k][1] == 0) continue;
-      const double w = (k == 0) ? 1.0 / 3.0 : 1.0 / 36.0;
-      a.XP[((size_t)k * nqd + q) * N + r] += 3.0 * w * ps * (PV[k][0] * dx + PV[k][1] * dy);
+      const long long pl = (long long)k * nqd + q;
+      T &v = a.XP[(size_t)pl * N + r];
+      v = stored<T>(full(v, rv(ref.XP, pl)) +
+                        3.0 * (1.0 / 36.0) * ps * (PV[k][0] * dx + PV[k][1] * dy),
+                    rv(ref.XP, pl));
     }
   }
   a.FLD[(size_t)F_UX * N + r] += dx;
   a.FLD[(size_t)F_UY * N + r] += dy;
 }
 
-hipError_t launch_perturb_apply(int nqd, long long N, const double *du,
-                                const double *scale, StateView a,
+template <typename T>
+hipError_t launch_perturb_apply(int nqd, int nx, int ny, const double *du,
+                                const double *scale, StateT<T> a, RefView ref,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_perturb_apply, dim3((unsigned)((N + 255) / 256)),
-                     dim3(256), 0, s, nqd, N, du, scale, a);
+  const long long N = (long long)nx * ny;
+  hipLaunchKernelGGL(k_perturb_apply<T>, dim3((unsigned)((N + 255) / 256)),
+                     dim3(256), 0, s, nqd, nx, ny, du, scale, a, ref);
   return hipGetLastError();
 }
+template hipError_t launch_perturb_apply<double>(int, int, int, const double *,
+                                                 const double *, StateT<double>, RefView,
+                                                 hipStream_t);
+template hipError_t launch_perturb_apply<float>(int, int, int, const double *,
+                                                const double *, StateT<float>, RefView,
+                                                hipStream_t);
 
 // out[c] = sum_i partial[i*ncomp + c] (one workgroup, fixed order).
 __global__ void k_sum(const double *__restrict__ partial, int n, int ncomp,
@@ -550,9 +756,11 @@ hipError_t launch_amplitude_rows(int nx, int ny, const double *FLD,
 
 // Diagnostics, one partial per workgroup: masses, population momentum,
 // enstrophy, sum psi |Q|^2, sum psi, min psi.
+template <typename T>
 __global__ void k_diag(int nx, int ny, int nqd, const QNode *__restrict__ qtab,
-                       StateView a, double *__restrict__ partial) {
+                       StateT<T> a, RefView ref, double *__restrict__ partial) {
   __shared__ double sh[256];
+  constexpr bool F32 = std::is_same<T, float>::value;
   const long long N = (long long)nx * ny;
   double v[kDiagComp] = {0, 0, 0, 0, 0, 0, 0, 1e300};
   for (long long r = (long long)blockIdx.x * 256 + threadIdx.x; r < N;
@@ -577,7 +785,7 @@ __global__ void k_diag(int nx, int ny, int nqd, const QNode *__restrict__ qtab,
                      0.5 * (ux[(size_t)yp * nx + x] - ux[(size_t)ym * nx + x]);
     v[4] += 0.5 * w * w;
     for (int q = 0; q < nqd; ++q) {
-      const double ps = a.PSI[(size_t)q * N + r];
+      const double ps = full(a.PSI[(size_t)q * N + r], F32 ? (double)ref.PSI[(size_t)q * ny + y] : 0.0);
       v[5] += ps * (qtab[q].qx * qtab[q].qx + qtab[q].qy * qtab[q].qy);
       v[6] += ps;
       v[7] = fmin(v[7], ps);
@@ -591,17 +799,22 @@ __global__ void k_diag(int nx, int ny, int nqd, const QNode *__restrict__ qtab,
   if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kDiagComp + 7] = mn;
 }
 
+template <typename T>
 hipError_t launch_diag(int nx, int ny, int nqd, const QNode *qtab,
-                       StateView a, double *partial, int *nblocks,
+                       StateT<T> a, RefView ref, double *partial, int *nblocks,
                        hipStream_t s) {
   const long long N = (long long)nx * ny;
   long long nb = (N + 255) / 256;
   if (nb > 1024) nb = 1024;
   *nblocks = (int)nb;
-  hipLaunchKernelGGL(k_diag, dim3((unsigned)nb), dim3(256), 0, s, nx, ny, nqd,
-                     qtab, a, partial);
+  hipLaunchKernelGGL(k_diag<T>, dim3((unsigned)nb), dim3(256), 0, s, nx, ny, nqd,
+                     qtab, a, ref, partial);
   return hipGetLastError();
 }
+template hipError_t launch_diag<double>(int, int, int, const QNode *, StateT<double>,
+                                        RefView, double *, int *, hipStream_t);
+template hipError_t launch_diag<float>(int, int, int, const QNode *, StateT<float>,
+                                       RefView, double *, int *, hipStream_t);
 
 __global__ void k_diag_final(const double *__restrict__ partial, int n,
                              double *__restrict__ out) {
@@ -625,15 +838,18 @@ hipError_t launch_diag_final(const double *partial, int nblocks, double *out,
 }
 
 // Observables: rho, Ux, Uy, rhoP, C (3), tau_p (3).
-__global__ void k_observables(int nqd, long long N,
-                              const QNode *__restrict__ qtab, double inv_s2,
-                              double G, double mref, StateView a,
-                              double *__restrict__ out) {
+template <typename T>
+__global__ void k_observables(int nqd, int nx, int ny, const QNode *__restrict__ qtab,
+                              double inv_s2, double G, double mref, StateT<T> a,
+                              RefView ref, double *__restrict__ out) {
+  constexpr bool F32 = std::is_same<T, float>::value;
+  const long long N = (long long)nx * ny;
   const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= N) return;
+  const int y = (int)(r / nx);
   double ps = 0.0, cxx = 0.0, cxy = 0.0, cyy = 0.0;
   for (int q = 0; q < nqd; ++q) {
-    const double v = a.PSI[(size_t)q * N + r];
+    const double v = full(a.PSI[(size_t)q * N + r], F32 ? (double)ref.PSI[(size_t)q * ny + y] : 0.0);
     ps += v;
     cxx += v * qtab[q].qx * qtab[q].qx;
     cxy += v * qtab[q].qx * qtab[q].qy;
@@ -654,13 +870,22 @@ __global__ void k_observables(int nqd, long long N,
   out[9 * N + r] = mref > 0.0 ? g * F[(size_t)F_MYY * N + r] - G : 0.0;
 }
 
-hipError_t launch_observables(int nqd, long long N, const QNode *qtab,
+template <typename T>
+hipError_t launch_observables(int nqd, int nx, int ny, const QNode *qtab,
                               double inv_s2, double G, double mref,
-                              StateView a, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_observables, dim3((unsigned)((N + 255) / 256)),
-                     dim3(256), 0, s, nqd, N, qtab, inv_s2, G, mref, a, out);
+                              StateT<T> a, RefView ref, double *out,
+                              hipStream_t s) {
+  const long long N = (long long)nx * ny;
+  hipLaunchKernelGGL(k_observables<T>, dim3((unsigned)((N + 255) / 256)),
+                     dim3(256), 0, s, nqd, nx, ny, qtab, inv_s2, G, mref, a, ref, out);
   return hipGetLastError();
 }
+template hipError_t launch_observables<double>(int, int, int, const QNode *, double, double,
+                                               double, StateT<double>, RefView, double *,
+                                               hipStream_t);
+template hipError_t launch_observables<float>(int, int, int, const QNode *, double, double,
+                                              double, StateT<float>, RefView, double *,
+                                              hipStream_t);
 
 // Count non-finite mixture-velocity entries per workgroup into partial[], as
 // doubles, so that the generic sum kernel can reduce them.
@@ -688,9 +913,11 @@ hipError_t launch_nan_check(long long N, const double *FLD, double *partial,
 }
 
 // Gather a w x h window (periodic wrap) of XS, XP, PSI and U into
-// dst[plane][h][w] with planes 9 | 25 nqd | nqd | 2.
+// dst[plane][h][w] with planes 9 | 25 nqd | nqd | 2, as full FP64 values.
+template <typename T>
 __global__ void k_window(int nx, int ny, int nqd, int x0, int y0, int w,
-                         int h, StateView a, double *__restrict__ dst) {
+                         int h, StateT<T> a, RefView ref, double *__restrict__ dst) {
+  constexpr bool F32 = std::is_same<T, float>::value;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int plane = blockIdx.y;
   if (i >= w * h) return;
@@ -699,23 +926,31 @@ __global__ void k_window(int nx, int ny, int nqd, int x0, int y0, int w,
   const long long N = (long long)nx * ny;
   const size_t r = (size_t)y * nx + x;
   double v;
-  if (plane < 9)
-    v = a.XS[(size_t)plane * N + r];
-  else if (plane < 9 + 25 * nqd)
-    v = a.XP[(size_t)(plane - 9) * N + r];
-  else if (plane < 9 + 26 * nqd)
-    v = a.PSI[(size_t)(plane - 9 - 25 * nqd) * N + r];
-  else
+  if (plane < 9) {
+    v = full(a.XS[(size_t)plane * N + r], F32 ? (double)ref.XS[(size_t)plane * ny + y] : 0.0);
+  } else if (plane < 9 + 25 * nqd) {
+    const size_t pl = plane - 9;
+    v = full(a.XP[pl * N + r], F32 ? (double)ref.XP[pl * ny + y] : 0.0);
+  } else if (plane < 9 + 26 * nqd) {
+    const size_t pl = plane - 9 - 25 * nqd;
+    v = full(a.PSI[pl * N + r], F32 ? (double)ref.PSI[pl * ny + y] : 0.0);
+  } else {
     v = a.FLD[(size_t)(F_UX + plane - 9 - 26 * nqd) * N + r];
+  }
   dst[(size_t)plane * w * h + i] = v;
 }
 
+template <typename T>
 hipError_t launch_window(int nx, int ny, int nqd, int x0, int y0, int w, int h,
-                         StateView a, double *dst, hipStream_t s) {
+                         StateT<T> a, RefView ref, double *dst, hipStream_t s) {
   dim3 grid((unsigned)((w * h + 255) / 256), 9 + 26 * nqd + 2);
-  hipLaunchKernelGGL(k_window, grid, dim3(256), 0, s, nx, ny, nqd, x0, y0, w,
-                     h, a, dst);
+  hipLaunchKernelGGL(k_window<T>, grid, dim3(256), 0, s, nx, ny, nqd, x0, y0, w,
+                     h, a, ref, dst);
   return hipGetLastError();
 }
+template hipError_t launch_window<double>(int, int, int, int, int, int, int, StateT<double>,
+                                          RefView, double *, hipStream_t);
+template hipError_t launch_window<float>(int, int, int, int, int, int, int, StateT<float>,
+                                         RefView, double *, hipStream_t);
 
 }  // namespace tplk

@@ -165,12 +165,19 @@ int derive(const Config &c, Derived &d) {
   return TPL_OK;
 }
 
-struct Buffers {  // double-buffered state: element offsets of each half
-  double *XS = nullptr, *XP = nullptr, *PSI = nullptr, *FLD = nullptr;
+// Double-buffered state.  XS, XP and PSI hold elements of esize bytes (8:
+// FP64 values, 4: FP32 deviations from the reference); FLD is FP64.
+struct Buffers {
+  void *XS = nullptr, *XP = nullptr, *PSI = nullptr;
+  double *FLD = nullptr;
   size_t nXS = 0, nXP = 0, nPSI = 0, nFLD = 0;  // elements per half
-  StateView half(int h) const {
-    return StateView{XS + h * nXS, XP + h * nXP, PSI + h * nPSI, FLD + h * nFLD};
+  size_t esize = 8;
+  template <typename T>
+  StateT<T> half(int h) const {
+    return StateT<T>{static_cast<T *>(XS) + h * nXS, static_cast<T *>(XP) + h * nXP,
+                     static_cast<T *>(PSI) + h * nPSI, FLD + h * nFLD};
   }
+  StateView half64(int h) const { return half<double>(h); }
 };
 
 }  // namespace
@@ -185,6 +192,8 @@ struct tpl_ctx {
   long long step = 0;
   QNode *qtab_d = nullptr;
   double *peq_d = nullptr;
+  float *ref = nullptr;   // FP32 form: reference state [9 + 26 nqd planes][ny]
+  float *sref = nullptr;  // FP32 form: the same values regrouped for the step kernel
   double *scratch = nullptr;  // reductions, perturbation field, windows
   size_t scratch_n = 0;
   double kernel_ms = 0.0;
@@ -253,6 +262,9 @@ int ensure_scratch(tpl_ctx *x, size_t n) {
   return TPL_OK;
 }
 
+size_t elem_size(const tpl_ctx *x) { return x->c.precision == TPL_FP32 ? 4 : 8; }
+bool fp32(const tpl_ctx *x) { return x->c.precision == TPL_FP32; }
+
 int alloc_state(tpl_ctx *x) {
   if (x->buf.XS) return TPL_OK;
   Buffers &B = x->buf;
@@ -260,23 +272,49 @@ int alloc_state(tpl_ctx *x) {
   B.nXP = state_elems(x, 1);
   B.nPSI = state_elems(x, 2);
   B.nFLD = state_elems(x, 3);
-  double **ptrs[4] = {&B.XS, &B.XP, &B.PSI, &B.FLD};
-  size_t n[4] = {B.nXS, B.nXP, B.nPSI, B.nFLD};
+  B.esize = elem_size(x);
+  void **ptrs[4] = {&B.XS, &B.XP, &B.PSI, reinterpret_cast<void **>(&B.FLD)};
+  size_t bytes[4] = {2 * B.nXS * B.esize, 2 * B.nXP * B.esize, 2 * B.nPSI * B.esize,
+                     2 * B.nFLD * sizeof(double)};
   for (int i = 0; i < 4; ++i) {
-    if (hipMalloc(ptrs[i], 2 * n[i] * sizeof(double)) != hipSuccess) {
+    if (hipMalloc(ptrs[i], bytes[i]) != hipSuccess) {
       (void)hipGetLastError();
       for (int j = 0; j < i; ++j) {
         (void)hipFree(*ptrs[j]);
         *ptrs[j] = nullptr;
       }
-      B.XS = B.XP = B.PSI = B.FLD = nullptr;
+      B.XS = B.XP = B.PSI = nullptr;
+      B.FLD = nullptr;
       char msg[160];
-      snprintf(msg, sizeof msg, "device allocation of %.2f GB failed",
-               2.0 * n[i] * sizeof(double) / 1e9);
+      snprintf(msg, sizeof msg, "device allocation of %.2f GB failed", bytes[i] / 1e9);
       return fail(TPL_ENOMEM, msg);
     }
   }
   x->owned = true;
+  return TPL_OK;
+}
+
+RefView ref_view(const tpl_ctx *x) {
+  const size_t ny = x->c.ny, nqd = x->d.nqd;
+  if (!x->ref) return RefView{nullptr, nullptr, nullptr, x->c.ny};
+  return RefView{x->ref, x->ref + 9 * ny, x->ref + (9 + 25 * nqd) * ny, x->c.ny};
+}
+size_t ref_elems(const tpl_ctx *x) { return (9 + 26 * (size_t)x->d.nqd) * x->c.ny; }
+size_t sref_elems(const tpl_ctx *x) {
+  return (50 * (size_t)x->d.nqd + x->d.nqd + 18) * x->c.ny;
+}
+StepRef step_ref(const tpl_ctx *x) {
+  if (!x->sref) return StepRef{nullptr, nullptr, nullptr, nullptr, nullptr};
+  const size_t ny = x->c.ny, nqd = x->d.nqd;
+  float *p = x->sref;
+  return StepRef{p, p + 25 * nqd * ny, p + 50 * nqd * ny, p + 51 * nqd * ny,
+                 p + 51 * nqd * ny + 9 * ny};
+}
+int build_step_ref(tpl_ctx *x) {
+  const StepRef r = step_ref(x);
+  HIPCHK(launch_step_ref(x->d.nqd, x->c.ny, x->qtab_d, ref_view(x), const_cast<float *>(r.pull),
+                         const_cast<float *>(r.store), const_cast<float *>(r.psi),
+                         const_cast<float *>(r.spull), const_cast<float *>(r.sstore), x->stream));
   return TPL_OK;
 }
 
@@ -295,9 +333,11 @@ int upload_tables(tpl_ctx *x) {
 }
 
 // Enqueue n steps of an nx x ny lattice held in B (halves *cur and 1-*cur).
+// B's element size selects the FP64 or the FP32 step.
 int run_steps(tpl_ctx *x, const Buffers &B, int nx, int ny, int *cur,
               long long n, bool timed) {
   StepParams p = make_step_params(x, nx, ny, x->c.qsplit);
+  const StepRef ref = B.esize == 4 ? step_ref(x) : StepRef{nullptr, nullptr, nullptr, nullptr, nullptr};
   x->qs_used = p.qs;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
@@ -306,7 +346,12 @@ int run_steps(tpl_ctx *x, const Buffers &B, int nx, int ny, int *cur,
   }
   for (long long i = 0; i < n; ++i) {
     if (timed) HIPCHK(hipEventRecord(e0, x->stream));
-    HIPCHK(launch_step_f64(p, B.half(*cur), B.half(1 - *cur), x->qtab_d, x->stream));
+    if (B.esize == 4)
+      HIPCHK(launch_step<float>(p, B.half<float>(*cur), B.half<float>(1 - *cur), ref,
+                                x->qtab_d, x->stream));
+    else
+      HIPCHK(launch_step<double>(p, B.half<double>(*cur), B.half<double>(1 - *cur), ref,
+                                 x->qtab_d, x->stream));
     if (timed) {
       HIPCHK(hipEventRecord(e1, x->stream));
       HIPCHK(hipEventSynchronize(e1));
@@ -381,8 +426,17 @@ int perturb(tpl_ctx *x, uint64_t seed, double amp) {
   }
   HIPCHK(hipMemcpyAsync(scale, &h_scale, sizeof(double), hipMemcpyHostToDevice,
                         x->stream));
-  HIPCHK(launch_perturb_apply(x->d.nqd, N, du, scale, x->buf.half(x->cur), x->stream));
-  HIPCHK(launch_refresh(x->d.nqd, N, x->qtab_d, x->buf.half(x->cur), x->stream));
+  if (fp32(x)) {
+    HIPCHK(launch_perturb_apply<float>(x->d.nqd, nx, ny, du, scale, x->buf.half<float>(x->cur),
+                                       ref_view(x), x->stream));
+    HIPCHK(launch_refresh<float>(x->d.nqd, nx, ny, x->qtab_d, x->buf.half<float>(x->cur),
+                                 ref_view(x), x->stream));
+  } else {
+    HIPCHK(launch_perturb_apply<double>(x->d.nqd, nx, ny, du, scale, x->buf.half64(x->cur),
+                                        ref_view(x), x->stream));
+    HIPCHK(launch_refresh<double>(x->d.nqd, nx, ny, x->qtab_d, x->buf.half64(x->cur),
+                                  ref_view(x), x->stream));
+  }
   HIPCHK(hipStreamSynchronize(x->stream));
   return TPL_OK;
 }
@@ -469,8 +523,8 @@ int tpl_set_param(tpl_ctx *x, const char *key, double v) {
   }
   if (!found) return fail(TPL_EINVAL, std::string("unknown parameter ") + key);
   if (c.spring != 0 && c.spring != 1) return fail(TPL_EINVAL, "spring must be 0 or 1");
-  if (c.precision != TPL_FP64)
-    return fail(TPL_EINVAL, "precision: only TPL_FP64 is built in this library");
+  if (c.precision != TPL_FP64 && c.precision != TPL_FP32)
+    return fail(TPL_EINVAL, "precision must be TPL_FP64 or TPL_FP32");
   if (c.qsplit < 0 || c.qsplit > 8) return fail(TPL_EINVAL, "qsplit must be in [0,8]");
   if (!(c.drift_cap >= 0)) return fail(TPL_EINVAL, "drift_cap must be >= 0");
   if (runtime_knob) {
@@ -494,6 +548,7 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
     }
   const Derived &d = x->d;
   const double N = (double)x->c.nx * x->c.ny;
+  const double es = x->c.precision == TPL_FP32 ? 4.0 : 8.0;
   struct {
     const char *n;
     double v;
@@ -506,12 +561,12 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
       {"R", d.R}, {"DQ", d.DQ}, {"F0", d.F0}, {"kappa", d.kappa},
       {"meq", d.meq}, {"Sc", d.Sc}, {"rhoS0", d.rhoS0}, {"rhoP0", d.rhoP0},
       {"step", (double)x->step},
-      {"bytes_XS", 16.0 * 9 * N}, {"bytes_XP", 16.0 * 25 * d.nqd * N},
-      {"bytes_PSI", 16.0 * d.nqd * N}, {"bytes_FLD", 16.0 * NF * N},
-      {"bytes_state", 16.0 * N * (9 + 26.0 * d.nqd + NF)},
+      {"bytes_XS", 2.0 * es * 9 * N}, {"bytes_XP", 2.0 * es * 25 * d.nqd * N},
+      {"bytes_PSI", 2.0 * es * d.nqd * N}, {"bytes_FLD", 16.0 * NF * N},
+      {"bytes_state", 2.0 * N * (es * (9 + 26.0 * d.nqd) + 8.0 * NF)},
       // algorithmic HBM bytes of one step: populations read + written,
       // lagged psi written + read, lagged per-node fields written + read
-      {"bytes_per_step", 8.0 * N * (2.0 * (9 + 25.0 * d.nqd) + 2.0 * d.nqd + 2.0 * NF)},
+      {"bytes_per_step", N * (es * (2.0 * (9 + 25.0 * d.nqd) + 2.0 * d.nqd) + 8.0 * 2.0 * NF)},
       {"kernel_ms", x->kernel_ms}, {"kernel_launches", (double)x->kernel_launches},
       {"qsplit_used", (double)x->qs_used},
   };
@@ -538,16 +593,18 @@ int tpl_adopt_buffers(tpl_ctx *x, void *const *dptrs, const size_t *bytes, int n
   B.nXP = state_elems(x, 1);
   B.nPSI = state_elems(x, 2);
   B.nFLD = state_elems(x, 3);
-  size_t need[4] = {B.nXS, B.nXP, B.nPSI, B.nFLD};
+  B.esize = elem_size(x);
+  const size_t need[4] = {2 * B.nXS * B.esize, 2 * B.nXP * B.esize, 2 * B.nPSI * B.esize,
+                          2 * B.nFLD * sizeof(double)};
   for (int i = 0; i < 4; ++i) {
-    if (!dptrs[i] || bytes[i] < 2 * need[i] * sizeof(double))
+    if (!dptrs[i] || bytes[i] < need[i])
       return fail(TPL_EINVAL, "adopted buffer " + std::to_string(i) + " too small");
     if (((uintptr_t)dptrs[i]) & 255) return fail(TPL_EINVAL, "adopted buffer not 256-byte aligned");
   }
-  B.XS = (double *)dptrs[0];
-  B.XP = (double *)dptrs[1];
-  B.PSI = (double *)dptrs[2];
-  B.FLD = (double *)dptrs[3];
+  B.XS = dptrs[0];
+  B.XP = dptrs[1];
+  B.PSI = dptrs[2];
+  B.FLD = static_cast<double *>(dptrs[3]);
   x->buf = B;
   x->owned = false;
   return TPL_OK;
@@ -568,13 +625,15 @@ int tpl_init(tpl_ctx *x, uint64_t seed, double perturbation) {
   x->step = 0;
   long long npre = x->c.pre_steps;
   if (npre < 0) npre = (long long)std::ceil(5.0 * std::max(d.l * d.l / d.nu, d.lambda));
-  // base state on one column, then copied to every column
+  // base state on one FP64 column, then copied to every column (FP32 form:
+  // the column becomes the reference and every deviation starts at zero)
   {
     Buffers C;
     C.nXS = 9 * (size_t)ny;
     C.nXP = 25 * (size_t)d.nqd * ny;
     C.nPSI = (size_t)d.nqd * ny;
     C.nFLD = (size_t)NF * ny;
+    C.esize = 8;
     double *col = nullptr;
     const size_t tot = 2 * (C.nXS + C.nXP + C.nPSI + C.nFLD);
     if (hipMalloc(&col, tot * sizeof(double)) != hipSuccess) {
@@ -582,21 +641,43 @@ int tpl_init(tpl_ctx *x, uint64_t seed, double perturbation) {
       return fail(TPL_ENOMEM, "column allocation failed");
     }
     C.XS = col;
-    C.XP = C.XS + 2 * C.nXS;
-    C.PSI = C.XP + 2 * C.nXP;
-    C.FLD = C.PSI + 2 * C.nPSI;
+    C.XP = col + 2 * C.nXS;
+    C.PSI = col + 2 * (C.nXS + C.nXP);
+    C.FLD = col + 2 * (C.nXS + C.nXP + C.nPSI);
     int ccur = 0;
-    int e = TPL_OK;
     auto run = [&]() -> int {
-      HIPCHK(launch_rest(d.nqd, ny, d.rhoS0, d.rhoP0, x->peq_d, C.half(0), x->stream));
-      HIPCHK(launch_refresh(d.nqd, ny, x->qtab_d, C.half(0), x->stream));
+      const RefView none{nullptr, nullptr, nullptr, ny};
+      HIPCHK(launch_rest(d.nqd, ny, d.rhoS0, d.rhoP0, x->peq_d, C.half64(0), x->stream));
+      HIPCHK(launch_refresh<double>(d.nqd, 1, ny, x->qtab_d, C.half64(0), none, x->stream));
       int r2 = run_steps(x, C, 1, ny, &ccur, npre, false);
       if (r2) return r2;
-      HIPCHK(launch_tile(d.nqd, nx, ny, C.half(ccur), x->buf.half(0), x->stream));
+      const StateView cv = C.half64(ccur);
+      if (!fp32(x)) {
+        HIPCHK(launch_tile(d.nqd, nx, ny, cv, x->buf.half64(0), x->stream));
+      } else {
+        if (!x->ref) {
+          if (hipMalloc(&x->ref, ref_elems(x) * sizeof(float)) != hipSuccess ||
+              hipMalloc(&x->sref, sref_elems(x) * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(TPL_ENOMEM, "reference allocation failed");
+          }
+        }
+        // reference = the column's populations and lagged psi rounded to FP32,
+        // [plane][ny]; the stored deviations start as the rounding residual
+        HIPCHK(launch_make_ref(d.nqd, ny, cv, x->ref, x->stream));
+        int r3 = build_step_ref(x);
+        if (r3) return r3;
+        const RefView rv = ref_view(x);
+        const StateView32 h0 = x->buf.half<float>(0);
+        HIPCHK(launch_tile_dev(9, nx, ny, cv.XS, rv.XS, h0.XS, x->stream));
+        HIPCHK(launch_tile_dev(25 * d.nqd, nx, ny, cv.XP, rv.XP, h0.XP, x->stream));
+        HIPCHK(launch_tile_dev(d.nqd, nx, ny, cv.PSI, rv.PSI, h0.PSI, x->stream));
+        HIPCHK(launch_tile_fields(nx, ny, cv.FLD, h0.FLD, x->stream));
+      }
       HIPCHK(hipStreamSynchronize(x->stream));
       return TPL_OK;
     };
-    e = run();
+    const int e = run();
     (void)hipFree(col);
     if (e) return e;
   }
@@ -622,7 +703,7 @@ int tpl_step(tpl_ctx *x, int64_t n) {
   rc = ensure_scratch(x, 1024 + 1);
   if (rc) return rc;
   int nb = 0;
-  HIPCHK(launch_nan_check(N, x->buf.half(x->cur).FLD, x->scratch, &nb, x->stream));
+  HIPCHK(launch_nan_check(N, x->buf.half64(x->cur).FLD, x->scratch, &nb, x->stream));
   HIPCHK(launch_sum(x->scratch, nb, 1, x->scratch + 1024, x->stream));
   double bad = 0.0;
   HIPCHK(hipMemcpyAsync(&bad, x->scratch + 1024, sizeof(double), hipMemcpyDeviceToHost,
@@ -640,9 +721,15 @@ int tpl_moments_device(tpl_ctx *x, void *dptr, size_t len) {
   const long long N = (long long)x->c.nx * x->c.ny;
   if (!dptr || len < (size_t)TPL_NFIELDS * N) return fail(TPL_EINVAL, "output too small");
   const double s2 = x->d.sigma * x->d.sigma;
-  HIPCHK(launch_observables(x->d.nqd, N, x->qtab_d, 1.0 / s2, x->d.G,
-                            x->d.rhoP0 * x->d.meq, x->buf.half(x->cur),
-                            (double *)dptr, x->stream));
+  const double G = x->d.G, mref = x->d.rhoP0 * x->d.meq;
+  if (fp32(x))
+    HIPCHK(launch_observables<float>(x->d.nqd, x->c.nx, x->c.ny, x->qtab_d, 1.0 / s2, G, mref,
+                                     x->buf.half<float>(x->cur), ref_view(x), (double *)dptr,
+                                     x->stream));
+  else
+    HIPCHK(launch_observables<double>(x->d.nqd, x->c.nx, x->c.ny, x->qtab_d, 1.0 / s2, G, mref,
+                                      x->buf.half64(x->cur), ref_view(x), (double *)dptr,
+                                      x->stream));
   return TPL_OK;
 }
 
@@ -665,7 +752,7 @@ double tpl_perturbation_amplitude(tpl_ctx *x) {
   if (check_ready(x)) return NAN;
   const int nx = x->c.nx, ny = x->c.ny;
   if (ensure_scratch(x, (size_t)ny + 1)) return NAN;
-  if (launch_amplitude_rows(nx, ny, x->buf.half(x->cur).FLD, x->scratch, x->stream) != hipSuccess ||
+  if (launch_amplitude_rows(nx, ny, x->buf.half64(x->cur).FLD, x->scratch, x->stream) != hipSuccess ||
       launch_sum(x->scratch, ny, 1, x->scratch + ny, x->stream) != hipSuccess) {
     fail(TPL_EHIP, "amplitude kernels failed");
     return NAN;
@@ -686,8 +773,12 @@ int tpl_diagnostics(tpl_ctx *x, tpl_diag *out) {
   rc = ensure_scratch(x, (size_t)1024 * kDiagComp + kDiagComp);
   if (rc) return rc;
   int nb = 0;
-  HIPCHK(launch_diag(x->c.nx, x->c.ny, x->d.nqd, x->qtab_d, x->buf.half(x->cur),
-                     x->scratch, &nb, x->stream));
+  if (fp32(x))
+    HIPCHK(launch_diag<float>(x->c.nx, x->c.ny, x->d.nqd, x->qtab_d, x->buf.half<float>(x->cur),
+                              ref_view(x), x->scratch, &nb, x->stream));
+  else
+    HIPCHK(launch_diag<double>(x->c.nx, x->c.ny, x->d.nqd, x->qtab_d, x->buf.half64(x->cur),
+                               ref_view(x), x->scratch, &nb, x->stream));
   double *res = x->scratch + (size_t)1024 * kDiagComp;
   HIPCHK(launch_diag_final(x->scratch, nb, res, x->stream));
   double h[kDiagComp];
@@ -715,8 +806,12 @@ int tpl_get_window(tpl_ctx *x, int x0, int y0, int w, int h, double *XS,
   const size_t planes = 9 + 26 * nqd + 2;
   rc = ensure_scratch(x, planes * wh);
   if (rc) return rc;
-  HIPCHK(launch_window(x->c.nx, x->c.ny, (int)nqd, x0, y0, w, h, x->buf.half(x->cur),
-                       x->scratch, x->stream));
+  if (fp32(x))
+    HIPCHK(launch_window<float>(x->c.nx, x->c.ny, (int)nqd, x0, y0, w, h,
+                                x->buf.half<float>(x->cur), ref_view(x), x->scratch, x->stream));
+  else
+    HIPCHK(launch_window<double>(x->c.nx, x->c.ny, (int)nqd, x0, y0, w, h,
+                                 x->buf.half64(x->cur), ref_view(x), x->scratch, x->stream));
   const double *s = x->scratch;
   auto cp = [&](double *dst, size_t off, size_t n) -> int {
     if (dst)
@@ -731,19 +826,65 @@ int tpl_get_window(tpl_ctx *x, int x0, int y0, int w, int h, double *XS,
   return TPL_OK;
 }
 
+// One stored array <-> full FP64 host values (planes of N), through scratch
+// for the FP32 form.
+static int array_to_host(tpl_ctx *x, const void *src, int planes, const float *ref,
+                         double *host) {
+  const size_t N = (size_t)x->c.nx * x->c.ny;
+  if (!fp32(x)) {
+    HIPCHK(hipMemcpyAsync(host, src, planes * N * 8, hipMemcpyDeviceToHost, x->stream));
+    return TPL_OK;
+  }
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(planes, (64u << 20) / (8 * N)));
+  int rc = ensure_scratch(x, (size_t)chunk * N);
+  if (rc) return rc;
+  for (int p0 = 0; p0 < planes; p0 += chunk) {
+    const int np = std::min(chunk, planes - p0);
+    HIPCHK(launch_to_f64(x->c.nx, x->c.ny, np, static_cast<const float *>(src) + (size_t)p0 * N,
+                         ref + (size_t)p0 * x->c.ny, x->scratch, x->stream));
+    HIPCHK(hipMemcpyAsync(host + (size_t)p0 * N, x->scratch, np * N * 8, hipMemcpyDeviceToHost,
+                          x->stream));
+    HIPCHK(hipStreamSynchronize(x->stream));
+  }
+  return TPL_OK;
+}
+static int array_from_host(tpl_ctx *x, void *dst, int planes, const float *ref,
+                           const double *host) {
+  const size_t N = (size_t)x->c.nx * x->c.ny;
+  if (!fp32(x)) {
+    HIPCHK(hipMemcpyAsync(dst, host, planes * N * 8, hipMemcpyHostToDevice, x->stream));
+    return TPL_OK;
+  }
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(planes, (64u << 20) / (8 * N)));
+  int rc = ensure_scratch(x, (size_t)chunk * N);
+  if (rc) return rc;
+  for (int p0 = 0; p0 < planes; p0 += chunk) {
+    const int np = std::min(chunk, planes - p0);
+    HIPCHK(hipMemcpyAsync(x->scratch, host + (size_t)p0 * N, np * N * 8, hipMemcpyHostToDevice,
+                          x->stream));
+    HIPCHK(launch_from_f64(x->c.nx, x->c.ny, np, x->scratch, ref + (size_t)p0 * x->c.ny,
+                           static_cast<float *>(dst) + (size_t)p0 * N, x->stream));
+    HIPCHK(hipStreamSynchronize(x->stream));
+  }
+  return TPL_OK;
+}
+
 int tpl_get_state(tpl_ctx *x, double *XS, double *XP, double *psi, double *U) {
   int rc = check_ready(x);
   if (rc) return rc;
   const size_t N = (size_t)x->c.nx * x->c.ny;
-  StateView v = x->buf.half(x->cur);
-  if (XS) HIPCHK(hipMemcpyAsync(XS, v.XS, 9 * N * 8, hipMemcpyDeviceToHost, x->stream));
-  if (XP)
-    HIPCHK(hipMemcpyAsync(XP, v.XP, 25 * x->d.nqd * N * 8, hipMemcpyDeviceToHost, x->stream));
-  if (psi)
-    HIPCHK(hipMemcpyAsync(psi, v.PSI, x->d.nqd * N * 8, hipMemcpyDeviceToHost, x->stream));
+  const int nqd = x->d.nqd, cur = x->cur;
+  const RefView r = ref_view(x);
+  const size_t es = x->buf.esize;
+  const char *XSd = static_cast<const char *>(x->buf.XS) + cur * x->buf.nXS * es;
+  const char *XPd = static_cast<const char *>(x->buf.XP) + cur * x->buf.nXP * es;
+  const char *PSd = static_cast<const char *>(x->buf.PSI) + cur * x->buf.nPSI * es;
+  if (XS && (rc = array_to_host(x, XSd, 9, r.XS, XS))) return rc;
+  if (XP && (rc = array_to_host(x, XPd, 25 * nqd, r.XP, XP))) return rc;
+  if (psi && (rc = array_to_host(x, PSd, nqd, r.PSI, psi))) return rc;
   if (U)
-    HIPCHK(hipMemcpyAsync(U, v.FLD + (size_t)F_UX * N, 2 * N * 8, hipMemcpyDeviceToHost,
-                          x->stream));
+    HIPCHK(hipMemcpyAsync(U, x->buf.half64(cur).FLD + (size_t)F_UX * N, 2 * N * 8,
+                          hipMemcpyDeviceToHost, x->stream));
   HIPCHK(hipStreamSynchronize(x->stream));
   return TPL_OK;
 }
@@ -753,16 +894,24 @@ int tpl_set_state(tpl_ctx *x, const double *XS, const double *XP,
   int rc = check_ready(x);
   if (rc) return rc;
   const size_t N = (size_t)x->c.nx * x->c.ny;
-  StateView v = x->buf.half(x->cur);
-  if (XS) HIPCHK(hipMemcpyAsync(v.XS, XS, 9 * N * 8, hipMemcpyHostToDevice, x->stream));
-  if (XP)
-    HIPCHK(hipMemcpyAsync(v.XP, XP, 25 * x->d.nqd * N * 8, hipMemcpyHostToDevice, x->stream));
-  if (psi)
-    HIPCHK(hipMemcpyAsync(v.PSI, psi, x->d.nqd * N * 8, hipMemcpyHostToDevice, x->stream));
+  const int nqd = x->d.nqd, cur = x->cur;
+  const RefView r = ref_view(x);
+  const size_t es = x->buf.esize;
+  char *XSd = static_cast<char *>(x->buf.XS) + cur * x->buf.nXS * es;
+  char *XPd = static_cast<char *>(x->buf.XP) + cur * x->buf.nXP * es;
+  char *PSd = static_cast<char *>(x->buf.PSI) + cur * x->buf.nPSI * es;
+  if (XS && (rc = array_from_host(x, XSd, 9, r.XS, XS))) return rc;
+  if (XP && (rc = array_from_host(x, XPd, 25 * nqd, r.XP, XP))) return rc;
+  if (psi && (rc = array_from_host(x, PSd, nqd, r.PSI, psi))) return rc;
   if (U)
-    HIPCHK(hipMemcpyAsync(v.FLD + (size_t)F_UX * N, U, 2 * N * 8, hipMemcpyHostToDevice,
-                          x->stream));
-  HIPCHK(launch_refresh(x->d.nqd, (long long)N, x->qtab_d, v, x->stream));
+    HIPCHK(hipMemcpyAsync(x->buf.half64(cur).FLD + (size_t)F_UX * N, U, 2 * N * 8,
+                          hipMemcpyHostToDevice, x->stream));
+  if (fp32(x))
+    HIPCHK(launch_refresh<float>(nqd, x->c.nx, x->c.ny, x->qtab_d, x->buf.half<float>(cur), r,
+                                 x->stream));
+  else
+    HIPCHK(launch_refresh<double>(nqd, x->c.nx, x->c.ny, x->qtab_d, x->buf.half64(cur), r,
+                                  x->stream));
   HIPCHK(hipStreamSynchronize(x->stream));
   return TPL_OK;
 }
@@ -792,6 +941,9 @@ int tpl_set_populations(tpl_ctx *x, int species, const void *host, size_t bytes)
 
 static const char kMagic[8] = {'T', 'P', 'L', 'C', 'K', 'P', 'T', '1'};
 
+// Checkpoint layout: magic, Config, step, then each stored array of the
+// current half in storage precision (XS, XP, PSI, FLD) and, for the FP32
+// form, the FP64 reference.
 int tpl_save(tpl_ctx *x, const char *path) {
   int rc = check_ready(x);
   if (rc) return rc;
@@ -799,19 +951,24 @@ int tpl_save(tpl_ctx *x, const char *path) {
   FILE *f = std::fopen(path, "wb");
   if (!f) return fail(TPL_EINVAL, std::string("cannot open ") + path);
   HIPCHK(hipStreamSynchronize(x->stream));
-  StateView v = x->buf.half(x->cur);
-  const size_t n[4] = {x->buf.nXS, x->buf.nXP, x->buf.nPSI, x->buf.nFLD};
-  const double *src[4] = {v.XS, v.XP, v.PSI, v.FLD};
+  const size_t es = x->buf.esize, cur = x->cur;
+  const void *src[5] = {static_cast<const char *>(x->buf.XS) + cur * x->buf.nXS * es,
+                        static_cast<const char *>(x->buf.XP) + cur * x->buf.nXP * es,
+                        static_cast<const char *>(x->buf.PSI) + cur * x->buf.nPSI * es,
+                        x->buf.FLD + cur * x->buf.nFLD, x->ref};
+  const size_t nb[5] = {x->buf.nXS * es, x->buf.nXP * es, x->buf.nPSI * es, x->buf.nFLD * 8,
+                        x->ref ? ref_elems(x) * sizeof(float) : 0};
   bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(&x->c, sizeof(Config), 1, f) == 1 &&
             std::fwrite(&x->step, sizeof x->step, 1, f) == 1;
-  std::vector<double> h;
-  for (int i = 0; i < 4 && ok; ++i) {
-    h.resize(n[i]);
-    if (hipMemcpy(h.data(), src[i], n[i] * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+  std::vector<char> h;
+  for (int i = 0; i < 5 && ok; ++i) {
+    if (!nb[i]) continue;
+    h.resize(nb[i]);
+    if (hipMemcpy(h.data(), src[i], nb[i], hipMemcpyDeviceToHost) != hipSuccess) {
       std::fclose(f);
       return fail(TPL_EHIP, "checkpoint copy failed");
     }
-    ok = std::fwrite(h.data(), 8, n[i], f) == n[i];
+    ok = std::fwrite(h.data(), 1, nb[i], f) == nb[i];
   }
   ok = (std::fclose(f) == 0) && ok;
   return ok ? TPL_OK : fail(TPL_EINVAL, "checkpoint write failed");
@@ -832,21 +989,31 @@ int tpl_load(tpl_ctx *x, const char *path) {
     std::fclose(f);
     return fail(TPL_EINVAL, "checkpoint does not match this context");
   }
-  StateView v = x->buf.half(x->cur);
-  const size_t n[4] = {x->buf.nXS, x->buf.nXP, x->buf.nPSI, x->buf.nFLD};
-  double *dst[4] = {v.XS, v.XP, v.PSI, v.FLD};
-  std::vector<double> h;
+  const size_t es = x->buf.esize, cur = x->cur;
+  void *dst[5] = {static_cast<char *>(x->buf.XS) + cur * x->buf.nXS * es,
+                  static_cast<char *>(x->buf.XP) + cur * x->buf.nXP * es,
+                  static_cast<char *>(x->buf.PSI) + cur * x->buf.nPSI * es,
+                  x->buf.FLD + cur * x->buf.nFLD, x->ref};
+  const size_t nb[5] = {x->buf.nXS * es, x->buf.nXP * es, x->buf.nPSI * es, x->buf.nFLD * 8,
+                        x->ref ? ref_elems(x) * sizeof(float) : 0};
+  std::vector<char> h;
   HIPCHK(hipStreamSynchronize(x->stream));
-  for (int i = 0; i < 4 && ok; ++i) {
-    h.resize(n[i]);
-    ok = std::fread(h.data(), 8, n[i], f) == n[i];
-    if (ok && hipMemcpy(dst[i], h.data(), n[i] * 8, hipMemcpyHostToDevice) != hipSuccess) {
+  for (int i = 0; i < 5 && ok; ++i) {
+    if (!nb[i]) continue;
+    h.resize(nb[i]);
+    ok = std::fread(h.data(), 1, nb[i], f) == nb[i];
+    if (ok && hipMemcpy(dst[i], h.data(), nb[i], hipMemcpyHostToDevice) != hipSuccess) {
       std::fclose(f);
       return fail(TPL_EHIP, "checkpoint upload failed");
     }
   }
   std::fclose(f);
   if (!ok) return fail(TPL_EINVAL, "checkpoint truncated");
+  if (x->ref) {
+    rc = build_step_ref(x);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(x->stream));
+  }
   x->step = step;
   return TPL_OK;
 }
@@ -861,6 +1028,8 @@ void tpl_destroy(tpl_ctx *x) {
   }
   (void)hipFree(x->qtab_d);
   (void)hipFree(x->peq_d);
+  (void)hipFree(x->ref);
+  (void)hipFree(x->sref);
   (void)hipFree(x->scratch);
   delete x;
 }
