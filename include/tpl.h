@@ -189,6 +189,85 @@ int tpl_load(tpl_ctx *ctx, const char *path);
 /* Release everything the context owns.  NULL is ignored. */
 void tpl_destroy(tpl_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent Kolmogorov lattices (instances) with their
+ * own sizes and parameters, advanced together.  Every step is one launch of
+ * the step kernel over the flat list of all instances' 64-node tiles; the
+ * launches of graph_steps consecutive steps are replayed from one HIP graph.
+ * Each instance computes exactly what a context of its own computes (same
+ * kernel arithmetic, bitwise the same results); only the launch differs.
+ */
+typedef struct tpl_batch tpl_batch;
+
+typedef struct {
+  int nx, ny;        /* lattice */
+  int periods;       /* forcing periods over ny */
+  double Re, Wi, beta, u0;
+  uint64_t seed;       /* perturbation seed (SplitMix64) */
+  double perturbation; /* RMS amplitude / u0 of the multimode perturbation */
+} tpl_instance;
+
+/* Create n >= 1 instances, each validated as by tpl_create (NULL and
+ * tpl_last_error naming the instance on failure), all stored in precision
+ * (TPL_FP64 or TPL_FP32).  All work of the batch is enqueued on one HIP
+ * stream: the caller's (tpl_batch_set_stream) or one the batch creates at
+ * tpl_batch_init (non-blocking, default priority).  The array is copied. */
+tpl_batch *tpl_batch_create(const tpl_instance *inst, int n, int precision);
+
+/* Launch keys, settable at any time (a change after tpl_batch_init re-chooses
+ * the launch shape):
+ *   qsplit 0       Q-slices per tile (0: chosen by the autotuner)
+ *   grid 0         workgroups per launch (0: chosen by the autotuner)
+ *   autotune 1     time the candidate shapes at tpl_batch_init (qsplit 1, 2,
+ *                  4, 8 x one workgroup per tile or a persistent grid of one
+ *                  or two workgroups per CU slot) and keep the fastest;
+ *                  0: heuristic shape
+ *   graph_steps 20 steps captured per HIP graph (< 2: plain launches)
+ *   time_kernels 0 1 = time tpl_batch_step with HIP events (kernel_ms)
+ * Any other key is a tpl_set_param key applied to every instance before
+ * tpl_batch_init (TPL_ESTATE afterwards; precision is rejected). */
+int tpl_batch_set_param(tpl_batch *b, const char *key, double value);
+
+/* Keys: the launch keys above and instances, active (not flagged unstable),
+ * unstable, items (tiles per launch), nodes (r-nodes of the active
+ * instances), bytes_per_step (algorithmic bytes of the active instances),
+ * bytes_state (all instances), qsplit_used, grid_used, rowtile, kernel_ms
+ * (mean time of one step, needs time_kernels), kernel_steps, tune_ms, step. */
+int tpl_batch_query(const tpl_batch *b, const char *key, double *out);
+
+/* Bind a caller's hipStream_t to the batch and every instance (NULL: the
+ * batch's own stream).  Discards the captured graph.  A graph is captured
+ * only on a stream other than the null stream. */
+int tpl_batch_set_stream(tpl_batch *b, void *hip_stream);
+
+/* Allocate and initialise every instance as tpl_init does (base state from
+ * its own column pre-run, all columns stepped together; then its seeded
+ * perturbation), then choose the launch shape.  TPL_ENOMEM if the instances
+ * do not fit (tpl_query key bytes_state of the instances, summed, plus about
+ * 12 bytes per node of working memory).  Synchronises before returning. */
+int tpl_batch_init(tpl_batch *b);
+
+/* Advance every active instance n >= 0 steps, then check each for NaN/Inf:
+ * an instance that diverged is flagged (tpl_batch_status), dropped from
+ * later launches and keeps its last state; the others go on.  Returns TPL_OK
+ * unless a call fails.  Synchronises before returning. */
+int tpl_batch_step(tpl_batch *b, int64_t n);
+
+/* tpl_perturbation_amplitude of every instance (NaN for an unstable one);
+ * out holds n >= instances doubles. */
+int tpl_batch_amplitudes(tpl_batch *b, double *out, int n);
+
+/* 1 for each instance flagged unstable, else 0; n >= instances ints. */
+int tpl_batch_status(const tpl_batch *b, int *unstable, int n);
+
+/* The context of instance i, owned by the batch (do not destroy it).  Every
+ * single-context call works on it (state exchange, diagnostics, checkpoint,
+ * even tpl_step: the next tpl_batch_step continues from its current state). */
+tpl_ctx *tpl_batch_instance(tpl_batch *b, int i);
+
+/* Release the batch and all its instances.  NULL is ignored. */
+void tpl_batch_destroy(tpl_batch *b);
+
 /* Thread-local description of the last error ("" if none). */
 const char *tpl_last_error(void);
 

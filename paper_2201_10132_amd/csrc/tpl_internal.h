@@ -78,6 +78,20 @@ struct StepRef {
   const float *pull, *store, *psi, *spull, *sstore;
 };
 
+// One instance of a batch as the batched step kernel sees it: parameters,
+// both halves of its state (untyped: the batch's storage type), its FP32
+// reference tables, its Q-node table and the index of its first item
+// (64-node tile) in the batch's flat item list.  Half (parity ^ cur0) is read.
+struct InstDev {
+  StepParams p;
+  void *XS[2], *XP[2], *PSI[2];
+  double *FLD[2];
+  const float *rpull, *rstore, *rpsi, *rspull, *rsstore;
+  const QNode *qtab;
+  int item0;
+  int cur0;
+};
+
 // Launchers (tpl_kernels.hip).  All enqueue on stream and return the launch
 // status.  T = double or float.
 template <typename T>
@@ -93,6 +107,9 @@ hipError_t launch_step_ref(int nqd, int ny, const QNode *qtab, RefView ref,
 // dst[plane][N] = (float)(col[plane][y] - ref[plane][y]) for every x.
 hipError_t launch_tile_dev(int planes, int nx, int ny, const double *col,
                            const float *ref, float *dst, hipStream_t s);
+template <typename T>
+hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs, int grid,
+                             bool rowtile, int parity, hipStream_t s);
 hipError_t launch_rest(int nqd, long long N, double rhoS0, double rhoP0,
                        const double *peq, StateView a, hipStream_t s);
 template <typename T>

@@ -88,6 +88,15 @@ template <typename T>
 __device__ __forceinline__ void sto(T *base, uint32_t off, T v) {
   *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
 }
+// Read-only tables (reference values, instance records) are read through the
+// constant address space, which the compiler turns into scalar loads whenever
+// the address is wave-uniform.
+#define CONSTANT_AS __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const T CONSTANT_AS *cst(const T *p) {
+  return (const T CONSTANT_AS *)(p);
+}
+
 // Full value from a stored one: identity for FP64, reference + deviation for
 // the FP32 form (ref = the plane's reference value at this row).
 __device__ __forceinline__ double full(double v, double) { return v; }
@@ -116,17 +125,19 @@ __device__ __forceinline__ float stored<float>(double v, double ref) { return (f
 // Arithmetic is FP64 for both storage types.  ROWTILE: every 64-node tile
 // lies in one lattice row (nx % 64 == 0), so the FP32 form's reference values
 // are wave-uniform (scalar loads).
-template <typename T, int MAXT, bool ROWTILE>
-__global__ void __launch_bounds__(MAXT)
-    k_step(StepParams p, StateT<T> a, StateT<T> b, const float *__restrict__ rpull,
-           const float *__restrict__ rstore, const float *__restrict__ rpsi,
-           const float *__restrict__ rspull, const float *__restrict__ rsstore,
-           const QNode *__restrict__ qtab) {
+// One 64-node tile of one lattice (all qs slices of the workgroup take part).
+// red: LDS of qs * 12 * 64 doubles.
+template <typename T, bool ROWTILE>
+__device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &a,
+                                          const StateT<T> &b, const float *__restrict__ rpull,
+                                          const float *__restrict__ rstore,
+                                          const float *__restrict__ rpsi,
+                                          const float *__restrict__ rspull,
+                                          const float *__restrict__ rsstore,
+                                          const QNode *__restrict__ qtab, const int tile,
+                                          double *red) {
   constexpr bool F32 = std::is_same<T, float>::value;
   constexpr uint32_t SZ = sizeof(T);
-  extern __shared__ double red[];  // [qs][12][64]
-  const int tile = xcd_tile(blockIdx.x, p.tiles_per_xcd);
-  if (tile >= p.ntiles) return;  // whole workgroup leaves together
   const int lane = threadIdx.x & 63;
   const int slice = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const long long N = p.N;
@@ -159,13 +170,13 @@ __global__ void __launch_bounds__(MAXT)
   auto wfplane = [&](double *arr, long long i) { return uni(arr + (size_t)i * N); };
   // FP32 form: reference values, [row][q][k] / [row][q] / [row][d]
   auto rq = [&](const float *tab, int row, int q, int k) -> double {
-    return F32 ? (double)tab[((size_t)row * p.nqd + q) * 25 + k] : 0.0;
+    return F32 ? (double)cst(tab)[((size_t)row * p.nqd + q) * 25 + k] : 0.0;
   };
   auto rpq = [&](int row, int q) -> double {
-    return F32 ? (double)rpsi[(size_t)row * p.nqd + q] : 0.0;
+    return F32 ? (double)cst(rpsi)[(size_t)row * p.nqd + q] : 0.0;
   };
   auto rsd = [&](const float *tab, int d) -> double {
-    return F32 ? (double)tab[(size_t)y * 9 + d] : 0.0;
+    return F32 ? (double)cst(tab)[(size_t)y * 9 + d] : 0.0;
   };
 
   // ---- solvent pull and moments
@@ -320,7 +331,89 @@ __global__ void __launch_bounds__(MAXT)
 #pragma unroll
     for (int d = 0; d < 9; ++d) sto(wfplane(b.FLD, F_M0 + d), fR, mg[d]);
   }
+  if (p.qs > 1) __syncthreads();  // red is reused by the workgroup's next tile
 }
+
+template <typename T, int MAXT, bool ROWTILE>
+__global__ void __launch_bounds__(MAXT)
+    k_step(StepParams p, StateT<T> a, StateT<T> b, const float *__restrict__ rpull,
+           const float *__restrict__ rstore, const float *__restrict__ rpsi,
+           const float *__restrict__ rspull, const float *__restrict__ rsstore,
+           const QNode *__restrict__ qtab) {
+  extern __shared__ double red[];  // [qs][12][64]
+  const int tile = xcd_tile(blockIdx.x, p.tiles_per_xcd);
+  if (tile >= p.ntiles) return;  // whole workgroup leaves together
+  step_tile<T, ROWTILE>(p, a, b, rpull, rstore, rpsi, rspull, rsstore, qtab, tile, red);
+}
+
+
+// Batched step: one launch advances every instance of a batch by one step.
+// Workgroups walk a flat list of (instance, tile) items with a fixed stride;
+// the item index is remapped so that each XCD works through a contiguous
+// range of items.  parity selects which half of every instance is read.
+template <typename T, int MAXT, bool ROWTILE>
+__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)))
+    k_step_batch(const InstDev *__restrict__ inst, int ninst, int nitems, int items_per_xcd,
+                 int parity) {
+  extern __shared__ double red[];
+  const int span = items_per_xcd > 0 ? 8 * items_per_xcd : nitems;
+  for (int it = blockIdx.x; it < span; it += gridDim.x) {
+    const int item = items_per_xcd > 0 ? (it & 7) * items_per_xcd + (it >> 3) : it;
+    if (item >= nitems) continue;  // uniform over the workgroup
+    int lo = 0, hi = ninst - 1;    // last instance with item0 <= item
+    const InstDev CONSTANT_AS *ci = cst(inst);  // read-only table: scalar loads
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ci[mid].item0 <= item) lo = mid; else hi = mid - 1;
+    }
+    // Field-by-field reads through the constant address space keep every
+    // value in SGPRs (a whole-struct copy would go through private memory).
+    const InstDev CONSTANT_AS &d = ci[lo];
+    StepParams pp;
+#define TPL_LD(f) pp.f = d.p.f;
+    TPL_LD(nx) TPL_LD(ny) TPL_LD(nqd) TPL_LD(qs) TPL_LD(ntiles) TPL_LD(tiles_per_xcd)
+    TPL_LD(y0) TPL_LD(N) TPL_LD(aS) TPL_LD(aP) TPL_LD(tau2S) TPL_LD(tau2P) TPL_LD(c1S)
+    TPL_LD(c2S) TPL_LD(rS) TPL_LD(c1P) TPL_LD(c2P) TPL_LD(rP) TPL_LD(kappa) TPL_LD(DQ)
+    TPL_LD(F0) TPL_LD(kf)
+#undef TPL_LD
+    pp.pad = 0;
+    const int rd = parity ^ d.cur0;
+    const StateT<T> a{static_cast<T *>(d.XS[rd]), static_cast<T *>(d.XP[rd]),
+                      static_cast<T *>(d.PSI[rd]), d.FLD[rd]};
+    const StateT<T> b{static_cast<T *>(d.XS[rd ^ 1]), static_cast<T *>(d.XP[rd ^ 1]),
+                      static_cast<T *>(d.PSI[rd ^ 1]), d.FLD[rd ^ 1]};
+    step_tile<T, ROWTILE>(pp, a, b, d.rpull, d.rstore, d.rpsi, d.rspull, d.rsstore, d.qtab,
+                          item - d.item0, red);
+  }
+}
+
+template <typename T>
+hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs, int grid,
+                             bool rowtile, int parity, hipStream_t s) {
+  const size_t lds = qs > 1 ? (size_t)qs * 12 * 64 * sizeof(double) : 0;
+  const int per_xcd = (grid % 8 == 0 && nitems >= 64) ? (nitems + 7) / 8 : 0;
+  const dim3 g(grid), blk(64 * qs);
+  if (qs <= 4) {
+    if (rowtile)
+      hipLaunchKernelGGL((k_step_batch<T, 256, true>), g, blk, lds, s, inst, ninst, nitems,
+                         per_xcd, parity);
+    else
+      hipLaunchKernelGGL((k_step_batch<T, 256, false>), g, blk, lds, s, inst, ninst, nitems,
+                         per_xcd, parity);
+  } else {
+    if (rowtile)
+      hipLaunchKernelGGL((k_step_batch<T, 512, true>), g, blk, lds, s, inst, ninst, nitems,
+                         per_xcd, parity);
+    else
+      hipLaunchKernelGGL((k_step_batch<T, 512, false>), g, blk, lds, s, inst, ninst, nitems,
+                         per_xcd, parity);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_step_batch<double>(const InstDev *, int, int, int, int, bool, int,
+                                              hipStream_t);
+template hipError_t launch_step_batch<float>(const InstDev *, int, int, int, int, bool, int,
+                                             hipStream_t);
 
 template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,

@@ -332,13 +332,17 @@ int upload_tables(tpl_ctx *x) {
   return TPL_OK;
 }
 
-// Enqueue n steps of an nx x ny lattice held in B (halves *cur and 1-*cur).
-// B's element size selects the FP64 or the FP32 step.
+// Q-slices of the base-state column steps (single and batched alike, so that
+// both produce the same base state).
+constexpr int kColumnQs = 8;
+
+// Enqueue n steps of an nx x ny lattice held in B (halves *cur and 1-*cur)
+// with qs_req Q-slices (0: automatic).  B's element size selects the FP64 or
+// the FP32 step.
 int run_steps(tpl_ctx *x, const Buffers &B, int nx, int ny, int *cur,
-              long long n, bool timed) {
-  StepParams p = make_step_params(x, nx, ny, x->c.qsplit);
+              long long n, bool timed, int qs_req) {
+  StepParams p = make_step_params(x, nx, ny, qs_req);
   const StepRef ref = B.esize == 4 ? step_ref(x) : StepRef{nullptr, nullptr, nullptr, nullptr, nullptr};
-  x->qs_used = p.qs;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     HIPCHK(hipEventCreate(&e0));
@@ -438,6 +442,107 @@ int perturb(tpl_ctx *x, uint64_t seed, double amp) {
                                   ref_view(x), x->stream));
   }
   HIPCHK(hipStreamSynchronize(x->stream));
+  return TPL_OK;
+}
+
+// Allocate the state and upload the Q-node tables (first part of tpl_init).
+int prepare_state(tpl_ctx *x) {
+  int rc = alloc_state(x);
+  if (rc) return rc;
+  if (!x->qtab_d) {
+    rc = upload_tables(x);
+    if (rc) return rc;
+  }
+  if (fp32(x) && !x->ref) {
+    if (hipMalloc(&x->ref, ref_elems(x) * sizeof(float)) != hipSuccess ||
+        hipMalloc(&x->sref, sref_elems(x) * sizeof(float)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(TPL_ENOMEM, "reference allocation failed");
+    }
+  }
+  x->cur = 0;
+  x->step = 0;
+  x->inited = false;
+  return TPL_OK;
+}
+
+long long pre_steps_of(const tpl_ctx *x) {
+  const Derived &d = x->d;
+  long long npre = x->c.pre_steps;
+  if (npre < 0) npre = (long long)std::ceil(5.0 * std::max(d.l * d.l / d.nu, d.lambda));
+  return npre;
+}
+
+// Double-buffered FP64 state of one ny-row column (the x-invariant base state).
+struct ColumnBuf {
+  Buffers B;
+  double *mem = nullptr;
+  int alloc(int ny, int nqd) {
+    B.nXS = 9 * (size_t)ny;
+    B.nXP = 25 * (size_t)nqd * ny;
+    B.nPSI = (size_t)nqd * ny;
+    B.nFLD = (size_t)NF * ny;
+    B.esize = 8;
+    const size_t tot = 2 * (B.nXS + B.nXP + B.nPSI + B.nFLD);
+    if (hipMalloc(&mem, tot * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      mem = nullptr;
+      return fail(TPL_ENOMEM, "column allocation failed");
+    }
+    B.XS = mem;
+    B.XP = mem + 2 * B.nXS;
+    B.PSI = mem + 2 * (B.nXS + B.nXP);
+    B.FLD = mem + 2 * (B.nXS + B.nXP + B.nPSI);
+    return TPL_OK;
+  }
+  void release() {
+    if (mem) (void)hipFree(mem);
+    mem = nullptr;
+  }
+};
+
+// Rest state (equilibrium at zero velocity) in half 0 of a column.
+int column_rest(tpl_ctx *x, ColumnBuf &C) {
+  const Derived &d = x->d;
+  const int ny = x->c.ny;
+  const RefView none{nullptr, nullptr, nullptr, ny};
+  HIPCHK(launch_rest(d.nqd, ny, d.rhoS0, d.rhoP0, x->peq_d, C.B.half64(0), x->stream));
+  HIPCHK(launch_refresh<double>(d.nqd, 1, ny, x->qtab_d, C.B.half64(0), none, x->stream));
+  return TPL_OK;
+}
+
+// Copy the converged column to every column of the lattice (half 0).  FP32
+// form: the column rounded to FP32 becomes the reference and the stored
+// deviations start as the rounding residual.
+int seed_from_column(tpl_ctx *x, const StateView &cv) {
+  const Derived &d = x->d;
+  const int nx = x->c.nx, ny = x->c.ny;
+  if (!fp32(x)) {
+    HIPCHK(launch_tile(d.nqd, nx, ny, cv, x->buf.half64(0), x->stream));
+  } else {
+    HIPCHK(launch_make_ref(d.nqd, ny, cv, x->ref, x->stream));
+    int rc = build_step_ref(x);
+    if (rc) return rc;
+    const RefView rv = ref_view(x);
+    const StateView32 h0 = x->buf.half<float>(0);
+    HIPCHK(launch_tile_dev(9, nx, ny, cv.XS, rv.XS, h0.XS, x->stream));
+    HIPCHK(launch_tile_dev(25 * d.nqd, nx, ny, cv.XP, rv.XP, h0.XP, x->stream));
+    HIPCHK(launch_tile_dev(d.nqd, nx, ny, cv.PSI, rv.PSI, h0.PSI, x->stream));
+    HIPCHK(launch_tile_fields(nx, ny, cv.FLD, h0.FLD, x->stream));
+  }
+  HIPCHK(hipStreamSynchronize(x->stream));
+  return TPL_OK;
+}
+
+// Perturbation and counters (last part of tpl_init).
+int finish_init(tpl_ctx *x, uint64_t seed, double perturbation) {
+  x->inited = true;
+  if (perturbation > 0) {
+    const int rc = perturb(x, seed, perturbation);
+    if (rc) return rc;
+  }
+  x->kernel_ms = 0.0;
+  x->kernel_launches = 0;
   return TPL_OK;
 }
 
@@ -613,89 +718,29 @@ int tpl_adopt_buffers(tpl_ctx *x, void *const *dptrs, const size_t *bytes, int n
 int tpl_init(tpl_ctx *x, uint64_t seed, double perturbation) {
   if (!x) return fail(TPL_EINVAL, "null context");
   if (!(perturbation >= 0)) return fail(TPL_EINVAL, "perturbation must be >= 0");
-  int rc = alloc_state(x);
+  int rc = prepare_state(x);
   if (rc) return rc;
-  if (!x->inited || !x->qtab_d) {
-    rc = upload_tables(x);
-    if (rc) return rc;
-  }
   const Derived &d = x->d;
-  const int nx = x->c.nx, ny = x->c.ny;
-  x->cur = 0;
-  x->step = 0;
-  long long npre = x->c.pre_steps;
-  if (npre < 0) npre = (long long)std::ceil(5.0 * std::max(d.l * d.l / d.nu, d.lambda));
-  // base state on one FP64 column, then copied to every column (FP32 form:
-  // the column becomes the reference and every deviation starts at zero)
-  {
-    Buffers C;
-    C.nXS = 9 * (size_t)ny;
-    C.nXP = 25 * (size_t)d.nqd * ny;
-    C.nPSI = (size_t)d.nqd * ny;
-    C.nFLD = (size_t)NF * ny;
-    C.esize = 8;
-    double *col = nullptr;
-    const size_t tot = 2 * (C.nXS + C.nXP + C.nPSI + C.nFLD);
-    if (hipMalloc(&col, tot * sizeof(double)) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(TPL_ENOMEM, "column allocation failed");
-    }
-    C.XS = col;
-    C.XP = col + 2 * C.nXS;
-    C.PSI = col + 2 * (C.nXS + C.nXP);
-    C.FLD = col + 2 * (C.nXS + C.nXP + C.nPSI);
-    int ccur = 0;
-    auto run = [&]() -> int {
-      const RefView none{nullptr, nullptr, nullptr, ny};
-      HIPCHK(launch_rest(d.nqd, ny, d.rhoS0, d.rhoP0, x->peq_d, C.half64(0), x->stream));
-      HIPCHK(launch_refresh<double>(d.nqd, 1, ny, x->qtab_d, C.half64(0), none, x->stream));
-      int r2 = run_steps(x, C, 1, ny, &ccur, npre, false);
-      if (r2) return r2;
-      const StateView cv = C.half64(ccur);
-      if (!fp32(x)) {
-        HIPCHK(launch_tile(d.nqd, nx, ny, cv, x->buf.half64(0), x->stream));
-      } else {
-        if (!x->ref) {
-          if (hipMalloc(&x->ref, ref_elems(x) * sizeof(float)) != hipSuccess ||
-              hipMalloc(&x->sref, sref_elems(x) * sizeof(float)) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(TPL_ENOMEM, "reference allocation failed");
-          }
-        }
-        // reference = the column's populations and lagged psi rounded to FP32,
-        // [plane][ny]; the stored deviations start as the rounding residual
-        HIPCHK(launch_make_ref(d.nqd, ny, cv, x->ref, x->stream));
-        int r3 = build_step_ref(x);
-        if (r3) return r3;
-        const RefView rv = ref_view(x);
-        const StateView32 h0 = x->buf.half<float>(0);
-        HIPCHK(launch_tile_dev(9, nx, ny, cv.XS, rv.XS, h0.XS, x->stream));
-        HIPCHK(launch_tile_dev(25 * d.nqd, nx, ny, cv.XP, rv.XP, h0.XP, x->stream));
-        HIPCHK(launch_tile_dev(d.nqd, nx, ny, cv.PSI, rv.PSI, h0.PSI, x->stream));
-        HIPCHK(launch_tile_fields(nx, ny, cv.FLD, h0.FLD, x->stream));
-      }
-      HIPCHK(hipStreamSynchronize(x->stream));
-      return TPL_OK;
-    };
-    const int e = run();
-    (void)hipFree(col);
-    if (e) return e;
-  }
-  x->inited = true;
-  if (perturbation > 0) {
-    rc = perturb(x, seed, perturbation);
-    if (rc) return rc;
-  }
-  x->kernel_ms = 0.0;
-  x->kernel_launches = 0;
-  return TPL_OK;
+  const int ny = x->c.ny;
+  // base state on one FP64 column, then copied to every column
+  ColumnBuf C;
+  rc = C.alloc(ny, d.nqd);
+  if (rc) return rc;
+  int ccur = 0;
+  rc = column_rest(x, C);
+  if (!rc) rc = run_steps(x, C.B, 1, ny, &ccur, pre_steps_of(x), false, kColumnQs);
+  if (!rc) rc = seed_from_column(x, C.B.half64(ccur));
+  C.release();
+  if (rc) return rc;
+  return finish_init(x, seed, perturbation);
 }
 
 int tpl_step(tpl_ctx *x, int64_t n) {
   int rc = check_ready(x);
   if (rc) return rc;
   if (n < 0) return fail(TPL_EINVAL, "n must be >= 0");
-  rc = run_steps(x, x->buf, x->c.nx, x->c.ny, &x->cur, n, x->c.time_kernels != 0);
+  x->qs_used = make_step_params(x, x->c.nx, x->c.ny, x->c.qsplit).qs;
+  rc = run_steps(x, x->buf, x->c.nx, x->c.ny, &x->cur, n, x->c.time_kernels != 0, x->c.qsplit);
   if (rc) return rc;
   x->step += n;
   // divergence check on the mixture velocity
@@ -1032,6 +1077,573 @@ void tpl_destroy(tpl_ctx *x) {
   (void)hipFree(x->sref);
   (void)hipFree(x->scratch);
   delete x;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched form: many independent lattices, each a full context, advanced
+// together by one launch per step over the flat list of all their 64-node
+// tiles (the "items"); the launches of several steps are captured in a HIP
+// graph.  Unstable instances are dropped from the item list and flagged.
+
+struct tpl_batch {
+  std::vector<tpl_ctx *> inst;
+  std::vector<tpl_instance> spec;
+  std::vector<int> unstable;
+  int precision = TPL_FP64;
+  hipStream_t stream = nullptr, own_stream = nullptr;
+  bool inited = false;
+  // launch shape of the batched step
+  int qsplit = 0, grid = 0, autotune = 1, graph_steps = 20, time_kernels = 0;
+  int qs_used = 0, grid_used = 0;
+  bool rowtile = false;
+  // device instance table of the active instances
+  std::vector<InstDev> tab;
+  InstDev *tab_d = nullptr;
+  int tab_cap = 0, nitems = 0;
+  bool tab_dirty = true;
+  // captured graph: graph_steps launches with parities 0, 1, 0, 1, ...
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  double *scratch = nullptr;
+  int scratch_n = 0;
+  double kernel_ms = 0.0, tune_ms = 0.0;
+  long long kernel_steps = 0;
+  long long step = 0;
+};
+
+namespace {
+
+void drop_graph(tpl_batch *b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+}
+
+// Instance record of one context for the step kernel: both halves of its
+// state, its tables and the batch's Q-slice count.
+InstDev inst_record(tpl_ctx *x, const Buffers &B, int nx, int ny, int qs, int item0,
+                    int cur0) {
+  InstDev r{};
+  r.p = make_step_params(x, nx, ny, qs);
+  r.p.qs = qs;
+  r.p.tiles_per_xcd = 0;
+  for (int h = 0; h < 2; ++h) {
+    r.XS[h] = static_cast<char *>(B.XS) + h * B.nXS * B.esize;
+    r.XP[h] = static_cast<char *>(B.XP) + h * B.nXP * B.esize;
+    r.PSI[h] = static_cast<char *>(B.PSI) + h * B.nPSI * B.esize;
+    r.FLD[h] = B.FLD + h * B.nFLD;
+  }
+  const StepRef ref = B.esize == 4 ? step_ref(x) : StepRef{nullptr, nullptr, nullptr, nullptr, nullptr};
+  r.rpull = ref.pull;
+  r.rstore = ref.store;
+  r.rpsi = ref.psi;
+  r.rspull = ref.spull;
+  r.rsstore = ref.sstore;
+  r.qtab = x->qtab_d;
+  r.item0 = item0;
+  r.cur0 = cur0;
+  return r;
+}
+
+int upload_table(tpl_batch *b, const std::vector<InstDev> &tab) {
+  if ((int)tab.size() > b->tab_cap) {
+    if (b->tab_d) HIPCHK(hipFree(b->tab_d));
+    b->tab_d = nullptr;
+    b->tab_cap = 0;
+    if (hipMalloc(&b->tab_d, sizeof(InstDev) * tab.size()) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(TPL_ENOMEM, "instance table allocation failed");
+    }
+    b->tab_cap = (int)tab.size();
+  }
+  // synchronous: the host vector may change right after
+  HIPCHK(hipMemcpyAsync(b->tab_d, tab.data(), sizeof(InstDev) * tab.size(),
+                        hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return TPL_OK;
+}
+
+hipError_t batch_launch(const tpl_batch *b, int esize, int ninst, int nitems, int qs, int grid,
+                        bool rowtile, int parity) {
+  return esize == 4 ? launch_step_batch<float>(b->tab_d, ninst, nitems, qs, grid, rowtile, parity,
+                                               b->stream)
+                    : launch_step_batch<double>(b->tab_d, ninst, nitems, qs, grid, rowtile,
+                                                parity, b->stream);
+}
+
+// Enqueue n launches of the uploaded table with parities p0, p0^1, ...
+int batch_run(tpl_batch *b, int esize, int ninst, int nitems, int qs, int grid, bool rowtile,
+              int p0, long long n) {
+  for (long long i = 0; i < n; ++i)
+    HIPCHK(batch_launch(b, esize, ninst, nitems, qs, grid, rowtile, (int)((p0 + i) & 1)));
+  return TPL_OK;
+}
+
+int batch_scratch(tpl_batch *b, int n) {
+  if (b->scratch_n >= n) return TPL_OK;
+  if (b->scratch) HIPCHK(hipFree(b->scratch));
+  b->scratch = nullptr;
+  b->scratch_n = 0;
+  if (hipMalloc(&b->scratch, sizeof(double) * n) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TPL_ENOMEM, "batch scratch allocation failed");
+  }
+  b->scratch_n = n;
+  return TPL_OK;
+}
+
+// Base states of every instance: all columns stepped together, in phases
+// that end when an instance has run its own number of column steps.
+int batch_columns(tpl_batch *b) {
+  const int n = (int)b->inst.size();
+  std::vector<ColumnBuf> col(n);
+  std::vector<long long> rem(n);
+  std::vector<int> ccur(n, 0);
+  int rc = TPL_OK;
+  for (int i = 0; i < n && !rc; ++i) {
+    tpl_ctx *x = b->inst[i];
+    rc = col[i].alloc(x->c.ny, x->d.nqd);
+    if (!rc) rc = column_rest(x, col[i]);
+    rem[i] = pre_steps_of(x);
+  }
+  const int qs = kColumnQs;
+  while (!rc) {
+    long long k = -1;
+    for (int i = 0; i < n; ++i)
+      if (rem[i] > 0 && (k < 0 || rem[i] < k)) k = rem[i];
+    if (k < 0) break;
+    std::vector<InstDev> tab;
+    int items = 0;
+    for (int i = 0; i < n; ++i) {
+      if (rem[i] <= 0) continue;
+      tpl_ctx *x = b->inst[i];
+      tab.push_back(inst_record(x, col[i].B, 1, x->c.ny, qs, items, ccur[i]));
+      items += tab.back().p.ntiles;
+    }
+    rc = upload_table(b, tab);
+    if (rc) break;
+    rc = batch_run(b, 8, (int)tab.size(), items, qs, items, false, 0, k);
+    if (rc) break;
+    for (int i = 0; i < n; ++i)
+      if (rem[i] > 0) {
+        rem[i] -= k;
+        ccur[i] ^= (int)(k & 1);
+      }
+  }
+  if (!rc) {
+    const hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) rc = fail(TPL_EHIP, std::string("column steps: ") + hipGetErrorString(e));
+  }
+  for (int i = 0; i < n && !rc; ++i) rc = seed_from_column(b->inst[i], col[i].B.half64(ccur[i]));
+  for (auto &c : col) c.release();
+  return rc;
+}
+
+// Table of the active instances for the main step.
+int build_main_table(tpl_batch *b, int qs) {
+  b->tab.clear();
+  int items = 0;
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    if (b->unstable[i]) continue;
+    tpl_ctx *x = b->inst[i];
+    b->tab.push_back(inst_record(x, x->buf, x->c.nx, x->c.ny, qs, items, x->cur));
+    items += b->tab.back().p.ntiles;
+  }
+  b->nitems = items;
+  b->tab_dirty = true;
+  drop_graph(b);
+  return TPL_OK;
+}
+
+int batch_esize(const tpl_batch *b) { return b->precision == TPL_FP32 ? 4 : 8; }
+
+// Average duration of one launch of the current table (read half cur0,
+// write the other half: repeating it leaves the state unchanged).
+int time_shape(tpl_batch *b, int qs, int grid, int reps, double *ms) {
+  const int esize = batch_esize(b);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int rc = batch_run(b, esize, (int)b->tab.size(), b->nitems, qs, grid, b->rowtile, 0, 1);
+  if (!rc) {
+    (void)hipEventRecord(e0, b->stream);
+    for (int i = 0; i < reps && !rc; ++i)
+      rc = batch_run(b, esize, (int)b->tab.size(), b->nitems, qs, grid, b->rowtile, 0, 1);
+    (void)hipEventRecord(e1, b->stream);
+  }
+  float t = 0.f;
+  if (!rc) {
+    const hipError_t e = hipEventSynchronize(e1);
+    if (e != hipSuccess) rc = fail(TPL_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+    else (void)hipEventElapsedTime(&t, e0, e1);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = t / reps;
+  return rc;
+}
+
+// Choose the Q-slice count and the grid: candidates are one workgroup per
+// item and persistent grids of one or two waves of workgroups per CU slot.
+int choose_shape(tpl_batch *b) {
+  int qs_list[4] = {1, 2, 4, 8}, nqs = 4;
+  if (b->qsplit > 0) {
+    const int q = b->qsplit >= 8 ? 8 : b->qsplit >= 4 ? 4 : b->qsplit >= 2 ? 2 : 1;
+    qs_list[0] = q;
+    nqs = 1;
+  }
+  int rc0 = build_main_table(b, qs_list[0]);  // sets nitems
+  if (rc0) return rc0;
+  if (!b->autotune) {
+    int qs = qs_list[0];
+    if (b->qsplit <= 0) {  // as for one lattice: >= 2048 waves, at most 8 slices
+      qs = 1;
+      while (qs < 8 && (long long)b->nitems * qs < 2048) qs *= 2;
+    }
+    b->qs_used = qs;
+    const int rc = build_main_table(b, qs);
+    b->grid_used = b->grid > 0 ? b->grid : b->nitems;
+    return rc;
+  }
+  double best = -1.0;
+  int bq = 1, bg = 1;
+  b->tune_ms = 0.0;
+  for (int iq = 0; iq < nqs; ++iq) {
+    const int qs = qs_list[iq];
+    int rc = build_main_table(b, qs);
+    if (!rc) rc = upload_table(b, b->tab);
+    if (rc) return rc;
+    b->tab_dirty = false;
+    std::vector<int> grids;
+    if (b->grid > 0) {
+      grids.push_back(b->grid);
+    } else {
+      grids.push_back(b->nitems);
+      const int slots = 256 * 12 / qs;  // 256 CUs x 12 waves (3 per SIMD)
+      for (int m = 1; m <= 2; ++m) {
+        const int g = ((slots * m + 7) / 8) * 8;
+        if (g < b->nitems) grids.push_back(g);
+      }
+    }
+    for (int g : grids) {
+      double ms = 0.0;
+      rc = time_shape(b, qs, g, 3, &ms);
+      if (rc) return rc;
+      b->tune_ms += 4 * ms;
+      if (best < 0 || ms < best) {
+        best = ms;
+        bq = qs;
+        bg = g;
+      }
+    }
+  }
+  b->qs_used = bq;
+  b->grid_used = bg;
+  return build_main_table(b, bq);
+}
+
+int capture_graph(tpl_batch *b) {
+  drop_graph(b);
+  if (b->graph_steps < 2 || b->stream == nullptr) return TPL_OK;
+  const int esize = batch_esize(b);
+  HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  int rc = batch_run(b, esize, (int)b->tab.size(), b->nitems, b->qs_used, b->grid_used,
+                     b->rowtile, 0, b->graph_steps);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(TPL_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  b->graph = g;
+  HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+  return TPL_OK;
+}
+
+// NaN/Inf check of every active instance's mixture velocity; newly unstable
+// instances are flagged and dropped from the table.
+int batch_check(tpl_batch *b, int *newly) {
+  *newly = 0;
+  const int n = (int)b->inst.size();
+  int rc = batch_scratch(b, n);
+  if (rc) return rc;
+  for (int i = 0; i < n; ++i) {
+    if (b->unstable[i]) continue;
+    tpl_ctx *x = b->inst[i];
+    rc = ensure_scratch(x, 1024);
+    if (rc) return rc;
+    int nb = 0;
+    HIPCHK(launch_nan_check((long long)x->c.nx * x->c.ny, x->buf.half64(x->cur).FLD, x->scratch,
+                            &nb, b->stream));
+    HIPCHK(launch_sum(x->scratch, nb, 1, b->scratch + i, b->stream));
+  }
+  std::vector<double> bad(n, 0.0);
+  HIPCHK(hipMemcpyAsync(bad.data(), b->scratch, sizeof(double) * n, hipMemcpyDeviceToHost,
+                        b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  for (int i = 0; i < n; ++i)
+    if (!b->unstable[i] && bad[i] != 0.0) {
+      b->unstable[i] = 1;
+      ++*newly;
+    }
+  return TPL_OK;
+}
+
+struct BatchKey {
+  const char *name;
+  int tpl_batch::*field;
+};
+const BatchKey kBatchKeys[] = {
+    {"qsplit", &tpl_batch::qsplit},           {"grid", &tpl_batch::grid},
+    {"autotune", &tpl_batch::autotune},       {"graph_steps", &tpl_batch::graph_steps},
+    {"time_kernels", &tpl_batch::time_kernels},
+};
+
+}  // namespace
+
+extern "C" {
+
+tpl_batch *tpl_batch_create(const tpl_instance *inst, int n, int precision) {
+  if (!inst || n < 1) {
+    fail(TPL_EINVAL, "need at least one instance");
+    return nullptr;
+  }
+  if (precision != TPL_FP64 && precision != TPL_FP32) {
+    fail(TPL_EINVAL, "precision must be TPL_FP64 or TPL_FP32");
+    return nullptr;
+  }
+  tpl_batch *b = new tpl_batch;
+  b->precision = precision;
+  for (int i = 0; i < n; ++i) {
+    tpl_ctx *x = tpl_create(inst[i].nx, inst[i].ny, inst[i].Re, inst[i].Wi, inst[i].beta,
+                            tpl_forcing{inst[i].periods, inst[i].u0});
+    if (!x || tpl_set_param(x, "precision", precision) != TPL_OK) {
+      const std::string msg = "instance " + std::to_string(i) + ": " + g_err;
+      tpl_destroy(x);
+      tpl_batch_destroy(b);
+      fail(TPL_EINVAL, msg);
+      return nullptr;
+    }
+    if (!(inst[i].perturbation >= 0)) {
+      tpl_destroy(x);
+      tpl_batch_destroy(b);
+      fail(TPL_EINVAL, "instance " + std::to_string(i) + ": perturbation must be >= 0");
+      return nullptr;
+    }
+    b->inst.push_back(x);
+    b->spec.push_back(inst[i]);
+  }
+  b->unstable.assign(n, 0);
+  return b;
+}
+
+int tpl_batch_set_param(tpl_batch *b, const char *key, double value) {
+  if (!b || !key) return fail(TPL_EINVAL, "null argument");
+  for (const BatchKey &k : kBatchKeys)
+    if (!strcmp(k.name, key)) {
+      if (!(value >= 0 && value <= (1 << 30))) return fail(TPL_EINVAL, "value out of range");
+      b->*k.field = (int)value;
+      if (b->inited && strcmp(key, "time_kernels")) {  // new launch shape
+        const int rc = choose_shape(b);
+        if (rc) return rc;
+        b->tab_dirty = true;
+      }
+      return TPL_OK;
+    }
+  if (!strcmp(key, "precision")) return fail(TPL_EINVAL, "precision is fixed at tpl_batch_create");
+  if (b->inited) return fail(TPL_ESTATE, "instance parameters are fixed after tpl_batch_init");
+  for (tpl_ctx *x : b->inst) {
+    const int rc = tpl_set_param(x, key, value);
+    if (rc) return rc;
+  }
+  return TPL_OK;
+}
+
+int tpl_batch_query(const tpl_batch *b, const char *key, double *out) {
+  if (!b || !key || !out) return fail(TPL_EINVAL, "null argument");
+  for (const BatchKey &k : kBatchKeys)
+    if (!strcmp(k.name, key)) {
+      *out = b->*k.field;
+      return TPL_OK;
+    }
+  const std::string s = key;
+  double v = 0.0;
+  if (s == "instances") v = (double)b->inst.size();
+  else if (s == "active") v = (double)b->tab.size();
+  else if (s == "unstable") {
+    for (int u : b->unstable) v += u;
+  } else if (s == "items") v = b->nitems;
+  else if (s == "nodes" || s == "bytes_per_step" || s == "bytes_state") {
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+      if (s != "bytes_state" && b->unstable[i]) continue;
+      double q = 0.0;
+      const int rc = tpl_query(b->inst[i], s == "nodes" ? "nx" : key, &q);
+      if (rc) return rc;
+      if (s == "nodes") {
+        double ny = 0.0;
+        tpl_query(b->inst[i], "ny", &ny);
+        q *= ny;
+      }
+      v += q;
+    }
+  } else if (s == "qsplit_used") v = b->qs_used;
+  else if (s == "grid_used") v = b->grid_used;
+  else if (s == "rowtile") v = b->rowtile;
+  else if (s == "kernel_ms") v = b->kernel_steps ? b->kernel_ms / b->kernel_steps : 0.0;
+  else if (s == "kernel_steps") v = (double)b->kernel_steps;
+  else if (s == "tune_ms") v = b->tune_ms;
+  else if (s == "step") v = (double)b->step;
+  else return fail(TPL_EINVAL, "unknown key " + s);
+  *out = v;
+  return TPL_OK;
+}
+
+int tpl_batch_set_stream(tpl_batch *b, void *hip_stream) {
+  if (!b) return fail(TPL_EINVAL, "null batch");
+  b->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : b->own_stream;
+  for (tpl_ctx *x : b->inst) x->stream = b->stream;
+  drop_graph(b);
+  b->tab_dirty = true;
+  return TPL_OK;
+}
+
+int tpl_batch_init(tpl_batch *b) {
+  if (!b) return fail(TPL_EINVAL, "null batch");
+  b->inited = false;
+  drop_graph(b);
+  if (!b->stream) {  // the batch's own stream, made on first use
+    if (!b->own_stream &&
+        hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      b->own_stream = nullptr;
+      return fail(TPL_EHIP, "stream creation failed");
+    }
+    b->stream = b->own_stream;
+    for (tpl_ctx *x : b->inst) x->stream = b->stream;
+  }
+  int rc = TPL_OK;
+  for (tpl_ctx *x : b->inst) {
+    rc = prepare_state(x);
+    if (rc) return rc;
+  }
+  rc = batch_columns(b);
+  if (rc) return rc;
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    rc = finish_init(b->inst[i], b->spec[i].seed, b->spec[i].perturbation);
+    if (rc) return rc;
+  }
+  b->unstable.assign(b->inst.size(), 0);
+  b->rowtile = true;
+  for (tpl_ctx *x : b->inst) b->rowtile = b->rowtile && (x->c.nx % 64 == 0);
+  b->step = 0;
+  b->kernel_ms = 0.0;
+  b->kernel_steps = 0;
+  b->inited = true;
+  return choose_shape(b);
+}
+
+int tpl_batch_step(tpl_batch *b, int64_t n) {
+  if (!b) return fail(TPL_EINVAL, "null batch");
+  if (!b->inited) return fail(TPL_ESTATE, "batch not initialised (call tpl_batch_init)");
+  if (n < 0) return fail(TPL_EINVAL, "n must be >= 0");
+  if (n == 0 || b->tab.empty()) return TPL_OK;
+  // instances may have been stepped on their own: refresh the halves read
+  for (size_t j = 0, i = 0; i < b->inst.size(); ++i) {
+    if (b->unstable[i]) continue;
+    if (b->tab[j].cur0 != b->inst[i]->cur) {
+      b->tab[j].cur0 = b->inst[i]->cur;
+      b->tab_dirty = true;
+    }
+    ++j;
+  }
+  int rc = TPL_OK;
+  if (b->tab_dirty) {
+    rc = upload_table(b, b->tab);
+    if (rc) return rc;
+    b->tab_dirty = false;
+  }
+  const int esize = batch_esize(b), G = b->graph_steps & ~1;
+  if (G >= 2 && n >= G && !b->gexec) {
+    rc = capture_graph(b);
+    if (rc) return rc;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (b->time_kernels) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, b->stream));
+  }
+  long long done = 0;
+  if (b->gexec)
+    for (; done + G <= n; done += G) HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+  rc = batch_run(b, esize, (int)b->tab.size(), b->nitems, b->qs_used, b->grid_used, b->rowtile,
+                 0, n - done);
+  if (rc) return rc;
+  if (b->time_kernels) {
+    HIPCHK(hipEventRecord(e1, b->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    b->kernel_ms += ms;
+    b->kernel_steps += n;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    if (b->unstable[i]) continue;
+    b->inst[i]->cur ^= (int)(n & 1);
+    b->inst[i]->step += n;
+  }
+  b->step += n;
+  int newly = 0;
+  rc = batch_check(b, &newly);
+  if (rc) return rc;
+  if (newly) {
+    rc = build_main_table(b, b->qs_used);
+    if (rc) return rc;
+    if (b->grid > 0 || b->autotune == 0) b->grid_used = b->grid > 0 ? b->grid : b->nitems;
+    if (b->grid_used > b->nitems && b->nitems > 0) b->grid_used = b->nitems;
+  }
+  return TPL_OK;
+}
+
+int tpl_batch_amplitudes(tpl_batch *b, double *out, int n) {
+  if (!b || !out) return fail(TPL_EINVAL, "null argument");
+  if (!b->inited) return fail(TPL_ESTATE, "batch not initialised (call tpl_batch_init)");
+  if (n < (int)b->inst.size()) return fail(TPL_EINVAL, "output too small");
+  for (size_t i = 0; i < b->inst.size(); ++i)
+    out[i] = b->unstable[i] ? NAN : tpl_perturbation_amplitude(b->inst[i]);
+  return TPL_OK;
+}
+
+int tpl_batch_status(const tpl_batch *b, int *unstable, int n) {
+  if (!b || !unstable) return fail(TPL_EINVAL, "null argument");
+  if (n < (int)b->inst.size()) return fail(TPL_EINVAL, "output too small");
+  for (size_t i = 0; i < b->inst.size(); ++i) unstable[i] = b->unstable[i];
+  return TPL_OK;
+}
+
+tpl_ctx *tpl_batch_instance(tpl_batch *b, int i) {
+  if (!b || i < 0 || i >= (int)b->inst.size()) {
+    fail(TPL_EINVAL, "instance index out of range");
+    return nullptr;
+  }
+  return b->inst[i];
+}
+
+void tpl_batch_destroy(tpl_batch *b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  for (tpl_ctx *x : b->inst) tpl_destroy(x);
+  if (b->tab_d) (void)hipFree(b->tab_d);
+  if (b->scratch) (void)hipFree(b->scratch);
+  if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+  delete b;
 }
 
 }  // extern "C"

@@ -39,6 +39,14 @@ class tpl_diag(C.Structure):
     _fields_ = [(n, C.c_double) for n in DIAG_NAMES]
 
 
+class tpl_instance(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("periods", C.c_int), ("Re", C.c_double),
+                ("Wi", C.c_double), ("beta", C.c_double), ("u0", C.c_double),
+                ("seed", C.c_uint64), ("perturbation", C.c_double)]
+
+INSTANCE_KEYS = ("nx", "ny", "periods", "Re", "Wi", "beta", "u0", "seed", "perturbation")
+
+
 _lib = None
 
 
@@ -76,6 +84,16 @@ def lib():
         "tpl_load": (C.c_int, [vp, cp]),
         "tpl_destroy": (None, [vp]),
         "tpl_last_error": (cp, []),
+        "tpl_batch_create": (vp, [C.POINTER(tpl_instance), C.c_int, C.c_int]),
+        "tpl_batch_set_param": (C.c_int, [vp, cp, C.c_double]),
+        "tpl_batch_query": (C.c_int, [vp, cp, dp]),
+        "tpl_batch_set_stream": (C.c_int, [vp, vp]),
+        "tpl_batch_init": (C.c_int, [vp]),
+        "tpl_batch_step": (C.c_int, [vp, C.c_int64]),
+        "tpl_batch_amplitudes": (C.c_int, [vp, dp, C.c_int]),
+        "tpl_batch_status": (C.c_int, [vp, C.POINTER(C.c_int), C.c_int]),
+        "tpl_batch_instance": (vp, [vp, C.c_int]),
+        "tpl_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -116,9 +134,17 @@ class Tpl:
         for k, v in params.items():
             self.set_param(k, v)
 
+    @classmethod
+    def _borrow(cls, handle, nx, ny, owner):
+        """A view of a context owned by someone else (a batch instance)."""
+        t = cls.__new__(cls)
+        t._h, t.nx, t.ny, t._owner = C.c_void_p(handle), int(nx), int(ny), owner
+        return t
+
     def close(self):
         if getattr(self, "_h", None) is not None:
-            lib().tpl_destroy(self._h)
+            if getattr(self, "_owner", None) is None:
+                lib().tpl_destroy(self._h)
             self._h = None
 
     __del__ = close
@@ -210,3 +236,74 @@ class Tpl:
 
     def load(self, path):
         _check(lib().tpl_load(self._h, os.fspath(path).encode()))
+
+
+class Batch:
+    """Many instances advanced together (tpl_batch_create ... tpl_batch_destroy).
+
+    instances: sequence of dicts with the tpl_instance fields (nx, ny, Re,
+    Wi, beta; periods 1, u0 0.05, seed 0, perturbation 0 by default)."""
+
+    def __init__(self, instances, precision=TPL_FP64, **params):
+        L = lib()
+        n = len(instances)
+        arr = (tpl_instance * n)()
+        for i, d in enumerate(instances):
+            full = {**dict(periods=1, u0=0.05, seed=0, perturbation=0.0), **d}
+            for k in INSTANCE_KEYS:
+                setattr(arr[i], k, full[k])
+        h = L.tpl_batch_create(arr, n, int(precision))
+        if not h:
+            raise TplError(TPL_EINVAL, tpl_last_error())
+        self._h = C.c_void_p(h)
+        self.n = n
+        self.sizes = [(int(d["nx"]), int(d["ny"])) for d in instances]
+        for k, v in params.items():
+            self.set_param(k, v)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().tpl_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_param(self, key, value):
+        _check(lib().tpl_batch_set_param(self._h, key.encode(), float(value)))
+
+    def query(self, key) -> float:
+        out = C.c_double()
+        _check(lib().tpl_batch_query(self._h, key.encode(), C.byref(out)))
+        return out.value
+
+    def set_stream(self, stream_ptr: int):
+        _check(lib().tpl_batch_set_stream(self._h, C.c_void_p(stream_ptr)))
+
+    def init(self):
+        _check(lib().tpl_batch_init(self._h))
+
+    def step(self, n=1):
+        _check(lib().tpl_batch_step(self._h, int(n)))
+
+    def amplitudes(self) -> np.ndarray:
+        out = np.zeros(self.n)
+        _check(lib().tpl_batch_amplitudes(self._h, _dptr(out), self.n))
+        return out
+
+    def status(self) -> np.ndarray:
+        out = (C.c_int * self.n)()
+        _check(lib().tpl_batch_status(self._h, out, self.n))
+        return np.array(out[:], dtype=np.int32)
+
+    def instance(self, i) -> Tpl:
+        h = lib().tpl_batch_instance(self._h, int(i))
+        if not h:
+            raise TplError(TPL_EINVAL, tpl_last_error())
+        nx, ny = self.sizes[i]
+        return Tpl._borrow(h, nx, ny, self)

@@ -82,3 +82,59 @@ def test_algorithmic_bytes_formula():
     # populations read + written, lagged psi written + read, per-node fields
     want = 8 * N * (2 * (9 + 25 * nqd) + 2 * nqd + 2 * 18)
     assert t.query("bytes_per_step") == want
+
+
+def test_batch_host_logic():
+    """Batch creation, validation and parameter forwarding (no device work)."""
+    insts = [dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8),
+             dict(nx=32, ny=48, Re=30.0, Wi=1.0, beta=0.7, periods=2, seed=3, perturbation=1e-3)]
+    b = P.Batch(insts, nq=8, spring=1)
+    assert b.query("instances") == 2
+    for i, d in enumerate(insts):
+        t = b.instance(i)
+        assert (t.query("nx"), t.query("ny")) == (d["nx"], d["ny"])
+        assert t.query("nq") == 8 and t.query("spring") == 1
+        assert t.query("periods") == d.get("periods", 1)
+    want = sum(P.Tpl(d["nx"], d["ny"], d["Re"], d["Wi"], d["beta"], periods=d.get("periods", 1),
+                     nq=8).query("bytes_state") for d in insts)
+    assert b.query("bytes_state") == want
+    with pytest.raises(P.TplError) as e:
+        b.set_param("precision", 1)
+    assert e.value.code == P.tpl.TPL_EINVAL
+    with pytest.raises(P.TplError) as e:
+        b.step(1)
+    assert e.value.code == P.tpl.TPL_ESTATE
+    with pytest.raises(P.TplError):
+        b.instance(2)
+    with pytest.raises(P.TplError) as e:
+        P.Batch([dict(nx=8, ny=8, Re=20.0, Wi=0.5, beta=0.8),
+                 dict(nx=8, ny=2, Re=20.0, Wi=0.5, beta=0.8)])
+    assert "instance 1" in str(e.value)
+    with pytest.raises(P.TplError):
+        P.Batch([dict(nx=8, ny=8, Re=20.0, Wi=0.5, beta=0.8)], precision=7)
+    b.close()
+
+
+def test_batched_sweep_draw():
+    """The seeded draw of the batched sweep: SplitMix64 pinned to its
+    published vectors, values in their ranges, reproducible."""
+    from tests import inputs
+
+    path = os.path.join(ROOT, "tests", "golden", "splitmix64_vectors.txt")
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        seed, *outs = [int(v) for v in line.split()]
+        g = inputs.splitmix64(seed)
+        assert [next(g) for _ in outs] == outs
+    c = inputs.c4_instances()
+    assert len(c) == 256 and c == inputs.c4_instances()
+    assert [d["seed"] for d in c] == list(range(256))
+    for d in c:
+        assert d["nx"] in inputs.C4_SIZES and d["ny"] in inputs.C4_SIZES
+        assert 10 <= d["Re"] < 100 and 0 <= d["Wi"] < 2 and 0.5 <= d["beta"] < 0.9
+    # every size appears on both axes
+    assert {d["nx"] for d in c} == set(inputs.C4_SIZES) == {d["ny"] for d in c}
+    # every instance is a valid configuration for the library
+    for d in c[:16]:
+        P.Tpl(d["nx"], d["ny"], d["Re"], d["Wi"], d["beta"], periods=d["periods"]).close()

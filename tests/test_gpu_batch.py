@@ -1,0 +1,207 @@
+"""GPU tests of the batched form (tpl_batch_*): every instance of a batch
+must reproduce the oracle and a context of its own, whatever the launch
+shape, through graph replays, interleaved single steps and the loss of an
+unstable instance.
+
+Tolerances: against the oracle as for one lattice (1e-12 after a 100-step
+base state and 20 steps, FP64).  Against a context of its own with the same
+Q-slice count the batch runs the same arithmetic in the same order, so the
+states agree bitwise; across Q-slice counts the slice reduction changes the
+summation order (1e-13).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2201_10132_amd as P
+from tests import inputs
+from tests.gpu_common import compare_states
+
+pytestmark = pytest.mark.gpu
+
+# Mixed sizes: ragged tiles (nx * ny not a multiple of 64), a column-height
+# spread for the batched base-state phases, different parameters.
+MIXED = [
+    dict(nx=16, ny=16, Re=20.0, Wi=0.5, beta=0.8, periods=1, seed=1, perturbation=1e-2),
+    dict(nx=24, ny=20, Re=35.0, Wi=1.2, beta=0.6, periods=2, seed=2, perturbation=1e-2),
+    dict(nx=13, ny=9, Re=12.0, Wi=0.0, beta=0.9, periods=1, seed=3, perturbation=1e-2),
+    dict(nx=70, ny=12, Re=50.0, Wi=0.3, beta=0.5, periods=3, seed=4, perturbation=1e-2),
+]
+# Every nx a multiple of 64: the row-tile kernel variant.
+ROWS = [
+    dict(nx=64, ny=16, Re=20.0, Wi=0.5, beta=0.8, periods=1, seed=5, perturbation=1e-2),
+    dict(nx=128, ny=12, Re=40.0, Wi=1.5, beta=0.7, periods=2, seed=6, perturbation=1e-2),
+    dict(nx=64, ny=40, Re=25.0, Wi=0.8, beta=0.6, periods=2, seed=7, perturbation=1e-2),
+]
+
+
+def _single(d, precision, **params):
+    t = P.Tpl(d["nx"], d["ny"], d["Re"], d["Wi"], d["beta"], periods=d["periods"],
+              u0=d.get("u0", 0.05), precision=precision, **params)
+    t.init(seed=d["seed"], perturbation=d["perturbation"])
+    return t
+
+
+def _states_equal(a, b):
+    return {k: float(np.abs(a[k] - b[k]).max()) for k in a}
+
+
+@pytest.mark.parametrize("insts", [MIXED, ROWS], ids=["mixed", "rowtile"])
+def test_batch_matches_oracle(insts):
+    print(f"batch vs oracle: {len(insts)} instances", flush=True)
+    b = P.Batch(insts, nq=6, pre_steps=100, graph_steps=4)
+    b.init()
+    assert b.query("rowtile") == (insts is ROWS)
+    b.step(20)  # 5 graph replays
+    for i, d in enumerate(insts):
+        o = oracle.OracleSim(d["nx"], d["ny"], nq=6, Re=d["Re"], Wi=d["Wi"], beta=d["beta"],
+                             periods=d["periods"])
+        o.base_state(100)
+        o.perturb(d["seed"], d["perturbation"], True)
+        o.step(20)
+        compare_states(b.instance(i).get_state(), o.get_state(), 1e-12)
+    b.close()
+
+
+@pytest.mark.parametrize("precision", [P.TPL_FP64, P.TPL_FP32], ids=["fp64", "fp32"])
+def test_batch_bitwise_vs_single(precision):
+    insts = MIXED + ROWS
+    print(f"batch vs single contexts, precision={precision}", flush=True)
+    b = P.Batch(insts, precision=precision, nq=8, pre_steps=60, graph_steps=4)
+    b.init()
+    qs = int(b.query("qsplit_used"))
+    b.step(10)  # two graph replays and two plain launches
+    for i, d in enumerate(insts):
+        t = _single(d, precision, nq=8, pre_steps=60, qsplit=qs)
+        t.step(10)
+        diff = _states_equal(b.instance(i).get_state(), t.get_state())
+        assert all(v == 0.0 for v in diff.values()), (i, diff)
+        assert b.instance(i).query("step") == 10
+        t.close()
+    b.close()
+
+
+def test_batch_shapes_agree():
+    """Forced launch shapes: grid changes nothing, Q-slices only rounding."""
+    insts = MIXED
+    ref = None
+    for qs, grid in [(1, 0), (1, 8), (2, 16), (4, 0), (8, 24)]:
+        print(f"shape qsplit={qs} grid={grid}", flush=True)
+        b = P.Batch(insts, nq=8, pre_steps=40, autotune=0, qsplit=qs, grid=grid,
+                    graph_steps=0)
+        b.init()
+        assert b.query("qsplit_used") == qs
+        assert b.query("grid_used") == (grid if grid else b.query("items"))
+        b.step(6)
+        st = [b.instance(i).get_state() for i in range(len(insts))]
+        if ref is None:
+            ref = st
+        else:
+            for a, r in zip(st, ref):
+                compare_states(a, r, 1e-13)
+        b.close()
+
+
+def test_graph_replays_match_plain_launches():
+    """Replays of the captured graph, with eager work in between, against
+    the same steps launched one by one."""
+    insts = ROWS
+    g = P.Batch(insts, nq=6, pre_steps=30, autotune=0, qsplit=2, graph_steps=4)
+    e = P.Batch(insts, nq=6, pre_steps=30, autotune=0, qsplit=2, graph_steps=0)
+    g.init()
+    e.init()
+    for rep in range(3):
+        print(f"replay {rep}", flush=True)
+        g.step(4)
+        e.step(4)
+        _ = g.amplitudes()  # eager work and synchronisation between replays
+        for i in range(len(insts)):
+            diff = _states_equal(g.instance(i).get_state(), e.instance(i).get_state())
+            assert all(v == 0.0 for v in diff.values()), (rep, i, diff)
+    g.close()
+    e.close()
+
+
+def test_interleaved_single_steps():
+    """An instance stepped on its own: the next batch step continues from
+    its current half."""
+    insts = MIXED
+    b = P.Batch(insts, nq=6, pre_steps=30, autotune=0, qsplit=4, graph_steps=4)
+    b.init()
+    b.step(5)
+    b.instance(1).set_param("qsplit", 4)  # its own launches: same Q-slices
+    b.instance(1).step(3)
+    b.step(4)
+    for i, d in enumerate(insts):
+        t = _single(d, P.TPL_FP64, nq=6, pre_steps=30, qsplit=4)
+        t.step(5 + (3 if i == 1 else 0) + 4)
+        diff = _states_equal(b.instance(i).get_state(), t.get_state())
+        assert all(v == 0.0 for v in diff.values()), (i, diff)
+        t.close()
+    b.close()
+
+
+def test_unstable_instance_is_dropped():
+    """NaN planted (from the host) in one instance: it is flagged and left
+    alone, the others continue exactly as on their own."""
+    insts = MIXED
+    b = P.Batch(insts, nq=6, pre_steps=30, autotune=0, qsplit=4, graph_steps=4)
+    b.init()
+    b.step(2)
+    bad = b.instance(2)
+    st = bad.get_state()
+    st["XS"][0, 3, 4] = np.nan
+    bad.set_state(**st)
+    b.step(3)
+    assert list(b.status()) == [0, 0, 1, 0]
+    assert b.query("active") == 3 and b.query("unstable") == 1
+    amps = b.amplitudes()
+    assert np.isnan(amps[2]) and np.all(np.isfinite(np.delete(amps, 2)))
+    b.step(5)
+    for i, d in enumerate(insts):
+        if i == 2:
+            continue
+        t = _single(d, P.TPL_FP64, nq=6, pre_steps=30, qsplit=4)
+        t.step(10)
+        diff = _states_equal(b.instance(i).get_state(), t.get_state())
+        assert all(v == 0.0 for v in diff.values()), (i, diff)
+        t.close()
+    assert b.instance(2).query("step") == 5
+    b.close()
+
+
+def test_c4_draw_small_sample():
+    """The first instances of the batched sweep's seeded draw, at FP32 and
+    NQ = 8: all stay finite over a graph of steps and the amplitudes match
+    contexts of their own."""
+    insts = inputs.c4_instances(4)
+    b = P.Batch(insts, precision=P.TPL_FP32, nq=8, pre_steps=200)
+    b.init()
+    b.step(40)
+    assert b.query("unstable") == 0
+    amps = b.amplitudes()
+    qs = int(b.query("qsplit_used"))
+    for i, d in enumerate(insts):
+        t = _single(d, P.TPL_FP32, nq=8, pre_steps=200, qsplit=qs)
+        t.step(40)
+        assert amps[i] == t.amplitude()
+        t.close()
+    b.close()
+
+
+def test_batch_errors():
+    b = P.Batch(MIXED[:1], nq=6, pre_steps=10)
+    with pytest.raises(P.TplError) as e:
+        b.step(1)
+    assert e.value.code == -4  # TPL_ESTATE before init
+    b.init()
+    with pytest.raises(P.TplError) as e:
+        b.set_param("nq", 8)
+    assert e.value.code == -4
+    with pytest.raises(P.TplError) as e:
+        b.step(-1)
+    assert e.value.code == -1
+    b.set_param("qsplit", 2)  # launch keys may change at any time
+    assert b.query("qsplit_used") == 2
+    b.step(2)
+    b.close()
