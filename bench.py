@@ -10,7 +10,11 @@ of both species, lagged-field write) over the lattice.
 
 Prints one JSON line: MLUPS (10^6 r-node updates per second, each carrying
 9 + 25 * 208 populations), the roofline of the step kernel, and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+oracle timed on a bounded sample of the same workload.  Extra entries: the
+FP32 storage form (1024^2 and 4096^2), FP64 and FP32 at NQ = 8, and the
+batched sweep of 256 seeded instances against the same instances stepped
+one by one.  Every workload starts from a base state of --pre-steps column
+steps (outside the timed region).
 """
 from __future__ import annotations
 
@@ -29,6 +33,12 @@ WORKLOAD = dict(nx=1024, ny=1024, periods=4, Re=60.0, Wi=1.0, beta=0.7, nq=16, s
 # diverges at these parameters, and NQ = 8 fits only with FP32 storage)
 WORKLOAD_FP32_LARGE = dict(nx=4096, ny=4096, periods=16, Re=60.0, Wi=1.0, beta=0.7, nq=8,
                            spring=0, seed=0, perturbation=1e-4)
+# batched sweep: 256 seeded instances (sizes from {128..512}^2, Re, Wi, beta
+# drawn per instance), FP32 storage, NQ = 8
+BATCH = dict(instances=256, nq=8, precision=1)
+# base-state column steps before the timed steps (init only, never timed);
+# the library's own default is 5 max(l^2/nu, lambda), ~244k steps here
+DEFAULT_PRE_STEPS = 3000
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 
@@ -60,12 +70,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--pre-steps", type=int, default=-1,
+    ap.add_argument("--pre-steps", type=int, default=DEFAULT_PRE_STEPS,
                     help="base-state column steps (-1: 5 max(l^2/nu, lambda))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 form measurements")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched sweep")
+    ap.add_argument("--batch-instances", type=int, default=BATCH["instances"])
+    ap.add_argument("--one-by-one-steps", type=int, default=10,
+                    help="steps per instance of the one-by-one comparison")
     ap.add_argument("--traffic-file", default=os.path.join(
-        ROOT, "profiles", "k_step_f64_kolmogorov1024_nq16_traffic.txt"))
+        ROOT, "profiles", "k_step_fp64_kolmogorov1024_nq16_traffic.txt"))
+    ap.add_argument("--batch-traffic-file", default=os.path.join(
+        ROOT, "profiles", "k_step_batch_fp32_kolmogorov_batch256_nq8_traffic.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -93,7 +109,7 @@ def main():
         "config": {"workload": "kolmogorov_1024x1024_nq16_fene_fp64", "nx": w["nx"], "ny": w["ny"],
                    "nq": w["nq"], "nqd": main64["nqd"], "periods": w["periods"], "Re": w["Re"],
                    "Wi": w["Wi"], "beta": w["beta"], "perturbation": w["perturbation"],
-                   "parallelism": "single GPU"},
+                   "base_state_pre_steps": args.pre_steps, "parallelism": "single GPU"},
         "roofline": roofline(main64, traffic_bytes(args.traffic_file)),
         "mqlups": round(main64["mlups"] * main64["nqd"], 1),
         "kernel_ms": round(main64["kernel_ms"], 4),
@@ -108,7 +124,22 @@ def main():
         w3 = WORKLOAD_FP32_LARGE
         f32l = measure(torch, w3, 1, max(5, args.steps // 2), args.warmup, args.pre_steps)
         forms["fp32_4096x4096_nq8"] = form_entry(f32l, None)
+        # FP64 at the batched sweep's NQ (the matched-NQ reference)
+        w8 = dict(w, nq=BATCH["nq"])
+        f64q8 = measure(torch, w8, 0, args.steps, args.warmup, args.pre_steps)
+        forms["fp64_1024x1024_nq8"] = form_entry(f64q8, None)
+        f32q8 = measure(torch, w8, 1, args.steps, args.warmup, args.pre_steps)
+        forms["fp32_1024x1024_nq8"] = form_entry(f32q8, f64q8)
         out["precision_forms"] = forms
+    if not args.no_batch:
+        out["batched"] = measure_batch(torch, args.batch_instances, max(5, args.steps // 2),
+                                       args.warmup, args.pre_steps, args.one_by_one_steps)
+        if args.batch_instances == BATCH["instances"]:
+            # counters were taken with every instance active: scale to the active ones
+            tb = traffic_bytes(args.batch_traffic_file)
+            bt = out["batched"]
+            if tb is not None:
+                bt["roofline"]["traffic"] = round(tb * bt["bytes_active_fraction"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
@@ -148,6 +179,68 @@ def measure(torch, w, precision, steps, warmup, pre_steps) -> dict:
     print(f"# precision={precision} {w['nx']}x{w['ny']} nq={w['nq']}: init {init_s:.1f} s, "
           f"{res['kernel_ms']:.3f} ms/step, qsplit={res['qsplit']:.0f}", file=sys.stderr, flush=True)
     t.close()
+    return res
+
+
+def measure_batch(torch, n, steps, warmup, pre_steps, obo_steps) -> dict:
+    """The batched sweep: all instances advanced together (graph replays of
+    the batched step), then the same instances stepped one by one."""
+    import math
+
+    import paper_2201_10132_amd as P
+    from tests import inputs
+
+    insts = inputs.c4_instances(n)
+    stream = torch.cuda.Stream()
+    b = P.Batch(insts, precision=BATCH["precision"], nq=BATCH["nq"], pre_steps=pre_steps,
+                time_kernels=1)
+    b.set_stream(stream.cuda_stream)
+    t0 = time.perf_counter()
+    b.init()
+    init_s = time.perf_counter() - t0
+    b.step(warmup)
+    a0 = b.amplitudes()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)  # synchronises before returning
+    wall = time.perf_counter() - t0
+    kernel_ms = b.query("kernel_ms")  # HIP events around the step launches only
+    a1 = b.amplitudes()
+    nodes = b.query("nodes")
+    bytes_all = sum(b.instance(i).query("bytes_per_step") for i in range(n))
+    res = {
+        "workload": f"kolmogorov_batch_{n}_seeded_fp32_nq{BATCH['nq']}",
+        "instances": n, "nodes": int(nodes), "nq": BATCH["nq"],
+        "nqd": int(b.instance(0).nqd), "precision": "fp32",
+        "steps": steps, "mlups": round(nodes * steps / wall / 1e6, 3),
+        "ms_per_step": round(wall / steps * 1e3, 4), "kernel_ms": round(kernel_ms, 4),
+        "roofline": roofline(dict(bytes_step=b.query("bytes_per_step"), kernel_ms=kernel_ms), None),
+        "qsplit": int(b.query("qsplit_used")), "grid": int(b.query("grid_used")),
+        "items": int(b.query("items")), "graph_steps": int(b.query("graph_steps")),
+        "tune_ms": round(b.query("tune_ms"), 1), "init_s": round(init_s, 2),
+        "pre_steps": pre_steps, "unstable": int(b.query("unstable")),
+        "bytes_active_fraction": b.query("bytes_per_step") / bytes_all,
+    }
+    g = [math.log(y / x) / steps for x, y in zip(a0, a1) if x > 0 and y > 0]
+    if g:
+        g.sort()
+        res["growth_rate_median"] = g[len(g) // 2]
+        res["growth_rate_range"] = [g[0], g[-1]]
+    # the same instances one after another, each with its own launches
+    status = b.status()
+    res["unstable_instances"] = [i for i, u in enumerate(status) if u]
+    active = [i for i, u in enumerate(status) if not u]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in active:
+        b.instance(i).step(obo_steps)
+    wall1 = time.perf_counter() - t0
+    res["one_by_one_mlups"] = round(nodes * obo_steps / wall1 / 1e6, 3)
+    res["speedup_vs_one_by_one"] = round(res["mlups"] / res["one_by_one_mlups"], 3)
+    print(f"# batch {n} instances: init {init_s:.1f} s, {kernel_ms:.3f} ms/step, "
+          f"qsplit={res['qsplit']} grid={res['grid']}, one-by-one "
+          f"{res['one_by_one_mlups']} MLUPS", file=sys.stderr, flush=True)
+    b.close()
     return res
 
 

@@ -244,7 +244,7 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   const double c2w0 = p.c2P * (1.0 / 3.0), c2w1 = p.c2P * (1.0 / 36.0);
   const double one_r = 1.0 - p.rP;
   for (int q = slice; q < nqd; q += p.qs) {
-    const QNode &qn = qtab[q];
+    const QNode CONSTANT_AS &qn = cst(qtab)[q];  // scalar loads
     double g[25];
 #pragma unroll
     for (int k = 0; k < 25; ++k)

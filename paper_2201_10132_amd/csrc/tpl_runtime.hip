@@ -1308,35 +1308,38 @@ int choose_shape(tpl_batch *b) {
     b->grid_used = b->grid > 0 ? b->grid : b->nitems;
     return rc;
   }
+  // first the Q-slice count at one workgroup per item, then persistent grids
+  // (one or two workgroups per CU slot) at the best count
   double best = -1.0;
-  int bq = 1, bg = 1;
+  int bq = qs_list[0], bg = b->nitems;
   b->tune_ms = 0.0;
+  auto trial = [&](int qs, int g) -> int {
+    double ms = 0.0;
+    const int rc = time_shape(b, qs, g, 2, &ms);
+    b->tune_ms += 3 * ms;
+    if (!rc && (best < 0 || ms < best)) {
+      best = ms;
+      bq = qs;
+      bg = g;
+    }
+    return rc;
+  };
   for (int iq = 0; iq < nqs; ++iq) {
-    const int qs = qs_list[iq];
-    int rc = build_main_table(b, qs);
+    int rc = build_main_table(b, qs_list[iq]);
+    if (!rc) rc = upload_table(b, b->tab);
+    if (!rc) rc = trial(qs_list[iq], b->grid > 0 ? b->grid : b->nitems);
+    if (rc) return rc;
+  }
+  if (b->grid <= 0) {
+    int rc = build_main_table(b, bq);
     if (!rc) rc = upload_table(b, b->tab);
     if (rc) return rc;
-    b->tab_dirty = false;
-    std::vector<int> grids;
-    if (b->grid > 0) {
-      grids.push_back(b->grid);
-    } else {
-      grids.push_back(b->nitems);
-      const int slots = 256 * 12 / qs;  // 256 CUs x 12 waves (3 per SIMD)
-      for (int m = 1; m <= 2; ++m) {
-        const int g = ((slots * m + 7) / 8) * 8;
-        if (g < b->nitems) grids.push_back(g);
-      }
-    }
-    for (int g : grids) {
-      double ms = 0.0;
-      rc = time_shape(b, qs, g, 3, &ms);
-      if (rc) return rc;
-      b->tune_ms += 4 * ms;
-      if (best < 0 || ms < best) {
-        best = ms;
-        bq = qs;
-        bg = g;
+    const int slots = 256 * 12 / bq;  // 256 CUs x 12 waves (3 per SIMD)
+    for (int m = 1; m <= 2; ++m) {
+      const int g = ((slots * m + 7) / 8) * 8;
+      if (g < b->nitems) {
+        rc = trial(bq, g);
+        if (rc) return rc;
       }
     }
   }

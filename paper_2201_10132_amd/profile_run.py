@@ -3,7 +3,10 @@
 Runs, in one process: a plain device-to-device copy of a known size (the
 calibration for the HBM byte counters), then the 1024 x 1024, NQ = 16 FP64
 workload for a few steps (short base-state run, since only the step kernel
-is measured).  Usage under the profiler:
+is measured), or with --batch N the first N instances of the seeded batched
+sweep (FP32, NQ = 8) stepped together with a fixed launch shape (plain
+launches, no graph, so that every dispatch is the measured step).  Usage
+under the profiler:
   rocprofv3 --pmc FETCH_SIZE -d <dir> -o run -- python paper_2201_10132_amd/profile_run.py
 """
 import argparse
@@ -22,6 +25,8 @@ def main():
     ap.add_argument("--ny", type=int, default=1024)
     ap.add_argument("--nq", type=int, default=16)
     ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=0, help="instances of the batched sweep")
+    ap.add_argument("--qsplit", type=int, default=4, help="Q-slices of the batched step")
     args = ap.parse_args()
     import torch
     import paper_2201_10132_amd as P
@@ -33,6 +38,17 @@ def main():
     torch.cuda.synchronize()
     del src, dst
     torch.cuda.empty_cache()
+    if args.batch:
+        from tests import inputs
+
+        b = P.Batch(inputs.c4_instances(args.batch), precision=1, nq=8, pre_steps=100,
+                    autotune=0, qsplit=args.qsplit, graph_steps=0)
+        b.init()
+        b.step(args.steps)
+        print(f"bytes_per_step={b.query('bytes_per_step'):.0f} items={b.query('items'):.0f} "
+              f"copy_bytes={8 * n}", flush=True)
+        b.close()
+        return
     t = P.Tpl(args.nx, args.ny, 60.0, 1.0, 0.7, periods=4, nq=args.nq, pre_steps=100,
               pert_modes=1)
     if args.precision:
