@@ -5,7 +5,9 @@ CPU-baseline leg of ``bench.py`` may import this package.  The product library
 (``paper_2201_10132_amd``) never imports, links or calls it, and the two share
 no code.
 
-The arithmetic lives in ``tpl_oracle.c`` (plain C, FP64); this module only
-compiles it and marshals numpy arrays through ctypes.
+The scheme's arithmetic lives in ``tpl_oracle.c`` (plain C, FP64); this module
+only compiles it and marshals numpy arrays through ctypes.  ``learned.py``
+holds the FP64 numpy reference of the learned coarse-lattice correction
+(network, training update, restriction, features, momentum source).
 """
 from .oracle import OracleSim, build, lib_path, splitmix64_next  # noqa: F401

@@ -80,6 +80,8 @@ def _L():
         lib.orc_get_state.argtypes = [C.c_void_p, dp, dp, dp, dp]
         lib.orc_set_state.argtypes = [C.c_void_p, dp, dp, dp, dp]
         lib.orc_observables.argtypes = [C.c_void_p, dp]
+        lib.orc_set_source.argtypes = [C.c_void_p, dp]
+        lib.orc_set_source.restype = None
         lib.orc_amplitude.restype = C.c_double
         lib.orc_amplitude.argtypes = [C.c_void_p]
         lib.orc_diagnostics.argtypes = [C.c_void_p, dp]
@@ -202,6 +204,15 @@ class OracleSim:
         out = np.zeros((10, self.ny, self.nx))
         _L().orc_observables(self._h, _ptr(out))
         return out
+
+    def set_source(self, F=None):
+        """Extra body force F[2][ny][nx] added in every later step (None: off)."""
+        if F is None:
+            _L().orc_set_source(self._h, None)
+            return
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        assert F.shape == (2, self.ny, self.nx), F.shape
+        _L().orc_set_source(self._h, _ptr(F))
 
     def amplitude(self) -> float:
         return float(_L().orc_amplitude(self._h))

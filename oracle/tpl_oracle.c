@@ -49,6 +49,7 @@ struct orc_sim {
   long nstep;
   /* work arrays */
   double *GS, *GP, *psi_new, *U_new;
+  double *src;  /* [ny][nx][2] extra body force (NULL: none) */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -281,10 +282,28 @@ void orc_free(orc_sim *s) {
   free(s->XS); free(s->XP); free(s->psi); free(s->U);
   free(s->rhoS); free(s->rhoP);
   free(s->GS); free(s->GP); free(s->psi_new); free(s->U_new);
+  free(s->src);
   free(s);
 }
 
 int orc_nqd(const orc_sim *s) { return s->nqd; }
+
+/* Extra body force per r-node, added to the Kolmogorov force in every later
+ * step (the momentum source through which a learned correction acts).
+ * F is [2][ny][nx] (canonical layout); NULL removes it. */
+void orc_set_source(orc_sim *s, const double *F) {
+  const size_t N = (size_t)s->nx * s->ny;
+  if (!F) {
+    free(s->src);
+    s->src = NULL;
+    return;
+  }
+  if (!s->src) s->src = malloc(sizeof(double) * 2 * N);
+  for (size_t n = 0; n < N; ++n) {
+    s->src[2 * n] = F[n];
+    s->src[2 * n + 1] = F[N + n];
+  }
+}
 void orc_get_derived(const orc_sim *s, orc_derived *out) { *out = s->p; }
 long orc_step_count(const orc_sim *s) { return s->nstep; }
 
@@ -489,6 +508,10 @@ static void step_once(orc_sim *s) {
           sq[2 * q + 1] = kappa * s->Fh[2 * q + 1] * qg;
         }
         double Fb[2] = {body_force_x(s, y), 0.0};
+        if (s->src) {
+          Fb[0] += s->src[2 * n];
+          Fb[1] += s->src[2 * n + 1];
+        }
         double Un[2];
         orc_collide_node(s, s->GS + 9 * n, s->GP + n * nqd * 25, K, sq, Fb,
                          s->XS + 9 * n, s->XP + n * nqd * 25, Un);

@@ -103,6 +103,8 @@ void orc_set_state(orc_sim *s, const double *XS, const double *XP,
 /* Observables of the last completed step (step 9), SoA [10][ny][nx]:
  * rho, Ux, Uy, rhoP, Cxx, Cxy, Cyy, tau_xx, tau_xy, tau_yy. */
 void orc_observables(const orc_sim *s, double *out);
+/* Extra body force F[2][ny][nx] added in every later step; NULL removes it. */
+void orc_set_source(orc_sim *s, const double *F);
 double orc_amplitude(const orc_sim *s);
 /* out[9]: step, massS, massP, momx, momy, amplitude, enstrophy, qrms, minpsi */
 void orc_diagnostics(const orc_sim *s, double *out);
