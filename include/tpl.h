@@ -268,6 +268,83 @@ tpl_ctx *tpl_batch_instance(tpl_batch *b, int i);
 /* Release the batch and all its instances.  NULL is ignored. */
 void tpl_batch_destroy(tpl_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Learned coarse-lattice correction.  A coarse lattice (the scheme above on
+ * an m-times coarser grid, same Re, Wi, beta: acoustic scaling) is corrected
+ * every step by a per-node network that sees the 3x3 neighbourhood of
+ * (rho, Ux, Uy, Cxx, Cxy, Cyy) (54 features) and predicts the correction
+ * (dJx, dJy, dtau_xx, dtau_xy, dtau_yy) of momentum and polymer stress that
+ * one coarse step misses against the restricted fine solution.  The
+ * correction acts as an extra body force F = dJ + div_h(dtau) (central
+ * differences) in the next step.  Network: in -> 64 -> 64 -> out, exact GELU,
+ * BF16 weights and activations, FP32 accumulation on the matrix cores, FP32
+ * master parameters, Adam, loss = mean of squared errors of standardised
+ * outputs.  Flat parameter layout (FP32): W1 [64][in], b1 [64], W2 [64][64],
+ * b2 [64], W3 [out][64], b3 [out], each W acting as z = W x + b.
+ */
+typedef struct tpl_mlp tpl_mlp;
+
+/* hidden must be 64, 1 <= in <= 64, 1 <= out <= 16 (else NULL, TPL_EINVAL).
+ * Weights ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from SplitMix64(seed), zero
+ * biases, identity standardisation.  Device memory is allocated on first
+ * use. */
+tpl_mlp *tpl_mlp_create(int in, int hidden, int out, uint64_t seed);
+/* hipStream_t for the network's own calls (NULL: the null stream). */
+int tpl_mlp_set_stream(tpl_mlp *m, void *hip_stream);
+/* Keys: nparams in hidden out adam_steps. */
+int tpl_mlp_query(const tpl_mlp *m, const char *key, double *out);
+/* FP32 master parameters to / from a host array of exactly nparams floats.
+ * Setting them also resets Adam's moments and step count. */
+int tpl_mlp_get_params(tpl_mlp *m, float *host, size_t n);
+int tpl_mlp_set_params(tpl_mlp *m, const float *host, size_t n);
+/* Standardisation (host arrays): the network sees (x - in_mean) / in_std
+ * and its outputs are y * out_std + out_mean; scales must be > 0. */
+int tpl_mlp_set_norm(tpl_mlp *m, const float *in_mean, const float *in_std,
+                     const float *out_mean, const float *out_std);
+/* Y[n][out] = network(X[n][in]) in physical units.  X and Y are device
+ * pointers (FP32); synchronises before returning. */
+int tpl_mlp_forward(tpl_mlp *m, const float *X, float *Y, int64_t n);
+/* Gradients of the loss over the n rows of X and T (device, FP32, T raw
+ * targets [n][out]) into the host array dW (nparams floats, the flat layout);
+ * the loss into *loss if non-NULL.  Parameters are not changed. */
+int tpl_mlp_grads(tpl_mlp *m, const float *X, const float *T, int64_t n,
+                  float *dW, float *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * loss over the n rows; *loss (if non-NULL) receives the loss before it. */
+int tpl_mlp_train_step(tpl_mlp *m, const float *X, const float *T, int64_t n,
+                       float lr, float *loss);
+void tpl_mlp_destroy(tpl_mlp *m);
+
+/* Coarse state := full-weighting restriction of the fine state: coarse node
+ * (X, Y) averages fine nodes (m X + i, m Y + j), |i|, |j| <= m/2, with weight
+ * 1/2 on the window's edges (m = nx_fine / nx_coarse = ny_fine / ny_coarse,
+ * even), applied to both species' populations and the lagged psi and U; the
+ * other per-node fields are recomputed.  Both contexts initialised, FP64
+ * storage, same nq. */
+int tpl_restrict(const tpl_ctx *fine, tpl_ctx *coarse);
+/* Raw features of the current state into the device array X [nx ny][54]:
+ * feature 6 s + f is field f of (rho, Ux, Uy, Cxx, Cxy, Cyy) at stencil
+ * position s = 3 (dy + 1) + (dx + 1) (periodic). */
+int tpl_features(tpl_ctx *ctx, float *X, size_t len);
+/* Targets into the device array T [nx ny][5]: (rho Ux, rho Uy, tau_xx,
+ * tau_xy, tau_yy) of the device observables obs_ref ([TPL_NFIELDS][ny][nx],
+ * as tpl_moments_device writes them) minus those of the current state. */
+int tpl_targets(tpl_ctx *ctx, const double *obs_ref, float *T, size_t len);
+/* Extra body force F[2][ny][nx] (host doubles, len = 2 nx ny) added to the
+ * forcing of every later step; NULL removes it.  TPL_ESTATE while a network
+ * is attached. */
+int tpl_set_source(tpl_ctx *ctx, const double *F, size_t len);
+/* The extra body force of the last step (zeros if none), host doubles. */
+int tpl_get_source(tpl_ctx *ctx, double *F, size_t len);
+/* Attach a correction network (in = 54, out = 5) to a context: before every
+ * later tpl_step step the library computes the features, the network's
+ * correction and the source F from the current state.  Drift gate: if
+ * max |F| / rho exceeds drift_bound u0 (the velocity change the correction
+ * would make in one step), tpl_step returns TPL_EREJECTED before that step
+ * (the state stays at the last completed step).  m = NULL detaches.  The
+ * network must outlive the attachment. */
+int tpl_attach_mlp(tpl_ctx *ctx, tpl_mlp *m, double drift_bound);
+
 /* Thread-local description of the last error ("" if none). */
 const char *tpl_last_error(void);
 

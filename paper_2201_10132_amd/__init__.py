@@ -6,4 +6,4 @@ package only marshals arguments.  Importing it fails loudly when the library
 has not been built.
 """
 from .tpl import (TPL_FP32, TPL_FP64, TPL_NFIELDS, TPL_POLYMER, TPL_SOLVENT,  # noqa: F401
-                  Batch, TplError, Tpl, lib, lib_path, tpl_last_error)
+                  Batch, Mlp, TplError, Tpl, lib, lib_path, tpl_last_error)

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpl.so")
-SOURCES = ["tpl_runtime.hip", "tpl_kernels.hip"]
+SOURCES = ["tpl_runtime.hip", "tpl_kernels.hip", "tpl_learned.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

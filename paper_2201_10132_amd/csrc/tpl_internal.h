@@ -49,6 +49,7 @@ struct StepParams {
   double c1S, c2S, rS;   // relaxation: g' = c1 g + c2 [(1-r) f* + r f_eq]
   double c1P, c2P, rP;
   double kappa, DQ, F0, kf;
+  const double *src;  // extra body force [2][N] added to the forcing (null: none)
 };
 
 // One half of the double-buffered state.  Populations and the lagged psi are
@@ -153,6 +154,41 @@ hipError_t launch_to_f64(int nx, int ny, int planes, const float *src,
                          const float *ref, double *dst, hipStream_t s);
 hipError_t launch_from_f64(int nx, int ny, int planes, const double *src,
                            const float *ref, float *dst, hipStream_t s);
+
+// Learned correction: device view of a network 64-wide hidden layers, nin <= 64
+// inputs, nout <= 16 outputs (BF16 operand arrays, FP32 biases and output
+// standardisation).
+struct MlpDev {
+  const uint16_t *W1b, *W2b, *W3b, *W2Tb, *W3Tb;
+  const float *b1, *b2, *b3;
+  const float *out_mean, *out_std;
+  int nin, nout;
+};
+// Floats of one wave's gradient record (see k_mlp_train).
+constexpr int kMlpRecord = 4096 + 64 + 4096 + 64 + 1024 + 16 + 1;
+
+hipError_t launch_mlp_forward(const MlpDev &w, const uint16_t *Xb, long long n, float *Y,
+                              hipStream_t s);
+hipError_t launch_mlp_train(const MlpDev &w, const uint16_t *Xb, const float *T, long long n,
+                            int nrec, float *partial, hipStream_t s);
+hipError_t launch_mlp_reduce(const float *partial, int nrec, int nin, int nout, float *grad,
+                             hipStream_t s);
+hipError_t launch_mlp_adam(float *theta, float *m, float *v, const float *grad, int np, float lr,
+                           int t, hipStream_t s);
+hipError_t launch_mlp_pack(const float *theta, int nin, int nout, const MlpDev &w,
+                           hipStream_t s);
+hipError_t launch_mlp_prep(const float *X, long long n, int nin, const float *mean,
+                           const float *stdv, uint16_t *Xb, hipStream_t s);
+hipError_t launch_features(const double *obs, int nx, int ny, const float *mean,
+                           const float *stdv, float *X, uint16_t *Xb, hipStream_t s);
+hipError_t launch_targets(const double *ref, const double *obs, long long N, float *T,
+                          hipStream_t s);
+hipError_t launch_source(const float *corr, int nx, int ny, double *F, hipStream_t s);
+hipError_t launch_source_drift(const double *F, const double *FLD, long long N, double *partial,
+                               int *nblocks, hipStream_t s);
+template <typename T>
+hipError_t launch_restrict(int planes, int nxf, int nyf, int m, const T *src, double *dst,
+                           hipStream_t s);
 
 constexpr int kDiagComp = 8;  // massS massP momx momy enstrophy psiQ2 psi minpsi
 

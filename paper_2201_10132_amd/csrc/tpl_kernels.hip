@@ -203,19 +203,23 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   const double Kxx = dX(F_UX), Kxy = dY(F_UX), Kyx = dX(F_UY), Kyy = dY(F_UY);
   const double Sx = p.kappa * (dX(F_MXX) + dY(F_MXY));
   const double Sy = p.kappa * (dX(F_MXY) + dY(F_MYY));
-  const double Fbx = p.F0 * sin(p.kf * (double)(y + p.y0));
+  double Fbx = p.F0 * sin(p.kf * (double)(y + p.y0)), Fby = 0.0;
+  if (p.src != nullptr) {  // extra body force (a learned correction's source)
+    Fbx += p.src[r];
+    Fby = p.src[N + r];
+  }
   // ---- mixture velocity: exchange of the two species cancels
   const double den = rhoS * p.aS + rhoP * p.aP;
   const double Ux = ((JSx + 0.5 * Fbx) * p.aS + (JPx + Sx / (2.0 * p.tau2P)) * p.aP) / den;
-  const double Uy = (JSy * p.aS + (JPy + Sy / (2.0 * p.tau2P)) * p.aP) / den;
+  const double Uy = ((JSy + 0.5 * Fby) * p.aS + (JPy + Sy / (2.0 * p.tau2P)) * p.aP) / den;
   const bool writer = (slice == 0) && active;
 
   // ---- solvent collision (slice 0 writes)
   {
     const double JfX = (2.0 * p.tau2S * JSx + rhoS * Ux + p.tau2S * Fbx) * p.aS;
-    const double JfY = (2.0 * p.tau2S * JSy + rhoS * Uy) * p.aS;
+    const double JfY = (2.0 * p.tau2S * JSy + rhoS * Uy + p.tau2S * Fby) * p.aS;
     const double usx = JfX / rhoS, usy = JfY / rhoS;
-    const double vx = Ux + p.tau2S * Fbx / rhoS, vy = Uy;
+    const double vx = Ux + p.tau2S * Fbx / rhoS, vy = Uy + p.tau2S * Fby / rhoS;
     const double us2 = usx * usx + usy * usy, v2 = vx * vx + vy * vy;
     double jx = 0.0, jy = 0.0;
 #pragma unroll
@@ -374,7 +378,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)
     TPL_LD(nx) TPL_LD(ny) TPL_LD(nqd) TPL_LD(qs) TPL_LD(ntiles) TPL_LD(tiles_per_xcd)
     TPL_LD(y0) TPL_LD(N) TPL_LD(aS) TPL_LD(aP) TPL_LD(tau2S) TPL_LD(tau2P) TPL_LD(c1S)
     TPL_LD(c2S) TPL_LD(rS) TPL_LD(c1P) TPL_LD(c2P) TPL_LD(rP) TPL_LD(kappa) TPL_LD(DQ)
-    TPL_LD(F0) TPL_LD(kf)
+    TPL_LD(F0) TPL_LD(kf) TPL_LD(src)
 #undef TPL_LD
     pp.pad = 0;
     const int rd = parity ^ d.cur0;

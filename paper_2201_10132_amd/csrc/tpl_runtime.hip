@@ -182,6 +182,8 @@ struct Buffers {
 
 }  // namespace
 
+struct tpl_mlp;
+
 struct tpl_ctx {
   Config c;
   Derived d;
@@ -199,6 +201,15 @@ struct tpl_ctx {
   double kernel_ms = 0.0;
   long long kernel_launches = 0;
   int qs_used = 0;
+  // extra body force [2][N] (a caller's field or an attached correction's)
+  double *src_d = nullptr;
+  bool src_on = false;
+  // attached learned correction and its working arrays
+  tpl_mlp *mlp = nullptr;
+  double drift_bound = 0.0, last_drift = 0.0;
+  double *obs_d = nullptr;    // [10][N] observables
+  uint16_t *xb_d = nullptr;   // [N][64] standardised features (BF16)
+  float *corr_d = nullptr;    // [N][5] correction
 };
 
 namespace {
@@ -246,6 +257,7 @@ StepParams make_step_params(const tpl_ctx *x, int nx, int ny, int qs_req) {
   p.DQ = d.DQ;
   p.F0 = d.F0;
   p.kf = d.kf;
+  p.src = (x->src_on && nx == x->c.nx && ny == x->c.ny) ? x->src_d : nullptr;
   return p;
 }
 
@@ -580,6 +592,8 @@ const Key kKeys[] = {
 
 }  // namespace
 
+int learned_source(tpl_ctx *x);  // attached correction -> x->src_d (below)
+
 // ===========================================================================
 // C ABI
 extern "C" {
@@ -740,9 +754,27 @@ int tpl_step(tpl_ctx *x, int64_t n) {
   if (rc) return rc;
   if (n < 0) return fail(TPL_EINVAL, "n must be >= 0");
   x->qs_used = make_step_params(x, x->c.nx, x->c.ny, x->c.qsplit).qs;
-  rc = run_steps(x, x->buf, x->c.nx, x->c.ny, &x->cur, n, x->c.time_kernels != 0, x->c.qsplit);
-  if (rc) return rc;
-  x->step += n;
+  if (x->mlp) {  // learned correction: a new source before every step
+    for (int64_t i = 0; i < n; ++i) {
+      rc = learned_source(x);
+      if (rc) return rc;
+      if (!(x->last_drift <= x->drift_bound)) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "correction rejected before step %lld: max |F|/rho = %.3e u0 "
+                 "exceeds the drift bound %.3e u0", x->step + 1, x->last_drift, x->drift_bound);
+        return fail(TPL_EREJECTED, msg);
+      }
+      rc = run_steps(x, x->buf, x->c.nx, x->c.ny, &x->cur, 1, x->c.time_kernels != 0,
+                     x->c.qsplit);
+      if (rc) return rc;
+      x->step += 1;
+    }
+  } else {
+    rc = run_steps(x, x->buf, x->c.nx, x->c.ny, &x->cur, n, x->c.time_kernels != 0,
+                   x->c.qsplit);
+    if (rc) return rc;
+    x->step += n;
+  }
   // divergence check on the mixture velocity
   const long long N = (long long)x->c.nx * x->c.ny;
   rc = ensure_scratch(x, 1024 + 1);
@@ -1076,6 +1108,10 @@ void tpl_destroy(tpl_ctx *x) {
   (void)hipFree(x->ref);
   (void)hipFree(x->sref);
   (void)hipFree(x->scratch);
+  (void)hipFree(x->src_d);
+  (void)hipFree(x->obs_d);
+  (void)hipFree(x->xb_d);
+  (void)hipFree(x->corr_d);
   delete x;
 }
 
@@ -1647,6 +1683,416 @@ void tpl_batch_destroy(tpl_batch *b) {
   if (b->scratch) (void)hipFree(b->scratch);
   if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
   delete b;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Learned coarse-lattice correction: the network object, its training step,
+// and the lattice side (restriction, features, targets, momentum source).
+
+struct tpl_mlp {
+  int nin = 0, hidden = 64, nout = 0, np = 0;
+  hipStream_t stream = nullptr;
+  std::vector<float> theta_h;          // master parameters until the device copy exists
+  std::vector<float> norm_h;           // in_mean[64] in_std[64] out_mean[16] out_std[16]
+  bool on_device = false;
+  float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;  // [np] (+1: sse)
+  uint16_t *wb = nullptr;              // W1b | W2b | W3b | W2Tb | W3Tb
+  float *fb = nullptr;                 // b1[64] b2[64] b3[16] | norm (160)
+  float *partial = nullptr;
+  int nrec = 0;
+  uint16_t *xb = nullptr;
+  long long xb_n = 0;
+  int t = 0;  // Adam steps taken
+};
+
+namespace {
+
+constexpr int kMlpRecs = 512;  // gradient records (waves) of a training pass
+
+MlpDev mlp_dev(const tpl_mlp *m) {
+  MlpDev w;
+  w.W1b = m->wb;
+  w.W2b = m->wb + 4096;
+  w.W3b = m->wb + 8192;
+  w.W2Tb = m->wb + 9216;
+  w.W3Tb = m->wb + 13312;
+  w.b1 = m->fb;
+  w.b2 = m->fb + 64;
+  w.b3 = m->fb + 128;
+  w.out_mean = m->fb + 144 + 128;
+  w.out_std = m->fb + 144 + 144;
+  w.nin = m->nin;
+  w.nout = m->nout;
+  return w;
+}
+const float *mlp_in_mean(const tpl_mlp *m) { return m->fb + 144; }
+const float *mlp_in_std(const tpl_mlp *m) { return m->fb + 144 + 64; }
+
+// Device arrays of the network, made on first use (the object itself can be
+// created and filled without a GPU).
+int mlp_ready(tpl_mlp *m) {
+  if (m->on_device) return TPL_OK;
+  auto alloc = [&](void **p, size_t bytes) -> bool {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return false;
+    }
+    return true;
+  };
+  const size_t np = m->np;
+  if (!alloc((void **)&m->theta, np * 4) || !alloc((void **)&m->m, np * 4) ||
+      !alloc((void **)&m->v, np * 4) || !alloc((void **)&m->grad, (np + 1) * 4) ||
+      !alloc((void **)&m->wb, 14336 * 2) || !alloc((void **)&m->fb, (144 + 160) * 4) ||
+      !alloc((void **)&m->partial, (size_t)kMlpRecs * kMlpRecord * 4))
+    return fail(TPL_ENOMEM, "network allocation failed");
+  m->nrec = kMlpRecs;
+  HIPCHK(hipMemcpyAsync(m->theta, m->theta_h.data(), np * 4, hipMemcpyHostToDevice, m->stream));
+  HIPCHK(hipMemsetAsync(m->m, 0, np * 4, m->stream));
+  HIPCHK(hipMemsetAsync(m->v, 0, np * 4, m->stream));
+  HIPCHK(hipMemcpyAsync(m->fb + 144, m->norm_h.data(), 160 * 4, hipMemcpyHostToDevice,
+                        m->stream));
+  m->on_device = true;
+  HIPCHK(launch_mlp_pack(m->theta, m->nin, m->nout, mlp_dev(m), m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return TPL_OK;
+}
+
+int mlp_inputs(tpl_mlp *m, const float *X, long long n) {
+  if (n > m->xb_n) {
+    if (m->xb) HIPCHK(hipFree(m->xb));
+    m->xb = nullptr;
+    m->xb_n = 0;
+    if (hipMalloc(&m->xb, (size_t)n * 64 * 2) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(TPL_ENOMEM, "input staging allocation failed");
+    }
+    m->xb_n = n;
+  }
+  HIPCHK(launch_mlp_prep(X, n, m->nin, mlp_in_mean(m), mlp_in_std(m), m->xb, m->stream));
+  return TPL_OK;
+}
+
+// One training pass: gradients (canonical layout) and sum of squared errors
+// in m->grad[np].
+int mlp_pass(tpl_mlp *m, const float *X, const float *T, long long n) {
+  int rc = mlp_ready(m);
+  if (!rc) rc = mlp_inputs(m, X, n);
+  if (rc) return rc;
+  HIPCHK(launch_mlp_train(mlp_dev(m), m->xb, T, n, m->nrec, m->partial, m->stream));
+  HIPCHK(launch_mlp_reduce(m->partial, m->nrec, m->nin, m->nout, m->grad, m->stream));
+  return TPL_OK;
+}
+
+int ensure_dev(double **p, size_t n) {
+  if (*p) return TPL_OK;
+  if (hipMalloc(p, n * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(TPL_ENOMEM, "device allocation failed");
+  }
+  return TPL_OK;
+}
+
+int ctx_observables(tpl_ctx *x) {
+  const long long N = (long long)x->c.nx * x->c.ny;
+  int rc = ensure_dev(&x->obs_d, (size_t)TPL_NFIELDS * N);
+  if (rc) return rc;
+  return tpl_moments_device(x, x->obs_d, (size_t)TPL_NFIELDS * N);
+}
+
+}  // namespace
+
+// Source of the attached network for the current state; sets last_drift.
+int learned_source(tpl_ctx *x) {
+  tpl_mlp *m = x->mlp;
+  const long long N = (long long)x->c.nx * x->c.ny;
+  int rc = mlp_ready(m);
+  if (!rc) rc = ctx_observables(x);
+  if (!rc) rc = ensure_dev(&x->src_d, 2 * (size_t)N);
+  if (rc) return rc;
+  if (!x->xb_d && hipMalloc(&x->xb_d, (size_t)N * 64 * 2) != hipSuccess) {
+    (void)hipGetLastError();
+    x->xb_d = nullptr;
+    return fail(TPL_ENOMEM, "feature allocation failed");
+  }
+  if (!x->corr_d && hipMalloc(&x->corr_d, (size_t)N * 5 * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    x->corr_d = nullptr;
+    return fail(TPL_ENOMEM, "correction allocation failed");
+  }
+  // the network's work goes on the context's stream
+  HIPCHK(launch_features(x->obs_d, x->c.nx, x->c.ny, mlp_in_mean(m), mlp_in_std(m), nullptr,
+                         x->xb_d, x->stream));
+  HIPCHK(launch_mlp_forward(mlp_dev(m), x->xb_d, N, x->corr_d, x->stream));
+  HIPCHK(launch_source(x->corr_d, x->c.nx, x->c.ny, x->src_d, x->stream));
+  x->src_on = true;
+  rc = ensure_scratch(x, 1024 + 1);
+  if (rc) return rc;
+  int nb = 0;
+  HIPCHK(launch_source_drift(x->src_d, x->buf.half64(x->cur).FLD, N, x->scratch, &nb,
+                             x->stream));
+  std::vector<double> part(nb);
+  HIPCHK(hipMemcpyAsync(part.data(), x->scratch, sizeof(double) * nb, hipMemcpyDeviceToHost,
+                        x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  double mx = 0.0;
+  for (double v : part) mx = (v > mx || !(v == v)) ? v : mx;
+  x->last_drift = mx / x->c.u0;
+  return TPL_OK;
+}
+
+extern "C" {
+
+tpl_mlp *tpl_mlp_create(int in, int hidden, int out, uint64_t seed) {
+  if (hidden != 64 || in < 1 || in > 64 || out < 1 || out > 16) {
+    fail(TPL_EINVAL, "network shape must be in (1..64) -> 64 -> 64 -> out (1..16)");
+    return nullptr;
+  }
+  tpl_mlp *m = new tpl_mlp;
+  m->nin = in;
+  m->nout = out;
+  m->np = 64 * in + 64 + 64 * 64 + 64 + out * 64 + out;
+  m->theta_h.assign(m->np, 0.0f);
+  // U(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights from SplitMix64(seed), zero biases
+  SplitMix64 rng{seed};
+  auto fill = [&](size_t off, int rows, int fan_in) {
+    const double a = 1.0 / std::sqrt((double)fan_in);
+    for (int i = 0; i < rows * fan_in; ++i)
+      m->theta_h[off + i] = (float)(a * (2.0 * rng.uniform() - 1.0));
+  };
+  fill(0, 64, in);
+  fill(64 * in + 64, 64, 64);
+  fill(64 * in + 64 + 4096 + 64, out, 64);
+  m->norm_h.assign(160, 0.0f);
+  for (int i = 0; i < 64; ++i) m->norm_h[64 + i] = 1.0f;
+  for (int i = 0; i < 16; ++i) m->norm_h[144 + i] = 1.0f;
+  return m;
+}
+
+int tpl_mlp_set_stream(tpl_mlp *m, void *hip_stream) {
+  if (!m) return fail(TPL_EINVAL, "null network");
+  m->stream = static_cast<hipStream_t>(hip_stream);
+  return TPL_OK;
+}
+
+int tpl_mlp_query(const tpl_mlp *m, const char *key, double *out) {
+  if (!m || !key || !out) return fail(TPL_EINVAL, "null argument");
+  const std::string k = key;
+  if (k == "nparams") *out = m->np;
+  else if (k == "in") *out = m->nin;
+  else if (k == "hidden") *out = m->hidden;
+  else if (k == "out") *out = m->nout;
+  else if (k == "adam_steps") *out = m->t;
+  else return fail(TPL_EINVAL, "unknown key " + k);
+  return TPL_OK;
+}
+
+int tpl_mlp_get_params(tpl_mlp *m, float *host, size_t n) {
+  if (!m || !host) return fail(TPL_EINVAL, "null argument");
+  if (n != (size_t)m->np) return fail(TPL_EINVAL, "parameter count mismatch");
+  if (!m->on_device) {
+    std::copy(m->theta_h.begin(), m->theta_h.end(), host);
+    return TPL_OK;
+  }
+  HIPCHK(hipMemcpyAsync(host, m->theta, n * 4, hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return TPL_OK;
+}
+
+int tpl_mlp_set_params(tpl_mlp *m, const float *host, size_t n) {
+  if (!m || !host) return fail(TPL_EINVAL, "null argument");
+  if (n != (size_t)m->np) return fail(TPL_EINVAL, "parameter count mismatch");
+  std::copy(host, host + n, m->theta_h.begin());
+  m->t = 0;
+  if (!m->on_device) return TPL_OK;
+  HIPCHK(hipMemcpyAsync(m->theta, host, n * 4, hipMemcpyHostToDevice, m->stream));
+  HIPCHK(hipMemsetAsync(m->m, 0, n * 4, m->stream));
+  HIPCHK(hipMemsetAsync(m->v, 0, n * 4, m->stream));
+  HIPCHK(launch_mlp_pack(m->theta, m->nin, m->nout, mlp_dev(m), m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return TPL_OK;
+}
+
+int tpl_mlp_set_norm(tpl_mlp *m, const float *in_mean, const float *in_std,
+                     const float *out_mean, const float *out_std) {
+  if (!m || !in_mean || !in_std || !out_mean || !out_std) return fail(TPL_EINVAL, "null argument");
+  for (int i = 0; i < m->nin; ++i)
+    if (!(in_std[i] > 0)) return fail(TPL_EINVAL, "input scales must be > 0");
+  for (int i = 0; i < m->nout; ++i)
+    if (!(out_std[i] > 0)) return fail(TPL_EINVAL, "output scales must be > 0");
+  for (int i = 0; i < m->nin; ++i) {
+    m->norm_h[i] = in_mean[i];
+    m->norm_h[64 + i] = in_std[i];
+  }
+  for (int i = 0; i < m->nout; ++i) {
+    m->norm_h[128 + i] = out_mean[i];
+    m->norm_h[144 + i] = out_std[i];
+  }
+  if (!m->on_device) return TPL_OK;
+  HIPCHK(hipMemcpyAsync(m->fb + 144, m->norm_h.data(), 160 * 4, hipMemcpyHostToDevice,
+                        m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return TPL_OK;
+}
+
+int tpl_mlp_forward(tpl_mlp *m, const float *X, float *Y, int64_t n) {
+  if (!m || (n > 0 && (!X || !Y))) return fail(TPL_EINVAL, "null argument");
+  if (n < 0) return fail(TPL_EINVAL, "n must be >= 0");
+  if (n == 0) return TPL_OK;
+  int rc = mlp_ready(m);
+  if (!rc) rc = mlp_inputs(m, X, n);
+  if (rc) return rc;
+  HIPCHK(launch_mlp_forward(mlp_dev(m), m->xb, n, Y, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  return TPL_OK;
+}
+
+int tpl_mlp_grads(tpl_mlp *m, const float *X, const float *T, int64_t n, float *dW,
+                  float *loss) {
+  if (!m || !X || !T || !dW) return fail(TPL_EINVAL, "null argument");
+  if (n < 1) return fail(TPL_EINVAL, "n must be >= 1");
+  int rc = mlp_pass(m, X, T, n);
+  if (rc) return rc;
+  std::vector<float> g(m->np + 1);
+  HIPCHK(hipMemcpyAsync(g.data(), m->grad, (m->np + 1) * 4, hipMemcpyDeviceToHost, m->stream));
+  HIPCHK(hipStreamSynchronize(m->stream));
+  std::copy(g.begin(), g.begin() + m->np, dW);
+  if (loss) *loss = (float)(g[m->np] / ((double)n * m->nout));
+  return TPL_OK;
+}
+
+int tpl_mlp_train_step(tpl_mlp *m, const float *X, const float *T, int64_t n, float lr,
+                       float *loss) {
+  if (!m || !X || !T) return fail(TPL_EINVAL, "null argument");
+  if (n < 1) return fail(TPL_EINVAL, "n must be >= 1");
+  if (!(lr > 0)) return fail(TPL_EINVAL, "lr must be > 0");
+  int rc = mlp_pass(m, X, T, n);
+  if (rc) return rc;
+  m->t += 1;
+  HIPCHK(launch_mlp_adam(m->theta, m->m, m->v, m->grad, m->np, lr, m->t, m->stream));
+  HIPCHK(launch_mlp_pack(m->theta, m->nin, m->nout, mlp_dev(m), m->stream));
+  if (loss) {
+    float sse = 0.0f;
+    HIPCHK(hipMemcpyAsync(&sse, m->grad + m->np, 4, hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    *loss = (float)(sse / ((double)n * m->nout));
+  }
+  return TPL_OK;
+}
+
+void tpl_mlp_destroy(tpl_mlp *m) {
+  if (!m) return;
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  (void)hipFree(m->theta);
+  (void)hipFree(m->m);
+  (void)hipFree(m->v);
+  (void)hipFree(m->grad);
+  (void)hipFree(m->wb);
+  (void)hipFree(m->fb);
+  (void)hipFree(m->partial);
+  (void)hipFree(m->xb);
+  delete m;
+}
+
+int tpl_restrict(const tpl_ctx *fine, tpl_ctx *coarse) {
+  int rc = check_ready(fine);
+  if (!rc) rc = check_ready(coarse);
+  if (rc) return rc;
+  const int nxf = fine->c.nx, nyf = fine->c.ny, nxc = coarse->c.nx, nyc = coarse->c.ny;
+  if (nxc < 1 || nyc < 1 || nxf % nxc || nyf % nyc || nxf / nxc != nyf / nyc)
+    return fail(TPL_EINVAL, "fine lattice must be the coarse one refined by one factor");
+  const int mfac = nxf / nxc;
+  if (mfac < 2 || (mfac & 1)) return fail(TPL_EINVAL, "refinement factor must be even");
+  if (fine->d.nqd != coarse->d.nqd) return fail(TPL_EINVAL, "both lattices need the same nq");
+  if (fp32(fine) || fp32(coarse)) return fail(TPL_EINVAL, "restriction needs FP64 storage");
+  const int nqd = fine->d.nqd;
+  const StateView f = fine->buf.half64(fine->cur), c = coarse->buf.half64(coarse->cur);
+  hipStream_t s = coarse->stream;
+  HIPCHK(hipStreamSynchronize(fine->stream));
+  HIPCHK(launch_restrict<double>(9, nxf, nyf, mfac, f.XS, c.XS, s));
+  HIPCHK(launch_restrict<double>(25 * nqd, nxf, nyf, mfac, f.XP, c.XP, s));
+  HIPCHK(launch_restrict<double>(nqd, nxf, nyf, mfac, f.PSI, c.PSI, s));
+  const size_t Nf = (size_t)nxf * nyf, Nc = (size_t)nxc * nyc;
+  HIPCHK(launch_restrict<double>(2, nxf, nyf, mfac, f.FLD + F_UX * Nf, c.FLD + F_UX * Nc, s));
+  const RefView none{nullptr, nullptr, nullptr, nyc};
+  HIPCHK(launch_refresh<double>(nqd, nxc, nyc, coarse->qtab_d, c, none, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return TPL_OK;
+}
+
+int tpl_features(tpl_ctx *x, float *X, size_t len) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  const long long N = (long long)x->c.nx * x->c.ny;
+  if (!X || len < (size_t)N * 54) return fail(TPL_EINVAL, "output too small");
+  rc = ctx_observables(x);
+  if (rc) return rc;
+  HIPCHK(launch_features(x->obs_d, x->c.nx, x->c.ny, nullptr, nullptr, X, nullptr, x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  return TPL_OK;
+}
+
+int tpl_targets(tpl_ctx *x, const double *obs_ref, float *T, size_t len) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  const long long N = (long long)x->c.nx * x->c.ny;
+  if (!obs_ref || !T || len < (size_t)N * 5) return fail(TPL_EINVAL, "bad buffer");
+  rc = ctx_observables(x);
+  if (rc) return rc;
+  HIPCHK(launch_targets(obs_ref, x->obs_d, N, T, x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  return TPL_OK;
+}
+
+int tpl_set_source(tpl_ctx *x, const double *F, size_t len) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  if (x->mlp) return fail(TPL_ESTATE, "a network is attached (tpl_attach_mlp(ctx, NULL, 0) first)");
+  const size_t N = (size_t)x->c.nx * x->c.ny;
+  if (!F) {
+    x->src_on = false;
+    return TPL_OK;
+  }
+  if (len != 2 * N) return fail(TPL_EINVAL, "source must hold 2 nx ny doubles");
+  rc = ensure_dev(&x->src_d, 2 * N);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(x->src_d, F, 2 * N * sizeof(double), hipMemcpyHostToDevice, x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  x->src_on = true;
+  return TPL_OK;
+}
+
+int tpl_get_source(tpl_ctx *x, double *F, size_t len) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  const size_t N = (size_t)x->c.nx * x->c.ny;
+  if (!F || len != 2 * N) return fail(TPL_EINVAL, "source must hold 2 nx ny doubles");
+  if (!x->src_on) {
+    std::fill(F, F + 2 * N, 0.0);
+    return TPL_OK;
+  }
+  HIPCHK(hipMemcpyAsync(F, x->src_d, 2 * N * sizeof(double), hipMemcpyDeviceToHost, x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  return TPL_OK;
+}
+
+int tpl_attach_mlp(tpl_ctx *x, tpl_mlp *m, double drift_bound) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  if (!m) {
+    x->mlp = nullptr;
+    x->src_on = false;
+    return TPL_OK;
+  }
+  if (m->nin != 54 || m->nout != 5)
+    return fail(TPL_EINVAL, "a correction network maps 54 features to 5 outputs");
+  if (!(drift_bound > 0)) return fail(TPL_EINVAL, "drift bound must be > 0");
+  x->mlp = m;
+  x->drift_bound = drift_bound;
+  return TPL_OK;
 }
 
 }  // extern "C"

@@ -63,6 +63,7 @@ def lib():
         raise ImportError(f"{_LIB} not built: run python -c 'import __graft_entry__ as g; g.build()'")
     L = C.CDLL(_LIB)
     vp, dp, cp = C.c_void_p, C.POINTER(C.c_double), C.c_char_p
+    fp = C.POINTER(C.c_float)
     sig = {
         "tpl_create": (vp, [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, tpl_forcing]),
         "tpl_set_param": (C.c_int, [vp, cp, C.c_double]),
@@ -94,6 +95,22 @@ def lib():
         "tpl_batch_status": (C.c_int, [vp, C.POINTER(C.c_int), C.c_int]),
         "tpl_batch_instance": (vp, [vp, C.c_int]),
         "tpl_batch_destroy": (None, [vp]),
+        "tpl_mlp_create": (vp, [C.c_int, C.c_int, C.c_int, C.c_uint64]),
+        "tpl_mlp_set_stream": (C.c_int, [vp, vp]),
+        "tpl_mlp_query": (C.c_int, [vp, cp, dp]),
+        "tpl_mlp_get_params": (C.c_int, [vp, fp, C.c_size_t]),
+        "tpl_mlp_set_params": (C.c_int, [vp, fp, C.c_size_t]),
+        "tpl_mlp_set_norm": (C.c_int, [vp, fp, fp, fp, fp]),
+        "tpl_mlp_forward": (C.c_int, [vp, vp, vp, C.c_int64]),
+        "tpl_mlp_grads": (C.c_int, [vp, vp, vp, C.c_int64, fp, fp]),
+        "tpl_mlp_train_step": (C.c_int, [vp, vp, vp, C.c_int64, C.c_float, fp]),
+        "tpl_mlp_destroy": (None, [vp]),
+        "tpl_restrict": (C.c_int, [vp, vp]),
+        "tpl_features": (C.c_int, [vp, vp, C.c_size_t]),
+        "tpl_targets": (C.c_int, [vp, vp, vp, C.c_size_t]),
+        "tpl_set_source": (C.c_int, [vp, dp, C.c_size_t]),
+        "tpl_get_source": (C.c_int, [vp, dp, C.c_size_t]),
+        "tpl_attach_mlp": (C.c_int, [vp, vp, C.c_double]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -231,6 +248,35 @@ class Tpl:
                                     _dptr(XP), _dptr(psi), _dptr(U)))
         return dict(XS=XS, XP=XP, psi=psi, U=U)
 
+    # -- learned correction ------------------------------------------------------------
+    def restrict_from(self, fine: "Tpl"):
+        """This (coarse) state := restriction of the fine context's state."""
+        _check(lib().tpl_restrict(fine._h, self._h))
+
+    def features_device(self, dptr: int, length: int):
+        _check(lib().tpl_features(self._h, C.c_void_p(dptr), int(length)))
+
+    def targets_device(self, obs_ref_dptr: int, dptr: int, length: int):
+        _check(lib().tpl_targets(self._h, C.c_void_p(obs_ref_dptr), C.c_void_p(dptr), int(length)))
+
+    def set_source(self, F=None):
+        if F is None:
+            _check(lib().tpl_set_source(self._h, None, 0))
+            return
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        if F.shape != (2, self.ny, self.nx):
+            raise ValueError(f"source shape {F.shape} != {(2, self.ny, self.nx)}")
+        _check(lib().tpl_set_source(self._h, _dptr(F), F.size))
+
+    def get_source(self) -> np.ndarray:
+        F = np.zeros((2, self.ny, self.nx))
+        _check(lib().tpl_get_source(self._h, _dptr(F), F.size))
+        return F
+
+    def attach(self, mlp, drift_bound=0.0):
+        _check(lib().tpl_attach_mlp(self._h, None if mlp is None else mlp._h, float(drift_bound)))
+        self._mlp = mlp  # keep the network alive while attached
+
     def save(self, path):
         _check(lib().tpl_save(self._h, os.fspath(path).encode()))
 
@@ -307,3 +353,67 @@ class Batch:
             raise TplError(TPL_EINVAL, tpl_last_error())
         nx, ny = self.sizes[i]
         return Tpl._borrow(h, nx, ny, self)
+
+
+def _fptr(a):
+    if not (a.dtype == np.float32 and a.flags["C_CONTIGUOUS"]):
+        raise TypeError("expected a C-contiguous float32 array")
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Mlp:
+    """Correction network (tpl_mlp_create ... tpl_mlp_destroy).  Inputs and
+    targets of forward/grads/train_step are device pointers (FP32, e.g. from
+    torch tensors)."""
+
+    def __init__(self, n_in=54, hidden=64, n_out=5, seed=0):
+        h = lib().tpl_mlp_create(int(n_in), int(hidden), int(n_out), C.c_uint64(seed))
+        if not h:
+            raise TplError(TPL_EINVAL, tpl_last_error())
+        self._h = C.c_void_p(h)
+        self.n_in, self.hidden, self.n_out = int(n_in), int(hidden), int(n_out)
+        self.nparams = int(self.query("nparams"))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().tpl_mlp_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def query(self, key) -> float:
+        out = C.c_double()
+        _check(lib().tpl_mlp_query(self._h, key.encode(), C.byref(out)))
+        return out.value
+
+    def set_stream(self, stream_ptr: int):
+        _check(lib().tpl_mlp_set_stream(self._h, C.c_void_p(stream_ptr)))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.nparams, dtype=np.float32)
+        _check(lib().tpl_mlp_get_params(self._h, _fptr(out), out.size))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(lib().tpl_mlp_set_params(self._h, _fptr(theta), theta.size))
+
+    def set_norm(self, in_mean, in_std, out_mean, out_std):
+        a = [np.ascontiguousarray(v, dtype=np.float32) for v in (in_mean, in_std, out_mean, out_std)]
+        _check(lib().tpl_mlp_set_norm(self._h, *[_fptr(v) for v in a]))
+
+    def forward(self, X_dptr: int, Y_dptr: int, n: int):
+        _check(lib().tpl_mlp_forward(self._h, C.c_void_p(X_dptr), C.c_void_p(Y_dptr), int(n)))
+
+    def grads(self, X_dptr: int, T_dptr: int, n: int):
+        dW = np.zeros(self.nparams, dtype=np.float32)
+        loss = C.c_float()
+        _check(lib().tpl_mlp_grads(self._h, C.c_void_p(X_dptr), C.c_void_p(T_dptr), int(n),
+                                   _fptr(dW), C.byref(loss)))
+        return dW, loss.value
+
+    def train_step(self, X_dptr: int, T_dptr: int, n: int, lr: float = 1e-3) -> float:
+        loss = C.c_float()
+        _check(lib().tpl_mlp_train_step(self._h, C.c_void_p(X_dptr), C.c_void_p(T_dptr), int(n),
+                                        C.c_float(lr), C.byref(loss)))
+        return loss.value
