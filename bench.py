@@ -13,8 +13,9 @@ Prints one JSON line: MLUPS (10^6 r-node updates per second, each carrying
 oracle timed on a bounded sample of the same workload.  Extra entries: the
 FP32 storage form (1024^2 and 4096^2), FP64 and FP32 at NQ = 8, and the
 batched sweep of 256 seeded instances against the same instances stepped
-one by one.  Every workload starts from a base state of --pre-steps column
-steps (outside the timed region).
+one by one, and the learned coarse correction (training pipeline, judged
+errors, corrected-step cost).  Every workload starts from a base state of
+--pre-steps column steps (outside the timed region).
 """
 from __future__ import annotations
 
@@ -75,6 +76,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 form measurements")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched sweep")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned correction")
     ap.add_argument("--batch-instances", type=int, default=BATCH["instances"])
     ap.add_argument("--one-by-one-steps", type=int, default=10,
                     help="steps per instance of the one-by-one comparison")
@@ -140,6 +142,8 @@ def main():
             bt = out["batched"]
             if tb is not None:
                 bt["roofline"]["traffic"] = round(tb * bt["bytes_active_fraction"])
+    if not args.no_learned:
+        out["learned"] = measure_learned(torch, args.pre_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
@@ -241,6 +245,53 @@ def measure_batch(torch, n, steps, warmup, pre_steps, obo_steps) -> dict:
           f"qsplit={res['qsplit']} grid={res['grid']}, one-by-one "
           f"{res['one_by_one_mlups']} MLUPS", file=sys.stderr, flush=True)
     b.close()
+    return res
+
+
+def measure_learned(torch, pre_steps) -> dict:
+    """Learned coarse correction, scaled down from the 64-trajectory plan:
+    4 fine 1024^2 FP64 trajectories (NQ = 8, Re ~ U[20, 80], Wi ~ U[0, 1.5],
+    beta 0.7, 4 periods, seeds 1000-1003) of 400 fine steps sampled every 40,
+    a 256^2 coarse lattice (4x restriction), 40 epochs of Adam; judged on
+    held-out seeds 2000 and 2001 over 400 fine steps."""
+    import paper_2201_10132_amd.learned as LL
+    from tests import inputs
+
+    t0 = time.perf_counter()
+    trs = inputs.c5_trajectories(range(1000, 1004))
+    X, T, t_fine = LL.generate(torch, trs, pre_steps=pre_steps)
+    t1 = time.perf_counter()
+    torch.cuda.synchronize()
+    mlp, l0, l1 = LL.train(torch, X, T, epochs=40, lr=1e-3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    rows = X.shape[0] * X.shape[1] * 40
+    # matrix-core work per training row: 92 16x16x16 MFMAs per 16 rows
+    flops_row = 92 * 2 * 16 ** 3 / 16
+    evals = [LL.evaluate(torch, mlp, cfg, pre_steps=pre_steps)
+             for cfg in inputs.c5_trajectories([2000, 2001])]
+    plain_ms, corr_ms = LL.coarse_step_ms(torch, mlp, trs[0])
+    nc = 256 * 256
+    res = {
+        "workload": "kolmogorov_learned_coarse256_from_fine1024_nq8",
+        "train_trajectories": len(trs), "fine_steps": 400, "samples": int(X.shape[0]),
+        "generate_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+        "loss_first_epoch": round(l0, 5), "loss_last_epoch": round(l1, 5),
+        "mlp_train_tflops": round(rows * flops_row / (t2 - t1) / 1e12, 3),
+        "eval": [{"seed": cfg["seed"], "err_plain": e["err_plain"][-1],
+                  "err_corrected": e["err_corrected"][-1], "gain": e["gain"],
+                  "accepted": e["accepted"], "rejected_by_drift_gate": e["rejected_by_drift_gate"]}
+                 for cfg, e in zip(inputs.c5_trajectories([2000, 2001]), evals)],
+        "coarse_ms_per_step_plain": round(plain_ms, 4),
+        "coarse_ms_per_step_corrected": round(corr_ms, 4),
+        # fine-lattice node updates the corrected coarse step stands for:
+        # 16 fine nodes per coarse node, 4 fine steps per coarse step
+        "mlups_equivalent": round(nc * 64 / (corr_ms * 1e-3) / 1e6, 1),
+    }
+    print(f"# learned: generate {res['generate_s']} s, train {res['train_s']} s, loss "
+          f"{l0:.3f} -> {l1:.3f}, coarse {plain_ms:.3f}/{corr_ms:.3f} ms", file=sys.stderr,
+          flush=True)
+    mlp.close()
     return res
 
 

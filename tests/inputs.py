@@ -65,3 +65,17 @@ def c4_instances(n: int = 256, periods: int = 4, perturbation: float = 1e-4):
         out.append(dict(nx=nx, ny=ny, periods=periods, Re=Re, Wi=Wi, beta=beta, u0=0.05,
                         seed=i, perturbation=perturbation))
     return out
+
+
+# Learned-correction trajectories: fine runs with beta = 0.7 and 4 forcing
+# periods; trajectory seed s draws Re ~ U[20, 80] and Wi ~ U[0, 1.5] from
+# SplitMix64(s), in that order.
+def c5_trajectories(seeds, nx=1024, ny=1024, periods=4, beta=0.7, Re=(20.0, 80.0),
+                    Wi=(0.0, 1.5)):
+    out = []
+    for s in seeds:
+        g = splitmix64(s)
+        re = Re[0] + (Re[1] - Re[0]) * uniform01(g)
+        wi = Wi[0] + (Wi[1] - Wi[0]) * uniform01(g)
+        out.append(dict(nx=nx, ny=ny, periods=periods, beta=beta, seed=s, Re=re, Wi=wi))
+    return out
