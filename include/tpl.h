@@ -54,7 +54,18 @@ enum {
   TPL_EREJECTED = -6  /* a learned correction was rejected by its drift gate */
 };
 
-enum { TPL_FP64 = 0, TPL_FP32 = 1 };
+/* Storage forms of the populations (arithmetic is FP64 in all of them):
+ *   TPL_FP64     FP64 values
+ *   TPL_FP32     FP32 deviations from an x-invariant FP32 reference (the
+ *                base state), FP64 per-node fields
+ *   TPL_BF16NEQ  solvent and psi as TPL_FP32; each polymer (r, Q)-node stores
+ *                FP32 moments of its deviations (density and the fluxes
+ *                J^r, J^Q) and, per population, the BF16 remainder after the
+ *                linear equilibrium of those moments; the moments are stored
+ *                net of the rounded remainders' moments, so density and
+ *                fluxes are exact to FP32 (74 bytes per (r, Q)-node against
+ *                104 (FP32) and 208 (FP64)) */
+enum { TPL_FP64 = 0, TPL_FP32 = 1, TPL_BF16NEQ = 2 };
 enum { TPL_SOLVENT = 0, TPL_POLYMER = 1 };
 
 #define TPL_NFIELDS 10
@@ -104,7 +115,7 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *   force_scale 1 multiplies F0
  *   lambda 0      > 0: polymer relaxation time in steps instead of Wi l / u0
  *   drift_cap 0.1 cap on the Q-drift D_Q |F/kT| per step (0 = none)
- *   precision 0   TPL_FP64 or TPL_FP32 population storage
+ *   precision 0   TPL_FP64, TPL_FP32 or TPL_BF16NEQ population storage
  *   pert_modes 1  0 = single x-mode, 1 = multimode perturbation
  *   pre_steps -1  base-state column steps (-1 = 5 max(l^2/nu, lambda))
  *   qsplit 0      Q-slices per r-tile in the step kernel: 0 (automatic),
@@ -116,7 +127,7 @@ int tpl_set_param(tpl_ctx *ctx, const char *key, double value);
 /* Read a parameter, a derived value or a size.  Keys: every tpl_set_param key
  * and nx ny nqd Re Wi beta u0 periods kf l nu nuS G tau1S tau2S tau1P tau2P
  * lambda_eff sigma R DQ F0 kappa meq Sc rhoS0 rhoP0 step bytes_XS bytes_XP
- * bytes_PSI bytes_FLD bytes_state bytes_per_step
+ * bytes_PSI bytes_FLD bytes_MOM bytes_state bytes_per_step
  * kernel_ms kernel_launches qsplit_used.  Host only; TPL_EINVAL for an
  * unknown key. */
 int tpl_query(const tpl_ctx *ctx, const char *key, double *out);
@@ -129,7 +140,8 @@ int tpl_set_stream(tpl_ctx *ctx, void *hip_stream);
  * Call before tpl_init.  dptrs[i] must be a device pointer of at least
  * bytes[i] bytes, 256-byte aligned, for i = 0..3 in the order returned by
  * tpl_query keys bytes_XS, bytes_XP, bytes_PSI, bytes_FLD (each holds the
- * double-buffered array).  The caller keeps ownership. */
+ * double-buffered array).  The caller keeps ownership.  Not available for
+ * TPL_BF16NEQ (TPL_EINVAL). */
 int tpl_adopt_buffers(tpl_ctx *ctx, void *const *dptrs, const size_t *bytes,
                       int n);
 

@@ -58,6 +58,9 @@ template <typename T>
 struct StateT {
   T *XS, *XP, *PSI;
   double *FLD;
+  // BF16 non-equilibrium form only: XP holds BF16 (uint16) remainders and MOM
+  // the FP32 moments [5][nqd][N] (m0, J^r_x, J^r_y, J^Q_x, J^Q_y)
+  float *MOM;
 };
 using StateView = StateT<double>;
 using StateView32 = StateT<float>;
@@ -97,7 +100,13 @@ struct InstDev {
 // status.  T = double or float.
 template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
-                       StepRef ref, const QNode *qtab, hipStream_t s);
+                       StepRef ref, const QNode *qtab, hipStream_t s, bool neq = false);
+// BF16 non-equilibrium form <-> FP32 deviations from the reference, node by
+// node: dev [25][nqd][N] = w_k (m0 + 3 (v_k . J)) + n_k (decode), and the
+// inverse (encode: writes MOM and n).
+hipError_t launch_neq_decode(int nqd, long long N, StateT<float> a, float *dev, hipStream_t s);
+hipError_t launch_neq_encode(int nqd, long long N, const float *dev, StateT<float> a,
+                             hipStream_t s);
 // Build the FP32 form's reference from the FP64 column state (ref = the
 // column rounded to FP32) and the step kernel's regrouped tables.
 hipError_t launch_make_ref(int nqd, int ny, StateView col, float *ref,

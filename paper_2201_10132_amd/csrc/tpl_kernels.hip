@@ -108,6 +108,56 @@ __device__ __forceinline__ double stored<double>(double v, double) { return v; }
 template <>
 __device__ __forceinline__ float stored<float>(double v, double ref) { return (float)(v - ref); }
 
+// BF16 non-equilibrium form: a polymer population is its reference value
+// plus the linear equilibrium of its node's FP32 deviation moments
+// (m0, J^r, J^Q) plus a BF16 remainder n.  The stored moments are the node's
+// exact deviation moments minus those of its rounded remainders, so that the
+// reconstructed populations carry the exact density and fluxes (to FP32) and
+// the rounding touches only higher moments.  BF16 keeps FP32's exponent
+// range, so the remainder needs no scaling.
+__device__ __forceinline__ uint16_t to_bf16(double v) {
+  uint32_t u = __float_as_uint((float)v);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ double from_bf16(uint16_t b) {
+  return (double)__uint_as_float(((uint32_t)b) << 16);
+}
+// w_k (m0 + 3 (v_k . J)) with J = (Jrx, Jry, JQx, JQy); sq = -1 flips the
+// Q-velocity (the stored population of a bounced-back pull is k*)
+__device__ __forceinline__ double neq_lin(int k, double ps, const double J[4], double sq) {
+  double t = ps;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (PV[k][c]) t += 3.0 * (c < 2 ? 1.0 : sq) * PV[k][c] * J[c];
+  return (k == 0 ? 1.0 / 3.0 : 1.0 / 36.0) * t;
+}
+// Encode the deviations d[25] of one (r, Q)-node: BF16 remainders nb[25] and
+// the stored moments m[5] (m0, Jrx, Jry, JQx, JQy) as FP32.
+__device__ __forceinline__ void neq_encode(const double d[25], uint16_t nb[25], float m[5]) {
+  double m0 = 0.0, J[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 25; ++k) {
+    m0 += d[k];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (PV[k][c]) J[c] += PV[k][c] * d[k];
+  }
+  double s0 = 0.0, sJ[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 25; ++k) {
+    nb[k] = to_bf16(d[k] - neq_lin(k, m0, J, 1.0));
+    const double r = from_bf16(nb[k]);
+    s0 += r;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (PV[k][c]) sJ[c] += PV[k][c] * r;
+  }
+  m[0] = (float)(m0 - s0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) m[1 + c] = (float)(J[c] - sJ[c]);
+}
+
 // ---------------------------------------------------------------------------
 // The fused step.  One lane per r-node; the Q-disk of that node is split over
 // qs waves (slices) of the workgroup, each walking its Q-nodes in order.  All
@@ -127,7 +177,7 @@ __device__ __forceinline__ float stored<float>(double v, double ref) { return (f
 // are wave-uniform (scalar loads).
 // One 64-node tile of one lattice (all qs slices of the workgroup take part).
 // red: LDS of qs * 12 * 64 doubles.
-template <typename T, bool ROWTILE>
+template <typename T, bool ROWTILE, bool NEQ = false>
 __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &a,
                                           const StateT<T> &b, const float *__restrict__ rpull,
                                           const float *__restrict__ rstore,
@@ -250,9 +300,29 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   for (int q = slice; q < nqd; q += p.qs) {
     const QNode CONSTANT_AS &qn = cst(qtab)[q];  // scalar loads
     double g[25];
+    if constexpr (!NEQ) {
 #pragma unroll
-    for (int k = 0; k < 25; ++k)
-      g[k] = full(ldo(plane(a.XP, qn.plane[k]), osrc[pdir(k)]), rq(rpull, y, q, k));
+      for (int k = 0; k < 25; ++k)
+        g[k] = full(ldo(plane(a.XP, qn.plane[k]), osrc[pdir(k)]), rq(rpull, y, q, k));
+    } else {
+      // source population: the source node's moments and remainder
+      const uint16_t *XPn = reinterpret_cast<const uint16_t *>(a.XP);
+#pragma unroll
+      for (int k = 0; k < 25; ++k) {
+        const int pk = qn.plane[k];
+        const int dq = pk - k * nqd;                 // in [0, nqd): no bounce-back
+        const bool bb = (dq < 0) || (dq >= nqd);
+        const int qsrc = bb ? q : dq;
+        const uint32_t o = osrc[pdir(k)];
+        double J[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          J[c] = PV[k][c] ? (double)ldo(uni(a.MOM + (size_t)((c + 1) * nqd + qsrc) * N), o) : 0.0;
+        const double m0 = (double)ldo(uni(a.MOM + (size_t)qsrc * N), o);
+        g[k] = rq(rpull, y, q, k) + neq_lin(k, m0, J, bb ? -1.0 : 1.0) +
+               from_bf16(ldo(uni(XPn + (size_t)pk * N), o >> 1));
+      }
+    }
     double psi = 0.0, Jrx = 0.0, Jry = 0.0, JQx = 0.0, JQy = 0.0;
 #pragma unroll
     for (int k = 0; k < 25; ++k) {
@@ -294,10 +364,25 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
       mg[pdir(k)] += g[k];
     }
     if (active) {
+      if constexpr (!NEQ) {
 #pragma unroll
-      for (int k = 0; k < 25; ++k)
-        sto(wplane(b.XP, (long long)k * nqd + q), oR, stored<T>(g[k], rq(rstore, y, q, k)));
-      sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
+        for (int k = 0; k < 25; ++k)
+          sto(wplane(b.XP, (long long)k * nqd + q), oR, stored<T>(g[k], rq(rstore, y, q, k)));
+        sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
+      } else {
+        // deviations -> BF16 remainders and FP32 moments
+        sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
+#pragma unroll
+        for (int k = 0; k < 25; ++k) g[k] -= rq(rstore, y, q, k);
+        uint16_t nb[25];
+        float m[5];
+        neq_encode(g, nb, m);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) sto(uni(b.MOM + (size_t)(c * nqd + q) * N), oR, m[c]);
+        uint16_t *XPw = reinterpret_cast<uint16_t *>(b.XP);
+#pragma unroll
+        for (int k = 0; k < 25; ++k) sto(uni(XPw + (size_t)(k * nqd + q) * N), oR >> 1, nb[k]);
+      }
     }
     Mxx += psi * qn.qx * qn.fx;
     Mxy += psi * qn.qx * qn.fy;
@@ -338,7 +423,7 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   if (p.qs > 1) __syncthreads();  // red is reused by the workgroup's next tile
 }
 
-template <typename T, int MAXT, bool ROWTILE>
+template <typename T, int MAXT, bool ROWTILE, bool NEQ = false>
 __global__ void __launch_bounds__(MAXT)
     k_step(StepParams p, StateT<T> a, StateT<T> b, const float *__restrict__ rpull,
            const float *__restrict__ rstore, const float *__restrict__ rpsi,
@@ -347,7 +432,7 @@ __global__ void __launch_bounds__(MAXT)
   extern __shared__ double red[];  // [qs][12][64]
   const int tile = xcd_tile(blockIdx.x, p.tiles_per_xcd);
   if (tile >= p.ntiles) return;  // whole workgroup leaves together
-  step_tile<T, ROWTILE>(p, a, b, rpull, rstore, rpsi, rspull, rsstore, qtab, tile, red);
+  step_tile<T, ROWTILE, NEQ>(p, a, b, rpull, rstore, rpsi, rspull, rsstore, qtab, tile, red);
 }
 
 
@@ -421,30 +506,94 @@ template hipError_t launch_step_batch<float>(const InstDev *, int, int, int, int
 
 template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
-                       StepRef r, const QNode *qtab, hipStream_t s) {
+                       StepRef r, const QNode *qtab, hipStream_t s, bool neq) {
   const int grid = p.tiles_per_xcd > 0 ? 8 * p.tiles_per_xcd : p.ntiles;
   const size_t lds = p.qs > 1 ? (size_t)p.qs * 12 * 64 * sizeof(double) : 0;
   const bool rowtile = (p.nx % 64) == 0;
   const dim3 g(grid), blk(64 * p.qs);
 #define TPL_STEP_ARGS p, a, b, r.pull, r.store, r.psi, r.spull, r.sstore, qtab
-  if (p.qs <= 4) {
-    if (rowtile)
-      hipLaunchKernelGGL((k_step<T, 256, true>), g, blk, lds, s, TPL_STEP_ARGS);
-    else
-      hipLaunchKernelGGL((k_step<T, 256, false>), g, blk, lds, s, TPL_STEP_ARGS);
-  } else {
-    if (rowtile)
-      hipLaunchKernelGGL((k_step<T, 512, true>), g, blk, lds, s, TPL_STEP_ARGS);
-    else
-      hipLaunchKernelGGL((k_step<T, 512, false>), g, blk, lds, s, TPL_STEP_ARGS);
+#define TPL_STEP_LAUNCH(NEQ)                                                     \
+  if (p.qs <= 4) {                                                               \
+    if (rowtile)                                                                 \
+      hipLaunchKernelGGL((k_step<T, 256, true, NEQ>), g, blk, lds, s, TPL_STEP_ARGS);  \
+    else                                                                         \
+      hipLaunchKernelGGL((k_step<T, 256, false, NEQ>), g, blk, lds, s, TPL_STEP_ARGS); \
+  } else {                                                                       \
+    if (rowtile)                                                                 \
+      hipLaunchKernelGGL((k_step<T, 512, true, NEQ>), g, blk, lds, s, TPL_STEP_ARGS);  \
+    else                                                                         \
+      hipLaunchKernelGGL((k_step<T, 512, false, NEQ>), g, blk, lds, s, TPL_STEP_ARGS); \
   }
+  if constexpr (std::is_same<T, float>::value) {
+    if (neq) {
+      TPL_STEP_LAUNCH(true)
+    } else {
+      TPL_STEP_LAUNCH(false)
+    }
+  } else {
+    if (neq) return hipErrorInvalidValue;
+    TPL_STEP_LAUNCH(false)
+  }
+#undef TPL_STEP_LAUNCH
 #undef TPL_STEP_ARGS
   return hipGetLastError();
 }
 template hipError_t launch_step<double>(const StepParams &, StateT<double>, StateT<double>,
-                                        StepRef, const QNode *, hipStream_t);
+                                        StepRef, const QNode *, hipStream_t, bool);
 template hipError_t launch_step<float>(const StepParams &, StateT<float>, StateT<float>,
-                                       StepRef, const QNode *, hipStream_t);
+                                       StepRef, const QNode *, hipStream_t, bool);
+
+// BF16 non-equilibrium form: node-local conversions to and from FP32
+// deviations (auxiliary paths: initialisation, state exchange, diagnostics).
+__global__ void k_neq_decode(int nqd, long long N, StateT<float> a, float *__restrict__ dev) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N * nqd) return;
+  const int q = (int)(j / N);
+  const long long r = j - (long long)q * N;
+  const uint16_t *n = reinterpret_cast<const uint16_t *>(a.XP);
+  double J[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) J[c] = (double)a.MOM[(size_t)((c + 1) * nqd + q) * N + r];
+  const double m0 = (double)a.MOM[(size_t)q * N + r];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) {
+    const size_t i = (size_t)(k * nqd + q) * N + r;
+    dev[i] = (float)(neq_lin(k, m0, J, 1.0) + from_bf16(n[i]));
+  }
+}
+
+__global__ void k_neq_encode(int nqd, long long N, const float *__restrict__ dev,
+                             StateT<float> a) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N * nqd) return;
+  const int q = (int)(j / N);
+  const long long r = j - (long long)q * N;
+  uint16_t *n = reinterpret_cast<uint16_t *>(a.XP);
+  double d[25];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) d[k] = (double)dev[(size_t)(k * nqd + q) * N + r];
+  uint16_t nb[25];
+  float m[5];
+  neq_encode(d, nb, m);
+#pragma unroll
+  for (int c = 0; c < 5; ++c) a.MOM[(size_t)(c * nqd + q) * N + r] = m[c];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) n[(size_t)(k * nqd + q) * N + r] = nb[k];
+}
+
+hipError_t launch_neq_decode(int nqd, long long N, StateT<float> a, float *dev, hipStream_t s) {
+  const long long n = N * nqd;
+  hipLaunchKernelGGL(k_neq_decode, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nqd, N, a,
+                     dev);
+  return hipGetLastError();
+}
+hipError_t launch_neq_encode(int nqd, long long N, const float *dev, StateT<float> a,
+                             hipStream_t s) {
+  const long long n = N * nqd;
+  hipLaunchKernelGGL(k_neq_encode, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nqd, N,
+                     dev, a);
+  return hipGetLastError();
+}
 
 // FP32 form reference: ref[plane][y] = (float) column[plane][y] for the 9
 // solvent, 25 nqd polymer and nqd psi planes.

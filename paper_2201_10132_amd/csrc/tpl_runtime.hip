@@ -165,17 +165,22 @@ int derive(const Config &c, Derived &d) {
   return TPL_OK;
 }
 
-// Double-buffered state.  XS, XP and PSI hold elements of esize bytes (8:
-// FP64 values, 4: FP32 deviations from the reference); FLD is FP64.
+// Double-buffered state.  XS and PSI hold elements of esize bytes (8: FP64
+// values, 4: FP32 deviations from the reference), XP elements of xsize bytes
+// (8, 4, or 2: the BF16 remainders of the BF16 non-equilibrium form, whose
+// FP32 deviation fluxes are in MOM); FLD is FP64.
 struct Buffers {
   void *XS = nullptr, *XP = nullptr, *PSI = nullptr;
   double *FLD = nullptr;
-  size_t nXS = 0, nXP = 0, nPSI = 0, nFLD = 0;  // elements per half
-  size_t esize = 8;
+  float *MOM = nullptr;
+  size_t nXS = 0, nXP = 0, nPSI = 0, nFLD = 0, nMOM = 0;  // elements per half
+  size_t esize = 8, xsize = 8;
   template <typename T>
   StateT<T> half(int h) const {
-    return StateT<T>{static_cast<T *>(XS) + h * nXS, static_cast<T *>(XP) + h * nXP,
-                     static_cast<T *>(PSI) + h * nPSI, FLD + h * nFLD};
+    return StateT<T>{static_cast<T *>(XS) + h * nXS,
+                     reinterpret_cast<T *>(static_cast<char *>(XP) + h * nXP * xsize),
+                     static_cast<T *>(PSI) + h * nPSI, FLD + h * nFLD,
+                     MOM ? MOM + h * nMOM : nullptr};
   }
   StateView half64(int h) const { return half<double>(h); }
 };
@@ -274,8 +279,13 @@ int ensure_scratch(tpl_ctx *x, size_t n) {
   return TPL_OK;
 }
 
-size_t elem_size(const tpl_ctx *x) { return x->c.precision == TPL_FP32 ? 4 : 8; }
-bool fp32(const tpl_ctx *x) { return x->c.precision == TPL_FP32; }
+size_t elem_size(const tpl_ctx *x) { return x->c.precision == TPL_FP64 ? 8 : 4; }
+size_t xp_size(const tpl_ctx *x) {
+  return x->c.precision == TPL_FP64 ? 8 : x->c.precision == TPL_FP32 ? 4 : 2;
+}
+// FP32 reference forms (FP32 storage and the BF16 non-equilibrium form)
+bool fp32(const tpl_ctx *x) { return x->c.precision != TPL_FP64; }
+bool neq(const tpl_ctx *x) { return x->c.precision == TPL_BF16NEQ; }
 
 int alloc_state(tpl_ctx *x) {
   if (x->buf.XS) return TPL_OK;
@@ -284,11 +294,14 @@ int alloc_state(tpl_ctx *x) {
   B.nXP = state_elems(x, 1);
   B.nPSI = state_elems(x, 2);
   B.nFLD = state_elems(x, 3);
+  B.nMOM = neq(x) ? 5 * B.nPSI : 0;
   B.esize = elem_size(x);
-  void **ptrs[4] = {&B.XS, &B.XP, &B.PSI, reinterpret_cast<void **>(&B.FLD)};
-  size_t bytes[4] = {2 * B.nXS * B.esize, 2 * B.nXP * B.esize, 2 * B.nPSI * B.esize,
-                     2 * B.nFLD * sizeof(double)};
-  for (int i = 0; i < 4; ++i) {
+  B.xsize = xp_size(x);
+  void **ptrs[5] = {&B.XS, &B.XP, &B.PSI, reinterpret_cast<void **>(&B.FLD),
+                    reinterpret_cast<void **>(&B.MOM)};
+  size_t bytes[5] = {2 * B.nXS * B.esize, 2 * B.nXP * B.xsize, 2 * B.nPSI * B.esize,
+                     2 * B.nFLD * sizeof(double), 2 * B.nMOM * sizeof(float)};
+  for (int i = 0; i < (neq(x) ? 5 : 4); ++i) {
     if (hipMalloc(ptrs[i], bytes[i]) != hipSuccess) {
       (void)hipGetLastError();
       for (int j = 0; j < i; ++j) {
@@ -297,6 +310,7 @@ int alloc_state(tpl_ctx *x) {
       }
       B.XS = B.XP = B.PSI = nullptr;
       B.FLD = nullptr;
+      B.MOM = nullptr;
       char msg[160];
       snprintf(msg, sizeof msg, "device allocation of %.2f GB failed", bytes[i] / 1e9);
       return fail(TPL_ENOMEM, msg);
@@ -327,6 +341,38 @@ int build_step_ref(tpl_ctx *x) {
   HIPCHK(launch_step_ref(x->d.nqd, x->c.ny, x->qtab_d, ref_view(x), const_cast<float *>(r.pull),
                          const_cast<float *>(r.store), const_cast<float *>(r.psi),
                          const_cast<float *>(r.spull), const_cast<float *>(r.sstore), x->stream));
+  return TPL_OK;
+}
+
+// BF16 non-equilibrium form: an FP32 view of one half whose polymer
+// populations are decoded into a temporary (FP32 deviations), for the
+// auxiliary kernels; write-back re-encodes them.
+// For the other forms the view is the stored half itself.
+struct FloatView {
+  StateView32 v{};
+  float *tmp = nullptr;
+  ~FloatView() {
+    if (tmp) (void)hipFree(tmp);
+  }
+};
+int float_view(tpl_ctx *x, int h, FloatView &fv) {
+  fv.v = x->buf.half<float>(h);
+  if (!neq(x)) return TPL_OK;
+  const long long N = (long long)x->c.nx * x->c.ny;
+  if (hipMalloc(&fv.tmp, 25 * (size_t)x->d.nqd * N * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    fv.tmp = nullptr;
+    return fail(TPL_ENOMEM, "decode buffer allocation failed");
+  }
+  HIPCHK(launch_neq_decode(x->d.nqd, N, fv.v, fv.tmp, x->stream));
+  fv.v.XP = fv.tmp;
+  return TPL_OK;
+}
+int float_writeback(tpl_ctx *x, int h, FloatView &fv) {
+  if (!neq(x)) return TPL_OK;
+  const long long N = (long long)x->c.nx * x->c.ny;
+  HIPCHK(launch_neq_encode(x->d.nqd, N, fv.tmp, x->buf.half<float>(h), x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
   return TPL_OK;
 }
 
@@ -364,7 +410,7 @@ int run_steps(tpl_ctx *x, const Buffers &B, int nx, int ny, int *cur,
     if (timed) HIPCHK(hipEventRecord(e0, x->stream));
     if (B.esize == 4)
       HIPCHK(launch_step<float>(p, B.half<float>(*cur), B.half<float>(1 - *cur), ref,
-                                x->qtab_d, x->stream));
+                                x->qtab_d, x->stream, B.xsize == 2));
     else
       HIPCHK(launch_step<double>(p, B.half<double>(*cur), B.half<double>(1 - *cur), ref,
                                  x->qtab_d, x->stream));
@@ -443,10 +489,14 @@ int perturb(tpl_ctx *x, uint64_t seed, double amp) {
   HIPCHK(hipMemcpyAsync(scale, &h_scale, sizeof(double), hipMemcpyHostToDevice,
                         x->stream));
   if (fp32(x)) {
-    HIPCHK(launch_perturb_apply<float>(x->d.nqd, nx, ny, du, scale, x->buf.half<float>(x->cur),
-                                       ref_view(x), x->stream));
-    HIPCHK(launch_refresh<float>(x->d.nqd, nx, ny, x->qtab_d, x->buf.half<float>(x->cur),
-                                 ref_view(x), x->stream));
+    FloatView fv;
+    int r2 = float_view(x, x->cur, fv);
+    if (r2) return r2;
+    HIPCHK(launch_perturb_apply<float>(x->d.nqd, nx, ny, du, scale, fv.v, ref_view(x),
+                                       x->stream));
+    HIPCHK(launch_refresh<float>(x->d.nqd, nx, ny, x->qtab_d, fv.v, ref_view(x), x->stream));
+    r2 = float_writeback(x, x->cur, fv);
+    if (r2) return r2;
   } else {
     HIPCHK(launch_perturb_apply<double>(x->d.nqd, nx, ny, du, scale, x->buf.half64(x->cur),
                                         ref_view(x), x->stream));
@@ -538,9 +588,23 @@ int seed_from_column(tpl_ctx *x, const StateView &cv) {
     const RefView rv = ref_view(x);
     const StateView32 h0 = x->buf.half<float>(0);
     HIPCHK(launch_tile_dev(9, nx, ny, cv.XS, rv.XS, h0.XS, x->stream));
-    HIPCHK(launch_tile_dev(25 * d.nqd, nx, ny, cv.XP, rv.XP, h0.XP, x->stream));
     HIPCHK(launch_tile_dev(d.nqd, nx, ny, cv.PSI, rv.PSI, h0.PSI, x->stream));
     HIPCHK(launch_tile_fields(nx, ny, cv.FLD, h0.FLD, x->stream));
+    if (!neq(x)) {
+      HIPCHK(launch_tile_dev(25 * d.nqd, nx, ny, cv.XP, rv.XP, h0.XP, x->stream));
+    } else {  // FP32 deviations of the column, then their BF16 encoding
+      const long long N = (long long)nx * ny;
+      float *tmp = nullptr;
+      if (hipMalloc(&tmp, 25 * (size_t)d.nqd * N * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TPL_ENOMEM, "encode buffer allocation failed");
+      }
+      hipError_t e = launch_tile_dev(25 * d.nqd, nx, ny, cv.XP, rv.XP, tmp, x->stream);
+      if (e == hipSuccess) e = launch_neq_encode(d.nqd, N, tmp, h0, x->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
+      (void)hipFree(tmp);
+      if (e != hipSuccess) return fail(TPL_EHIP, std::string("encode: ") + hipGetErrorString(e));
+    }
   }
   HIPCHK(hipStreamSynchronize(x->stream));
   return TPL_OK;
@@ -642,8 +706,8 @@ int tpl_set_param(tpl_ctx *x, const char *key, double v) {
   }
   if (!found) return fail(TPL_EINVAL, std::string("unknown parameter ") + key);
   if (c.spring != 0 && c.spring != 1) return fail(TPL_EINVAL, "spring must be 0 or 1");
-  if (c.precision != TPL_FP64 && c.precision != TPL_FP32)
-    return fail(TPL_EINVAL, "precision must be TPL_FP64 or TPL_FP32");
+  if (c.precision != TPL_FP64 && c.precision != TPL_FP32 && c.precision != TPL_BF16NEQ)
+    return fail(TPL_EINVAL, "precision must be TPL_FP64, TPL_FP32 or TPL_BF16NEQ");
   if (c.qsplit < 0 || c.qsplit > 8) return fail(TPL_EINVAL, "qsplit must be in [0,8]");
   if (!(c.drift_cap >= 0)) return fail(TPL_EINVAL, "drift_cap must be >= 0");
   if (runtime_knob) {
@@ -667,7 +731,9 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
     }
   const Derived &d = x->d;
   const double N = (double)x->c.nx * x->c.ny;
-  const double es = x->c.precision == TPL_FP32 ? 4.0 : 8.0;
+  const double es = x->c.precision == TPL_FP64 ? 8.0 : 4.0;
+  const double xs = x->c.precision == TPL_FP64 ? 8.0 : x->c.precision == TPL_FP32 ? 4.0 : 2.0;
+  const double ms = x->c.precision == TPL_BF16NEQ ? 5.0 * 4.0 : 0.0;  // MOM per (r, Q)
   struct {
     const char *n;
     double v;
@@ -680,12 +746,15 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
       {"R", d.R}, {"DQ", d.DQ}, {"F0", d.F0}, {"kappa", d.kappa},
       {"meq", d.meq}, {"Sc", d.Sc}, {"rhoS0", d.rhoS0}, {"rhoP0", d.rhoP0},
       {"step", (double)x->step},
-      {"bytes_XS", 2.0 * es * 9 * N}, {"bytes_XP", 2.0 * es * 25 * d.nqd * N},
+      {"bytes_XS", 2.0 * es * 9 * N}, {"bytes_XP", 2.0 * xs * 25 * d.nqd * N},
       {"bytes_PSI", 2.0 * es * d.nqd * N}, {"bytes_FLD", 16.0 * NF * N},
-      {"bytes_state", 2.0 * N * (es * (9 + 26.0 * d.nqd) + 8.0 * NF)},
+      {"bytes_MOM", 2.0 * ms * d.nqd * N},
+      {"bytes_state", 2.0 * N * (es * (9 + d.nqd) + xs * 25.0 * d.nqd + ms * d.nqd + 8.0 * NF)},
       // algorithmic HBM bytes of one step: populations read + written,
       // lagged psi written + read, lagged per-node fields written + read
-      {"bytes_per_step", N * (es * (2.0 * (9 + 25.0 * d.nqd) + 2.0 * d.nqd) + 8.0 * 2.0 * NF)},
+      // (BF16 form: remainders and FP32 fluxes read + written once)
+      {"bytes_per_step",
+       N * (2.0 * es * (9 + d.nqd) + 2.0 * (xs * 25.0 + ms) * d.nqd + 8.0 * 2.0 * NF)},
       {"kernel_ms", x->kernel_ms}, {"kernel_launches", (double)x->kernel_launches},
       {"qsplit_used", (double)x->qs_used},
   };
@@ -707,6 +776,7 @@ int tpl_adopt_buffers(tpl_ctx *x, void *const *dptrs, const size_t *bytes, int n
   if (!x || !dptrs || !bytes) return fail(TPL_EINVAL, "null argument");
   if (x->inited || x->buf.XS) return fail(TPL_ESTATE, "buffers already allocated");
   if (n != 4) return fail(TPL_EINVAL, "expected 4 buffers (XS, XP, PSI, FLD)");
+  if (neq(x)) return fail(TPL_EINVAL, "the BF16 form allocates its own buffers");
   Buffers B;
   B.nXS = state_elems(x, 0);
   B.nXP = state_elems(x, 1);
@@ -850,9 +920,11 @@ int tpl_diagnostics(tpl_ctx *x, tpl_diag *out) {
   rc = ensure_scratch(x, (size_t)1024 * kDiagComp + kDiagComp);
   if (rc) return rc;
   int nb = 0;
+  FloatView fv;
+  if (fp32(x) && (rc = float_view(x, x->cur, fv))) return rc;
   if (fp32(x))
-    HIPCHK(launch_diag<float>(x->c.nx, x->c.ny, x->d.nqd, x->qtab_d, x->buf.half<float>(x->cur),
-                              ref_view(x), x->scratch, &nb, x->stream));
+    HIPCHK(launch_diag<float>(x->c.nx, x->c.ny, x->d.nqd, x->qtab_d, fv.v, ref_view(x),
+                              x->scratch, &nb, x->stream));
   else
     HIPCHK(launch_diag<double>(x->c.nx, x->c.ny, x->d.nqd, x->qtab_d, x->buf.half64(x->cur),
                                ref_view(x), x->scratch, &nb, x->stream));
@@ -883,9 +955,11 @@ int tpl_get_window(tpl_ctx *x, int x0, int y0, int w, int h, double *XS,
   const size_t planes = 9 + 26 * nqd + 2;
   rc = ensure_scratch(x, planes * wh);
   if (rc) return rc;
+  FloatView fv;
+  if (fp32(x) && (rc = float_view(x, x->cur, fv))) return rc;
   if (fp32(x))
-    HIPCHK(launch_window<float>(x->c.nx, x->c.ny, (int)nqd, x0, y0, w, h,
-                                x->buf.half<float>(x->cur), ref_view(x), x->scratch, x->stream));
+    HIPCHK(launch_window<float>(x->c.nx, x->c.ny, (int)nqd, x0, y0, w, h, fv.v, ref_view(x),
+                                x->scratch, x->stream));
   else
     HIPCHK(launch_window<double>(x->c.nx, x->c.ny, (int)nqd, x0, y0, w, h,
                                  x->buf.half64(x->cur), ref_view(x), x->scratch, x->stream));
@@ -954,8 +1028,13 @@ int tpl_get_state(tpl_ctx *x, double *XS, double *XP, double *psi, double *U) {
   const RefView r = ref_view(x);
   const size_t es = x->buf.esize;
   const char *XSd = static_cast<const char *>(x->buf.XS) + cur * x->buf.nXS * es;
-  const char *XPd = static_cast<const char *>(x->buf.XP) + cur * x->buf.nXP * es;
+  const char *XPd = static_cast<const char *>(x->buf.XP) + cur * x->buf.nXP * x->buf.xsize;
   const char *PSd = static_cast<const char *>(x->buf.PSI) + cur * x->buf.nPSI * es;
+  FloatView fv;
+  if (XP && neq(x)) {
+    if ((rc = float_view(x, cur, fv))) return rc;
+    XPd = reinterpret_cast<const char *>(fv.v.XP);
+  }
   if (XS && (rc = array_to_host(x, XSd, 9, r.XS, XS))) return rc;
   if (XP && (rc = array_to_host(x, XPd, 25 * nqd, r.XP, XP))) return rc;
   if (psi && (rc = array_to_host(x, PSd, nqd, r.PSI, psi))) return rc;
@@ -975,17 +1054,26 @@ int tpl_set_state(tpl_ctx *x, const double *XS, const double *XP,
   const RefView r = ref_view(x);
   const size_t es = x->buf.esize;
   char *XSd = static_cast<char *>(x->buf.XS) + cur * x->buf.nXS * es;
-  char *XPd = static_cast<char *>(x->buf.XP) + cur * x->buf.nXP * es;
+  char *XPd = static_cast<char *>(x->buf.XP) + cur * x->buf.nXP * x->buf.xsize;
   char *PSd = static_cast<char *>(x->buf.PSI) + cur * x->buf.nPSI * es;
   if (XS && (rc = array_from_host(x, XSd, 9, r.XS, XS))) return rc;
-  if (XP && (rc = array_from_host(x, XPd, 25 * nqd, r.XP, XP))) return rc;
-  if (psi && (rc = array_from_host(x, PSd, nqd, r.PSI, psi))) return rc;
+  if (neq(x) && XP) {
+    FloatView fv;
+    if ((rc = float_view(x, cur, fv))) return rc;
+    if (XP && (rc = array_from_host(x, fv.tmp, 25 * nqd, r.XP, XP))) return rc;
+    if (psi && (rc = array_from_host(x, PSd, nqd, r.PSI, psi))) return rc;
+    if ((rc = float_writeback(x, cur, fv))) return rc;
+  } else {
+    if (XP && (rc = array_from_host(x, XPd, 25 * nqd, r.XP, XP))) return rc;
+    if (psi && (rc = array_from_host(x, PSd, nqd, r.PSI, psi))) return rc;
+  }
   if (U)
     HIPCHK(hipMemcpyAsync(x->buf.half64(cur).FLD + (size_t)F_UX * N, U, 2 * N * 8,
                           hipMemcpyHostToDevice, x->stream));
+  FloatView fr;
+  if (fp32(x) && (rc = float_view(x, cur, fr))) return rc;
   if (fp32(x))
-    HIPCHK(launch_refresh<float>(nqd, x->c.nx, x->c.ny, x->qtab_d, x->buf.half<float>(cur), r,
-                                 x->stream));
+    HIPCHK(launch_refresh<float>(nqd, x->c.nx, x->c.ny, x->qtab_d, fr.v, r, x->stream));
   else
     HIPCHK(launch_refresh<double>(nqd, x->c.nx, x->c.ny, x->qtab_d, x->buf.half64(cur), r,
                                   x->stream));
@@ -1028,17 +1116,18 @@ int tpl_save(tpl_ctx *x, const char *path) {
   FILE *f = std::fopen(path, "wb");
   if (!f) return fail(TPL_EINVAL, std::string("cannot open ") + path);
   HIPCHK(hipStreamSynchronize(x->stream));
-  const size_t es = x->buf.esize, cur = x->cur;
-  const void *src[5] = {static_cast<const char *>(x->buf.XS) + cur * x->buf.nXS * es,
-                        static_cast<const char *>(x->buf.XP) + cur * x->buf.nXP * es,
+  const size_t es = x->buf.esize, xs = x->buf.xsize, cur = x->cur;
+  const void *src[6] = {static_cast<const char *>(x->buf.XS) + cur * x->buf.nXS * es,
+                        static_cast<const char *>(x->buf.XP) + cur * x->buf.nXP * xs,
                         static_cast<const char *>(x->buf.PSI) + cur * x->buf.nPSI * es,
-                        x->buf.FLD + cur * x->buf.nFLD, x->ref};
-  const size_t nb[5] = {x->buf.nXS * es, x->buf.nXP * es, x->buf.nPSI * es, x->buf.nFLD * 8,
-                        x->ref ? ref_elems(x) * sizeof(float) : 0};
+                        x->buf.FLD + cur * x->buf.nFLD, x->ref,
+                        x->buf.MOM ? x->buf.MOM + cur * x->buf.nMOM : nullptr};
+  const size_t nb[6] = {x->buf.nXS * es, x->buf.nXP * xs, x->buf.nPSI * es, x->buf.nFLD * 8,
+                        x->ref ? ref_elems(x) * sizeof(float) : 0, x->buf.nMOM * sizeof(float)};
   bool ok = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(&x->c, sizeof(Config), 1, f) == 1 &&
             std::fwrite(&x->step, sizeof x->step, 1, f) == 1;
   std::vector<char> h;
-  for (int i = 0; i < 5 && ok; ++i) {
+  for (int i = 0; i < 6 && ok; ++i) {
     if (!nb[i]) continue;
     h.resize(nb[i]);
     if (hipMemcpy(h.data(), src[i], nb[i], hipMemcpyDeviceToHost) != hipSuccess) {
@@ -1066,16 +1155,17 @@ int tpl_load(tpl_ctx *x, const char *path) {
     std::fclose(f);
     return fail(TPL_EINVAL, "checkpoint does not match this context");
   }
-  const size_t es = x->buf.esize, cur = x->cur;
-  void *dst[5] = {static_cast<char *>(x->buf.XS) + cur * x->buf.nXS * es,
-                  static_cast<char *>(x->buf.XP) + cur * x->buf.nXP * es,
+  const size_t es = x->buf.esize, xs = x->buf.xsize, cur = x->cur;
+  void *dst[6] = {static_cast<char *>(x->buf.XS) + cur * x->buf.nXS * es,
+                  static_cast<char *>(x->buf.XP) + cur * x->buf.nXP * xs,
                   static_cast<char *>(x->buf.PSI) + cur * x->buf.nPSI * es,
-                  x->buf.FLD + cur * x->buf.nFLD, x->ref};
-  const size_t nb[5] = {x->buf.nXS * es, x->buf.nXP * es, x->buf.nPSI * es, x->buf.nFLD * 8,
-                        x->ref ? ref_elems(x) * sizeof(float) : 0};
+                  x->buf.FLD + cur * x->buf.nFLD, x->ref,
+                  x->buf.MOM ? x->buf.MOM + cur * x->buf.nMOM : nullptr};
+  const size_t nb[6] = {x->buf.nXS * es, x->buf.nXP * xs, x->buf.nPSI * es, x->buf.nFLD * 8,
+                        x->ref ? ref_elems(x) * sizeof(float) : 0, x->buf.nMOM * sizeof(float)};
   std::vector<char> h;
   HIPCHK(hipStreamSynchronize(x->stream));
-  for (int i = 0; i < 5 && ok; ++i) {
+  for (int i = 0; i < 6 && ok; ++i) {
     if (!nb[i]) continue;
     h.resize(nb[i]);
     ok = std::fread(h.data(), 1, nb[i], f) == nb[i];
@@ -1102,6 +1192,7 @@ void tpl_destroy(tpl_ctx *x) {
     (void)hipFree(x->buf.XP);
     (void)hipFree(x->buf.PSI);
     (void)hipFree(x->buf.FLD);
+    (void)hipFree(x->buf.MOM);
   }
   (void)hipFree(x->qtab_d);
   (void)hipFree(x->peq_d);
@@ -1452,7 +1543,7 @@ tpl_batch *tpl_batch_create(const tpl_instance *inst, int n, int precision) {
     return nullptr;
   }
   if (precision != TPL_FP64 && precision != TPL_FP32) {
-    fail(TPL_EINVAL, "precision must be TPL_FP64 or TPL_FP32");
+    fail(TPL_EINVAL, "a batch runs TPL_FP64 or TPL_FP32");
     return nullptr;
   }
   tpl_batch *b = new tpl_batch;
