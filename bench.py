@@ -132,6 +132,13 @@ def main():
         forms["fp64_1024x1024_nq8"] = form_entry(f64q8, None)
         f32q8 = measure(torch, w8, 1, args.steps, args.warmup, args.pre_steps)
         forms["fp32_1024x1024_nq8"] = form_entry(f32q8, f64q8)
+        # BF16 non-equilibrium form (precision 2)
+        b16 = measure(torch, w, 2, args.steps, args.warmup, args.pre_steps)
+        forms["bf16neq_1024x1024_nq16"] = form_entry(b16, main64)
+        forms["bf16neq_1024x1024_nq16"]["speedup_vs_fp32"] = round(b16["mlups"] / f32["mlups"], 3)
+        b16l = measure(torch, w3, 2, max(5, args.steps // 2), args.warmup, args.pre_steps)
+        forms["bf16neq_4096x4096_nq8"] = form_entry(b16l, None)
+        forms["bf16neq_4096x4096_nq8"]["speedup_vs_fp32"] = round(b16l["mlups"] / f32l["mlups"], 3)
         out["precision_forms"] = forms
     if not args.no_batch:
         out["batched"] = measure_batch(torch, args.batch_instances, max(5, args.steps // 2),

@@ -80,13 +80,18 @@ __device__ __forceinline__ T *uni(T *p) {
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
   return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
 }
+// Accesses go through the global address space explicitly: a generic
+// (flat) pointer would force 64-bit per-lane addresses and FLAT instructions.
+#define GLOBAL_AS __attribute__((address_space(1)))
 template <typename T>
 __device__ __forceinline__ T ldo(const T *base, uint32_t off) {
-  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+  const char GLOBAL_AS *b = (const char GLOBAL_AS *)(base);
+  return *(const T GLOBAL_AS *)(b + off);
 }
 template <typename T>
 __device__ __forceinline__ void sto(T *base, uint32_t off, T v) {
-  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off) = v;
+  char GLOBAL_AS *b = (char GLOBAL_AS *)(base);
+  *(T GLOBAL_AS *)(b + off) = v;
 }
 // Read-only tables (reference values, instance records) are read through the
 // constant address space, which the compiler turns into scalar loads whenever
@@ -296,6 +301,9 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   double Mxx = 0.0, Mxy = 0.0, Myy = 0.0;
   const int nqd = p.nqd;
   const double c2w0 = p.c2P * (1.0 / 3.0), c2w1 = p.c2P * (1.0 / 36.0);
+  const float *momb[5];  // BF16 form: base of each moment component
+#pragma unroll
+  for (int c = 0; c < 5; ++c) momb[c] = NEQ ? uni(a.MOM + (size_t)c * nqd * N) : nullptr;
   const double one_r = 1.0 - p.rP;
   for (int q = slice; q < nqd; q += p.qs) {
     const QNode CONSTANT_AS &qn = cst(qtab)[q];  // scalar loads
@@ -305,8 +313,11 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
       for (int k = 0; k < 25; ++k)
         g[k] = full(ldo(plane(a.XP, qn.plane[k]), osrc[pdir(k)]), rq(rpull, y, q, k));
     } else {
-      // source population: the source node's moments and remainder
+      // source population: the source node's moments and remainder; the
+      // moment planes of one component lie within 2^32 bytes, so a source
+      // Q-node is a 32-bit offset from the component's base
       const uint16_t *XPn = reinterpret_cast<const uint16_t *>(a.XP);
+      const uint32_t qstride = 4u * (uint32_t)N;
 #pragma unroll
       for (int k = 0; k < 25; ++k) {
         const int pk = qn.plane[k];
@@ -314,11 +325,12 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
         const bool bb = (dq < 0) || (dq >= nqd);
         const int qsrc = bb ? q : dq;
         const uint32_t o = osrc[pdir(k)];
+        const uint32_t oq = o + (uint32_t)qsrc * qstride;
         double J[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-          J[c] = PV[k][c] ? (double)ldo(uni(a.MOM + (size_t)((c + 1) * nqd + qsrc) * N), o) : 0.0;
-        const double m0 = (double)ldo(uni(a.MOM + (size_t)qsrc * N), o);
+          J[c] = PV[k][c] ? (double)ldo(momb[c + 1], oq) : 0.0;
+        const double m0 = (double)ldo(momb[0], oq);
         g[k] = rq(rpull, y, q, k) + neq_lin(k, m0, J, bb ? -1.0 : 1.0) +
                from_bf16(ldo(uni(XPn + (size_t)pk * N), o >> 1));
       }

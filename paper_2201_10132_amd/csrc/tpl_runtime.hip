@@ -162,6 +162,9 @@ int derive(const Config &c, Derived &d) {
   }
   d.meq = 0.5 * m;
   d.kappa = d.rhoP0 > 0 ? d.G * d.tau2P / (d.rhoP0 * d.meq) : 0.0;
+  // the BF16 form addresses one moment component's planes with 32-bit offsets
+  if (c.precision == TPL_BF16NEQ && 4LL * d.nqd * c.nx * c.ny >= (1LL << 32))
+    return fail(TPL_EINVAL, "lattice too large for the BF16 form (4 nqd nx ny >= 2^32)");
   return TPL_OK;
 }
 
