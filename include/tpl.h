@@ -64,7 +64,8 @@ enum {
  *                linear equilibrium of those moments; the moments are stored
  *                net of the rounded remainders' moments, so density and
  *                fluxes are exact to FP32 (74 bytes per (r, Q)-node against
- *                104 (FP32) and 208 (FP64)) */
+ *                104 (FP32) and 208 (FP64)); needs nx ny even and
+ *                70 nx ny < 2^32; bytes_XP counts remainders and moments */
 enum { TPL_FP64 = 0, TPL_FP32 = 1, TPL_BF16NEQ = 2 };
 enum { TPL_SOLVENT = 0, TPL_POLYMER = 1 };
 

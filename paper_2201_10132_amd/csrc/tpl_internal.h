@@ -29,13 +29,15 @@ enum Field : int {
 // velocity k the plane (k' nqd + q') of the population it is pulled from:
 // k' = k, q' = the node at Q - Qdot_k when that node is in the disk,
 // otherwise k' = the reversed-Qdot velocity and q' = this node
-// (bounce-back on the Q-circle).
+// (bounce-back on the Q-circle).  qnb[d]: the node at Q - c_d for the nine
+// D2Q9 directions c_d of a Q-velocity, or -1 outside the disk.
 struct alignas(16) QNode {
   double qx, qy, fx, fy;
   int plane[25];
-  int pad[3];
+  int qnb[9];
+  int pad[2];
 };
-static_assert(sizeof(QNode) == 144, "QNode layout");
+static_assert(sizeof(QNode) == 176, "QNode layout");
 
 struct StepParams {
   int nx, ny, nqd, qs;  // lattice, Q-nodes, Q-slices per r-tile
@@ -58,8 +60,9 @@ template <typename T>
 struct StateT {
   T *XS, *XP, *PSI;
   double *FLD;
-  // BF16 non-equilibrium form only: XP holds BF16 (uint16) remainders and MOM
-  // the FP32 moments [5][nqd][N] (m0, J^r_x, J^r_y, J^Q_x, J^Q_y)
+  // BF16 non-equilibrium form: XP holds one 70 N-byte record per Q-node:
+  // the BF16 (uint16) remainders [25][N], then the FP32 moments [5][N]
+  // (m0, J^r_x, J^r_y, J^Q_x, J^Q_y).  MOM is unused (kept null).
   float *MOM;
 };
 using StateView = StateT<double>;

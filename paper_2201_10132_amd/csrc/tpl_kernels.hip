@@ -301,9 +301,6 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   double Mxx = 0.0, Mxy = 0.0, Myy = 0.0;
   const int nqd = p.nqd;
   const double c2w0 = p.c2P * (1.0 / 3.0), c2w1 = p.c2P * (1.0 / 36.0);
-  const float *momb[5];  // BF16 form: base of each moment component
-#pragma unroll
-  for (int c = 0; c < 5; ++c) momb[c] = NEQ ? uni(a.MOM + (size_t)c * nqd * N) : nullptr;
   const double one_r = 1.0 - p.rP;
   for (int q = slice; q < nqd; q += p.qs) {
     const QNode CONSTANT_AS &qn = cst(qtab)[q];  // scalar loads
@@ -313,27 +310,53 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
       for (int k = 0; k < 25; ++k)
         g[k] = full(ldo(plane(a.XP, qn.plane[k]), osrc[pdir(k)]), rq(rpull, y, q, k));
     } else {
-      // source population: the source node's moments and remainder; the
-      // moment planes of one component lie within 2^32 bytes, so a source
-      // Q-node is a 32-bit offset from the component's base
-      const uint16_t *XPn = reinterpret_cast<const uint16_t *>(a.XP);
-      const uint32_t qstride = 4u * (uint32_t)N;
+      // source population: the source node's moments and remainder.  One
+      // Q-node's record holds its 25 remainder planes (BF16) then its 5
+      // moment planes (FP32), so the nine Q-neighbours' records are nine
+      // bases and every load is a 32-bit offset from one of them.  Loads are
+      // issued in two batches, each in full before its values are used;
+      // remainders are read as aligned dwords (16-bit loads into register
+      // halves would chain one load behind the other).
+      const char *rec[9];
+      const uint32_t n2 = 2u * (uint32_t)N, n4 = 4u * (uint32_t)N, mo = 50u * (uint32_t)N;
 #pragma unroll
-      for (int k = 0; k < 25; ++k) {
-        const int pk = qn.plane[k];
-        const int dq = pk - k * nqd;                 // in [0, nqd): no bounce-back
-        const bool bb = (dq < 0) || (dq >= nqd);
-        const int qsrc = bb ? q : dq;
-        const uint32_t o = osrc[pdir(k)];
-        const uint32_t oq = o + (uint32_t)qsrc * qstride;
-        double J[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          J[c] = PV[k][c] ? (double)ldo(momb[c + 1], oq) : 0.0;
-        const double m0 = (double)ldo(momb[0], oq);
-        g[k] = rq(rpull, y, q, k) + neq_lin(k, m0, J, bb ? -1.0 : 1.0) +
-               from_bf16(ldo(uni(XPn + (size_t)pk * N), o >> 1));
+      for (int d = 0; d < 9; ++d) {
+        const int qq = qn.qnb[d] >= 0 ? qn.qnb[d] : q;
+        rec[d] = uni(reinterpret_cast<const char *>(a.XP) + (size_t)qq * 70 * N);
       }
+      auto pull = [&](auto K0, auto K1) {
+        constexpr int k0 = decltype(K0)::value, k1 = decltype(K1)::value;
+        float lm0[k1 - k0], lj[k1 - k0][2];
+        uint32_t ln[k1 - k0];
+#pragma unroll
+        for (int k = k0; k < k1; ++k) {
+          const int d = dir9(PV[k][2], PV[k][3]);
+          const bool bb = qn.qnb[d] < 0;
+          const uint32_t o = osrc[pdir(k)];
+          const uint32_t on = (uint32_t)(bb ? kstar(k) : k) * n2 + (o >> 1);
+          const uint32_t *rw = reinterpret_cast<const uint32_t *>(rec[d]);
+          const float *rf = reinterpret_cast<const float *>(rec[d]);
+          ln[k - k0] = ldo(rw, on & ~3u) >> ((on & 2u) * 8u);
+          lm0[k - k0] = ldo(rf, mo + o);
+          int j = 0;
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (PV[k][c]) lj[k - k0][j++] = ldo(rf, mo + (uint32_t)(c + 1) * n4 + o);
+        }
+#pragma unroll
+        for (int k = k0; k < k1; ++k) {
+          const bool bb = qn.qnb[dir9(PV[k][2], PV[k][3])] < 0;
+          double J[4] = {0.0, 0.0, 0.0, 0.0};
+          int j = 0;
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (PV[k][c]) J[c] = (double)lj[k - k0][j++];
+          g[k] = rq(rpull, y, q, k) + neq_lin(k, (double)lm0[k - k0], J, bb ? -1.0 : 1.0) +
+                 from_bf16((uint16_t)ln[k - k0]);
+        }
+      };
+      pull(std::integral_constant<int, 0>{}, std::integral_constant<int, 13>{});
+      pull(std::integral_constant<int, 13>{}, std::integral_constant<int, 25>{});
     }
     double psi = 0.0, Jrx = 0.0, Jry = 0.0, JQx = 0.0, JQy = 0.0;
 #pragma unroll
@@ -389,11 +412,14 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
         uint16_t nb[25];
         float m[5];
         neq_encode(g, nb, m);
+        char *rw = uni(reinterpret_cast<char *>(b.XP) + (size_t)q * 70 * N);
+        const uint32_t n2 = 2u * (uint32_t)N, n4 = 4u * (uint32_t)N, mo = 50u * (uint32_t)N;
 #pragma unroll
-        for (int c = 0; c < 5; ++c) sto(uni(b.MOM + (size_t)(c * nqd + q) * N), oR, m[c]);
-        uint16_t *XPw = reinterpret_cast<uint16_t *>(b.XP);
+        for (int c = 0; c < 5; ++c)
+          sto(reinterpret_cast<float *>(rw), mo + (uint32_t)c * n4 + oR, m[c]);
 #pragma unroll
-        for (int k = 0; k < 25; ++k) sto(uni(XPw + (size_t)(k * nqd + q) * N), oR >> 1, nb[k]);
+        for (int k = 0; k < 25; ++k)
+          sto(reinterpret_cast<uint16_t *>(rw), (uint32_t)k * n2 + (oR >> 1), nb[k]);
       }
     }
     Mxx += psi * qn.qx * qn.fx;
@@ -562,16 +588,17 @@ __global__ void k_neq_decode(int nqd, long long N, StateT<float> a, float *__res
   if (j >= N * nqd) return;
   const int q = (int)(j / N);
   const long long r = j - (long long)q * N;
-  const uint16_t *n = reinterpret_cast<const uint16_t *>(a.XP);
+  const char *rec = reinterpret_cast<const char *>(a.XP) + (size_t)q * 70 * N;
+  const uint16_t *n = reinterpret_cast<const uint16_t *>(rec);
+  const float *mom = reinterpret_cast<const float *>(rec + 50 * N);
   double J[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) J[c] = (double)a.MOM[(size_t)((c + 1) * nqd + q) * N + r];
-  const double m0 = (double)a.MOM[(size_t)q * N + r];
+  for (int c = 0; c < 4; ++c) J[c] = (double)mom[(size_t)(c + 1) * N + r];
+  const double m0 = (double)mom[r];
 #pragma unroll
-  for (int k = 0; k < 25; ++k) {
-    const size_t i = (size_t)(k * nqd + q) * N + r;
-    dev[i] = (float)(neq_lin(k, m0, J, 1.0) + from_bf16(n[i]));
-  }
+  for (int k = 0; k < 25; ++k)
+    dev[(size_t)(k * nqd + q) * N + r] =
+        (float)(neq_lin(k, m0, J, 1.0) + from_bf16(n[(size_t)k * N + r]));
 }
 
 __global__ void k_neq_encode(int nqd, long long N, const float *__restrict__ dev,
@@ -580,17 +607,19 @@ __global__ void k_neq_encode(int nqd, long long N, const float *__restrict__ dev
   if (j >= N * nqd) return;
   const int q = (int)(j / N);
   const long long r = j - (long long)q * N;
-  uint16_t *n = reinterpret_cast<uint16_t *>(a.XP);
   double d[25];
 #pragma unroll
   for (int k = 0; k < 25; ++k) d[k] = (double)dev[(size_t)(k * nqd + q) * N + r];
   uint16_t nb[25];
   float m[5];
   neq_encode(d, nb, m);
+  char *rec = reinterpret_cast<char *>(a.XP) + (size_t)q * 70 * N;
+  float *mom = reinterpret_cast<float *>(rec + 50 * N);
+  uint16_t *nr = reinterpret_cast<uint16_t *>(rec);
 #pragma unroll
-  for (int c = 0; c < 5; ++c) a.MOM[(size_t)(c * nqd + q) * N + r] = m[c];
+  for (int c = 0; c < 5; ++c) mom[(size_t)c * N + r] = m[c];
 #pragma unroll
-  for (int k = 0; k < 25; ++k) n[(size_t)(k * nqd + q) * N + r] = nb[k];
+  for (int k = 0; k < 25; ++k) nr[(size_t)k * N + r] = nb[k];
 }
 
 hipError_t launch_neq_decode(int nqd, long long N, StateT<float> a, float *dev, hipStream_t s) {

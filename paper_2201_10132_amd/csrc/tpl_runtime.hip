@@ -149,7 +149,13 @@ int derive(const Config &c, Derived &d) {
           ks = j;
       n.plane[k] = src >= 0 ? k * d.nqd + src : ks * d.nqd + q;
     }
-    n.pad[0] = n.pad[1] = n.pad[2] = 0;
+    static const int C9[9][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1},
+                                 {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+    for (int dd = 0; dd < 9; ++dd) {
+      const int sa = ia[q] - C9[dd][0], sb = ib[q] - C9[dd][1];
+      n.qnb[dd] = (sa >= 0 && sb >= 0 && sa < nq && sb < nq) ? idx[sb * nq + sa] : -1;
+    }
+    n.pad[0] = n.pad[1] = 0;
     const double w = c.spring == 0 ? std::pow(1.0 - q2 / bs2, 0.5 * c.b)
                                    : std::exp(-0.5 * q2 / s2);
     d.peq[q] = w;
@@ -162,9 +168,10 @@ int derive(const Config &c, Derived &d) {
   }
   d.meq = 0.5 * m;
   d.kappa = d.rhoP0 > 0 ? d.G * d.tau2P / (d.rhoP0 * d.meq) : 0.0;
-  // the BF16 form addresses one moment component's planes with 32-bit offsets
-  if (c.precision == TPL_BF16NEQ && 4LL * d.nqd * c.nx * c.ny >= (1LL << 32))
-    return fail(TPL_EINVAL, "lattice too large for the BF16 form (4 nqd nx ny >= 2^32)");
+  // the BF16 form addresses one Q-node's 25 remainder planes (and 5 moment
+  // planes) with 32-bit offsets and reads remainders as aligned dwords
+  if (c.precision == TPL_BF16NEQ && (70LL * c.nx * c.ny >= (1LL << 32) || (c.nx * c.ny) % 2))
+    return fail(TPL_EINVAL, "the BF16 form needs nx ny even and 70 nx ny < 2^32");
   return TPL_OK;
 }
 
@@ -297,7 +304,8 @@ int alloc_state(tpl_ctx *x) {
   B.nXP = state_elems(x, 1);
   B.nPSI = state_elems(x, 2);
   B.nFLD = state_elems(x, 3);
-  B.nMOM = neq(x) ? 5 * B.nPSI : 0;
+  B.nMOM = 0;
+  if (neq(x)) B.nXP = 35 * B.nPSI;  // per Q-node: 25 BF16 + 5 FP32 planes (70 N bytes)
   B.esize = elem_size(x);
   B.xsize = xp_size(x);
   void **ptrs[5] = {&B.XS, &B.XP, &B.PSI, reinterpret_cast<void **>(&B.FLD),
@@ -736,7 +744,9 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
   const double N = (double)x->c.nx * x->c.ny;
   const double es = x->c.precision == TPL_FP64 ? 8.0 : 4.0;
   const double xs = x->c.precision == TPL_FP64 ? 8.0 : x->c.precision == TPL_FP32 ? 4.0 : 2.0;
-  const double ms = x->c.precision == TPL_BF16NEQ ? 5.0 * 4.0 : 0.0;  // MOM per (r, Q)
+  // BF16 form: XP records carry the remainders and the 5 FP32 moments
+  const double ms = 0.0;
+  const double xq = x->c.precision == TPL_BF16NEQ ? 70.0 : 25.0 * xs;  // XP bytes per (r, Q)
   struct {
     const char *n;
     double v;
@@ -749,15 +759,15 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
       {"R", d.R}, {"DQ", d.DQ}, {"F0", d.F0}, {"kappa", d.kappa},
       {"meq", d.meq}, {"Sc", d.Sc}, {"rhoS0", d.rhoS0}, {"rhoP0", d.rhoP0},
       {"step", (double)x->step},
-      {"bytes_XS", 2.0 * es * 9 * N}, {"bytes_XP", 2.0 * xs * 25 * d.nqd * N},
+      {"bytes_XS", 2.0 * es * 9 * N}, {"bytes_XP", 2.0 * xq * d.nqd * N},
       {"bytes_PSI", 2.0 * es * d.nqd * N}, {"bytes_FLD", 16.0 * NF * N},
       {"bytes_MOM", 2.0 * ms * d.nqd * N},
-      {"bytes_state", 2.0 * N * (es * (9 + d.nqd) + xs * 25.0 * d.nqd + ms * d.nqd + 8.0 * NF)},
+      {"bytes_state", 2.0 * N * (es * (9 + d.nqd) + xq * d.nqd + ms * d.nqd + 8.0 * NF)},
       // algorithmic HBM bytes of one step: populations read + written,
       // lagged psi written + read, lagged per-node fields written + read
       // (BF16 form: remainders and FP32 fluxes read + written once)
       {"bytes_per_step",
-       N * (2.0 * es * (9 + d.nqd) + 2.0 * (xs * 25.0 + ms) * d.nqd + 8.0 * 2.0 * NF)},
+       N * (2.0 * es * (9 + d.nqd) + 2.0 * (xq + ms) * d.nqd + 8.0 * 2.0 * NF)},
       {"kernel_ms", x->kernel_ms}, {"kernel_launches", (double)x->kernel_launches},
       {"qsplit_used", (double)x->qs_used},
   };

@@ -145,11 +145,13 @@ def test_bf16_form_bytes_and_rejections():
     N, nqd = 64 * 64, t.nqd
     # FP32 solvent and psi, BF16 remainders + 5 FP32 moments (74 bytes per (r, Q))
     assert t.query("bytes_per_step") == N * (2 * 4 * (9 + nqd) + 2 * (2 * 25 + 20) * nqd + 16 * 18)
-    assert t.query("bytes_XP") == 2 * 2 * 25 * nqd * N
+    assert t.query("bytes_XP") == 2 * 70 * nqd * N
     with pytest.raises(P.TplError):
         t.adopt_buffers([0, 0, 0, 0], [1, 1, 1, 1])
     with pytest.raises(P.TplError):
         P.Batch([dict(nx=16, ny=16, Re=20.0, Wi=0.5, beta=0.8)], precision=P.TPL_BF16NEQ)
     with pytest.raises(P.TplError):
         t.set_param("precision", 3)
+    with pytest.raises(P.TplError):  # odd node count
+        P.Tpl(13, 9, 20.0, 0.5, 0.8, nq=4, precision=P.TPL_BF16NEQ)
     t.close()

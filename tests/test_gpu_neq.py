@@ -50,7 +50,7 @@ def _bound(n, states, base):
     return 4 * n * (2 * EPS_BF16 * rem + 4 * EPS32 * dev)
 
 
-@pytest.mark.parametrize("nx,ny,nq,spring", [(64, 16, 6, 0), (13, 9, 4, 1), (128, 8, 4, 0)])
+@pytest.mark.parametrize("nx,ny,nq,spring", [(64, 16, 6, 0), (14, 9, 4, 1), (128, 8, 4, 0)])
 def test_neq_parity_with_oracle(nx, ny, nq, spring):
     t, o = make_pair(nx, ny, 20.0, 0.5, 0.8, 2 if ny >= 8 else 1, nq=nq, spring=spring,
                      pre_steps=300, pert_modes=1)
