@@ -115,6 +115,8 @@ def main():
         "roofline": roofline(main64, traffic_bytes(args.traffic_file)),
         "mqlups": round(main64["mlups"] * main64["nqd"], 1),
         "kernel_ms": round(main64["kernel_ms"], 4),
+        "launch": {"qsplit": int(main64["qsplit"]), "group": main64["group"],
+                   "tune_ms": main64["tune_ms"]},
         "init_s": round(main64["init_s"], 2),
         "conservation": main64["conservation"],
         "amplitude": main64["amplitude"],
@@ -185,10 +187,13 @@ def measure(torch, w, precision, steps, warmup, pre_steps) -> dict:
                kernel_ms=ev0.elapsed_time(ev1) / steps, init_s=init_s, nqd=t.nqd,
                bytes_step=t.query("bytes_per_step"), amplitude=d1["amplitude"],
                qsplit=t.query("qsplit_used"),
+               group=[int(t.query(k)) for k in ("group_x_used", "group_y_used", "group_sync_used")],
+               tune_ms=round(t.query("tune_ms"), 1),
                conservation={"mass_S": abs(d1["mass_S"] / d0["mass_S"] - 1),
                              "mass_P": abs(d1["mass_P"] / d0["mass_P"] - 1)})
     print(f"# precision={precision} {w['nx']}x{w['ny']} nq={w['nq']}: init {init_s:.1f} s, "
-          f"{res['kernel_ms']:.3f} ms/step, qsplit={res['qsplit']:.0f}", file=sys.stderr, flush=True)
+          f"{res['kernel_ms']:.3f} ms/step, qsplit={res['qsplit']:.0f} group={res['group']}",
+          file=sys.stderr, flush=True)
     t.close()
     return res
 
@@ -241,6 +246,8 @@ def measure_batch(torch, n, steps, warmup, pre_steps, obo_steps) -> dict:
     status = b.status()
     res["unstable_instances"] = [i for i, u in enumerate(status) if u]
     active = [i for i, u in enumerate(status) if not u]
+    for i in active:  # untimed: each lattice's first step tunes its own launch shape
+        b.instance(i).step(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in active:
@@ -311,7 +318,7 @@ def roofline(m, traffic):
 def form_entry(m, ref64):
     e = {"mlups": round(m["mlups"], 3), "ms_per_step": round(m["wall_ms"], 4),
          "roofline": roofline(m, None), "conservation": m["conservation"],
-         "amplitude": m["amplitude"]}
+         "amplitude": m["amplitude"], "launch": {"qsplit": int(m["qsplit"]), "group": m["group"]}}
     if ref64 is not None:
         e["speedup_vs_fp64"] = round(m["mlups"] / ref64["mlups"], 3)
         e["amplitude_rel_err_vs_fp64"] = abs(m["amplitude"] / ref64["amplitude"] - 1)

@@ -105,7 +105,8 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
                     tpl_forcing forcing);
 
 /* Set a parameter before tpl_init (TPL_ESTATE afterwards, except for the
- * launch/timing knobs qsplit and time_kernels, which may be set at any time;
+ * launch/timing knobs qsplit, group_x, group_y, group_sync, autotune and
+ * time_kernels, which may be set at any time and change no result;
  * TPL_EINVAL for an unknown key or a value out of range).  Keys and defaults:
  *   nq 16         Q points per axis (even, 4..48)
  *   spring 0      0 = FENE (Warner), 1 = Hookean
@@ -121,6 +122,16 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *   pre_steps -1  base-state column steps (-1 = 5 max(l^2/nu, lambda))
  *   qsplit 0      Q-slices per r-tile in the step kernel: 0 (automatic),
  *                 1, 2, 4 or 8 (other values round down)
+ *   group_x 1, group_y 1, group_sync 0
+ *                 tile groups of the step kernel: group_x x group_y tiles of
+ *                 64 nodes (group_y consecutive rows) per workgroup, one wave
+ *                 each, group_sync 1 = a barrier per Q-node keeps them
+ *                 together; product at most 8; used with one Q-slice and
+ *                 nx a multiple of 64 group_x, ny of group_y (else ignored);
+ *                 a product > 1 overrides the autotuner
+ *   autotune 1    1 = on the first tpl_step, time the tile-group shapes of
+ *                 the full lattice (a few idempotent launches; tune_ms) and
+ *                 keep the fastest; every shape gives bitwise the same step
  *   time_kernels 0  1 = time every step-kernel launch with HIP events
  * Any parameter also fixes the derived values read by tpl_query. */
 int tpl_set_param(tpl_ctx *ctx, const char *key, double value);
@@ -129,8 +140,9 @@ int tpl_set_param(tpl_ctx *ctx, const char *key, double value);
  * and nx ny nqd Re Wi beta u0 periods kf l nu nuS G tau1S tau2S tau1P tau2P
  * lambda_eff sigma R DQ F0 kappa meq Sc rhoS0 rhoP0 step bytes_XS bytes_XP
  * bytes_PSI bytes_FLD bytes_MOM bytes_state bytes_per_step
- * kernel_ms kernel_launches qsplit_used.  Host only; TPL_EINVAL for an
- * unknown key. */
+ * kernel_ms kernel_launches qsplit_used group_x_used group_y_used
+ * group_sync_used tune_ms (the shape of the last tpl_step's launches).  Host
+ * only; TPL_EINVAL for an unknown key. */
 int tpl_query(const tpl_ctx *ctx, const char *key, double *out);
 
 /* Bind a hipStream_t (NULL = the null stream).  All device work of the

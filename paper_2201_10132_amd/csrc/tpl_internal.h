@@ -44,7 +44,8 @@ struct StepParams {
   int ntiles;           // r-tiles of 64 nodes
   int tiles_per_xcd;    // XCD-contiguous tile mapping (0 = off)
   int y0;               // absolute row of local row 0 (forcing phase)
-  int pad;
+  int wg;               // tile groups (qs == 1 only): tiles along x in bits 0-7,
+                        // rows in bits 8-15, bit 16: barrier per Q-node; 0 = off
   long long N;  // nx * ny
   double aS, aP;         // 1 / (2 tau2 + 1) per species
   double tau2S, tau2P;

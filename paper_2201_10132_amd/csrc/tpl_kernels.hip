@@ -194,7 +194,7 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   constexpr bool F32 = std::is_same<T, float>::value;
   constexpr uint32_t SZ = sizeof(T);
   const int lane = threadIdx.x & 63;
-  const int slice = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int slice = p.qs > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
   const long long N = p.N;
   const long long rr = (long long)tile * 64 + lane;
   const bool active = rr < N;
@@ -302,7 +302,9 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   const int nqd = p.nqd;
   const double c2w0 = p.c2P * (1.0 / 3.0), c2w1 = p.c2P * (1.0 / 36.0);
   const double one_r = 1.0 - p.rP;
+  const bool qsync = (p.wg >> 16) & 1;  // only with qs == 1: equal trip counts
   for (int q = slice; q < nqd; q += p.qs) {
+    if (qsync) __syncthreads();  // keep the group's waves on the same Q-node
     const QNode CONSTANT_AS &qn = cst(qtab)[q];  // scalar loads
     double g[25];
     if constexpr (!NEQ) {
@@ -468,8 +470,20 @@ __global__ void __launch_bounds__(MAXT)
            const float *__restrict__ rspull, const float *__restrict__ rsstore,
            const QNode *__restrict__ qtab) {
   extern __shared__ double red[];  // [qs][12][64]
-  const int tile = xcd_tile(blockIdx.x, p.tiles_per_xcd);
-  if (tile >= p.ntiles) return;  // whole workgroup leaves together
+  int tile;
+  if (p.wg == 0) {
+    tile = xcd_tile(blockIdx.x, p.tiles_per_xcd);
+    if (tile >= p.ntiles) return;  // whole workgroup leaves together
+  } else {
+    // a group of gx x gy tiles (one wave each) of gy consecutive rows;
+    // tiles_per_xcd counts groups
+    const int gx = p.wg & 255, gy = (p.wg >> 8) & 255;
+    const int grp = xcd_tile(blockIdx.x, p.tiles_per_xcd);
+    if (grp * gx * gy >= p.ntiles) return;  // whole workgroup leaves together
+    const int tpr = p.nx >> 6, gpr = tpr / gx;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    tile = ((grp / gpr) * gy + w / gx) * tpr + (grp % gpr) * gx + w % gx;
+  }
   step_tile<T, ROWTILE, NEQ>(p, a, b, rpull, rstore, rpsi, rspull, rsstore, qtab, tile, red);
 }
 
@@ -503,7 +517,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)
     TPL_LD(c2S) TPL_LD(rS) TPL_LD(c1P) TPL_LD(c2P) TPL_LD(rP) TPL_LD(kappa) TPL_LD(DQ)
     TPL_LD(F0) TPL_LD(kf) TPL_LD(src)
 #undef TPL_LD
-    pp.pad = 0;
+    pp.wg = 0;
     const int rd = parity ^ d.cur0;
     const StateT<T> a{static_cast<T *>(d.XS[rd]), static_cast<T *>(d.XP[rd]),
                       static_cast<T *>(d.PSI[rd]), d.FLD[rd]};
@@ -545,13 +559,15 @@ template hipError_t launch_step_batch<float>(const InstDev *, int, int, int, int
 template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
                        StepRef r, const QNode *qtab, hipStream_t s, bool neq) {
-  const int grid = p.tiles_per_xcd > 0 ? 8 * p.tiles_per_xcd : p.ntiles;
+  const int gsize = p.wg ? (p.wg & 255) * ((p.wg >> 8) & 255) : 1;
+  const int grid = p.tiles_per_xcd > 0 ? 8 * p.tiles_per_xcd : p.ntiles / gsize;
   const size_t lds = p.qs > 1 ? (size_t)p.qs * 12 * 64 * sizeof(double) : 0;
   const bool rowtile = (p.nx % 64) == 0;
-  const dim3 g(grid), blk(64 * p.qs);
+  if (p.wg && (p.qs != 1 || !rowtile || gsize > 8)) return hipErrorInvalidValue;
+  const dim3 g(grid), blk(64 * p.qs * gsize);
 #define TPL_STEP_ARGS p, a, b, r.pull, r.store, r.psi, r.spull, r.sstore, qtab
 #define TPL_STEP_LAUNCH(NEQ)                                                     \
-  if (p.qs <= 4) {                                                               \
+  if (p.qs * gsize <= 4) {                                                       \
     if (rowtile)                                                                 \
       hipLaunchKernelGGL((k_step<T, 256, true, NEQ>), g, blk, lds, s, TPL_STEP_ARGS);  \
     else                                                                         \

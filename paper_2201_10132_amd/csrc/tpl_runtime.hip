@@ -42,6 +42,7 @@ struct Config {
   double force_scale = 1.0, lambda_set = 0.0, drift_cap = 0.1;
   long long pre_steps = -1;
   int qsplit = 0, time_kernels = 0;
+  int group_x = 1, group_y = 1, group_sync = 0, autotune = 1;
 };
 
 struct Derived {
@@ -215,7 +216,10 @@ struct tpl_ctx {
   size_t scratch_n = 0;
   double kernel_ms = 0.0;
   long long kernel_launches = 0;
-  int qs_used = 0;
+  int qs_used = 0, wg_used = 0;
+  bool tuned = false;  // tile-group shape timed (first step)
+  int wg_tuned = 0;    // its StepParams::wg (0: one tile per workgroup)
+  double tune_ms = 0.0;
   // extra body force [2][N] (a caller's field or an attached correction's)
   double *src_d = nullptr;
   bool src_on = false;
@@ -239,6 +243,20 @@ size_t state_elems(const tpl_ctx *x, int which) {
   }
 }
 
+// Tile groups: gx x gy tiles of 64 nodes (gy consecutive rows) per
+// workgroup, one wave each, optionally kept on the same Q-node by a barrier,
+// so that the group's overlapping stencil reads (x-shifted pulls across tile
+// edges, psi of the rows above and below) meet in the caches.  Only for one
+// Q-slice and whole tiles per row; returns false (p unchanged) otherwise.
+bool set_group(StepParams &p, int gx, int gy, int sync) {
+  if (p.qs != 1 || gx * gy < 2 || gx * gy > 8 || p.nx % 64 || (p.nx / 64) % gx || p.ny % gy)
+    return false;
+  const int groups = p.ntiles / (gx * gy);
+  p.wg = gx | (gy << 8) | (sync ? 1 << 16 : 0);
+  p.tiles_per_xcd = groups >= 64 ? (groups + 7) / 8 : 0;
+  return true;
+}
+
 StepParams make_step_params(const tpl_ctx *x, int nx, int ny, int qs_req) {
   StepParams p{};
   const Derived &d = x->d;
@@ -256,6 +274,11 @@ StepParams make_step_params(const tpl_ctx *x, int nx, int ny, int qs_req) {
   qs = qs >= 8 ? 8 : qs >= 4 ? 4 : qs >= 2 ? 2 : 1;
   p.qs = qs;
   p.tiles_per_xcd = p.ntiles >= 64 ? (p.ntiles + 7) / 8 : 0;
+  p.wg = 0;
+  if (x->c.group_x * x->c.group_y > 1)
+    set_group(p, x->c.group_x, x->c.group_y, x->c.group_sync);
+  else if (x->tuned && nx == x->c.nx && ny == x->c.ny && x->wg_tuned)
+    set_group(p, x->wg_tuned & 255, (x->wg_tuned >> 8) & 255, (x->wg_tuned >> 16) & 1);
   p.y0 = 0;
   p.aS = 1.0 / (2.0 * d.tau2S + 1.0);
   p.aP = 1.0 / (2.0 * d.tau2P + 1.0);
@@ -440,6 +463,58 @@ int run_steps(tpl_ctx *x, const Buffers &B, int nx, int ny, int *cur,
     HIPCHK(hipEventDestroy(e1));
   }
   return TPL_OK;
+}
+
+// Times the tile-group shapes of the full lattice's step and keeps the
+// fastest (every shape computes bitwise the same step).  The timed launches
+// read the current half and write the other without swapping, so repeating
+// them changes nothing; the first launch of each shape is a warm-up.
+int tune_groups(tpl_ctx *x) {
+  x->tuned = true;
+  x->wg_tuned = 0;
+  StepParams p0 = make_step_params(x, x->c.nx, x->c.ny, x->c.qsplit);
+  if (p0.qs != 1 || p0.wg != 0 || x->c.group_x * x->c.group_y > 1) return TPL_OK;
+  const Buffers &B = x->buf;
+  const bool neq = B.xsize == 2;  // one wave per SIMD: at most 4 waves per group
+  const int cand[][3] = {{1, 1, 0}, {4, 1, 1}, {2, 2, 1}, {8, 1, 0}, {8, 1, 1}, {4, 2, 1}};
+  const StepRef ref =
+      B.esize == 4 ? step_ref(x) : StepRef{nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 0.f;
+  int rc = TPL_OK;
+  for (const auto &c : cand) {
+    StepParams p = p0;
+    if (c[0] * c[1] > 1 && (!set_group(p, c[0], c[1], c[2]) || (neq && c[0] * c[1] > 4)))
+      continue;
+    auto launch = [&]() {
+      return B.esize == 4
+                 ? launch_step<float>(p, B.half<float>(x->cur), B.half<float>(1 - x->cur), ref,
+                                      x->qtab_d, x->stream, neq)
+                 : launch_step<double>(p, B.half<double>(x->cur), B.half<double>(1 - x->cur),
+                                       ref, x->qtab_d, x->stream);
+    };
+    hipError_t e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e0, x->stream);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, x->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      rc = fail(TPL_EHIP, std::string("tile-group tuning: ") + hipGetErrorString(e));
+      break;
+    }
+    x->tune_ms += ms * 1.5;
+    if (best == 0.f || ms < best) {
+      best = ms;
+      x->wg_tuned = p.wg;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 // SplitMix64 (Steele, Lea & Flood 2014) and the uniform double it yields.
@@ -661,6 +736,10 @@ const Key kKeys[] = {
     {"pre_steps", nullptr, nullptr, &Config::pre_steps},
     {"qsplit", nullptr, &Config::qsplit, nullptr},
     {"time_kernels", nullptr, &Config::time_kernels, nullptr},
+    {"group_x", nullptr, &Config::group_x, nullptr},
+    {"group_y", nullptr, &Config::group_y, nullptr},
+    {"group_sync", nullptr, &Config::group_sync, nullptr},
+    {"autotune", nullptr, &Config::autotune, nullptr},
     {"u0", &Config::u0, nullptr, nullptr},
     {"periods", nullptr, &Config::periods, nullptr},
 };
@@ -700,7 +779,8 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
 int tpl_set_param(tpl_ctx *x, const char *key, double v) {
   if (!x || !key) return fail(TPL_EINVAL, "null argument");
   // launch and timing knobs change no state and may be set at any time
-  const bool runtime_knob = !std::strcmp(key, "qsplit") || !std::strcmp(key, "time_kernels");
+  const bool runtime_knob = !std::strcmp(key, "qsplit") || !std::strcmp(key, "time_kernels") ||
+                            !std::strncmp(key, "group_", 6) || !std::strcmp(key, "autotune");
   if (x->inited && !runtime_knob)
     return fail(TPL_ESTATE, "parameters are fixed after tpl_init");
   Config c = x->c;
@@ -720,6 +800,8 @@ int tpl_set_param(tpl_ctx *x, const char *key, double v) {
   if (c.precision != TPL_FP64 && c.precision != TPL_FP32 && c.precision != TPL_BF16NEQ)
     return fail(TPL_EINVAL, "precision must be TPL_FP64, TPL_FP32 or TPL_BF16NEQ");
   if (c.qsplit < 0 || c.qsplit > 8) return fail(TPL_EINVAL, "qsplit must be in [0,8]");
+  if (c.group_x < 1 || c.group_y < 1 || c.group_x * c.group_y > 8)
+    return fail(TPL_EINVAL, "group_x * group_y must be in [1,8]");
   if (!(c.drift_cap >= 0)) return fail(TPL_EINVAL, "drift_cap must be >= 0");
   if (runtime_knob) {
     x->c = c;
@@ -770,6 +852,10 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
        N * (2.0 * es * (9 + d.nqd) + 2.0 * (xq + ms) * d.nqd + 8.0 * 2.0 * NF)},
       {"kernel_ms", x->kernel_ms}, {"kernel_launches", (double)x->kernel_launches},
       {"qsplit_used", (double)x->qs_used},
+      {"group_x_used", (double)(x->wg_used & 255)},
+      {"group_y_used", (double)((x->wg_used >> 8) & 255)},
+      {"group_sync_used", (double)((x->wg_used >> 16) & 1)},
+      {"tune_ms", x->tune_ms},
   };
   for (auto &kv : vals)
     if (std::strcmp(kv.n, key) == 0) {
@@ -836,7 +922,15 @@ int tpl_step(tpl_ctx *x, int64_t n) {
   int rc = check_ready(x);
   if (rc) return rc;
   if (n < 0) return fail(TPL_EINVAL, "n must be >= 0");
-  x->qs_used = make_step_params(x, x->c.nx, x->c.ny, x->c.qsplit).qs;
+  if (!x->tuned && x->c.autotune && n > 0) {
+    rc = tune_groups(x);
+    if (rc) return rc;
+  }
+  {
+    const StepParams p = make_step_params(x, x->c.nx, x->c.ny, x->c.qsplit);
+    x->qs_used = p.qs;
+    x->wg_used = p.wg;
+  }
   if (x->mlp) {  // learned correction: a new source before every step
     for (int64_t i = 0; i < n; ++i) {
       rc = learned_source(x);
@@ -1270,6 +1364,7 @@ InstDev inst_record(tpl_ctx *x, const Buffers &B, int nx, int ny, int qs, int it
   r.p = make_step_params(x, nx, ny, qs);
   r.p.qs = qs;
   r.p.tiles_per_xcd = 0;
+  r.p.wg = 0;
   for (int h = 0; h < 2; ++h) {
     r.XS[h] = static_cast<char *>(B.XS) + h * B.nXS * B.esize;
     r.XP[h] = static_cast<char *>(B.XP) + h * B.nXP * B.esize;

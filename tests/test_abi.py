@@ -155,3 +155,20 @@ def test_bf16_form_bytes_and_rejections():
     with pytest.raises(P.TplError):  # odd node count
         P.Tpl(13, 9, 20.0, 0.5, 0.8, nq=4, precision=P.TPL_BF16NEQ)
     t.close()
+
+
+def test_tile_group_knobs():
+    """Tile-group knobs: launch knobs (settable after init), product of the
+    group sides at most 8; the shape in use is 0 before any step."""
+    t = P.Tpl(128, 64, 60.0, 1.0, 0.7, periods=2, nq=8)
+    with pytest.raises(P.TplError):
+        t.set_param("group_x", 16)
+    t.set_param("group_x", 4)
+    with pytest.raises(P.TplError):
+        t.set_param("group_y", 4)  # 16 waves per group
+    t.set_param("group_y", 2)
+    t.set_param("group_sync", 1)
+    t.set_param("autotune", 0)
+    assert t.query("group_x") == 4 and t.query("group_y") == 2 and t.query("autotune") == 0
+    assert t.query("group_x_used") == 0 and t.query("tune_ms") == 0
+    t.close()
