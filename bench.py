@@ -43,27 +43,38 @@ DEFAULT_PRE_STEPS = 3000
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 
-def cpu_baseline(seconds_target: float = 15.0) -> dict:
+def cpu_baseline(seconds_target: float = 15.0, seconds_1core: float = 8.0) -> dict:
     """The oracle, unchanged, on a 64 x 64 window-sized lattice that carries
-    the 1024^2 workload's parameters (same Q-grid, same per-node work)."""
+    the 1024^2 workload's parameters (same Q-grid, same per-node work):
+    first on every host thread, then on one."""
     import oracle
 
     w = WORKLOAD
-    o = oracle.OracleSim(64, 64, nq=w["nq"], spring=w["spring"], Re=w["Re"], Wi=w["Wi"],
-                         beta=w["beta"], periods=w["periods"], ny_param=w["ny"])
-    o.rest()
-    o.perturb(w["seed"], w["perturbation"] * 100, True)
-    o.step(2)  # warm caches and threads
-    t0 = time.perf_counter()
-    n = 0
-    while time.perf_counter() - t0 < seconds_target:
-        o.step(5)
-        n += 5
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    return {"value": 64 * 64 * n / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+
+    def rate(seconds):
+        o = oracle.OracleSim(64, 64, nq=w["nq"], spring=w["spring"], Re=w["Re"], Wi=w["Wi"],
+                             beta=w["beta"], periods=w["periods"], ny_param=w["ny"])
+        o.rest()
+        o.perturb(w["seed"], w["perturbation"] * 100, True)
+        o.step(1)  # warm caches and threads
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < seconds:
+            o.step(1)
+            n += 1
+        dt = time.perf_counter() - t0
+        return 64 * 64 * n / dt / 1e6, n, dt
+
+    cores = oracle.max_threads()
+    v, n, dt = rate(seconds_target)
+    oracle.set_threads(1)
+    v1, n1, dt1 = rate(seconds_1core)
+    oracle.set_threads(cores)
+    return {"value": v, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle, 64x64 lattice with the 1024^2 workload parameters "
-                      f"(nq=16, 208 Q-nodes, FENE), {n} steps in {dt:.1f} s, OpenMP over rows"}
+                      f"(nq=16, 208 Q-nodes, FENE), {n} steps in {dt:.1f} s, OpenMP over rows",
+            "value_1core": v1,
+            "sample_1core": f"same lattice, 1 thread, {n1} steps in {dt1:.1f} s"}
 
 
 def main():
@@ -77,6 +88,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 form measurements")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched sweep")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned correction")
+    ap.add_argument("--no-growth", action="store_true",
+                    help="skip the growth-rate comparison of the storage forms")
+    ap.add_argument("--growth-steps", type=int, default=2000)
     ap.add_argument("--batch-instances", type=int, default=BATCH["instances"])
     ap.add_argument("--one-by-one-steps", type=int, default=10,
                     help="steps per instance of the one-by-one comparison")
@@ -142,6 +156,9 @@ def main():
         forms["bf16neq_4096x4096_nq8"] = form_entry(b16l, None)
         forms["bf16neq_4096x4096_nq8"]["speedup_vs_fp32"] = round(b16l["mlups"] / f32l["mlups"], 3)
         out["precision_forms"] = forms
+    if not args.no_growth:
+        out["growth_rate"] = measure_growth(torch, dict(w, nq=BATCH["nq"]), args.pre_steps,
+                                            args.growth_steps)
     if not args.no_batch:
         out["batched"] = measure_batch(torch, args.batch_instances, max(5, args.steps // 2),
                                        args.warmup, args.pre_steps, args.one_by_one_steps)
@@ -151,6 +168,10 @@ def main():
             bt = out["batched"]
             if tb is not None:
                 bt["roofline"]["traffic"] = round(tb * bt["bytes_active_fraction"])
+        if "precision_forms" in out:  # (ii) plain FP64 lattice at the sweep's NQ
+            ref = out["precision_forms"]["fp64_1024x1024_nq8"]["mlups"]
+            out["batched"]["speedup_vs_fp64_plain_matched_nq"] = round(
+                out["batched"]["mlups"] / ref, 3)
     if not args.no_learned:
         out["learned"] = measure_learned(torch, args.pre_steps)
     if not args.no_cpu_baseline:
@@ -313,6 +334,43 @@ def roofline(m, traffic):
     achieved = m["bytes_step"] / (m["kernel_ms"] * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+
+def measure_growth(torch, w, pre_steps, steps, every=100):
+    """Growth rate of the perturbation amplitude, gamma = d ln A / dn (least
+    squares over samples every `every` steps from steps/4 on), of the same
+    seeded run stored in FP64, FP32 and BF16 non-equilibrium form; the
+    storage forms' error is stated against the FP64 run."""
+    import numpy as np
+    import paper_2201_10132_amd as P
+
+    n_fit = steps // 4
+    out = {"workload": f"kolmogorov_{w['nx']}x{w['ny']}_nq{w['nq']}", "steps": steps,
+           "sample_every": every, "fit_window": [n_fit, steps], "gamma": {}, "amplitude_end": {}}
+    for name, prec in (("fp64", P.TPL_FP64), ("fp32", P.TPL_FP32), ("bf16neq", P.TPL_BF16NEQ)):
+        t = P.Tpl(w["nx"], w["ny"], w["Re"], w["Wi"], w["beta"], periods=w["periods"],
+                  nq=w["nq"], spring=w["spring"], pre_steps=pre_steps, pert_modes=1,
+                  precision=prec)
+        t.init(seed=w["seed"], perturbation=w["perturbation"])
+        ns, amps = [0], [t.amplitude()]
+        t0 = time.perf_counter()
+        for n in range(every, steps + 1, every):
+            t.step(every)
+            ns.append(n)
+            amps.append(t.amplitude())
+        wall = time.perf_counter() - t0
+        t.close()
+        ns, amps = np.array(ns), np.array(amps)
+        sel = ns >= n_fit
+        out["gamma"][name] = float(np.polyfit(ns[sel], np.log(amps[sel]), 1)[0])
+        out["amplitude_end"][name] = float(amps[-1])
+        print(f"# growth {name}: gamma {out['gamma'][name]:.6e}, A(0) {amps[0]:.4e}, "
+              f"A({steps}) {amps[-1]:.4e}, {wall:.1f} s", file=sys.stderr, flush=True)
+    g64 = out["gamma"]["fp64"]
+    out["gamma_rel_err"] = {k: abs(out["gamma"][k] / g64 - 1) for k in ("fp32", "bf16neq")}
+    out["amplitude_end_rel_err"] = {k: abs(out["amplitude_end"][k] / out["amplitude_end"]["fp64"] - 1)
+                                    for k in ("fp32", "bf16neq")}
+    return out
 
 
 def form_entry(m, ref64):

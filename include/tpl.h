@@ -117,6 +117,9 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *   force_scale 1 multiplies F0
  *   lambda 0      > 0: polymer relaxation time in steps instead of Wi l / u0
  *   drift_cap 0.1 cap on the Q-drift D_Q |F/kT| per step (0 = none)
+ *   drift_relax 1 also cap that drift at drift_relax (2 - omega_P), the
+ *                 damping rate of the polymer's non-conserved moments,
+ *                 omega_P = 2 / (2 tau1_P + 1) (0 = none)
  *   precision 0   TPL_FP64, TPL_FP32 or TPL_BF16NEQ population storage
  *   pert_modes 1  0 = single x-mode, 1 = multimode perturbation
  *   pre_steps -1  base-state column steps (-1 = 5 max(l^2/nu, lambda))

@@ -10,4 +10,4 @@ only compiles it and marshals numpy arrays through ctypes.  ``learned.py``
 holds the FP64 numpy reference of the learned coarse-lattice correction
 (network, training update, restriction, features, momentum source).
 """
-from .oracle import OracleSim, build, lib_path, splitmix64_next  # noqa: F401
+from .oracle import OracleSim, build, lib_path, max_threads, set_threads, splitmix64_next  # noqa: F401

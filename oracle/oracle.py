@@ -39,7 +39,7 @@ class _Config(C.Structure):
                 ("b", C.c_double), ("tau_drag", C.c_double), ("tau_ratio_p", C.c_double),
                 ("force_scale", C.c_double), ("lambda_set", C.c_double),
                 ("ny_param", C.c_int), ("y_offset", C.c_int), ("x_offset", C.c_int),
-                ("nx_param", C.c_int), ("drift_cap", C.c_double)]
+                ("nx_param", C.c_int), ("drift_cap", C.c_double), ("drift_relax", C.c_double)]
 
 
 _DERIVED = ["kf", "l", "nu", "nuS", "lambda", "G", "tau1S", "tau2S", "tau1P", "tau2P",
@@ -88,10 +88,23 @@ def _L():
         lib.orc_solvent_eq.argtypes = [C.c_double, C.c_double, C.c_double, dp]
         lib.orc_polymer_eq.argtypes = [C.c_void_p, C.c_double, dp, dp, dp]
         lib.orc_collide_node.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, dp, dp]
+        lib.orc_set_threads.restype = None
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_max_threads.restype = C.c_int
+        lib.orc_max_threads.argtypes = []
         lib.orc_splitmix64_next.restype = C.c_uint64
         lib.orc_splitmix64_next.argtypes = [P(C.c_uint64)]
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's row loops (OpenMP)."""
+    _L().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_L().orc_max_threads())
 
 
 def _ptr(a):
@@ -109,7 +122,8 @@ def splitmix64_next(state: int):
 
 DEFAULTS = dict(nq=16, periods=1, Re=20.0, Wi=0.5, beta=0.8, u0=0.05, phi=0.01,
                 spring=0, b=25.0, tau_drag=1.0, tau_ratio_p=1.0, force_scale=1.0,
-                lambda_set=0.0, ny_param=0, y_offset=0, x_offset=0, nx_param=0, drift_cap=0.1)
+                lambda_set=0.0, ny_param=0, y_offset=0, x_offset=0, nx_param=0, drift_cap=0.1,
+                drift_relax=1.0)
 
 DIAG_NAMES = ["step", "mass_S", "mass_P", "mom_x", "mom_y", "amplitude",
               "enstrophy", "qrms", "min_psi"]

@@ -16,6 +16,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define CS2 (1.0 / 3.0)
 #define PI 3.14159265358979323846
@@ -115,10 +118,18 @@ static void spring_force(const orc_sim *s, double qx, double qy, double *fx,
   double s2 = s->p.sigma * s->p.sigma;
   double f = 1.0 / s2;
   if (s->c.spring == 0) f /= (1.0 - (qx * qx + qy * qy) / (s->c.b * s2));
-  /* lattice cap: the drift D_Q |Fhat| may not exceed drift_cap */
+  /* lattice caps: the drift D_Q |Fhat| per step may exceed neither
+   * drift_cap nor drift_relax times 2 - omega_P, the rate at which the
+   * relaxation damps the polymer's non-conserved moments
+   * (omega_P = 2 / (2 tau1_P + 1)) */
+  double cap = s->c.drift_cap > 0.0 ? s->c.drift_cap : HUGE_VAL;
+  if (s->c.drift_relax > 0.0) {
+    double omega = 2.0 / (2.0 * s->p.tau1P + 1.0);
+    double c2 = s->c.drift_relax * (2.0 - omega);
+    if (c2 < cap) cap = c2;
+  }
   double mag = f * sqrt(qx * qx + qy * qy);
-  if (s->c.drift_cap > 0.0 && s->p.DQ * mag > s->c.drift_cap)
-    f *= s->c.drift_cap / (s->p.DQ * mag);
+  if (s->p.DQ * mag > cap) f *= cap / (s->p.DQ * mag);
   *fx = f * qx;
   *fy = f * qy;
 }
@@ -823,4 +834,21 @@ void orc_diagnostics(const orc_sim *s, double *out) {
   out[6] = ens;
   out[7] = (pw > 0) ? sqrt(pq2 / pw) / s->p.R : 0.0;
   out[8] = minpsi;
+}
+
+/* Threads of the row loops (for timing the oracle at a given core count). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

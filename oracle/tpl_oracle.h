@@ -56,6 +56,7 @@ typedef struct {
   int x_offset;        /* absolute column index of local column 0            */
   int nx_param;        /* > 0: x-extent used for the perturbation modes      */
   double drift_cap;    /* > 0: cap on the Q-drift D_Q |Fhat| per step          */
+  double drift_relax;  /* > 0: also cap it at drift_relax (2 - omega_P)        */
 } orc_config;
 
 /* Derived lattice parameters (step 0 of the scheme contract). */
@@ -106,6 +107,10 @@ void orc_observables(const orc_sim *s, double *out);
 /* Extra body force F[2][ny][nx] added in every later step; NULL removes it. */
 void orc_set_source(orc_sim *s, const double *F);
 double orc_amplitude(const orc_sim *s);
+
+/* Threads used by the row loops: set (n > 0) and read back. */
+void orc_set_threads(int n);
+int orc_max_threads(void);
 /* out[9]: step, massS, massP, momx, momy, amplitude, enstrophy, qrms, minpsi */
 void orc_diagnostics(const orc_sim *s, double *out);
 

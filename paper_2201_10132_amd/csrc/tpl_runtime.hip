@@ -39,7 +39,7 @@ struct Config {
   double Re = 0, Wi = 0, beta = 1, u0 = 0.05;
   int nq = 16, spring = 0, precision = TPL_FP64, pert_modes = 1;
   double b = 25.0, phi = 0.01, tau_drag = 1.0, tau_ratio_p = 1.0;
-  double force_scale = 1.0, lambda_set = 0.0, drift_cap = 0.1;
+  double force_scale = 1.0, lambda_set = 0.0, drift_cap = 0.1, drift_relax = 1.0;
   long long pre_steps = -1;
   int qsplit = 0, time_kernels = 0;
   int group_x = 1, group_y = 1, group_sync = 0, autotune = 1;
@@ -125,6 +125,8 @@ int derive(const Config &c, Derived &d) {
       {0, -1, 0, -1}, {0, 0, 1, 1},   {0, 0, 1, -1},  {0, 0, -1, 1},
       {0, 0, -1, -1}};
   const double s2 = d.sigma * d.sigma, bs2 = c.b * s2;
+  double cap = c.drift_cap > 0 ? c.drift_cap : HUGE_VAL;
+  if (c.drift_relax > 0) cap = std::min(cap, c.drift_relax * (2.0 - 2.0 / (2.0 * d.tau1P + 1.0)));
   double wsum = 0.0;
   for (int q = 0; q < d.nqd; ++q) {
     QNode &n = d.qtab[q];
@@ -133,11 +135,12 @@ int derive(const Config &c, Derived &d) {
     const double q2 = n.qx * n.qx + n.qy * n.qy;
     // spring force / kT: Hookean Q/sigma^2 or Warner FENE
     // Q / (sigma^2 (1 - Q^2/(b sigma^2))), capped so that the Q-drift
-    // D_Q |F/kT| stays <= drift_cap per step
+    // D_Q |F/kT| per step stays <= drift_cap and <= drift_relax (2 - omega_P),
+    // the damping rate of the polymer's non-conserved moments
     double f = 1.0 / s2;
     if (c.spring == 0) f /= (1.0 - q2 / bs2);
     const double drift = d.DQ * f * std::sqrt(q2);
-    if (c.drift_cap > 0 && drift > c.drift_cap) f *= c.drift_cap / drift;
+    if (drift > cap) f *= cap / drift;
     n.fx = f * n.qx;
     n.fy = f * n.qy;
     for (int k = 0; k < 25; ++k) {
@@ -731,6 +734,7 @@ const Key kKeys[] = {
     {"force_scale", &Config::force_scale, nullptr, nullptr},
     {"lambda", &Config::lambda_set, nullptr, nullptr},
     {"drift_cap", &Config::drift_cap, nullptr, nullptr},
+    {"drift_relax", &Config::drift_relax, nullptr, nullptr},
     {"precision", nullptr, &Config::precision, nullptr},
     {"pert_modes", nullptr, &Config::pert_modes, nullptr},
     {"pre_steps", nullptr, nullptr, &Config::pre_steps},
@@ -803,6 +807,7 @@ int tpl_set_param(tpl_ctx *x, const char *key, double v) {
   if (c.group_x < 1 || c.group_y < 1 || c.group_x * c.group_y > 8)
     return fail(TPL_EINVAL, "group_x * group_y must be in [1,8]");
   if (!(c.drift_cap >= 0)) return fail(TPL_EINVAL, "drift_cap must be >= 0");
+  if (!(c.drift_relax >= 0)) return fail(TPL_EINVAL, "drift_relax must be >= 0");
   if (runtime_knob) {
     x->c = c;
     return TPL_OK;

@@ -48,3 +48,29 @@ def test_fullsize_sampled_node_parity_and_conservation():
     assert abs(d1["mom_x"] - d0["mom_x"]) < 1e-13 * scale
     assert abs(d1["mom_y"] - d0["mom_y"]) < 1e-13 * scale
     t.close()
+
+
+def test_fullsize_nq4_whole_lattice_parity():
+    """The whole 1024 x 1024 lattice at NQ = 4 (12 Q-nodes, so that the
+    oracle holds it): init (base state, multimode perturbation) and 10 steps
+    in the library's default launch configuration, every population, psi
+    and U against the oracle (tolerances of the plain parity tests)."""
+    from tests.gpu_common import compare_states
+
+    print("fullsize nq4: library init", flush=True)
+    t = P.Tpl(NX, NY, PARAMS["Re"], PARAMS["Wi"], PARAMS["beta"], periods=PARAMS["periods"],
+              nq=4, pre_steps=100, pert_modes=1)
+    t.init(seed=0, perturbation=1e-4)
+    print("fullsize nq4: oracle init", flush=True)
+    o = oracle.OracleSim(NX, NY, nq=4, **PARAMS)
+    o.base_state(100)
+    o.perturb(0, 1e-4, True)
+    compare_states(t.get_state(), o.get_state(), 1e-13)
+    t.step(10)
+    print(f"fullsize nq4: 10 steps (qsplit {t.query('qsplit_used'):.0f}, group "
+          f"{t.query('group_x_used'):.0f}x{t.query('group_y_used'):.0f}), oracle", flush=True)
+    o.step(10)
+    errs = compare_states(t.get_state(), o.get_state(), 1e-13)
+    print("fullsize nq4 errors", errs, flush=True)
+    assert max_rel(t.moments(), o.observables()) < 1e-13
+    t.close()

@@ -182,3 +182,24 @@ def test_perturbation_amplitude():
     sim2.base_state(50)
     sim2.perturb(seed=5, amp=1e-3, multimode=False)
     assert abs(sim2.amplitude() / (1e-3 / np.sqrt(2)) - 1) < 1e-12
+
+
+def test_thread_count_does_not_change_results():
+    """The oracle's OpenMP splits lattice rows only, so one thread and all
+    threads give bitwise the same state (its timing at both counts is
+    therefore of the same computation)."""
+    def run(threads):
+        oracle.set_threads(threads)
+        o = oracle.OracleSim(16, 12, nq=6, Re=20.0, Wi=0.5, beta=0.8, periods=1)
+        o.base_state(50)
+        o.perturb(2, 1e-2, True)
+        o.step(10)
+        return o.get_state()
+
+    n = oracle.max_threads()
+    try:
+        a, b = run(1), run(max(n, 2))
+    finally:
+        oracle.set_threads(n)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
