@@ -203,3 +203,51 @@ def test_thread_count_does_not_change_results():
         oracle.set_threads(n)
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+
+
+def _stiff_fene(relax, nq=8):
+    """A 16 x 16 lattice carrying the parameters of a 256^2 one-period
+    Kolmogorov flow at Re 60, Wi 1, beta 0.7 (lambda = 815 steps, so that
+    tau2_P ~ 1e-3 and omega_P ~ 2): the regime of the 1024^2 workloads."""
+    o = oracle.OracleSim(16, 16, nq=nq, Re=60.0, Wi=1.0, beta=0.7, periods=1, ny_param=256,
+                         nx_param=256, drift_relax=relax)
+    o.base_state(3000)
+    o.perturb(0, 1e-2, True)
+    return o
+
+
+def test_fene_drift_caps_in_the_force_table():
+    """Every Q-node's drift D_Q |Fhat| stays within both caps: the absolute
+    0.1 per step and 2 - omega_P (omega_P = 2 / (2 tau1_P + 1)); the caps
+    only bind where the continuous FENE force exceeds them."""
+    for kw in (dict(Re=60.0, Wi=1.0, beta=0.7, ny_param=256), dict(Re=20.0, Wi=0.5, beta=0.8)):
+        o = oracle.OracleSim(8, 8, nq=16, periods=1, **kw)
+        d, t = o.derived(), o.tables()
+        cap = min(0.1, 2.0 - 2.0 / (2.0 * d["tau1P"] + 1.0))
+        Q, F = t["Q"], t["Fhat"]
+        drift = d["DQ"] * np.hypot(F[:, 0], F[:, 1])
+        assert drift.max() <= cap * (1 + 1e-12)
+        s2 = d["sigma"] ** 2
+        free = np.hypot(Q[:, 0], Q[:, 1]) / (s2 * (1 - (Q ** 2).sum(1) / (25.0 * s2)))
+        binding = d["DQ"] * free > cap
+        assert np.allclose(F[~binding], Q[~binding] * (free / np.hypot(Q[:, 0], Q[:, 1]))[~binding, None],
+                           rtol=1e-13)
+        assert np.allclose(drift[binding], cap, rtol=1e-12)
+
+
+def test_stiff_fene_diverges_without_the_relative_cap():
+    """Regression test of the drift-cap reading: in the stiff regime the
+    scheme with only the absolute cap lets round-off grow into a divergence
+    within a few thousand steps, while the relative cap keeps the same run
+    stable (min psi stays at its initial level)."""
+    def healthy(d, floor):
+        # (min psi is not a number once the state holds NaN)
+        return bool(np.isfinite([d["amplitude"], d["mass_P"]]).all() and floor < d["min_psi"] < 1)
+
+    o = _stiff_fene(0.0)
+    o.step(5000)
+    assert not healthy(o.diagnostics(), -1e-3)
+    o = _stiff_fene(1.0)
+    m0 = o.diagnostics()["min_psi"]
+    o.step(8000)
+    assert healthy(o.diagnostics(), 2 * m0)
