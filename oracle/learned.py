@@ -198,7 +198,12 @@ def targets(obs_fine_restricted, obs_coarse):
 
 
 def source(corr, ny, nx):
-    """corr [ny nx][5] (dJx, dJy, dtau_xx, dtau_xy, dtau_yy) -> F [2][ny][nx]."""
+    """corr [ny nx][5] (dJx, dJy, dtau_xx, dtau_xy, dtau_yy) -> F [2][ny][nx]:
+    F = dJ - <dJ> + div_h(dtau), central differences, <.> the lattice mean.
+    Total momentum is conserved on the fine and on the coarse lattice and by
+    the restriction, so the exact correction dJ has zero lattice mean; the
+    mean of a predicted one is removed (the divergence has zero mean by
+    itself on a periodic lattice)."""
     c = np.asarray(corr, dtype=np.float64).T.reshape(5, ny, nx)
 
     def dx(a):
@@ -207,6 +212,6 @@ def source(corr, ny, nx):
     def dy(a):
         return 0.5 * (np.roll(a, -1, axis=0) - np.roll(a, 1, axis=0))
 
-    Fx = c[0] + dx(c[2]) + dy(c[3])
-    Fy = c[1] + dx(c[3]) + dy(c[4])
+    Fx = (c[0] - c[0].mean()) + dx(c[2]) + dy(c[3])
+    Fy = (c[1] - c[1].mean()) + dx(c[3]) + dy(c[4])
     return np.stack([Fx, Fy])

@@ -197,6 +197,9 @@ hipError_t launch_features(const double *obs, int nx, int ny, const float *mean,
 hipError_t launch_targets(const double *ref, const double *obs, long long N, float *T,
                           hipStream_t s);
 hipError_t launch_source(const float *corr, int nx, int ny, double *F, hipStream_t s);
+// Removes the lattice mean of both components of F [2][N]; scratch holds
+// 2048 + 2 doubles.
+hipError_t launch_source_center(double *F, long long N, double *scratch, hipStream_t s);
 hipError_t launch_source_drift(const double *F, const double *FLD, long long N, double *partial,
                                int *nblocks, hipStream_t s);
 template <typename T>

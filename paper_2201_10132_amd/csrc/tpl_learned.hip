@@ -420,6 +420,43 @@ __global__ void k_source(const float *__restrict__ corr, int nx, int ny,
   F[N + r] = cc(r, 1) + 0.5 * (cc(e, 3) - cc(wv, 3)) + 0.5 * (cc(nn, 4) - cc(s, 4));
 }
 
+// Per-workgroup sums of both source components, partial[blk][2] (fixed
+// order: the removal of the mean below is deterministic).
+__global__ void k_source_sums(const double *__restrict__ F, long long N,
+                              double *__restrict__ partial) {
+  __shared__ double sx[256], sy[256];
+  double a = 0.0, b = 0.0;
+  for (long long r = (long long)blockIdx.x * 256 + threadIdx.x; r < N;
+       r += (long long)gridDim.x * 256) {
+    a += F[r];
+    b += F[N + r];
+  }
+  sx[threadIdx.x] = a;
+  sy[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sx[threadIdx.x] += sx[threadIdx.x + s];
+      sy[threadIdx.x] += sy[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sx[0];
+    partial[2 * blockIdx.x + 1] = sy[0];
+  }
+}
+
+// F -= sum / N per component.
+__global__ void k_source_center(double *__restrict__ F, long long N,
+                                const double *__restrict__ sums) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  const double mx = sums[0] / (double)N, my = sums[1] / (double)N;
+  F[r] -= mx;
+  F[N + r] -= my;
+}
+
 // Largest |F| / rho over the lattice, per workgroup into partial[] (the
 // velocity change a source makes in one step).
 __global__ void k_source_drift(const double *__restrict__ F, const double *__restrict__ FLD,
@@ -546,6 +583,18 @@ hipError_t launch_source(const float *corr, int nx, int ny, double *F, hipStream
   const long long N = (long long)nx * ny;
   hipLaunchKernelGGL(k_source, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, corr, nx, ny,
                      F);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_center(double *F, long long N, double *scratch, hipStream_t s) {
+  const long long nb = std::min<long long>(1024, (N + 255) / 256);
+  hipLaunchKernelGGL(k_source_sums, dim3((unsigned)nb), dim3(256), 0, s, F, N, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_sum(scratch, (int)nb, 2, scratch + 2048, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_source_center, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, F, N,
+                     scratch + 2048);
   return hipGetLastError();
 }
 

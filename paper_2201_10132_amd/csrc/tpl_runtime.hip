@@ -2032,9 +2032,13 @@ int learned_source(tpl_ctx *x) {
                          x->xb_d, x->stream));
   HIPCHK(launch_mlp_forward(mlp_dev(m), x->xb_d, N, x->corr_d, x->stream));
   HIPCHK(launch_source(x->corr_d, x->c.nx, x->c.ny, x->src_d, x->stream));
-  x->src_on = true;
-  rc = ensure_scratch(x, 1024 + 1);
+  // total momentum is conserved on both lattices and by the restriction, so
+  // the exact correction has zero lattice mean: remove the predicted mean
+  // (the uniform momentum mode is undamped, a bias there would accumulate)
+  rc = ensure_scratch(x, 2048 + 2);
   if (rc) return rc;
+  HIPCHK(launch_source_center(x->src_d, N, x->scratch, x->stream));
+  x->src_on = true;
   int nb = 0;
   HIPCHK(launch_source_drift(x->src_d, x->buf.half64(x->cur).FLD, N, x->scratch, &nb,
                              x->stream));

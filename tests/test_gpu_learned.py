@@ -233,8 +233,10 @@ def test_attached_network_source_and_step():
     corr = L.correction(p, Xf, *m32)
     want = L.source(corr, ny, nx)
     bound = 2.0 * _bf16_bound(p, (Xf - m32[0]) / m32[1]) * 1e-6
-    # a source node combines 5 corrections (centre and the 4 neighbours)
-    assert np.abs(F - want).max() <= 5 * bound.max() + 1e-12 * np.abs(want).max()
+    # a source node combines 5 corrections (centre and the 4 neighbours),
+    # and the removed lattice mean carries at most the largest node error
+    assert np.abs(F - want).max() <= 10 * bound.max() + 1e-12 * np.abs(want).max()
+    assert np.abs(F.sum(axis=(1, 2))).max() <= 1e-12 * np.abs(F).sum()
     # the attached step is the plain step with that source
     u.set_source(F)
     u.step(1)

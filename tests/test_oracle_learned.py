@@ -144,13 +144,15 @@ def test_source_divergence_identity_and_momentum():
     corr[:, 0] = 1e-3
     corr[:, 2] = np.sin(kx * x).ravel()      # tau_xx
     corr[:, 3] = np.cos(ky * y).ravel()      # tau_xy
+    corr[:, 1] = np.cos(kx * x).ravel() * 1e-3 + 2e-4  # a mean and a mode
     F = L.source(corr, ny, nx)
-    # exact discrete identities of the central difference
-    assert np.allclose(F[0], 1e-3 + math.sin(kx) * np.cos(kx * x) - math.sin(ky) * np.sin(ky * y),
+    # exact discrete identities of the central difference; the uniform
+    # momentum correction is removed, its fluctuating part kept
+    assert np.allclose(F[0], math.sin(kx) * np.cos(kx * x) - math.sin(ky) * np.sin(ky * y),
                        atol=1e-14)
-    assert np.allclose(F[1], 0.0, atol=1e-14)
-    # the divergence part injects no net momentum
-    assert abs(F[0].sum() - 1e-3 * ny * nx) < 1e-12
+    assert np.allclose(F[1], 1e-3 * np.cos(kx * x), atol=1e-14)
+    # the source injects no net momentum
+    assert abs(F[0].sum()) < 1e-12 and abs(F[1].sum()) < 1e-12
 
 
 def test_oracle_source_injects_its_momentum():
