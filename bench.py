@@ -283,40 +283,54 @@ def measure_batch(torch, n, steps, warmup, pre_steps, obo_steps) -> dict:
     return res
 
 
+LEARNED = dict(train_seeds=range(1000, 1008), held_out_seeds=range(2000, 2004), fine_steps=960,
+               sample_every=120, settle=10, horizon=20, epochs=40)
+
+
 def measure_learned(torch, pre_steps) -> dict:
     """Learned coarse correction, scaled down from the 64-trajectory plan:
-    4 fine 1024^2 FP64 trajectories (NQ = 8, Re ~ U[20, 80], Wi ~ U[0, 1.5],
-    beta 0.7, 4 periods, seeds 1000-1003) of 400 fine steps sampled every 40,
-    a 256^2 coarse lattice (4x restriction), 40 epochs of Adam; judged on
-    held-out seeds 2000 and 2001 over 400 fine steps."""
+    8 fine 1024^2 FP64 trajectories (NQ = 8, Re ~ U[20, 80], Wi ~ U[0, 1.5],
+    beta 0.7, 4 periods, seeds 1000-1007) of 960 fine steps, one training
+    pair every 120 (coarse state 10 steps after the restriction, target the
+    growth of its difference from the restricted fine run over the next 20
+    coarse steps), a 256^2 coarse lattice (4x restriction), 40 epochs of
+    Adam; judged on held-out seeds 2000-2003 over 400 fine steps."""
     import paper_2201_10132_amd.learned as LL
     from tests import inputs
 
+    c = LEARNED
     t0 = time.perf_counter()
-    trs = inputs.c5_trajectories(range(1000, 1004))
-    X, T, t_fine = LL.generate(torch, trs, pre_steps=pre_steps)
-    t1 = time.perf_counter()
+    trs = inputs.c5_trajectories(c["train_seeds"])
+    X, T, t_fine = LL.generate(torch, trs, pre_steps=pre_steps, fine_steps=c["fine_steps"],
+                               sample_every=c["sample_every"], settle=c["settle"],
+                               horizon=c["horizon"])
     torch.cuda.synchronize()
-    mlp, l0, l1 = LL.train(torch, X, T, epochs=40, lr=1e-3)
+    t1 = time.perf_counter()
+    mlp, l0, l1 = LL.train(torch, X, T, epochs=c["epochs"], lr=1e-3)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    rows = X.shape[0] * X.shape[1] * 40
+    rows = X.shape[0] * X.shape[1] * c["epochs"]
     # matrix-core work per training row: 92 16x16x16 MFMAs per 16 rows
     flops_row = 92 * 2 * 16 ** 3 / 16
-    evals = [LL.evaluate(torch, mlp, cfg, pre_steps=pre_steps)
-             for cfg in inputs.c5_trajectories([2000, 2001])]
+    held = inputs.c5_trajectories(c["held_out_seeds"])
+    evals = [LL.evaluate(torch, mlp, cfg, pre_steps=pre_steps) for cfg in held]
     plain_ms, corr_ms = LL.coarse_step_ms(torch, mlp, trs[0])
     nc = 256 * 256
     res = {
         "workload": "kolmogorov_learned_coarse256_from_fine1024_nq8",
-        "train_trajectories": len(trs), "fine_steps": 400, "samples": int(X.shape[0]),
+        "train_trajectories": len(trs), "fine_steps": c["fine_steps"],
+        "sample_every": c["sample_every"], "settle": c["settle"], "horizon": c["horizon"],
+        "samples": int(X.shape[0]),
         "generate_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
         "loss_first_epoch": round(l0, 5), "loss_last_epoch": round(l1, 5),
         "mlp_train_tflops": round(rows * flops_row / (t2 - t1) / 1e12, 3),
-        "eval": [{"seed": cfg["seed"], "err_plain": e["err_plain"][-1],
-                  "err_corrected": e["err_corrected"][-1], "gain": e["gain"],
-                  "accepted": e["accepted"], "rejected_by_drift_gate": e["rejected_by_drift_gate"]}
-                 for cfg, e in zip(inputs.c5_trajectories([2000, 2001]), evals)],
+        "eval": [{"seed": cfg["seed"], "Re": round(cfg["Re"], 2), "Wi": round(cfg["Wi"], 3),
+                  "err_plain": e["err_plain"][-1], "err_corrected": e["err_corrected"][-1],
+                  "gain": e["gain"], "accepted": e["accepted"],
+                  "rejected_by_drift_gate": e["rejected_by_drift_gate"]}
+                 for cfg, e in zip(held, evals)],
+        "accepted": sum(e["accepted"] for e in evals),
+        "gain_min": min(e["gain"] for e in evals),
         "coarse_ms_per_step_plain": round(plain_ms, 4),
         "coarse_ms_per_step_corrected": round(corr_ms, 4),
         # fine-lattice node updates the corrected coarse step stands for:
@@ -324,8 +338,9 @@ def measure_learned(torch, pre_steps) -> dict:
         "mlups_equivalent": round(nc * 64 / (corr_ms * 1e-3) / 1e6, 1),
     }
     print(f"# learned: generate {res['generate_s']} s, train {res['train_s']} s, loss "
-          f"{l0:.3f} -> {l1:.3f}, coarse {plain_ms:.3f}/{corr_ms:.3f} ms", file=sys.stderr,
-          flush=True)
+          f"{l0:.3f} -> {l1:.3f}, accepted {res['accepted']}/{len(evals)}, gains "
+          f"{[round(e['gain'], 2) for e in evals]}, coarse {plain_ms:.3f}/{corr_ms:.3f} ms",
+          file=sys.stderr, flush=True)
     mlp.close()
     return res
 

@@ -439,6 +439,13 @@ int run_steps(tpl_ctx *x, const Buffers &B, int nx, int ny, int *cur,
   StepParams p = make_step_params(x, nx, ny, qs_req);
   const StepRef ref = B.esize == 4 ? step_ref(x) : StepRef{nullptr, nullptr, nullptr, nullptr, nullptr};
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  struct Events {  // destroyed on every return path
+    hipEvent_t *a, *b;
+    ~Events() {
+      if (*a) (void)hipEventDestroy(*a);
+      if (*b) (void)hipEventDestroy(*b);
+    }
+  } guard{&e0, &e1};
   if (timed) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -460,10 +467,6 @@ int run_steps(tpl_ctx *x, const Buffers &B, int nx, int ny, int *cur,
       x->kernel_launches++;
     }
     *cur = 1 - *cur;
-  }
-  if (timed) {
-    HIPCHK(hipEventDestroy(e0));
-    HIPCHK(hipEventDestroy(e1));
   }
   return TPL_OK;
 }

@@ -34,14 +34,18 @@ def _coarse_like(cfg, factor, nq):
 
 
 def generate(torch, trajectories, factor=4, nq=8, fine_steps=400, sample_every=40,
-             pre_steps=3000, perturbation=1e-2, horizon=None):
+             pre_steps=3000, perturbation=1e-2, horizon=None, settle=0):
     """Training pairs from fine runs.  trajectories: list of dicts with nx, ny,
     Re, Wi, beta, periods, seed.  horizon: coarse steps per target (default
-    sample_every / factor).  Returns (X, T) device tensors
-    [samples, N_coarse, 54] and [samples, N_coarse, 5] and the fine-step
-    time."""
+    sample_every / factor).  settle > 0: the coarse run first advances
+    `settle` steps from the restricted state (past the acoustic transient a
+    restricted state starts with); the features are those of the settled
+    coarse state and the target is the growth of its difference from the
+    restricted fine run over the next `horizon` steps, per step.  Returns
+    (X, T) device tensors [samples, N_coarse, 54] and [samples, N_coarse, 5]
+    and the fine-step time."""
     h = horizon or max(1, sample_every // factor)
-    assert h * factor <= sample_every
+    assert (h + settle) * factor <= sample_every
     Xs, Ts = [], []
     t_fine = 0.0
     for cfg in trajectories:
@@ -57,6 +61,16 @@ def generate(torch, trajectories, factor=4, nq=8, fine_steps=400, sample_every=4
             X = torch.zeros((N, 54), dtype=torch.float32, device="cuda")
             T = torch.zeros((N, 5), dtype=torch.float32, device="cuda")
             ca.restrict_from(fine)
+            T0 = None
+            if settle:
+                ca.step(settle)
+                t0 = time.perf_counter()
+                fine.step(settle * factor)
+                t_fine += time.perf_counter() - t0
+                cb.restrict_from(fine)
+                cb.moments_device(obs_ref.data_ptr(), obs_ref.numel())
+                T0 = torch.zeros_like(T)
+                ca.targets_device(obs_ref.data_ptr(), T0.data_ptr(), T0.numel())
             ca.features_device(X.data_ptr(), X.numel())
             ca.step(h)
             t0 = time.perf_counter()
@@ -65,10 +79,12 @@ def generate(torch, trajectories, factor=4, nq=8, fine_steps=400, sample_every=4
             cb.restrict_from(fine)
             cb.moments_device(obs_ref.data_ptr(), obs_ref.numel())
             ca.targets_device(obs_ref.data_ptr(), T.data_ptr(), T.numel())
+            if T0 is not None:
+                T -= T0
             T /= h
             Xs.append(X)
             Ts.append(T)
-            rest = min(sample_every, fine_steps - n) - h * factor
+            rest = min(sample_every, fine_steps - n) - (h + settle) * factor
             if rest > 0:
                 t0 = time.perf_counter()
                 fine.step(rest)

@@ -282,3 +282,43 @@ def test_pipeline_small():
         ev["err_corrected"][-1] <= 0.05
     assert ev["accepted"] == ok
     mlp.close()
+
+
+def test_settled_targets_bookkeeping():
+    """With a settle phase the first training pair is: features of the coarse
+    state s steps after the restriction, target = (e(s + h) - e(s)) / h, e(k)
+    the restricted fine state minus the coarse state after k coarse steps
+    (4k fine steps) in momentum and polymer stress."""
+    from paper_2201_10132_amd import learned as LL
+
+    kw = dict(nx=128, ny=128, periods=1, Re=(15.0, 25.0), Wi=(0.1, 0.3))
+    cfg = inputs.c5_trajectories([1003], **kw)[0]
+    s, h = 2, 3
+    X, T, _ = LL.generate(torch, [cfg], nq=8, fine_steps=20, sample_every=20, pre_steps=500,
+                          horizon=h, settle=s)
+    assert tuple(X.shape) == (1, 32 * 32, 54) and torch.isfinite(T).all()
+    # the same sequence by hand
+    fine = P.Tpl(128, 128, cfg["Re"], cfg["Wi"], cfg["beta"], periods=1, nq=8, pre_steps=500)
+    fine.init(seed=cfg["seed"], perturbation=1e-2)
+    ca, cb = (P.Tpl(32, 32, cfg["Re"], cfg["Wi"], cfg["beta"], periods=1, nq=8, pre_steps=0)
+              for _ in range(2))
+    ca.init(0, 0.0)
+    cb.init(0, 0.0)
+    N = 32 * 32
+    obs = torch.zeros((P.TPL_NFIELDS, N), dtype=torch.float64, device="cuda")
+    e = [torch.zeros((N, 5), dtype=torch.float32, device="cuda") for _ in range(2)]
+    Xw = torch.zeros((N, 54), dtype=torch.float32, device="cuda")
+    ca.restrict_from(fine)
+    for i, k in enumerate((s, h)):
+        ca.step(k)
+        fine.step(4 * k)
+        cb.restrict_from(fine)
+        cb.moments_device(obs.data_ptr(), obs.numel())
+        if i == 0:
+            ca.features_device(Xw.data_ptr(), Xw.numel())
+        ca.targets_device(obs.data_ptr(), e[i].data_ptr(), e[i].numel())
+    assert torch.equal(X[0], Xw)
+    want = (e[1] - e[0]) / h
+    assert torch.equal(T[0], want)
+    for c in (fine, ca, cb):
+        c.close()
