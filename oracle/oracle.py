@@ -39,7 +39,8 @@ class _Config(C.Structure):
                 ("b", C.c_double), ("tau_drag", C.c_double), ("tau_ratio_p", C.c_double),
                 ("force_scale", C.c_double), ("lambda_set", C.c_double),
                 ("ny_param", C.c_int), ("y_offset", C.c_int), ("x_offset", C.c_int),
-                ("nx_param", C.c_int), ("drift_cap", C.c_double), ("drift_relax", C.c_double)]
+                ("nx_param", C.c_int), ("drift_cap", C.c_double), ("drift_relax", C.c_double),
+                ("qe_model", C.c_int)]
 
 
 _DERIVED = ["kf", "l", "nu", "nuS", "lambda", "G", "tau1S", "tau2S", "tau1P", "tau2P",
@@ -87,6 +88,8 @@ def _L():
         lib.orc_diagnostics.argtypes = [C.c_void_p, dp]
         lib.orc_solvent_eq.argtypes = [C.c_double, C.c_double, C.c_double, dp]
         lib.orc_polymer_eq.argtypes = [C.c_void_p, C.c_double, dp, dp, dp]
+        lib.orc_solvent_qe2.argtypes = [C.c_double, dp, dp, dp]
+        lib.orc_polymer_qe2.argtypes = [C.c_void_p, C.c_double, dp, dp, dp]
         lib.orc_collide_node.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, dp, dp]
         lib.orc_set_threads.restype = None
         lib.orc_set_threads.argtypes = [C.c_int]
@@ -123,7 +126,7 @@ def splitmix64_next(state: int):
 DEFAULTS = dict(nq=16, periods=1, Re=20.0, Wi=0.5, beta=0.8, u0=0.05, phi=0.01,
                 spring=0, b=25.0, tau_drag=1.0, tau_ratio_p=1.0, force_scale=1.0,
                 lambda_set=0.0, ny_param=0, y_offset=0, x_offset=0, nx_param=0, drift_cap=0.1,
-                drift_relax=1.0)
+                drift_relax=1.0, qe_model=1)
 
 DIAG_NAMES = ["step", "mass_S", "mass_P", "mom_x", "mom_y", "amplitude",
               "enstrophy", "qrms", "min_psi"]
@@ -247,6 +250,22 @@ class OracleSim:
         out = np.zeros(25)
         Jr = np.ascontiguousarray(Jr, dtype=np.float64); JQ = np.ascontiguousarray(JQ, dtype=np.float64)
         _L().orc_polymer_eq(self._h, float(psi), _ptr(Jr), _ptr(JQ), _ptr(out))
+        return out
+
+    @staticmethod
+    def solvent_qe2(rho, J, P):
+        """Stress-model quasi-equilibrium on D2Q9, P = (xx, xy, yy)."""
+        out = np.zeros(9)
+        J = np.ascontiguousarray(J, dtype=np.float64); P = np.ascontiguousarray(P, dtype=np.float64)
+        _L().orc_solvent_qe2(float(rho), _ptr(J), _ptr(P), _ptr(out))
+        return out
+
+    def polymer_qe2(self, psi, J, P):
+        """Stress-model quasi-equilibrium on D4Q25, J[4], P = upper triangle
+        of the 4 x 4 second moment, row-major."""
+        out = np.zeros(25)
+        J = np.ascontiguousarray(J, dtype=np.float64); P = np.ascontiguousarray(P, dtype=np.float64)
+        _L().orc_polymer_qe2(self._h, float(psi), _ptr(J), _ptr(P), _ptr(out))
         return out
 
     def collide_node(self, gS, gP, K, sq, Fb):

@@ -213,16 +213,31 @@ static int derive(orc_sim *s, char *err) {
     p->G = p->G * p->lambda / c->lambda_set;
     p->lambda = c->lambda_set;
   }
-  p->tau1S = p->nuS / CS2; /* trapezoidal scheme: nu = c_s^2 tau1 */
-  p->tau2S = c->tau_drag;
-  /* Q-diffusivity D_Q = c_s^2 tau2_P sets lambda = sigma^2 / (2 D_Q) */
-  p->tau2P = p->sigma * p->sigma / (2.0 * CS2 * p->lambda);
-  p->tau1P = c->tau_ratio_p * p->tau2P;
-  p->DQ = CS2 * p->tau2P;
+  if (c->qe_model == 2) {
+    /* stress-tensor model (Sec. V (ii)): the stresses relax with tau2, so
+     * the viscosity is c_s^2 tau2; momenta and fluxes relax with tau1, so
+     * tau1 sets the drag and the diffusivities */
+    p->tau2S = p->nuS / CS2;
+    p->tau1S = c->tau_drag;
+    p->tau1P = p->sigma * p->sigma / (2.0 * CS2 * p->lambda);
+    p->tau2P = p->tau1P / c->tau_ratio_p;
+    p->DQ = CS2 * p->tau1P;
+  } else {
+    p->tau1S = p->nuS / CS2; /* trapezoidal scheme: nu = c_s^2 tau1 */
+    p->tau2S = c->tau_drag;
+    /* Q-diffusivity D_Q = c_s^2 tau2_P sets lambda = sigma^2 / (2 D_Q) */
+    p->tau2P = p->sigma * p->sigma / (2.0 * CS2 * p->lambda);
+    p->tau1P = c->tau_ratio_p * p->tau2P;
+    p->DQ = CS2 * p->tau2P;
+  }
   p->F0 = c->force_scale * 1.0 * p->nu * c->u0 * p->kf * p->kf;
-  p->Sc = p->nuS / (CS2 * p->tau2P);
+  p->Sc = p->nuS / p->DQ;
   if (p->tau1S > p->tau2S * (1.0 + 1e-12)) {
     if (err) snprintf(err, 256, "tau1_S=%g exceeds tau2_S=%g", p->tau1S, p->tau2S);
+    return -1;
+  }
+  if (c->qe_model != 1 && c->qe_model != 2) {
+    if (err) snprintf(err, 256, "qe_model must be 1 or 2");
     return -1;
   }
   if (c->tau_ratio_p > 1.0 || c->tau_ratio_p <= 0.0) {
@@ -240,9 +255,9 @@ static void derive_kappa(orc_sim *s) {
   for (int q = 0; q < s->nqd; ++q)
     m += s->peq[q] * (s->Q[2 * q] * s->Fh[2 * q] + s->Q[2 * q + 1] * s->Fh[2 * q + 1]);
   s->p.meq = 0.5 * m;
-  s->p.kappa = (s->p.rhoP0 > 0.0)
-                   ? s->p.G * s->p.tau2P / (s->p.rhoP0 * s->p.meq)
-                   : 0.0;
+  /* the polymer flux relaxes with tau2_P (model (i)) or tau1_P (model (ii)) */
+  double tJ = s->c.qe_model == 2 ? s->p.tau1P : s->p.tau2P;
+  s->p.kappa = (s->p.rhoP0 > 0.0) ? s->p.G * tJ / (s->p.rhoP0 * s->p.meq) : 0.0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -357,14 +372,59 @@ void orc_polymer_eq(const orc_sim *s, double psi, const double Jr[2],
                                 s->cp[k][2] * JQ[0] + s->cp[k][3] * JQ[1]) / CS2);
 }
 
+/* Second-order Hermite forms (model (ii)): w [rho + J.c/c_s^2 +
+ * (P - rho c_s^2 I):(c c - c_s^2 I) / (2 c_s^4)].  The printed lattice forms
+ * omit the 1/(2 c_s^4) normalisation; with it the populations carry exactly
+ * the prescribed second moments (both lattices are isotropic to fourth
+ * order). */
+void orc_solvent_qe2(double rho, const double J[2], const double P[3], double *out) {
+  double D[2][2] = {{P[0] - rho * CS2, P[1]}, {P[1], P[2] - rho * CS2}};
+  for (int i = 0; i < 9; ++i) {
+    double c[2] = {C9[i][0], C9[i][1]};
+    double h = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) h += D[a][b] * (c[a] * c[b] - (a == b ? CS2 : 0.0));
+    out[i] = W9[i] * (rho + (c[0] * J[0] + c[1] * J[1]) / CS2 + h / (2.0 * CS2 * CS2));
+  }
+}
+
+void orc_polymer_qe2(const orc_sim *s, double psi, const double J[4], const double P[10],
+                     double *out) {
+  double D[4][4];
+  int n = 0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = a; b < 4; ++b) {
+      D[a][b] = D[b][a] = P[n++] - (a == b ? psi * CS2 : 0.0);
+    }
+  for (int k = 0; k < 25; ++k) {
+    double lin = 0.0, h = 0.0;
+    for (int a = 0; a < 4; ++a) {
+      lin += s->cp[k][a] * J[a];
+      for (int b = 0; b < 4; ++b)
+        h += D[a][b] * (s->cp[k][a] * s->cp[k][b] - (a == b ? CS2 : 0.0));
+    }
+    out[k] = s->wp[k] * (psi + lin / CS2 + h / (2.0 * CS2 * CS2));
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Steps 4-7 at one r-node.
  *
- * Moment inversion (Sec. VI.C, with the component-momentum model's tau2):
- *   rho(f) = rho(g);  J(f) = (2 tau2 J(g) + J_target) / (2 tau2 + 1).
+ * Two quasi-equilibrium models (Sec. V):
+ *  (i)  component momenta quasi-conserved: f* carries each species' own
+ *       momentum (solvent) or fluxes (polymer); momenta relax to the mixture
+ *       with tau2, everything else with tau1;
+ *  (ii) component stresses quasi-conserved: f* carries each species' own
+ *       second moments and the mixture-velocity momentum (solvent) or the
+ *       imposed fluxes (polymer); momenta relax with tau1, stresses with tau2.
+ * Write tJ for the momentum relaxation time (tau2 in (i), tau1 in (ii)).
+ *
+ * Moment inversion (Sec. VI.C, g = f - Omega/2): rho(f) = rho(g);
+ *   J(f) = (2 tJ J(g) + J_target) / (2 tJ + 1);
+ *   model (ii) also P(f) = (2 tau2 P(g) + P_eq) / (2 tau2 + 1).
  * Mixture velocity: the velocity for which the cross-collision momentum
  * exchange of the two species cancels (Sec. IV/V), expressed in g-moments;
- * with equal tau2 it is U(g) + (body force)/2rho + S/(2 tau2 rho), the form of
+ * with equal tJ it is U(g) + (body force)/2rho + S/(2 tJ rho), the form of
  * Sec. VI.C.  Relaxation (Sec. VI.C, trapezoidal rule made explicit):
  *   g' = (1 - 2 beta) g + 2 beta [(1 - tau1/tau2) f* + (tau1/tau2) f_eq],
  *   beta = 1 / (2 tau1 + 1).
@@ -374,12 +434,17 @@ void orc_collide_node(const orc_sim *s, const double *gS, const double *gP,
                       double *outS, double *outP, double U[2]) {
   const orc_derived *p = &s->p;
   const int nqd = s->nqd;
+  const int m2 = s->c.qe_model == 2;
+  const double tJS = m2 ? p->tau1S : p->tau2S, tJP = m2 ? p->tau1P : p->tau2P;
   /* solvent moments of g */
-  double rhoS = 0, JSg[2] = {0, 0};
+  double rhoS = 0, JSg[2] = {0, 0}, PSg[3] = {0, 0, 0};
   for (int i = 0; i < 9; ++i) {
     rhoS += gS[i];
     JSg[0] += C9[i][0] * gS[i];
     JSg[1] += C9[i][1] * gS[i];
+    PSg[0] += C9[i][0] * C9[i][0] * gS[i];
+    PSg[1] += C9[i][0] * C9[i][1] * gS[i];
+    PSg[2] += C9[i][1] * C9[i][1] * gS[i];
   }
   /* polymer moments of g at every Q-node and their Q-sums */
   double rhoP = 0, JPg[2] = {0, 0}, S[2] = {0, 0};
@@ -394,19 +459,30 @@ void orc_collide_node(const orc_sim *s, const double *gS, const double *gP,
     S[1] += sq[2 * q + 1];
   }
   /* mixture velocity */
-  double aS = 1.0 / (2.0 * p->tau2S + 1.0), aP = 1.0 / (2.0 * p->tau2P + 1.0);
+  double aS = 1.0 / (2.0 * tJS + 1.0), aP = 1.0 / (2.0 * tJP + 1.0);
   double den = rhoS * aS + rhoP * aP;
   for (int a = 0; a < 2; ++a)
-    U[a] = ((JSg[a] + 0.5 * Fb[a]) * aS + (JPg[a] + S[a] / (2.0 * p->tau2P)) * aP) / den;
+    U[a] = ((JSg[a] + 0.5 * Fb[a]) * aS + (JPg[a] + S[a] / (2.0 * tJP)) * aP) / den;
 
-  /* solvent: u_S from the inverted momentum; equilibrium velocity shifted by
-   * the body force (target momentum rho_S U + tau2_S F) */
-  double JSf[2], fstar[9], feq[9];
-  for (int a = 0; a < 2; ++a)
-    JSf[a] = (2.0 * p->tau2S * JSg[a] + rhoS * U[a] + p->tau2S * Fb[a]) * aS;
-  orc_solvent_eq(rhoS, JSf[0] / rhoS, JSf[1] / rhoS, fstar);
-  orc_solvent_eq(rhoS, U[0] + p->tau2S * Fb[0] / rhoS,
-                 U[1] + p->tau2S * Fb[1] / rhoS, feq);
+  /* solvent: target momentum rho_S U + tJ_S F (the body force by a shift of
+   * the equilibrium velocity) */
+  double fstar[9], feq[9];
+  const double vS[2] = {U[0] + tJS * Fb[0] / rhoS, U[1] + tJS * Fb[1] / rhoS};
+  orc_solvent_eq(rhoS, vS[0], vS[1], feq);
+  if (!m2) {
+    double JSf[2];
+    for (int a = 0; a < 2; ++a)
+      JSf[a] = (2.0 * tJS * JSg[a] + rhoS * U[a] + tJS * Fb[a]) * aS;
+    orc_solvent_eq(rhoS, JSf[0] / rhoS, JSf[1] / rhoS, fstar);
+  } else {
+    /* own stress, inverted against the equilibrium's rho_S (c_s^2 I + v v) */
+    const double Peq[3] = {rhoS * (CS2 + vS[0] * vS[0]), rhoS * vS[0] * vS[1],
+                           rhoS * (CS2 + vS[1] * vS[1])};
+    double PSf[3], JS[2] = {rhoS * vS[0], rhoS * vS[1]};
+    for (int c = 0; c < 3; ++c)
+      PSf[c] = (2.0 * p->tau2S * PSg[c] + Peq[c]) / (2.0 * p->tau2S + 1.0);
+    orc_solvent_qe2(rhoS, JS, PSf, fstar);
+  }
   double bS = 1.0 / (2.0 * p->tau1S + 1.0), rS = p->tau1S / p->tau2S;
   for (int i = 0; i < 9; ++i)
     outS[i] = (1.0 - 2.0 * bS) * gS[i] +
@@ -416,13 +492,18 @@ void orc_collide_node(const orc_sim *s, const double *gS, const double *gP,
   double bP = 1.0 / (2.0 * p->tau1P + 1.0), rP = p->tau1P / p->tau2P;
   for (int q = 0; q < nqd; ++q) {
     const double *g = gP + 25 * q;
-    double psi = 0, Jrg[2] = {0, 0}, JQg[2] = {0, 0};
+    double psi = 0, Jrg[2] = {0, 0}, JQg[2] = {0, 0}, Pg[10] = {0};
     for (int k = 0; k < 25; ++k) {
       psi += g[k];
       Jrg[0] += s->cp[k][0] * g[k];
       Jrg[1] += s->cp[k][1] * g[k];
       JQg[0] += s->cp[k][2] * g[k];
       JQg[1] += s->cp[k][3] * g[k];
+      if (m2) {
+        int n = 0;
+        for (int a = 0; a < 4; ++a)
+          for (int b2 = a; b2 < 4; ++b2) Pg[n++] += s->cp[k][a] * s->cp[k][b2] * g[k];
+      }
     }
     const double Qx = s->Q[2 * q], Qy = s->Q[2 * q + 1];
     /* imposed fluxes (Sec. V): J^r_eq = psi U + spring term,
@@ -430,14 +511,25 @@ void orc_collide_node(const orc_sim *s, const double *gS, const double *gP,
     double Jreq[2] = {psi * U[0] + sq[2 * q], psi * U[1] + sq[2 * q + 1]};
     double JQeq[2] = {psi * (K[0] * Qx + K[1] * Qy - p->DQ * s->Fh[2 * q]),
                       psi * (K[2] * Qx + K[3] * Qy - p->DQ * s->Fh[2 * q + 1])};
-    double Jrf[2], JQf[2];
-    for (int a = 0; a < 2; ++a) {
-      Jrf[a] = (2.0 * p->tau2P * Jrg[a] + Jreq[a]) * aP;
-      JQf[a] = (2.0 * p->tau2P * JQg[a] + JQeq[a]) * aP;
-    }
     double fs[25], fe[25];
-    orc_polymer_eq(s, psi, Jrf, JQf, fs);
     orc_polymer_eq(s, psi, Jreq, JQeq, fe);
+    if (!m2) {
+      double Jrf[2], JQf[2];
+      for (int a = 0; a < 2; ++a) {
+        Jrf[a] = (2.0 * tJP * Jrg[a] + Jreq[a]) * aP;
+        JQf[a] = (2.0 * tJP * JQg[a] + JQeq[a]) * aP;
+      }
+      orc_polymer_eq(s, psi, Jrf, JQf, fs);
+    } else {
+      /* own stresses, inverted against the linear equilibrium's psi c_s^2 I */
+      double Pf[10], Jeq[4] = {Jreq[0], Jreq[1], JQeq[0], JQeq[1]};
+      int n = 0;
+      for (int a = 0; a < 4; ++a)
+        for (int b2 = a; b2 < 4; ++b2, ++n)
+          Pf[n] = (2.0 * p->tau2P * Pg[n] + (a == b2 ? psi * CS2 : 0.0)) /
+                  (2.0 * p->tau2P + 1.0);
+      orc_polymer_qe2(s, psi, Jeq, Pf, fs);
+    }
     double *o = outP + 25 * q;
     for (int k = 0; k < 25; ++k)
       o[k] = (1.0 - 2.0 * bP) * g[k] + 2.0 * bP * ((1.0 - rP) * fs[k] + rP * fe[k]);

@@ -57,6 +57,8 @@ typedef struct {
   int nx_param;        /* > 0: x-extent used for the perturbation modes      */
   double drift_cap;    /* > 0: cap on the Q-drift D_Q |Fhat| per step          */
   double drift_relax;  /* > 0: also cap it at drift_relax (2 - omega_P)        */
+  int qe_model;        /* 1: component-momentum quasi-equilibria (Sec. V (i));
+                        * 2: stress-tensor quasi-equilibria (Sec. V (ii))      */
 } orc_config;
 
 /* Derived lattice parameters (step 0 of the scheme contract). */
@@ -107,6 +109,15 @@ void orc_observables(const orc_sim *s, double *out);
 /* Extra body force F[2][ny][nx] added in every later step; NULL removes it. */
 void orc_set_source(orc_sim *s, const double *F);
 double orc_amplitude(const orc_sim *s);
+
+/* Second-order Hermite quasi-equilibria of the stress-tensor model (Sec. VI.A,
+ * VI.B, model (ii)): the populations with density rho, first moments J and
+ * second moments P.  Solvent on D2Q9: J[2], P = (xx, xy, yy).  Polymer on
+ * D4Q25 over xi = (v_x, v_y, Qdot_x, Qdot_y): J[4], P = upper triangle of the
+ * 4 x 4 tensor, row-major (00 01 02 03 11 12 13 22 23 33). */
+void orc_solvent_qe2(double rho, const double J[2], const double P[3], double *out);
+void orc_polymer_qe2(const orc_sim *s, double psi, const double J[4], const double P[10],
+                     double *out);
 
 /* Threads used by the row loops: set (n > 0) and read back. */
 void orc_set_threads(int n);
