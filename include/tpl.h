@@ -112,7 +112,8 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *   spring 0      0 = FENE (Warner), 1 = Hookean
  *   b 25          FENE extensibility; sigma = (nq/2) / sqrt(b)
  *   phi 0.01      polymer mass fraction
- *   tau_drag 1    solvent tau2 (drag time)
+ *   tau_drag 0    solvent drag time (model 1: tau2_S, model 2: tau1_S);
+ *                 0 = automatic: 1 (model 1) or tau2_S (model 2)
  *   tau_ratio_p 1 polymer tau1 / tau2
  *   force_scale 1 multiplies F0
  *   lambda 0      > 0: polymer relaxation time in steps instead of Wi l / u0
@@ -120,6 +121,12 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *   drift_relax 1 also cap that drift at drift_relax (2 - omega_P), the
  *                 damping rate of the polymer's non-conserved moments,
  *                 omega_P = 2 / (2 tau1_P + 1) (0 = none)
+ *   qe_model 1    quasi-equilibrium model (Sec. V): 1 = component momenta
+ *                 quasi-conserved (viscosity c_s^2 tau1_S, drag time
+ *                 tau2_S = tau_drag, D_Q = c_s^2 tau2_P); 2 = component
+ *                 stresses quasi-conserved (viscosity c_s^2 tau2_S, drag time
+ *                 tau1_S = tau_drag <= tau2_S, D_Q = c_s^2 tau1_P,
+ *                 tau2_P = tau1_P / tau_ratio_p); not for batches
  *   precision 0   TPL_FP64, TPL_FP32 or TPL_BF16NEQ population storage
  *   pert_modes 1  0 = single x-mode, 1 = multimode perturbation
  *   pre_steps -1  base-state column steps (-1 = 5 max(l^2/nu, lambda))

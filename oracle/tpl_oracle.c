@@ -218,13 +218,13 @@ static int derive(orc_sim *s, char *err) {
      * the viscosity is c_s^2 tau2; momenta and fluxes relax with tau1, so
      * tau1 sets the drag and the diffusivities */
     p->tau2S = p->nuS / CS2;
-    p->tau1S = c->tau_drag;
+    p->tau1S = c->tau_drag > 0.0 ? c->tau_drag : p->tau2S; /* 0: automatic */
     p->tau1P = p->sigma * p->sigma / (2.0 * CS2 * p->lambda);
     p->tau2P = p->tau1P / c->tau_ratio_p;
     p->DQ = CS2 * p->tau1P;
   } else {
     p->tau1S = p->nuS / CS2; /* trapezoidal scheme: nu = c_s^2 tau1 */
-    p->tau2S = c->tau_drag;
+    p->tau2S = c->tau_drag > 0.0 ? c->tau_drag : 1.0; /* 0: automatic */
     /* Q-diffusivity D_Q = c_s^2 tau2_P sets lambda = sigma^2 / (2 D_Q) */
     p->tau2P = p->sigma * p->sigma / (2.0 * CS2 * p->lambda);
     p->tau1P = c->tau_ratio_p * p->tau2P;

@@ -47,7 +47,8 @@ typedef struct {
   double phi;          /* polymer mass fraction rho_P / rho                  */
   int spring;          /* 0 = FENE (Warner), 1 = Hookean                     */
   double b;            /* FENE extensibility; sigma = R / sqrt(b)            */
-  double tau_drag;     /* tau2 of the solvent                                */
+  double tau_drag;     /* solvent drag time: tau2_S (model 1) or tau1_S
+                        * (model 2); 0 = automatic (1 or tau2_S)           */
   double tau_ratio_p;  /* tau1_P / tau2_P (<= 1)                             */
   double force_scale;  /* multiplies the Kolmogorov force amplitude F0       */
   double lambda_set;   /* > 0: use this relaxation time instead of Wi*l/u0   */

@@ -46,9 +46,12 @@ struct StepParams {
   int y0;               // absolute row of local row 0 (forcing phase)
   int wg;               // tile groups (qs == 1 only): tiles along x in bits 0-7,
                         // rows in bits 8-15, bit 16: barrier per Q-node; 0 = off
+  int qe;               // quasi-equilibrium model: 1 component momenta, 2 stresses
+  int pad;
   long long N;  // nx * ny
-  double aS, aP;         // 1 / (2 tau2 + 1) per species
-  double tau2S, tau2P;
+  double aS, aP;         // 1 / (2 tJ + 1) per species
+  double tJS, tJP;       // momentum relaxation time: tau2 (model 1), tau1 (model 2)
+  double pS, pP;         // model 2: 1 / (2 tau2 + 1), the stress inversion
   double c1S, c2S, rS;   // relaxation: g' = c1 g + c2 [(1-r) f* + r f_eq]
   double c1P, c2P, rP;
   double kappa, DQ, F0, kf;

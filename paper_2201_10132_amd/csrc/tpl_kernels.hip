@@ -182,7 +182,7 @@ __device__ __forceinline__ void neq_encode(const double d[25], uint16_t nb[25], 
 // are wave-uniform (scalar loads).
 // One 64-node tile of one lattice (all qs slices of the workgroup take part).
 // red: LDS of qs * 12 * 64 doubles.
-template <typename T, bool ROWTILE, bool NEQ = false>
+template <typename T, bool ROWTILE, bool NEQ = false, bool QE2 = false>
 __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &a,
                                           const StateT<T> &b, const float *__restrict__ rpull,
                                           const float *__restrict__ rstore,
@@ -265,24 +265,49 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   }
   // ---- mixture velocity: exchange of the two species cancels
   const double den = rhoS * p.aS + rhoP * p.aP;
-  const double Ux = ((JSx + 0.5 * Fbx) * p.aS + (JPx + Sx / (2.0 * p.tau2P)) * p.aP) / den;
-  const double Uy = ((JSy + 0.5 * Fby) * p.aS + (JPy + Sy / (2.0 * p.tau2P)) * p.aP) / den;
+  const double Ux = ((JSx + 0.5 * Fbx) * p.aS + (JPx + Sx / (2.0 * p.tJP)) * p.aP) / den;
+  const double Uy = ((JSy + 0.5 * Fby) * p.aS + (JPy + Sy / (2.0 * p.tJP)) * p.aP) / den;
   const bool writer = (slice == 0) && active;
 
   // ---- solvent collision (slice 0 writes)
   {
-    const double JfX = (2.0 * p.tau2S * JSx + rhoS * Ux + p.tau2S * Fbx) * p.aS;
-    const double JfY = (2.0 * p.tau2S * JSy + rhoS * Uy + p.tau2S * Fby) * p.aS;
-    const double usx = JfX / rhoS, usy = JfY / rhoS;
-    const double vx = Ux + p.tau2S * Fbx / rhoS, vy = Uy + p.tau2S * Fby / rhoS;
-    const double us2 = usx * usx + usy * usy, v2 = vx * vx + vy * vy;
+    // model 1: f* about the species' own (inverted) momentum; model 2: f*
+    // with the equilibrium's momentum and the species' own (inverted) stress
+    const double vx = Ux + p.tJS * Fbx / rhoS, vy = Uy + p.tJS * Fby / rhoS;
+    const double v2 = vx * vx + vy * vy;
+    double usx = 0.0, usy = 0.0, Dxx = 0.0, Dxy = 0.0, Dyy = 0.0;
+    if constexpr (!QE2) {
+      usx = (2.0 * p.tJS * JSx + rhoS * Ux + p.tJS * Fbx) * p.aS / rhoS;
+      usy = (2.0 * p.tJS * JSy + rhoS * Uy + p.tJS * Fby) * p.aS / rhoS;
+    } else {
+      // P(f) - rho c_s^2 I with P(f) = (2 tau2 P(g) + rho (c_s^2 I + v v)) / (2 tau2 + 1)
+      double Pxx = 0.0, Pxy = 0.0, Pyy = 0.0;
+#pragma unroll
+      for (int d = 0; d < 9; ++d) {
+        if (C9X[d]) Pxx += gS[d];
+        if (C9Y[d]) Pyy += gS[d];
+        if (C9X[d] && C9Y[d]) Pxy += C9X[d] * C9Y[d] * gS[d];
+      }
+      const double t2 = 1.0 - p.pS;  // 2 tau2 / (2 tau2 + 1)
+      Dxx = t2 * Pxx + p.pS * rhoS * (1.0 / 3.0 + vx * vx) - rhoS / 3.0;
+      Dyy = t2 * Pyy + p.pS * rhoS * (1.0 / 3.0 + vy * vy) - rhoS / 3.0;
+      Dxy = t2 * Pxy + p.pS * rhoS * vx * vy;
+    }
+    const double us2 = usx * usx + usy * usy;
     double jx = 0.0, jy = 0.0;
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
-      const double cu = C9X[d] * usx + C9Y[d] * usy;
       const double cv = C9X[d] * vx + C9Y[d] * vy;
-      const double fs = W9[d] * rhoS * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * us2);
       const double fe = W9[d] * rhoS * (1.0 + 3.0 * cv + 4.5 * cv * cv - 1.5 * v2);
+      double fs;
+      if constexpr (!QE2) {
+        const double cu = C9X[d] * usx + C9Y[d] * usy;
+        fs = W9[d] * rhoS * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * us2);
+      } else {  // second-order Hermite form with the stress D + rho c_s^2 I
+        const double h = Dxx * (C9X[d] * C9X[d] - 1.0 / 3.0) +
+                         Dyy * (C9Y[d] * C9Y[d] - 1.0 / 3.0) + 2.0 * Dxy * C9X[d] * C9Y[d];
+        fs = W9[d] * (rhoS + 3.0 * rhoS * cv + 4.5 * h);
+      }
       const double o = p.c1S * gS[d] + p.c2S * ((1.0 - p.rS) * fs + p.rS * fe);
       if (C9X[d]) jx += C9X[d] * o;
       if (C9Y[d]) jy += C9Y[d] * o;
@@ -361,6 +386,7 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
       pull(std::integral_constant<int, 13>{}, std::integral_constant<int, 25>{});
     }
     double psi = 0.0, Jrx = 0.0, Jry = 0.0, JQx = 0.0, JQy = 0.0;
+    double P2[4][4] = {};  // model 2: second moments sum xi_a xi_b g (a <= b)
 #pragma unroll
     for (int k = 0; k < 25; ++k) {
       psi += g[k];
@@ -368,6 +394,13 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
       if (PV[k][1]) Jry += PV[k][1] * g[k];
       if (PV[k][2]) JQx += PV[k][2] * g[k];
       if (PV[k][3]) JQy += PV[k][3] * g[k];
+      if constexpr (QE2) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b2 = a; b2 < 4; ++b2)
+            if (PV[k][a] && PV[k][b2]) P2[a][b2] += PV[k][a] * PV[k][b2] * g[k];
+      }
     }
     // spring term: kappa Fhat (Q . grad psi^{n-1})
     const T *P = plane(a.PSI, q);
@@ -380,23 +413,59 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
     const double Erx = psi * Ux + sx, Ery = psi * Uy + sy;
     const double EQx = psi * (Kxx * qn.qx + Kxy * qn.qy - p.DQ * qn.fx);
     const double EQy = psi * (Kyx * qn.qx + Kyy * qn.qy - p.DQ * qn.fy);
-    const double Frx = (2.0 * p.tau2P * Jrx + Erx) * p.aP;
-    const double Fry = (2.0 * p.tau2P * Jry + Ery) * p.aP;
-    const double FQx = (2.0 * p.tau2P * JQx + EQx) * p.aP;
-    const double FQy = (2.0 * p.tau2P * JQy + EQy) * p.aP;
-    // (1 - r) f* + r f_eq is the linear equilibrium of the blended fluxes
     double A[4];
-    A[0] = 3.0 * c2w1 * (one_r * Frx + p.rP * Erx);
-    A[1] = 3.0 * c2w1 * (one_r * Fry + p.rP * Ery);
-    A[2] = 3.0 * c2w1 * (one_r * FQx + p.rP * EQx);
-    A[3] = 3.0 * c2w1 * (one_r * FQy + p.rP * EQy);
+    if constexpr (!QE2) {
+      const double Frx = (2.0 * p.tJP * Jrx + Erx) * p.aP;
+      const double Fry = (2.0 * p.tJP * Jry + Ery) * p.aP;
+      const double FQx = (2.0 * p.tJP * JQx + EQx) * p.aP;
+      const double FQy = (2.0 * p.tJP * JQy + EQy) * p.aP;
+      // (1 - r) f* + r f_eq is the linear equilibrium of the blended fluxes
+      A[0] = 3.0 * c2w1 * (one_r * Frx + p.rP * Erx);
+      A[1] = 3.0 * c2w1 * (one_r * Fry + p.rP * Ery);
+      A[2] = 3.0 * c2w1 * (one_r * FQx + p.rP * EQx);
+      A[3] = 3.0 * c2w1 * (one_r * FQy + p.rP * EQy);
+    } else {
+      // f* and f_eq share the imposed fluxes; f* adds the Hermite term of
+      // D = P(f) - psi c_s^2 I, P(f) = (2 tau2 P(g) + psi c_s^2 I) / (2 tau2 + 1)
+      A[0] = 3.0 * c2w1 * Erx;
+      A[1] = 3.0 * c2w1 * Ery;
+      A[2] = 3.0 * c2w1 * EQx;
+      A[3] = 3.0 * c2w1 * EQy;
+      const double t2 = 1.0 - p.pP;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        P2[a][a] = t2 * P2[a][a] + p.pP * psi / 3.0 - psi / 3.0;
+#pragma unroll
+        for (int b2 = a + 1; b2 < 4; ++b2) P2[a][b2] *= t2;
+      }
+    }
     const double h = c2w1 * psi;
+    // model 2: the Hermite term's factor c2 (1 - r) 4.5 w_k, and -tr(D)/3
+    const double hw = 4.5 * one_r * c2w1;
+    const double trD3 = QE2 ? (P2[0][0] + P2[1][1] + P2[2][2] + P2[3][3]) / 3.0 : 0.0;
 #pragma unroll
     for (int k = 0; k < 25; ++k) {
       double t = (k == 0) ? c2w0 * psi : h;
 #pragma unroll
       for (int c = 0; c < 4; ++c)
         if (PV[k][c]) t += PV[k][c] * A[c];
+      if constexpr (QE2) {
+        if (k == 0) {
+          t -= 4.5 * one_r * c2w0 * trD3;
+        } else {
+          // sum_ab D_ab (xi_a xi_b - delta_ab / 3) for xi with two unit entries
+          double hk = -trD3;
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+            if (PV[k][a]) {
+              hk += P2[a][a];
+#pragma unroll
+              for (int b2 = a + 1; b2 < 4; ++b2)
+                if (PV[k][b2]) hk += 2.0 * PV[k][a] * PV[k][b2] * P2[a][b2];
+            }
+          t += hw * hk;
+        }
+      }
       g[k] = p.c1P * g[k] + t;  // post-collision population
       mg[pdir(k)] += g[k];
     }
@@ -463,7 +532,7 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   if (p.qs > 1) __syncthreads();  // red is reused by the workgroup's next tile
 }
 
-template <typename T, int MAXT, bool ROWTILE, bool NEQ = false>
+template <typename T, int MAXT, bool ROWTILE, bool NEQ = false, bool QE2 = false>
 __global__ void __launch_bounds__(MAXT)
     k_step(StepParams p, StateT<T> a, StateT<T> b, const float *__restrict__ rpull,
            const float *__restrict__ rstore, const float *__restrict__ rpsi,
@@ -484,7 +553,8 @@ __global__ void __launch_bounds__(MAXT)
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     tile = ((grp / gpr) * gy + w / gx) * tpr + (grp % gpr) * gx + w % gx;
   }
-  step_tile<T, ROWTILE, NEQ>(p, a, b, rpull, rstore, rpsi, rspull, rsstore, qtab, tile, red);
+  step_tile<T, ROWTILE, NEQ, QE2>(p, a, b, rpull, rstore, rpsi, rspull, rsstore, qtab, tile,
+                                  red);
 }
 
 
@@ -513,11 +583,14 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)
     StepParams pp;
 #define TPL_LD(f) pp.f = d.p.f;
     TPL_LD(nx) TPL_LD(ny) TPL_LD(nqd) TPL_LD(qs) TPL_LD(ntiles) TPL_LD(tiles_per_xcd)
-    TPL_LD(y0) TPL_LD(N) TPL_LD(aS) TPL_LD(aP) TPL_LD(tau2S) TPL_LD(tau2P) TPL_LD(c1S)
+    TPL_LD(y0) TPL_LD(N) TPL_LD(aS) TPL_LD(aP) TPL_LD(tJS) TPL_LD(tJP) TPL_LD(c1S)
     TPL_LD(c2S) TPL_LD(rS) TPL_LD(c1P) TPL_LD(c2P) TPL_LD(rP) TPL_LD(kappa) TPL_LD(DQ)
     TPL_LD(F0) TPL_LD(kf) TPL_LD(src)
 #undef TPL_LD
     pp.wg = 0;
+    pp.qe = 1;
+    pp.pad = 0;
+    pp.pS = pp.pP = 0.0;
     const int rd = parity ^ d.cur0;
     const StateT<T> a{static_cast<T *>(d.XS[rd]), static_cast<T *>(d.XP[rd]),
                       static_cast<T *>(d.PSI[rd]), d.FLD[rd]};
@@ -566,18 +639,25 @@ hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
   if (p.wg && (p.qs != 1 || !rowtile || gsize > 8)) return hipErrorInvalidValue;
   const dim3 g(grid), blk(64 * p.qs * gsize);
 #define TPL_STEP_ARGS p, a, b, r.pull, r.store, r.psi, r.spull, r.sstore, qtab
-#define TPL_STEP_LAUNCH(NEQ)                                                     \
-  if (p.qs * gsize <= 4) {                                                       \
-    if (rowtile)                                                                 \
-      hipLaunchKernelGGL((k_step<T, 256, true, NEQ>), g, blk, lds, s, TPL_STEP_ARGS);  \
-    else                                                                         \
-      hipLaunchKernelGGL((k_step<T, 256, false, NEQ>), g, blk, lds, s, TPL_STEP_ARGS); \
-  } else {                                                                       \
-    if (rowtile)                                                                 \
-      hipLaunchKernelGGL((k_step<T, 512, true, NEQ>), g, blk, lds, s, TPL_STEP_ARGS);  \
-    else                                                                         \
-      hipLaunchKernelGGL((k_step<T, 512, false, NEQ>), g, blk, lds, s, TPL_STEP_ARGS); \
+#define TPL_STEP_LAUNCH2(NEQ, QE2)                                                    \
+  if (p.qs * gsize <= 4) {                                                            \
+    if (rowtile)                                                                      \
+      hipLaunchKernelGGL((k_step<T, 256, true, NEQ, QE2>), g, blk, lds, s, TPL_STEP_ARGS);  \
+    else                                                                              \
+      hipLaunchKernelGGL((k_step<T, 256, false, NEQ, QE2>), g, blk, lds, s, TPL_STEP_ARGS); \
+  } else {                                                                            \
+    if (rowtile)                                                                      \
+      hipLaunchKernelGGL((k_step<T, 512, true, NEQ, QE2>), g, blk, lds, s, TPL_STEP_ARGS);  \
+    else                                                                              \
+      hipLaunchKernelGGL((k_step<T, 512, false, NEQ, QE2>), g, blk, lds, s, TPL_STEP_ARGS); \
   }
+#define TPL_STEP_LAUNCH(NEQ)     \
+  if (p.qe == 2) {               \
+    TPL_STEP_LAUNCH2(NEQ, true)  \
+  } else {                       \
+    TPL_STEP_LAUNCH2(NEQ, false) \
+  }
+  if (p.qe != 1 && p.qe != 2) return hipErrorInvalidValue;
   if constexpr (std::is_same<T, float>::value) {
     if (neq) {
       TPL_STEP_LAUNCH(true)
@@ -589,6 +669,7 @@ hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
     TPL_STEP_LAUNCH(false)
   }
 #undef TPL_STEP_LAUNCH
+#undef TPL_STEP_LAUNCH2
 #undef TPL_STEP_ARGS
   return hipGetLastError();
 }

@@ -38,11 +38,12 @@ struct Config {
   int nx = 0, ny = 0, periods = 1;
   double Re = 0, Wi = 0, beta = 1, u0 = 0.05;
   int nq = 16, spring = 0, precision = TPL_FP64, pert_modes = 1;
-  double b = 25.0, phi = 0.01, tau_drag = 1.0, tau_ratio_p = 1.0;
+  double b = 25.0, phi = 0.01, tau_drag = 0.0, tau_ratio_p = 1.0;
   double force_scale = 1.0, lambda_set = 0.0, drift_cap = 0.1, drift_relax = 1.0;
   long long pre_steps = -1;
   int qsplit = 0, time_kernels = 0;
   int group_x = 1, group_y = 1, group_sync = 0, autotune = 1;
+  int qe_model = 1;
 };
 
 struct Derived {
@@ -66,6 +67,7 @@ int derive(const Config &c, Derived &d) {
   if (!(c.b > 1)) return fail(TPL_EINVAL, "b must be > 1");
   if (!(c.tau_ratio_p > 0 && c.tau_ratio_p <= 1))
     return fail(TPL_EINVAL, "tau_ratio_p must be in (0,1] (tau1 <= tau2)");
+  if (c.qe_model != 1 && c.qe_model != 2) return fail(TPL_EINVAL, "qe_model must be 1 or 2");
   // the step kernel addresses a plane with 32-bit byte offsets: 8 N < 2^32
   if ((long long)c.nx * c.ny >= (1LL << 29)) return fail(TPL_EINVAL, "lattice too large");
 
@@ -89,16 +91,28 @@ int derive(const Config &c, Derived &d) {
     d.G *= d.lambda / c.lambda_set;
     d.lambda = c.lambda_set;
   }
-  d.tau1S = d.nuS / kCs2;
-  d.tau2S = c.tau_drag;
-  d.tau2P = d.sigma * d.sigma / (2.0 * kCs2 * d.lambda);
-  d.tau1P = c.tau_ratio_p * d.tau2P;
-  d.DQ = kCs2 * d.tau2P;
+  if (c.qe_model == 2) {
+    // stress-tensor quasi-equilibria (Sec. V model (ii)): stresses relax with
+    // tau2 (viscosity c_s^2 tau2), momenta and fluxes with tau1 (drag,
+    // diffusivities)
+    d.tau2S = d.nuS / kCs2;
+    d.tau1S = c.tau_drag > 0 ? c.tau_drag : d.tau2S;  // 0: automatic
+    d.tau1P = d.sigma * d.sigma / (2.0 * kCs2 * d.lambda);
+    d.tau2P = d.tau1P / c.tau_ratio_p;
+    d.DQ = kCs2 * d.tau1P;
+  } else {
+    d.tau1S = d.nuS / kCs2;
+    d.tau2S = c.tau_drag > 0 ? c.tau_drag : 1.0;  // 0: automatic
+    d.tau2P = d.sigma * d.sigma / (2.0 * kCs2 * d.lambda);
+    d.tau1P = c.tau_ratio_p * d.tau2P;
+    d.DQ = kCs2 * d.tau2P;
+  }
   d.F0 = c.force_scale * d.nu * c.u0 * d.kf * d.kf;
-  d.Sc = d.nuS / (kCs2 * d.tau2P);
+  d.Sc = d.nuS / d.DQ;
   if (d.tau1S > d.tau2S * (1.0 + 1e-12))
     return fail(TPL_EINVAL, "solvent tau1 = " + std::to_string(d.tau1S) +
-                                " exceeds tau2 = tau_drag (H-theorem ordering)");
+                                " exceeds tau2 = " + std::to_string(d.tau2S) +
+                                " (H-theorem ordering)");
 
   // Q-disk: half-integer nodes strictly inside |Q| < R, row by row.
   const int nq = c.nq;
@@ -171,7 +185,9 @@ int derive(const Config &c, Derived &d) {
     m += d.peq[q] * (d.qtab[q].qx * d.qtab[q].fx + d.qtab[q].qy * d.qtab[q].fy);
   }
   d.meq = 0.5 * m;
-  d.kappa = d.rhoP0 > 0 ? d.G * d.tau2P / (d.rhoP0 * d.meq) : 0.0;
+  // the polymer flux relaxes with tau2_P (model 1) or tau1_P (model 2)
+  const double tJ = c.qe_model == 2 ? d.tau1P : d.tau2P;
+  d.kappa = d.rhoP0 > 0 ? d.G * tJ / (d.rhoP0 * d.meq) : 0.0;
   // the BF16 form addresses one Q-node's 25 remainder planes (and 5 moment
   // planes) with 32-bit offsets and reads remainders as aligned dwords
   if (c.precision == TPL_BF16NEQ && (70LL * c.nx * c.ny >= (1LL << 32) || (c.nx * c.ny) % 2))
@@ -283,10 +299,14 @@ StepParams make_step_params(const tpl_ctx *x, int nx, int ny, int qs_req) {
   else if (x->tuned && nx == x->c.nx && ny == x->c.ny && x->wg_tuned)
     set_group(p, x->wg_tuned & 255, (x->wg_tuned >> 8) & 255, (x->wg_tuned >> 16) & 1);
   p.y0 = 0;
-  p.aS = 1.0 / (2.0 * d.tau2S + 1.0);
-  p.aP = 1.0 / (2.0 * d.tau2P + 1.0);
-  p.tau2S = d.tau2S;
-  p.tau2P = d.tau2P;
+  const bool m2 = x->c.qe_model == 2;
+  p.qe = m2 ? 2 : 1;
+  p.tJS = m2 ? d.tau1S : d.tau2S;
+  p.tJP = m2 ? d.tau1P : d.tau2P;
+  p.aS = 1.0 / (2.0 * p.tJS + 1.0);
+  p.aP = 1.0 / (2.0 * p.tJP + 1.0);
+  p.pS = 1.0 / (2.0 * d.tau2S + 1.0);
+  p.pP = 1.0 / (2.0 * d.tau2P + 1.0);
   const double bS = 1.0 / (2.0 * d.tau1S + 1.0), bP = 1.0 / (2.0 * d.tau1P + 1.0);
   p.c1S = 1.0 - 2.0 * bS;
   p.c2S = 2.0 * bS;
@@ -738,6 +758,7 @@ const Key kKeys[] = {
     {"lambda", &Config::lambda_set, nullptr, nullptr},
     {"drift_cap", &Config::drift_cap, nullptr, nullptr},
     {"drift_relax", &Config::drift_relax, nullptr, nullptr},
+    {"qe_model", nullptr, &Config::qe_model, nullptr},
     {"precision", nullptr, &Config::precision, nullptr},
     {"pert_modes", nullptr, &Config::pert_modes, nullptr},
     {"pre_steps", nullptr, nullptr, &Config::pre_steps},
@@ -1759,6 +1780,9 @@ int tpl_batch_set_stream(tpl_batch *b, void *hip_stream) {
 
 int tpl_batch_init(tpl_batch *b) {
   if (!b) return fail(TPL_EINVAL, "null batch");
+  for (tpl_ctx *x : b->inst)
+    if (x->c.qe_model != 1)
+      return fail(TPL_EINVAL, "the batched step runs the component-momentum model (qe_model 1)");
   b->inited = false;
   drop_graph(b);
   if (!b->stream) {  // the batch's own stream, made on first use

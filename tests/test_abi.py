@@ -32,6 +32,9 @@ CASES = [
     dict(nx=1024, ny=1024, Re=60.0, Wi=1.0, beta=0.7, periods=4),
     dict(nx=1024, ny=1024, Re=60.0, Wi=0.0, beta=0.7, periods=4),
     dict(nx=256, ny=256, Re=20.0, Wi=0.5, beta=0.7, periods=4, nq=8, spring=1),
+    dict(nx=256, ny=256, Re=20.0, Wi=0.5, beta=0.7, periods=4, nq=8, qe_model=2),
+    dict(nx=1024, ny=1024, Re=60.0, Wi=1.0, beta=0.7, periods=4, qe_model=2, tau_drag=0.01,
+         tau_ratio_p=0.5),
 ]
 
 
@@ -40,10 +43,11 @@ def test_derived_parameters_match_oracle(case):
     c = dict(case)
     nq = c.pop("nq", 16)
     spring = c.pop("spring", 0)
+    extra = {k: c.pop(k) for k in ("qe_model", "tau_drag", "tau_ratio_p") if k in c}
     t = P.Tpl(c["nx"], c["ny"], c["Re"], c["Wi"], c["beta"], periods=c["periods"], nq=nq,
-              spring=spring)
+              spring=spring, **extra)
     o = oracle.OracleSim(1, c["ny"], nq=nq, spring=spring, Re=c["Re"], Wi=c["Wi"],
-                         beta=c["beta"], periods=c["periods"]).derived()
+                         beta=c["beta"], periods=c["periods"], **extra).derived()
     assert t.nqd == oracle.OracleSim(1, 1, nq=nq).nqd
     pairs = dict(kf="kf", l="l", nu="nu", nuS="nuS", G="G", tau1S="tau1S", tau2S="tau2S",
                  tau1P="tau1P", tau2P="tau2P", lambda_eff="lambda", sigma="sigma", R="R",
