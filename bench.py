@@ -156,6 +156,23 @@ def main():
         forms["bf16neq_4096x4096_nq8"] = form_entry(b16l, None)
         forms["bf16neq_4096x4096_nq8"]["speedup_vs_fp32"] = round(b16l["mlups"] / f32l["mlups"], 3)
         out["precision_forms"] = forms
+    if not args.no_forms:
+        # the stress-tensor quasi-equilibrium model (Sec. V model (ii)): same
+        # bytes, second moments added to the arithmetic; drag time tau1_S =
+        # tau2_S / 4, polymer stresses relaxing at half the flux rate
+        nuS = main64["nuS"]
+        m2 = dict(qe_model=2, tau_drag=0.25 * nuS * 3.0, tau_ratio_p=0.5)
+        out["qe_model2"] = {
+            "params": {"tau_drag": m2["tau_drag"], "tau_ratio_p": 0.5},
+            "fp64_1024x1024_nq16": form_entry(
+                measure(torch, w, 0, args.steps, args.warmup, args.pre_steps, **m2), main64),
+            "fp32_1024x1024_nq16": form_entry(
+                measure(torch, w, 1, args.steps, args.warmup, args.pre_steps, **m2), main64),
+        }
+        for k in ("fp64_1024x1024_nq16", "fp32_1024x1024_nq16"):
+            e = out["qe_model2"][k]
+            e.pop("amplitude_rel_err_vs_fp64")  # another model: not comparable
+            e["speed_vs_model1_fp64"] = e.pop("speedup_vs_fp64")
     if not args.no_growth:
         out["growth_rate"] = measure_growth(torch, dict(w, nq=BATCH["nq"]), args.pre_steps,
                                             args.growth_steps)
@@ -179,15 +196,16 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def measure(torch, w, precision, steps, warmup, pre_steps) -> dict:
+def measure(torch, w, precision, steps, warmup, pre_steps, **params) -> dict:
     """Init the workload, then time `steps` steps (HIP events on the library's
-    stream and wall clock, both bracketed by device synchronisation)."""
+    stream and wall clock, both bracketed by device synchronisation).  params:
+    further library parameters (the collision model)."""
     import paper_2201_10132_amd as P
 
     stream = torch.cuda.Stream()
     t = P.Tpl(w["nx"], w["ny"], w["Re"], w["Wi"], w["beta"], periods=w["periods"],
               nq=w["nq"], spring=w["spring"], pre_steps=pre_steps, pert_modes=1,
-              precision=precision)
+              precision=precision, **params)
     t.set_stream(stream.cuda_stream)
     t0 = time.perf_counter()
     t.init(seed=w["seed"], perturbation=w["perturbation"])
@@ -207,7 +225,7 @@ def measure(torch, w, precision, steps, warmup, pre_steps) -> dict:
     res = dict(mlups=N * steps / wall / 1e6, wall_ms=wall / steps * 1e3,
                kernel_ms=ev0.elapsed_time(ev1) / steps, init_s=init_s, nqd=t.nqd,
                bytes_step=t.query("bytes_per_step"), amplitude=d1["amplitude"],
-               qsplit=t.query("qsplit_used"),
+               qsplit=t.query("qsplit_used"), nuS=t.query("nuS"),
                group=[int(t.query(k)) for k in ("group_x_used", "group_y_used", "group_sync_used")],
                tune_ms=round(t.query("tune_ms"), 1),
                conservation={"mass_S": abs(d1["mass_S"] / d0["mass_S"] - 1),

@@ -1,7 +1,11 @@
 """Summarise rocprofv3 result databases into short text files under profiles/.
 
-  python paper_2201_10132_amd/profile_summary.py stats <run_results.db> <out.md> <command>
-  python paper_2201_10132_amd/profile_summary.py traffic <fetch.db> <write.db> <kernel-substring> <out.md> <command...>
+  python paper_2201_10132_amd/profile_summary.py stats <run_results.db> <out.md> [--bench-log <log>] <command>
+  python paper_2201_10132_amd/profile_summary.py traffic <fetch.db> <write.db> <kernel-substring> <out.md> [--last N] <command...>
+
+--bench-log: the log of the profiled bench.py run; its HIP-event kernel time
+is quoted beside the trace's average.  --last N: only the last N matching
+dispatches (the steps after the launch-shape tuning of the first step).
 
 The traffic summary calibrates FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
 with the largest plain copy dispatch recorded in the same runs (a device copy
@@ -27,7 +31,7 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def stats(db, out, command):
+def stats(db, out, command, bench_log=None):
     c = sqlite3.connect(db)
     rows = list(c.execute("select name, total_calls, total_duration, average, percentage "
                           "from top_kernels order by total_duration desc limit 15"))
@@ -35,6 +39,18 @@ def stats(db, out, command):
              "| kernel | calls | total (ms) | average (ms) | % |", "|---|---|---|---|---|"]
     for n, calls, tot, avg, pct in rows:
         lines.append(f"| `{n[:90]}` | {calls} | {tot / 1e3:.1f} | {avg / 1e3:.3f} | {pct:.1f} |")
+    if bench_log:
+        import json
+        import re
+        for line in open(bench_log):
+            if line.startswith("{"):
+                rec = json.loads(line)
+                lines += ["", f"bench.py line of the same run: kernel_ms {rec.get('kernel_ms')} "
+                          f"(HIP events on the library's stream), launch {rec.get('launch')}"]
+            m = re.match(r"# precision=(\d) (\S+) nq=(\d+): .*?([0-9.]+) ms/step", line)
+            if m:
+                lines.append(f"- bench progress: precision {m.group(1)}, {m.group(2)}, nq {m.group(3)}: "
+                             f"{m.group(4)} ms/step")
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -46,13 +62,18 @@ def _per_kernel(db, counter):
     return list(c.execute(q, (counter,)))
 
 
-def traffic(fetch_db, write_db, kernel, out, command, copy_bytes=4 * 2 ** 30):
+def traffic(fetch_db, write_db, kernel, out, command, copy_bytes=4 * 2 ** 30, last=None):
     f = _per_kernel(fetch_db, "FETCH_SIZE")
     w = _per_kernel(write_db, "WRITE_SIZE")
     cf = max(v for n, g, v in f if "copyBuffer" in n) * 1024.0
     cw = max(v for n, g, v in w if "copyBuffer" in n) * 1024.0
-    kf = [v * 1024.0 for n, g, v in f if kernel in n]
-    kw = [v * 1024.0 for n, g, v in w if kernel in n]
+    mf = [(n, v) for n, g, v in f if kernel in n]
+    mw = [(n, v) for n, g, v in w if kernel in n]
+    if last:
+        mf, mw = mf[-last:], mw[-last:]
+    names = sorted({n.split("(")[0] for n, _ in mf + mw})
+    kf = [v * 1024.0 for n, v in mf]
+    kw = [v * 1024.0 for n, v in mw]
     ff, fw = copy_bytes / cf, copy_bytes / cw
     fetch = sum(kf) / len(kf) * ff
     write = sum(kw) / len(kw) * fw
@@ -60,7 +81,8 @@ def traffic(fetch_db, write_db, kernel, out, command, copy_bytes=4 * 2 ** 30):
     lines = [f"# HBM traffic of `{kernel}`", "", f"Commands: `{command}`", "",
              f"- calibration copy: {copy_bytes / 2**30:.1f} GiB read + written; FETCH_SIZE reads "
              f"{cf / 2**30:.3f} GiB (factor {ff:.3f}), WRITE_SIZE reads {cw / 2**30:.3f} GiB (factor {fw:.3f})",
-             f"- dispatches measured: {len(kf)} (fetch run), {len(kw)} (write run)",
+             f"- dispatches measured: {len(kf)} (fetch run), {len(kw)} (write run) of "
+             + ", ".join(f"`{n}`" for n in names),
              f"- fetched per launch (calibrated): {fetch / 1e9:.3f} GB",
              f"- written per launch (calibrated): {write / 1e9:.3f} GB",
              f"- total per launch: {(fetch + write) / 1e9:.3f} GB",
@@ -73,10 +95,22 @@ def traffic(fetch_db, write_db, kernel, out, command, copy_bytes=4 * 2 ** 30):
     print("\n".join(lines))
 
 
+def _option(args, name):
+    if name in args:
+        i = args.index(name)
+        v = args[i + 1]
+        del args[i:i + 2]
+        return v
+    return None
+
+
 if __name__ == "__main__":
-    if sys.argv[1] == "stats":
-        stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
-    elif sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], " ".join(sys.argv[6:]))
+    a = sys.argv[1:]
+    if a[0] == "stats":
+        log = _option(a, "--bench-log")
+        stats(a[1], a[2], " ".join(a[3:]), bench_log=log)
+    elif a[0] == "traffic":
+        last = _option(a, "--last")
+        traffic(a[1], a[2], a[3], a[4], " ".join(a[5:]), last=int(last) if last else None)
     else:
         raise SystemExit(__doc__)

@@ -176,3 +176,19 @@ def test_tile_group_knobs():
     assert t.query("group_x") == 4 and t.query("group_y") == 2 and t.query("autotune") == 0
     assert t.query("group_x_used") == 0 and t.query("tune_ms") == 0
     t.close()
+
+
+def test_qe_model_parameters():
+    """Model 2: viscosity from tau2_S, drag time tau1_S = tau_drag (automatic:
+    tau2_S) not above tau2_S; Q-diffusivity from tau1_P."""
+    t = P.Tpl(256, 256, 20.0, 0.5, 0.8, periods=2, nq=8)
+    nuS = t.query("nuS")
+    t.set_param("qe_model", 2)  # tau_drag automatic: a BGK solvent
+    assert abs(t.query("tau2S") - 3 * nuS) < 1e-15 and t.query("tau1S") == t.query("tau2S")
+    t.set_param("tau_drag", 0.5 * t.query("tau2S"))
+    assert abs(t.query("DQ") - t.query("tau1P") / 3) < 1e-15
+    with pytest.raises(P.TplError):
+        t.set_param("tau_drag", 2 * t.query("tau2S"))
+    with pytest.raises(P.TplError):
+        t.set_param("qe_model", 3)
+    t.close()
