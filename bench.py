@@ -11,10 +11,12 @@ of both species, lagged-field write) over the lattice.
 Prints one JSON line: MLUPS (10^6 r-node updates per second, each carrying
 9 + 25 * 208 populations), the roofline of the step kernel, and the FP64 CPU
 oracle timed on a bounded sample of the same workload.  Extra entries: the
-FP32 storage form (1024^2 and 4096^2), FP64 and FP32 at NQ = 8, and the
-batched sweep of 256 seeded instances against the same instances stepped
-one by one, and the learned coarse correction (training pipeline, judged
-errors, corrected-step cost).  Every workload starts from a base state of
+FP32 and BF16 storage forms (1024^2 at NQ 16; 4096^2 at NQ 6 beside its FP64
+run), FP64 and FP32 at NQ = 6, the stress-tensor collision model, the growth
+rate of the three storage forms over 2000 steps, the batched sweep of 256
+seeded instances against the same instances stepped one by one, and the
+learned coarse correction (training pipeline, judged errors, corrected-step
+cost).  Every workload starts from a base state of
 --pre-steps column steps (outside the timed region).
 """
 from __future__ import annotations
@@ -30,13 +32,13 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = dict(nx=1024, ny=1024, periods=4, Re=60.0, Wi=1.0, beta=0.7, nq=16, spring=0,
                 seed=0, perturbation=1e-4)
-# precision-form workload: 4096^2, 16 periods (same l as above), NQ = 8 (NQ = 6
-# diverges at these parameters, and NQ = 8 fits only with FP32 storage)
-WORKLOAD_FP32_LARGE = dict(nx=4096, ny=4096, periods=16, Re=60.0, Wi=1.0, beta=0.7, nq=8,
+# precision-form workload: 4096^2, 16 periods (same l as above), NQ = 6 (the
+# largest Q-grid at which the FP64 reference, 2 x 115 GB, fits one GPU)
+WORKLOAD_FP32_LARGE = dict(nx=4096, ny=4096, periods=16, Re=60.0, Wi=1.0, beta=0.7, nq=6,
                            spring=0, seed=0, perturbation=1e-4)
 # batched sweep: 256 seeded instances (sizes from {128..512}^2, Re, Wi, beta
-# drawn per instance), FP32 storage, NQ = 8
-BATCH = dict(instances=256, nq=8, precision=1)
+# drawn per instance), FP32 storage, NQ = 6
+BATCH = dict(instances=256, nq=6, precision=1)
 # base-state column steps before the timed steps (init only, never timed);
 # the library's own default is 5 max(l^2/nu, lambda), ~244k steps here
 DEFAULT_PRE_STEPS = 3000
@@ -97,7 +99,7 @@ def main():
     ap.add_argument("--traffic-file", default=os.path.join(
         ROOT, "profiles", "k_step_fp64_kolmogorov1024_nq16_traffic.txt"))
     ap.add_argument("--batch-traffic-file", default=os.path.join(
-        ROOT, "profiles", "k_step_batch_fp32_kolmogorov_batch256_nq8_traffic.txt"))
+        ROOT, "profiles", "k_step_batch_fp32_kolmogorov_batch256_nq6_traffic.txt"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -139,22 +141,28 @@ def main():
         forms = {}
         f32 = measure(torch, w, 1, args.steps, args.warmup, args.pre_steps)
         forms["fp32_1024x1024_nq16"] = form_entry(f32, main64)
-        w3 = WORKLOAD_FP32_LARGE
-        f32l = measure(torch, w3, 1, max(5, args.steps // 2), args.warmup, args.pre_steps)
-        forms["fp32_4096x4096_nq8"] = form_entry(f32l, None)
         # FP64 at the batched sweep's NQ (the matched-NQ reference)
-        w8 = dict(w, nq=BATCH["nq"])
-        f64q8 = measure(torch, w8, 0, args.steps, args.warmup, args.pre_steps)
-        forms["fp64_1024x1024_nq8"] = form_entry(f64q8, None)
-        f32q8 = measure(torch, w8, 1, args.steps, args.warmup, args.pre_steps)
-        forms["fp32_1024x1024_nq8"] = form_entry(f32q8, f64q8)
+        wq = dict(w, nq=BATCH["nq"])
+        nq = BATCH["nq"]
+        f64q = measure(torch, wq, 0, args.steps, args.warmup, args.pre_steps)
+        forms[f"fp64_1024x1024_nq{nq}"] = form_entry(f64q, None)
+        f32q = measure(torch, wq, 1, args.steps, args.warmup, args.pre_steps)
+        forms[f"fp32_1024x1024_nq{nq}"] = form_entry(f32q, f64q)
         # BF16 non-equilibrium form (precision 2)
         b16 = measure(torch, w, 2, args.steps, args.warmup, args.pre_steps)
         forms["bf16neq_1024x1024_nq16"] = form_entry(b16, main64)
         forms["bf16neq_1024x1024_nq16"]["speedup_vs_fp32"] = round(b16["mlups"] / f32["mlups"], 3)
-        b16l = measure(torch, w3, 2, max(5, args.steps // 2), args.warmup, args.pre_steps)
-        forms["bf16neq_4096x4096_nq8"] = form_entry(b16l, None)
-        forms["bf16neq_4096x4096_nq8"]["speedup_vs_fp32"] = round(b16l["mlups"] / f32l["mlups"], 3)
+        # the large precision-form workload, each form against the FP64 run
+        w3 = WORKLOAD_FP32_LARGE
+        tag = f"4096x4096_nq{w3['nq']}"
+        n3 = max(5, args.steps // 2)
+        f64l = measure(torch, w3, 0, n3, args.warmup, args.pre_steps)
+        forms[f"fp64_{tag}"] = form_entry(f64l, None)
+        f32l = measure(torch, w3, 1, n3, args.warmup, args.pre_steps)
+        forms[f"fp32_{tag}"] = form_entry(f32l, f64l)
+        b16l = measure(torch, w3, 2, n3, args.warmup, args.pre_steps)
+        forms[f"bf16neq_{tag}"] = form_entry(b16l, f64l)
+        forms[f"bf16neq_{tag}"]["speedup_vs_fp32"] = round(b16l["mlups"] / f32l["mlups"], 3)
         out["precision_forms"] = forms
     if not args.no_forms:
         # the stress-tensor quasi-equilibrium model (Sec. V model (ii)): same
@@ -186,7 +194,7 @@ def main():
             if tb is not None:
                 bt["roofline"]["traffic"] = round(tb * bt["bytes_active_fraction"])
         if "precision_forms" in out:  # (ii) plain FP64 lattice at the sweep's NQ
-            ref = out["precision_forms"]["fp64_1024x1024_nq8"]["mlups"]
+            ref = out["precision_forms"][f"fp64_1024x1024_nq{BATCH['nq']}"]["mlups"]
             out["batched"]["speedup_vs_fp64_plain_matched_nq"] = round(
                 out["batched"]["mlups"] / ref, 3)
     if not args.no_learned:

@@ -4,7 +4,7 @@ Runs, in one process: a plain device-to-device copy of a known size (the
 calibration for the HBM byte counters), then the 1024 x 1024, NQ = 16 FP64
 workload for a few steps (short base-state run, since only the step kernel
 is measured), or with --batch N the first N instances of the seeded batched
-sweep (FP32, NQ = 8) stepped together with a fixed launch shape (plain
+sweep (FP32, NQ = 6) stepped together with a fixed launch shape (plain
 launches, no graph, so that every dispatch is the measured step).  Usage
 under the profiler:
   rocprofv3 --pmc FETCH_SIZE -d <dir> -o run -- python paper_2201_10132_amd/profile_run.py
@@ -27,6 +27,7 @@ def main():
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--batch", type=int, default=0, help="instances of the batched sweep")
     ap.add_argument("--qsplit", type=int, default=4, help="Q-slices of the batched step")
+    ap.add_argument("--batch-nq", type=int, default=6, help="Q points per axis of the batched sweep")
     args = ap.parse_args()
     import torch
     import paper_2201_10132_amd as P
@@ -41,7 +42,7 @@ def main():
     if args.batch:
         from tests import inputs
 
-        b = P.Batch(inputs.c4_instances(args.batch), precision=1, nq=8, pre_steps=100,
+        b = P.Batch(inputs.c4_instances(args.batch), precision=1, nq=args.batch_nq, pre_steps=100,
                     autotune=0, qsplit=args.qsplit, graph_steps=0)
         b.init()
         b.step(args.steps)
