@@ -79,18 +79,22 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--every", type=int, default=None)
+    ap.add_argument("--pre-steps", type=int, default=3000,
+                    help="base-state column steps (-1: the library's 5 max(l^2/nu, lambda))")
     args = ap.parse_args()
     res = dict(run=args.what)
     if args.what == "stability":
         steps, nq, every = args.steps or 20000, args.nq or 6, args.every or 1000
-        r = track(256, 256, 1, 1.0, nq, TPL_FP64, steps, every, tag=f"stability nq{nq}")
+        r = track(256, 256, 1, 1.0, nq, TPL_FP64, steps, every, pre_steps=args.pre_steps,
+                  tag=f"stability nq{nq}")
         res.update(nq=nq, steps=steps, failed=r["failed"], A_end=r["A"][-1],
                    mass_S=r["mass_S"], mass_P=r["mass_P"], wall_s=round(r["wall_s"], 1))
     elif args.what == "c2":
         steps, nq, every = args.steps or 20000, args.nq or 16, args.every or 250
-        res.update(nq=nq, steps=steps, cases=[])
+        res.update(nq=nq, steps=steps, pre_steps=args.pre_steps, cases=[])
         for Wi in (0.0, 1.0):
-            r = track(1024, 1024, 4, Wi, nq, TPL_FP64, steps, every, tag=f"c2 Wi {Wi}")
+            r = track(1024, 1024, 4, Wi, nq, TPL_FP64, steps, every, pre_steps=args.pre_steps,
+                      tag=f"c2 Wi {Wi}")
             g, win = fit_gamma(r["n"], r["A"], 1000)
             res["cases"].append(dict(Wi=Wi, gamma=g, fit_window=win, A_end=r["A"][-1],
                                      A_max=float(np.nanmax(r["A"])), failed=r["failed"],
@@ -101,7 +105,8 @@ def main():
         steps, nq, every = args.steps or 2000, args.nq or 6, args.every or 100
         res.update(nq=nq, steps=steps, forms={})
         for name, prec in (("fp64", TPL_FP64), ("fp32", TPL_FP32), ("bf16neq", TPL_BF16NEQ)):
-            r = track(4096, 4096, 16, 1.0, nq, prec, steps, every, tag=f"c3 {name}")
+            r = track(4096, 4096, 16, 1.0, nq, prec, steps, every, pre_steps=args.pre_steps,
+                      tag=f"c3 {name}")
             g, win = fit_gamma(r["n"], r["A"], steps // 4)
             res["forms"][name] = dict(gamma=g, fit_window=win, A=r["A"], failed=r["failed"],
                                       mass_S=r["mass_S"], mass_P=r["mass_P"],
