@@ -278,7 +278,8 @@ def measure_batch(torch, n, steps, warmup, pre_steps, obo_steps) -> dict:
         "steps": steps, "mlups": round(nodes * steps / wall / 1e6, 3),
         "ms_per_step": round(wall / steps * 1e3, 4), "kernel_ms": round(kernel_ms, 4),
         "roofline": roofline(dict(bytes_step=b.query("bytes_per_step"), kernel_ms=kernel_ms), None),
-        "qsplit": int(b.query("qsplit_used")), "grid": int(b.query("grid_used")),
+        "qsplit": int(b.query("qsplit_used")), "group": int(b.query("group_used")),
+        "grid": int(b.query("grid_used")),
         "items": int(b.query("items")), "graph_steps": int(b.query("graph_steps")),
         "tune_ms": round(b.query("tune_ms"), 1), "init_s": round(init_s, 2),
         "pre_steps": pre_steps, "unstable": int(b.query("unstable")),
@@ -303,7 +304,7 @@ def measure_batch(torch, n, steps, warmup, pre_steps, obo_steps) -> dict:
     res["one_by_one_mlups"] = round(nodes * obo_steps / wall1 / 1e6, 3)
     res["speedup_vs_one_by_one"] = round(res["mlups"] / res["one_by_one_mlups"], 3)
     print(f"# batch {n} instances: init {init_s:.1f} s, {kernel_ms:.3f} ms/step, "
-          f"qsplit={res['qsplit']} grid={res['grid']}, one-by-one "
+          f"qsplit={res['qsplit']} group={res['group']} grid={res['grid']}, one-by-one "
           f"{res['one_by_one_mlups']} MLUPS", file=sys.stderr, flush=True)
     b.close()
     return res

@@ -253,10 +253,13 @@ tpl_batch *tpl_batch_create(const tpl_instance *inst, int n, int precision);
  * the launch shape):
  *   qsplit 0       Q-slices per tile (0: chosen by the autotuner)
  *   grid 0         workgroups per launch (0: chosen by the autotuner)
+ *   group 0        consecutive tiles per workgroup, one wave each, with one
+ *                  Q-slice: 1, 2, 4 or 8 (0: chosen by the autotuner)
  *   autotune 1     time the candidate shapes at tpl_batch_init (qsplit 1, 2,
- *                  4, 8 x one workgroup per tile or a persistent grid of one
- *                  or two workgroups per CU slot) and keep the fastest;
- *                  0: heuristic shape
+ *                  4, 8 at one tile per workgroup, then groups of 2, 4, 8
+ *                  tiles, then a persistent grid of one or two workgroups
+ *                  per CU slot for the best) and keep the fastest; every
+ *                  shape gives bitwise the same step; 0: heuristic shape
  *   graph_steps 20 steps captured per HIP graph (< 2: plain launches)
  *   time_kernels 0 1 = time tpl_batch_step with HIP events (kernel_ms)
  * Any other key is a tpl_set_param key applied to every instance before
@@ -266,7 +269,7 @@ int tpl_batch_set_param(tpl_batch *b, const char *key, double value);
 /* Keys: the launch keys above and instances, active (not flagged unstable),
  * unstable, items (tiles per launch), nodes (r-nodes of the active
  * instances), bytes_per_step (algorithmic bytes of the active instances),
- * bytes_state (all instances), qsplit_used, grid_used, rowtile, kernel_ms
+ * bytes_state (all instances), qsplit_used, group_used, grid_used, rowtile, kernel_ms
  * (mean time of one step, needs time_kernels), kernel_steps, tune_ms, step. */
 int tpl_batch_query(const tpl_batch *b, const char *key, double *out);
 

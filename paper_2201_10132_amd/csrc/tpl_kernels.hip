@@ -562,15 +562,24 @@ __global__ void __launch_bounds__(MAXT)
 // Workgroups walk a flat list of (instance, tile) items with a fixed stride;
 // the item index is remapped so that each XCD works through a contiguous
 // range of items.  parity selects which half of every instance is read.
+// With group > 1 (one Q-slice) a workgroup takes `group` consecutive items,
+// one wave each, so that neighbouring tiles' overlapping stencil reads meet
+// in the caches; units of `group` items are what the grid and the XCD
+// mapping count.
 template <typename T, int MAXT, bool ROWTILE>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)))
     k_step_batch(const InstDev *__restrict__ inst, int ninst, int nitems, int items_per_xcd,
-                 int parity) {
+                 int parity, int group) {
   extern __shared__ double red[];
-  const int span = items_per_xcd > 0 ? 8 * items_per_xcd : nitems;
+  const int nunits = (nitems + group - 1) / group;
+  const int span = items_per_xcd > 0 ? 8 * items_per_xcd : nunits;
+  const int w = group > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
   for (int it = blockIdx.x; it < span; it += gridDim.x) {
-    const int item = items_per_xcd > 0 ? (it & 7) * items_per_xcd + (it >> 3) : it;
-    if (item >= nitems) continue;  // uniform over the workgroup
+    const int unit = items_per_xcd > 0 ? (it & 7) * items_per_xcd + (it >> 3) : it;
+    const int item = unit * group + w;
+    // uniform over the wave; over the workgroup too when group == 1, where
+    // Q-slices synchronise (with group > 1 there is one slice and no barrier)
+    if (item >= nitems) continue;
     int lo = 0, hi = ninst - 1;    // last instance with item0 <= item
     const InstDev CONSTANT_AS *ci = cst(inst);  // read-only table: scalar loads
     while (lo < hi) {
@@ -603,31 +612,33 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)
 
 template <typename T>
 hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs, int grid,
-                             bool rowtile, int parity, hipStream_t s) {
+                             bool rowtile, int parity, hipStream_t s, int group) {
+  if (group < 1 || (group > 1 && qs != 1) || qs * group > 8) return hipErrorInvalidValue;
   const size_t lds = qs > 1 ? (size_t)qs * 12 * 64 * sizeof(double) : 0;
-  const int per_xcd = (grid % 8 == 0 && nitems >= 64) ? (nitems + 7) / 8 : 0;
-  const dim3 g(grid), blk(64 * qs);
-  if (qs <= 4) {
+  const int nunits = (nitems + group - 1) / group;
+  const int per_xcd = (grid % 8 == 0 && nunits >= 64) ? (nunits + 7) / 8 : 0;
+  const dim3 g(grid), blk(64 * qs * group);
+  if (qs * group <= 4) {
     if (rowtile)
       hipLaunchKernelGGL((k_step_batch<T, 256, true>), g, blk, lds, s, inst, ninst, nitems,
-                         per_xcd, parity);
+                         per_xcd, parity, group);
     else
       hipLaunchKernelGGL((k_step_batch<T, 256, false>), g, blk, lds, s, inst, ninst, nitems,
-                         per_xcd, parity);
+                         per_xcd, parity, group);
   } else {
     if (rowtile)
       hipLaunchKernelGGL((k_step_batch<T, 512, true>), g, blk, lds, s, inst, ninst, nitems,
-                         per_xcd, parity);
+                         per_xcd, parity, group);
     else
       hipLaunchKernelGGL((k_step_batch<T, 512, false>), g, blk, lds, s, inst, ninst, nitems,
-                         per_xcd, parity);
+                         per_xcd, parity, group);
   }
   return hipGetLastError();
 }
 template hipError_t launch_step_batch<double>(const InstDev *, int, int, int, int, bool, int,
-                                              hipStream_t);
+                                              hipStream_t, int);
 template hipError_t launch_step_batch<float>(const InstDev *, int, int, int, int, bool, int,
-                                             hipStream_t);
+                                             hipStream_t, int);
 
 template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,

@@ -1359,7 +1359,7 @@ struct tpl_batch {
   bool inited = false;
   // launch shape of the batched step
   int qsplit = 0, grid = 0, autotune = 1, graph_steps = 20, time_kernels = 0;
-  int qs_used = 0, grid_used = 0;
+  int qs_used = 0, grid_used = 0, group = 0, group_used = 1;
   bool rowtile = false;
   // device instance table of the active instances
   std::vector<InstDev> tab;
@@ -1431,18 +1431,18 @@ int upload_table(tpl_batch *b, const std::vector<InstDev> &tab) {
 }
 
 hipError_t batch_launch(const tpl_batch *b, int esize, int ninst, int nitems, int qs, int grid,
-                        bool rowtile, int parity) {
+                        bool rowtile, int parity, int group) {
   return esize == 4 ? launch_step_batch<float>(b->tab_d, ninst, nitems, qs, grid, rowtile, parity,
-                                               b->stream)
+                                               b->stream, group)
                     : launch_step_batch<double>(b->tab_d, ninst, nitems, qs, grid, rowtile,
-                                                parity, b->stream);
+                                                parity, b->stream, group);
 }
 
 // Enqueue n launches of the uploaded table with parities p0, p0^1, ...
 int batch_run(tpl_batch *b, int esize, int ninst, int nitems, int qs, int grid, bool rowtile,
-              int p0, long long n) {
+              int p0, long long n, int group = 1) {
   for (long long i = 0; i < n; ++i)
-    HIPCHK(batch_launch(b, esize, ninst, nitems, qs, grid, rowtile, (int)((p0 + i) & 1)));
+    HIPCHK(batch_launch(b, esize, ninst, nitems, qs, grid, rowtile, (int)((p0 + i) & 1), group));
   return TPL_OK;
 }
 
@@ -1526,16 +1526,17 @@ int batch_esize(const tpl_batch *b) { return b->precision == TPL_FP32 ? 4 : 8; }
 
 // Average duration of one launch of the current table (read half cur0,
 // write the other half: repeating it leaves the state unchanged).
-int time_shape(tpl_batch *b, int qs, int grid, int reps, double *ms) {
+int time_shape(tpl_batch *b, int qs, int grid, int reps, double *ms, int group = 1) {
   const int esize = batch_esize(b);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  int rc = batch_run(b, esize, (int)b->tab.size(), b->nitems, qs, grid, b->rowtile, 0, 1);
+  int rc = batch_run(b, esize, (int)b->tab.size(), b->nitems, qs, grid, b->rowtile, 0, 1, group);
   if (!rc) {
     (void)hipEventRecord(e0, b->stream);
     for (int i = 0; i < reps && !rc; ++i)
-      rc = batch_run(b, esize, (int)b->tab.size(), b->nitems, qs, grid, b->rowtile, 0, 1);
+      rc = batch_run(b, esize, (int)b->tab.size(), b->nitems, qs, grid, b->rowtile, 0, 1,
+                     group);
     (void)hipEventRecord(e1, b->stream);
   }
   float t = 0.f;
@@ -1552,6 +1553,9 @@ int time_shape(tpl_batch *b, int qs, int grid, int reps, double *ms) {
 
 // Choose the Q-slice count and the grid: candidates are one workgroup per
 // item and persistent grids of one or two waves of workgroups per CU slot.
+// Units of `group` consecutive items: what a grouped launch's grid counts.
+int batch_units(const tpl_batch *b, int group) { return (b->nitems + group - 1) / group; }
+
 int choose_shape(tpl_batch *b) {
   int qs_list[4] = {1, 2, 4, 8}, nqs = 4;
   if (b->qsplit > 0) {
@@ -1559,56 +1563,80 @@ int choose_shape(tpl_batch *b) {
     qs_list[0] = q;
     nqs = 1;
   }
+  if (b->group != 0 && b->group != 1 && b->group != 2 && b->group != 4 && b->group != 8)
+    return fail(TPL_EINVAL, "group must be 0 (tuned), 1, 2, 4 or 8");
+  if (b->group > 1 && b->qsplit > 1)
+    return fail(TPL_EINVAL, "item groups need one Q-slice (qsplit 0 or 1)");
   int rc0 = build_main_table(b, qs_list[0]);  // sets nitems
   if (rc0) return rc0;
   if (!b->autotune) {
     int qs = qs_list[0];
-    if (b->qsplit <= 0) {  // as for one lattice: >= 2048 waves, at most 8 slices
+    const int grp = b->group > 0 ? b->group : 1;
+    if (grp > 1) {
+      qs = 1;
+    } else if (b->qsplit <= 0) {  // as for one lattice: >= 2048 waves, at most 8 slices
       qs = 1;
       while (qs < 8 && (long long)b->nitems * qs < 2048) qs *= 2;
     }
     b->qs_used = qs;
+    b->group_used = grp;
     const int rc = build_main_table(b, qs);
-    b->grid_used = b->grid > 0 ? b->grid : b->nitems;
+    b->grid_used = b->grid > 0 ? b->grid : batch_units(b, grp);
     return rc;
   }
-  // first the Q-slice count at one workgroup per item, then persistent grids
-  // (one or two workgroups per CU slot) at the best count
+  // first the Q-slice count at one workgroup per item, then item groups
+  // (one slice), then persistent grids (one or two workgroups per CU slot) at
+  // the best shape
   double best = -1.0;
-  int bq = qs_list[0], bg = b->nitems;
+  int bq = qs_list[0], bg = b->nitems, bgrp = 1;
   b->tune_ms = 0.0;
-  auto trial = [&](int qs, int g) -> int {
+  auto trial = [&](int qs, int g, int grp) -> int {
     double ms = 0.0;
-    const int rc = time_shape(b, qs, g, 2, &ms);
+    const int rc = time_shape(b, qs, g, 2, &ms, grp);
     b->tune_ms += 3 * ms;
     if (!rc && (best < 0 || ms < best)) {
       best = ms;
       bq = qs;
       bg = g;
+      bgrp = grp;
     }
     return rc;
   };
-  for (int iq = 0; iq < nqs; ++iq) {
-    int rc = build_main_table(b, qs_list[iq]);
+  if (b->group <= 1) {
+    for (int iq = 0; iq < nqs; ++iq) {
+      int rc = build_main_table(b, qs_list[iq]);
+      if (!rc) rc = upload_table(b, b->tab);
+      if (!rc) rc = trial(qs_list[iq], b->grid > 0 ? b->grid : b->nitems, 1);
+      if (rc) return rc;
+    }
+  }
+  if (b->group != 1 && b->qsplit <= 1) {
+    int rc = build_main_table(b, 1);
     if (!rc) rc = upload_table(b, b->tab);
-    if (!rc) rc = trial(qs_list[iq], b->grid > 0 ? b->grid : b->nitems);
     if (rc) return rc;
+    const int cand[3] = {2, 4, 8};
+    for (int grp : cand) {
+      if (b->group > 1 && grp != b->group) continue;
+      rc = trial(1, b->grid > 0 ? b->grid : batch_units(b, grp), grp);
+      if (rc) return rc;
+    }
   }
   if (b->grid <= 0) {
     int rc = build_main_table(b, bq);
     if (!rc) rc = upload_table(b, b->tab);
     if (rc) return rc;
-    const int slots = 256 * 12 / bq;  // 256 CUs x 12 waves (3 per SIMD)
+    const int slots = 256 * 12 / (bq * bgrp);  // 256 CUs x 12 waves (3 per SIMD)
     for (int m = 1; m <= 2; ++m) {
       const int g = ((slots * m + 7) / 8) * 8;
-      if (g < b->nitems) {
-        rc = trial(bq, g);
+      if (g < batch_units(b, bgrp)) {
+        rc = trial(bq, g, bgrp);
         if (rc) return rc;
       }
     }
   }
   b->qs_used = bq;
   b->grid_used = bg;
+  b->group_used = bgrp;
   return build_main_table(b, bq);
 }
 
@@ -1618,7 +1646,7 @@ int capture_graph(tpl_batch *b) {
   const int esize = batch_esize(b);
   HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   int rc = batch_run(b, esize, (int)b->tab.size(), b->nitems, b->qs_used, b->grid_used,
-                     b->rowtile, 0, b->graph_steps);
+                     b->rowtile, 0, b->graph_steps, b->group_used);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(b->stream, &g);
   if (rc) {
@@ -1667,6 +1695,7 @@ struct BatchKey {
 const BatchKey kBatchKeys[] = {
     {"qsplit", &tpl_batch::qsplit},           {"grid", &tpl_batch::grid},
     {"autotune", &tpl_batch::autotune},       {"graph_steps", &tpl_batch::graph_steps},
+    {"group", &tpl_batch::group},
     {"time_kernels", &tpl_batch::time_kernels},
 };
 
@@ -1713,10 +1742,14 @@ int tpl_batch_set_param(tpl_batch *b, const char *key, double value) {
   for (const BatchKey &k : kBatchKeys)
     if (!strcmp(k.name, key)) {
       if (!(value >= 0 && value <= (1 << 30))) return fail(TPL_EINVAL, "value out of range");
+      const int old = b->*k.field;
       b->*k.field = (int)value;
       if (b->inited && strcmp(key, "time_kernels")) {  // new launch shape
         const int rc = choose_shape(b);
-        if (rc) return rc;
+        if (rc) {
+          b->*k.field = old;  // an invalid shape leaves the previous one
+          return rc;
+        }
         b->tab_dirty = true;
       }
       return TPL_OK;
@@ -1758,6 +1791,7 @@ int tpl_batch_query(const tpl_batch *b, const char *key, double *out) {
       v += q;
     }
   } else if (s == "qsplit_used") v = b->qs_used;
+  else if (s == "group_used") v = b->group_used;
   else if (s == "grid_used") v = b->grid_used;
   else if (s == "rowtile") v = b->rowtile;
   else if (s == "kernel_ms") v = b->kernel_steps ? b->kernel_ms / b->kernel_steps : 0.0;
@@ -1851,7 +1885,7 @@ int tpl_batch_step(tpl_batch *b, int64_t n) {
   if (b->gexec)
     for (; done + G <= n; done += G) HIPCHK(hipGraphLaunch(b->gexec, b->stream));
   rc = batch_run(b, esize, (int)b->tab.size(), b->nitems, b->qs_used, b->grid_used, b->rowtile,
-                 0, n - done);
+                 0, n - done, b->group_used);
   if (rc) return rc;
   if (b->time_kernels) {
     HIPCHK(hipEventRecord(e1, b->stream));
@@ -1875,8 +1909,9 @@ int tpl_batch_step(tpl_batch *b, int64_t n) {
   if (newly) {
     rc = build_main_table(b, b->qs_used);
     if (rc) return rc;
-    if (b->grid > 0 || b->autotune == 0) b->grid_used = b->grid > 0 ? b->grid : b->nitems;
-    if (b->grid_used > b->nitems && b->nitems > 0) b->grid_used = b->nitems;
+    const int units = batch_units(b, b->group_used);
+    if (b->grid > 0 || b->autotune == 0) b->grid_used = b->grid > 0 ? b->grid : units;
+    if (b->grid_used > units && units > 0) b->grid_used = units;
   }
   return TPL_OK;
 }

@@ -102,6 +102,33 @@ def test_batch_shapes_agree():
         b.close()
 
 
+@pytest.mark.parametrize("insts", [MIXED, ROWS], ids=["mixed", "rows"])
+def test_item_groups_are_bitwise_equal(insts):
+    """Consecutive tiles per workgroup (one Q-slice): which wave takes which
+    tile changes nothing, in plain launches, persistent grids, graph replays
+    and the autotuned shape; ragged tails leave idle waves in the last
+    group."""
+    def run(**kw):
+        b = P.Batch(insts, precision=1, nq=6, pre_steps=40, qsplit=1, **kw)
+        b.init()
+        shape = (b.query("group_used"), b.query("grid_used"))
+        b.step(7)
+        st = [b.instance(i).get_state() for i in range(len(insts))]
+        b.close()
+        return st, shape
+    ref, shape = run(autotune=0, group=1, graph_steps=0)
+    assert shape[0] == 1
+    for kw in (dict(autotune=0, group=2, graph_steps=0), dict(autotune=0, group=4, graph_steps=3),
+               dict(autotune=0, group=8, grid=8, graph_steps=0), dict(autotune=1, graph_steps=4)):
+        print("item groups", kw, flush=True)
+        st, shape = run(**kw)
+        if "group" in kw:
+            assert shape[0] == kw["group"]
+        for a, r in zip(st, ref):
+            for k in a:
+                assert np.array_equal(a[k], r[k]), (kw, k)
+
+
 def test_graph_replays_match_plain_launches():
     """Replays of the captured graph, with eager work in between, against
     the same steps launched one by one."""
@@ -203,5 +230,11 @@ def test_batch_errors():
     assert e.value.code == -1
     b.set_param("qsplit", 2)  # launch keys may change at any time
     assert b.query("qsplit_used") == 2
+    b.step(2)
+    with pytest.raises(P.TplError):
+        b.set_param("group", 3)
+    with pytest.raises(P.TplError):  # item groups need one Q-slice
+        b.set_param("group", 2)
+    assert b.query("qsplit_used") == 2 and b.query("group") == 0
     b.step(2)
     b.close()
