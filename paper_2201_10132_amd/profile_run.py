@@ -4,8 +4,9 @@ Runs, in one process: a plain device-to-device copy of a known size (the
 calibration for the HBM byte counters), then the 1024 x 1024, NQ = 16 FP64
 workload for a few steps (short base-state run, since only the step kernel
 is measured), or with --batch N the first N instances of the seeded batched
-sweep (FP32, NQ = 6) stepped together with a fixed launch shape (plain
-launches, no graph, so that every dispatch is the measured step).  Usage
+sweep (FP32, NQ = 6) stepped together with a fixed launch shape (one
+Q-slice, groups of 4 tiles: the autotuner's usual pick; plain launches, no
+graph, so that every dispatch is the measured step).  Usage
 under the profiler:
   rocprofv3 --pmc FETCH_SIZE -d <dir> -o run -- python paper_2201_10132_amd/profile_run.py
 """
@@ -26,7 +27,8 @@ def main():
     ap.add_argument("--nq", type=int, default=16)
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--batch", type=int, default=0, help="instances of the batched sweep")
-    ap.add_argument("--qsplit", type=int, default=4, help="Q-slices of the batched step")
+    ap.add_argument("--qsplit", type=int, default=1, help="Q-slices of the batched step")
+    ap.add_argument("--group", type=int, default=4, help="tiles per workgroup of the batched step")
     ap.add_argument("--batch-nq", type=int, default=6, help="Q points per axis of the batched sweep")
     args = ap.parse_args()
     import torch
@@ -43,7 +45,7 @@ def main():
         from tests import inputs
 
         b = P.Batch(inputs.c4_instances(args.batch), precision=1, nq=args.batch_nq, pre_steps=100,
-                    autotune=0, qsplit=args.qsplit, graph_steps=0)
+                    autotune=0, qsplit=args.qsplit, group=args.group, graph_steps=0)
         b.init()
         b.step(args.steps)
         print(f"bytes_per_step={b.query('bytes_per_step'):.0f} items={b.query('items'):.0f} "
