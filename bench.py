@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the FP32 form measurements")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched sweep")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned correction")
+    ap.add_argument("--no-inplace", action="store_true",
+                    help="skip the in-place (one population array) measurements")
     ap.add_argument("--no-growth", action="store_true",
                     help="skip the growth-rate comparison of the storage forms")
     ap.add_argument("--growth-steps", type=int, default=2000)
@@ -164,6 +166,8 @@ def main():
         forms[f"bf16neq_{tag}"] = form_entry(b16l, f64l)
         forms[f"bf16neq_{tag}"]["speedup_vs_fp32"] = round(b16l["mlups"] / f32l["mlups"], 3)
         out["precision_forms"] = forms
+    if not args.no_inplace:
+        out["inplace"] = measure_inplace(torch, out.get("precision_forms"), args)
     if not args.no_forms:
         # the stress-tensor quasi-equilibrium model (Sec. V model (ii)): same
         # bytes, second moments added to the arithmetic; drag time tau1_S =
@@ -219,7 +223,8 @@ def measure(torch, w, precision, steps, warmup, pre_steps, **params) -> dict:
     t.init(seed=w["seed"], perturbation=w["perturbation"])
     init_s = time.perf_counter() - t0
     d0 = t.diagnostics()
-    t.step(warmup)
+    # in place, the autotuner times its shapes on 24 real steps of one call
+    t.step(max(warmup, 24) if params.get("inplace") else warmup)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -235,7 +240,7 @@ def measure(torch, w, precision, steps, warmup, pre_steps, **params) -> dict:
                bytes_step=t.query("bytes_per_step"), amplitude=d1["amplitude"],
                qsplit=t.query("qsplit_used"), nuS=t.query("nuS"),
                group=[int(t.query(k)) for k in ("group_x_used", "group_y_used", "group_sync_used")],
-               tune_ms=round(t.query("tune_ms"), 1),
+               tune_ms=round(t.query("tune_ms"), 1), bytes_state=t.query("bytes_state"),
                conservation={"mass_S": abs(d1["mass_S"] / d0["mass_S"] - 1),
                              "mass_P": abs(d1["mass_P"] / d0["mass_P"] - 1)})
     print(f"# precision={precision} {w['nx']}x{w['ny']} nq={w['nq']}: init {init_s:.1f} s, "
@@ -413,6 +418,28 @@ def measure_growth(torch, w, pre_steps, steps, every=100):
     out["amplitude_end_rel_err"] = {k: abs(out["amplitude_end"][k] / out["amplitude_end"]["fp64"] - 1)
                                     for k in ("fp32", "bf16neq")}
     return out
+
+
+def measure_inplace(torch, forms, args) -> dict:
+    """In-place streaming (one population array): FP64 at 4096^2 and NQ 6
+    beside the two-array FP64 run of the same workload, and at NQ 8, which
+    only fits one GPU in place (194 GB; two arrays would need 370 GB)."""
+    w3 = WORKLOAD_FP32_LARGE
+    n3 = max(5, args.steps // 2)
+    res = {}
+    ref = (forms or {}).get(f"fp64_4096x4096_nq{w3['nq']}")
+    for nq in (w3["nq"], 8):
+        m = measure(torch, dict(w3, nq=nq), 0, n3, args.warmup, args.pre_steps, inplace=1)
+        e = form_entry(m, None)
+        e["bytes_state_gb"] = round(m["bytes_state"] / 1e9, 1)
+        e["two_array_bytes_state_gb"] = round(
+            (m["bytes_state"] + m["nqd"] * 25 * 8 * w3["nx"] * w3["ny"]
+             + 9 * 8 * w3["nx"] * w3["ny"]) / 1e9, 1)
+        e["tune_ms"] = m["tune_ms"]
+        if nq == w3["nq"] and ref is not None:
+            e["speed_vs_two_array"] = round(m["mlups"] / ref["mlups"], 3)
+        res[f"fp64_4096x4096_nq{nq}"] = e
+    return res
 
 
 def form_entry(m, ref64):

@@ -128,6 +128,23 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *                 tau1_S = tau_drag <= tau2_S, D_Q = c_s^2 tau1_P,
  *                 tau2_P = tau1_P / tau_ratio_p); not for batches
  *   precision 0   TPL_FP64, TPL_FP32 or TPL_BF16NEQ population storage
+ *   inplace 0     1 = one population array instead of two, streamed in place
+ *                 (Sec. VI streaming and Q-disk bounce-back, by the AA
+ *                 pattern of Bailey et al., ICPP 2009): steps alternate
+ *                 between pulling from the neighbours and writing back into
+ *                 the locations read, and reading and writing the node's
+ *                 own locations; results are bitwise those of the
+ *                 two-array step.  Halves the population memory.  FP64 and
+ *                 FP32 only, nx a multiple of 64, one Q-slice (qsplit is
+ *                 ignored), not for batches.  After an odd number of steps
+ *                 the populations are held in streamed order: the calls
+ *                 that read or write populations (tpl_get_state with XS or
+ *                 XP, tpl_set_state, tpl_get_window, tpl_get_populations,
+ *                 tpl_set_populations, tpl_save, tpl_restrict) return
+ *                 TPL_ESTATE until one more step is taken; observables,
+ *                 diagnostics and the amplitude are available after every
+ *                 step.  The autotuner times its shapes on the first
+ *                 tpl_step of at least 24 steps, as real steps
  *   pert_modes 1  0 = single x-mode, 1 = multimode perturbation
  *   pre_steps -1  base-state column steps (-1 = 5 max(l^2/nu, lambda))
  *   qsplit 0      Q-slices per r-tile in the step kernel: 0 (automatic),
@@ -151,8 +168,9 @@ int tpl_set_param(tpl_ctx *ctx, const char *key, double value);
  * lambda_eff sigma R DQ F0 kappa meq Sc rhoS0 rhoP0 step bytes_XS bytes_XP
  * bytes_PSI bytes_FLD bytes_MOM bytes_state bytes_per_step
  * kernel_ms kernel_launches qsplit_used group_x_used group_y_used
- * group_sync_used tune_ms (the shape of the last tpl_step's launches).  Host
- * only; TPL_EINVAL for an unknown key. */
+ * group_sync_used tune_ms (the shape of the last tpl_step's launches)
+ * inplace_odd (1: in-place populations held in streamed order).  Host only;
+ * TPL_EINVAL for an unknown key. */
 int tpl_query(const tpl_ctx *ctx, const char *key, double *out);
 
 /* Bind a hipStream_t (NULL = the null stream).  All device work of the
@@ -163,8 +181,8 @@ int tpl_set_stream(tpl_ctx *ctx, void *hip_stream);
  * Call before tpl_init.  dptrs[i] must be a device pointer of at least
  * bytes[i] bytes, 256-byte aligned, for i = 0..3 in the order returned by
  * tpl_query keys bytes_XS, bytes_XP, bytes_PSI, bytes_FLD (each holds the
- * double-buffered array).  The caller keeps ownership.  Not available for
- * TPL_BF16NEQ (TPL_EINVAL). */
+ * double-buffered array; XS and XP hold one array with inplace 1).  The
+ * caller keeps ownership.  Not available for TPL_BF16NEQ (TPL_EINVAL). */
 int tpl_adopt_buffers(tpl_ctx *ctx, void *const *dptrs, const size_t *bytes,
                       int n);
 
@@ -263,7 +281,8 @@ tpl_batch *tpl_batch_create(const tpl_instance *inst, int n, int precision);
  *   graph_steps 20 steps captured per HIP graph (< 2: plain launches)
  *   time_kernels 0 1 = time tpl_batch_step with HIP events (kernel_ms)
  * Any other key is a tpl_set_param key applied to every instance before
- * tpl_batch_init (TPL_ESTATE afterwards; precision is rejected). */
+ * tpl_batch_init (TPL_ESTATE afterwards; precision and inplace are
+ * rejected). */
 int tpl_batch_set_param(tpl_batch *b, const char *key, double value);
 
 /* Keys: the launch keys above and instances, active (not flagged unstable),

@@ -104,10 +104,13 @@ struct InstDev {
 };
 
 // Launchers (tpl_kernels.hip).  All enqueue on stream and return the launch
-// status.  T = double or float.
+// status.  T = double or float.  ip = 1, 2: the two alternating in-place
+// steps (a and b share XS and XP; nx a multiple of 64, one Q-slice, not the
+// BF16 form), 0: read a, write b.
 template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
-                       StepRef ref, const QNode *qtab, hipStream_t s, bool neq = false);
+                       StepRef ref, const QNode *qtab, hipStream_t s, bool neq = false,
+                       int ip = 0);
 // BF16 non-equilibrium form <-> FP32 deviations from the reference, node by
 // node: dev [25][nqd][N] = w_k (m0 + 3 (v_k . J)) + n_k (decode), and the
 // inverse (encode: writes MOM and n).

@@ -60,6 +60,21 @@ __host__ __device__ constexpr int kstar(int k) {
 static_assert(kstar(5) == 6 && kstar(21) == 24 && kstar(22) == 23 &&
                   kstar(1) == 1 && pdir(9) == 1 && pdir(16) == 4,
               "D4Q25 table");
+// Opposite velocities: -c_d (D2Q9) and -(v_k, Qdot_k) (D4Q25).
+__host__ __device__ constexpr int rev9(int d) {
+  return dir9(-C9X[d], -C9Y[d]);
+}
+__host__ __device__ constexpr int krev(int k) {
+  int j = 0;
+  for (int i = 0; i < 25; ++i)
+    if (PV[i][0] == -PV[k][0] && PV[i][1] == -PV[k][1] && PV[i][2] == -PV[k][2] &&
+        PV[i][3] == -PV[k][3])
+      j = i;
+  return j;
+}
+static_assert(rev9(1) == 3 && rev9(5) == 7 && rev9(8) == 6 && krev(0) == 0 && krev(1) == 4 &&
+                  krev(5) == 8 && krev(21) == 24 && krev(13) == 16,
+              "opposite velocities");
 
 __device__ __forceinline__ int xcd_tile(int bid, int tiles_per_xcd) {
   // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
@@ -182,7 +197,24 @@ __device__ __forceinline__ void neq_encode(const double d[25], uint16_t nb[25], 
 // are wave-uniform (scalar loads).
 // One 64-node tile of one lattice (all qs slices of the workgroup take part).
 // red: LDS of qs * 12 * 64 doubles.
-template <typename T, bool ROWTILE, bool NEQ = false, bool QE2 = false>
+// In-place streaming (IP != 0; one population array, a == b for XS and XP;
+// the AA pattern of Bailey et al., "Accelerating lattice Boltzmann fluid flow
+// simulations using graphics processors", ICPP 2009, with the Q-disk
+// bounce-back folded into its address maps).  Steps alternate:
+//   IP = 1: pull as in the two-array step, then write the post-collision
+//           population of velocity k where the pull of the opposite velocity
+//           -k read from (its source node, its plane): each node rewrites
+//           exactly the locations it read, so nodes never race;
+//   IP = 2: read velocity k's incoming value at the node itself, from the
+//           plane of -k, and write the post-collision value to plane k.
+// After an IP = 1 step the array holds the streamed populations in reversed
+// planes; after the following IP = 2 step it holds exactly what the
+// two-array step writes.  Both read and write with the same FP32 reference
+// tables as the two-array step, so the three forms agree bitwise.  The
+// solvent follows the same maps with the D2Q9 set.  Every wave of a
+// workgroup owns its own nodes (one Q-slice), and the per-node fields and
+// lagged psi stay double-buffered.
+template <typename T, bool ROWTILE, bool NEQ = false, bool QE2 = false, int IP = 0>
 __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &a,
                                           const StateT<T> &b, const float *__restrict__ rpull,
                                           const float *__restrict__ rstore,
@@ -238,7 +270,8 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   double gS[9], rhoS = 0.0, JSx = 0.0, JSy = 0.0;
 #pragma unroll
   for (int d = 0; d < 9; ++d) {
-    gS[d] = full(ldo(plane(a.XS, d), osrc[d]), rsd(rspull, d));
+    gS[d] = IP == 2 ? full(ldo(plane(a.XS, rev9(d)), oR), rsd(rspull, d))
+                    : full(ldo(plane(a.XS, d), osrc[d]), rsd(rspull, d));
     rhoS += gS[d];
     if (C9X[d]) JSx += C9X[d] * gS[d];
     if (C9Y[d]) JSy += C9Y[d] * gS[d];
@@ -311,7 +344,12 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
       const double o = p.c1S * gS[d] + p.c2S * ((1.0 - p.rS) * fs + p.rS * fe);
       if (C9X[d]) jx += C9X[d] * o;
       if (C9Y[d]) jy += C9Y[d] * o;
-      if (writer) sto(wplane(b.XS, d), oR, stored<T>(o, rsd(rsstore, d)));
+      if (writer) {
+        if constexpr (IP == 1)
+          sto(wplane(b.XS, rev9(d)), osrc[rev9(d)], stored<T>(o, rsd(rsstore, d)));
+        else
+          sto(wplane(b.XS, d), oR, stored<T>(o, rsd(rsstore, d)));
+      }
     }
     if (writer) {
       sto(wfplane(b.FLD, F_JSX), fR, jx);
@@ -332,7 +370,11 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
     if (qsync) __syncthreads();  // keep the group's waves on the same Q-node
     const QNode CONSTANT_AS &qn = cst(qtab)[q];  // scalar loads
     double g[25];
-    if constexpr (!NEQ) {
+    if constexpr (IP == 2) {
+#pragma unroll
+      for (int k = 0; k < 25; ++k)
+        g[k] = full(ldo(plane(a.XP, (long long)krev(k) * nqd + q), oR), rq(rpull, y, q, k));
+    } else if constexpr (!NEQ) {
 #pragma unroll
       for (int k = 0; k < 25; ++k)
         g[k] = full(ldo(plane(a.XP, qn.plane[k]), osrc[pdir(k)]), rq(rpull, y, q, k));
@@ -470,7 +512,13 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
       mg[pdir(k)] += g[k];
     }
     if (active) {
-      if constexpr (!NEQ) {
+      if constexpr (IP == 1) {
+#pragma unroll
+        for (int k = 0; k < 25; ++k)
+          sto(wplane(b.XP, qn.plane[krev(k)]), osrc[pdir(krev(k))],
+              stored<T>(g[k], rq(rstore, y, q, k)));
+        sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
+      } else if constexpr (!NEQ) {
 #pragma unroll
         for (int k = 0; k < 25; ++k)
           sto(wplane(b.XP, (long long)k * nqd + q), oR, stored<T>(g[k], rq(rstore, y, q, k)));
@@ -532,7 +580,7 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   if (p.qs > 1) __syncthreads();  // red is reused by the workgroup's next tile
 }
 
-template <typename T, int MAXT, bool ROWTILE, bool NEQ = false, bool QE2 = false>
+template <typename T, int MAXT, bool ROWTILE, bool NEQ = false, bool QE2 = false, int IP = 0>
 __global__ void __launch_bounds__(MAXT)
     k_step(StepParams p, StateT<T> a, StateT<T> b, const float *__restrict__ rpull,
            const float *__restrict__ rstore, const float *__restrict__ rpsi,
@@ -553,8 +601,8 @@ __global__ void __launch_bounds__(MAXT)
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     tile = ((grp / gpr) * gy + w / gx) * tpr + (grp % gpr) * gx + w % gx;
   }
-  step_tile<T, ROWTILE, NEQ, QE2>(p, a, b, rpull, rstore, rpsi, rspull, rsstore, qtab, tile,
-                                  red);
+  step_tile<T, ROWTILE, NEQ, QE2, IP>(p, a, b, rpull, rstore, rpsi, rspull, rsstore, qtab,
+                                      tile, red);
 }
 
 
@@ -642,14 +690,32 @@ template hipError_t launch_step_batch<float>(const InstDev *, int, int, int, int
 
 template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
-                       StepRef r, const QNode *qtab, hipStream_t s, bool neq) {
+                       StepRef r, const QNode *qtab, hipStream_t s, bool neq, int ip) {
   const int gsize = p.wg ? (p.wg & 255) * ((p.wg >> 8) & 255) : 1;
   const int grid = p.tiles_per_xcd > 0 ? 8 * p.tiles_per_xcd : p.ntiles / gsize;
   const size_t lds = p.qs > 1 ? (size_t)p.qs * 12 * 64 * sizeof(double) : 0;
   const bool rowtile = (p.nx % 64) == 0;
   if (p.wg && (p.qs != 1 || !rowtile || gsize > 8)) return hipErrorInvalidValue;
+  if (p.qe != 1 && p.qe != 2) return hipErrorInvalidValue;
   const dim3 g(grid), blk(64 * p.qs * gsize);
 #define TPL_STEP_ARGS p, a, b, r.pull, r.store, r.psi, r.spull, r.sstore, qtab
+  if (ip != 0) {
+    // in place: one population array, whole tiles, one Q-slice
+    if (ip != 1 && ip != 2) return hipErrorInvalidValue;
+    if (neq || !rowtile || p.qs != 1 || a.XS != b.XS || a.XP != b.XP) return hipErrorInvalidValue;
+#define TPL_STEP_IP(QE2, IP)                                                           \
+  if (gsize <= 4)                                                                      \
+    hipLaunchKernelGGL((k_step<T, 256, true, false, QE2, IP>), g, blk, lds, s, TPL_STEP_ARGS); \
+  else                                                                                 \
+    hipLaunchKernelGGL((k_step<T, 512, true, false, QE2, IP>), g, blk, lds, s, TPL_STEP_ARGS);
+    if (p.qe == 2) {
+      if (ip == 1) { TPL_STEP_IP(true, 1) } else { TPL_STEP_IP(true, 2) }
+    } else {
+      if (ip == 1) { TPL_STEP_IP(false, 1) } else { TPL_STEP_IP(false, 2) }
+    }
+#undef TPL_STEP_IP
+    return hipGetLastError();
+  }
 #define TPL_STEP_LAUNCH2(NEQ, QE2)                                                    \
   if (p.qs * gsize <= 4) {                                                            \
     if (rowtile)                                                                      \
@@ -668,7 +734,6 @@ hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
   } else {                       \
     TPL_STEP_LAUNCH2(NEQ, false) \
   }
-  if (p.qe != 1 && p.qe != 2) return hipErrorInvalidValue;
   if constexpr (std::is_same<T, float>::value) {
     if (neq) {
       TPL_STEP_LAUNCH(true)
@@ -685,9 +750,9 @@ hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
   return hipGetLastError();
 }
 template hipError_t launch_step<double>(const StepParams &, StateT<double>, StateT<double>,
-                                        StepRef, const QNode *, hipStream_t, bool);
+                                        StepRef, const QNode *, hipStream_t, bool, int);
 template hipError_t launch_step<float>(const StepParams &, StateT<float>, StateT<float>,
-                                       StepRef, const QNode *, hipStream_t, bool);
+                                       StepRef, const QNode *, hipStream_t, bool, int);
 
 // BF16 non-equilibrium form: node-local conversions to and from FP32
 // deviations (auxiliary paths: initialisation, state exchange, diagnostics).

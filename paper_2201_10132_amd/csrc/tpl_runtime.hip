@@ -44,6 +44,7 @@ struct Config {
   int qsplit = 0, time_kernels = 0;
   int group_x = 1, group_y = 1, group_sync = 0, autotune = 1;
   int qe_model = 1;
+  int inplace = 0;  // one population array, streamed in place
 };
 
 struct Derived {
@@ -68,6 +69,11 @@ int derive(const Config &c, Derived &d) {
   if (!(c.tau_ratio_p > 0 && c.tau_ratio_p <= 1))
     return fail(TPL_EINVAL, "tau_ratio_p must be in (0,1] (tau1 <= tau2)");
   if (c.qe_model != 1 && c.qe_model != 2) return fail(TPL_EINVAL, "qe_model must be 1 or 2");
+  if (c.inplace != 0 && c.inplace != 1) return fail(TPL_EINVAL, "inplace must be 0 or 1");
+  if (c.inplace && c.precision == TPL_BF16NEQ)
+    return fail(TPL_EINVAL, "in-place streaming is for the FP64 and FP32 forms");
+  if (c.inplace && c.nx % 64)
+    return fail(TPL_EINVAL, "in-place streaming needs nx a multiple of 64");
   // the step kernel addresses a plane with 32-bit byte offsets: 8 N < 2^32
   if ((long long)c.nx * c.ny >= (1LL << 29)) return fail(TPL_EINVAL, "lattice too large");
 
@@ -198,17 +204,21 @@ int derive(const Config &c, Derived &d) {
 // Double-buffered state.  XS and PSI hold elements of esize bytes (8: FP64
 // values, 4: FP32 deviations from the reference), XP elements of xsize bytes
 // (8, 4, or 2: the BF16 remainders of the BF16 non-equilibrium form, whose
-// FP32 deviation fluxes are in MOM); FLD is FP64.
+// FP32 deviation fluxes are in MOM); FLD is FP64.  With in-place streaming
+// both halves share one XS and one XP array.
 struct Buffers {
   void *XS = nullptr, *XP = nullptr, *PSI = nullptr;
   double *FLD = nullptr;
   float *MOM = nullptr;
   size_t nXS = 0, nXP = 0, nPSI = 0, nFLD = 0, nMOM = 0;  // elements per half
   size_t esize = 8, xsize = 8;
+  bool inplace = false;
+  int pop_copies() const { return inplace ? 1 : 2; }
+  size_t pop_half(int h) const { return inplace ? 0 : (size_t)h; }
   template <typename T>
   StateT<T> half(int h) const {
-    return StateT<T>{static_cast<T *>(XS) + h * nXS,
-                     reinterpret_cast<T *>(static_cast<char *>(XP) + h * nXP * xsize),
+    return StateT<T>{static_cast<T *>(XS) + pop_half(h) * nXS,
+                     reinterpret_cast<T *>(static_cast<char *>(XP) + pop_half(h) * nXP * xsize),
                      static_cast<T *>(PSI) + h * nPSI, FLD + h * nFLD,
                      MOM ? MOM + h * nMOM : nullptr};
   }
@@ -226,6 +236,7 @@ struct tpl_ctx {
   bool inited = false, owned = true;
   Buffers buf;
   int cur = 0;
+  int ip_odd = 0;  // in-place streaming: populations in streamed, reversed order
   long long step = 0;
   QNode *qtab_d = nullptr;
   double *peq_d = nullptr;
@@ -289,6 +300,8 @@ StepParams make_step_params(const tpl_ctx *x, int nx, int ny, int qs_req) {
     qs = 1;
     while (qs < 8 && (long long)p.ntiles * qs < 2048) qs *= 2;
   }
+  // in place, every wave owns its nodes' populations: one Q-slice
+  if (x->c.inplace && nx == x->c.nx && ny == x->c.ny) qs = 1;
   // 1, 2, 4 or 8 slices (the slice reduction uses qs * 6 KB of LDS)
   qs = qs >= 8 ? 8 : qs >= 4 ? 4 : qs >= 2 ? 2 : 1;
   p.qs = qs;
@@ -354,9 +367,11 @@ int alloc_state(tpl_ctx *x) {
   if (neq(x)) B.nXP = 35 * B.nPSI;  // per Q-node: 25 BF16 + 5 FP32 planes (70 N bytes)
   B.esize = elem_size(x);
   B.xsize = xp_size(x);
+  B.inplace = x->c.inplace != 0;
   void **ptrs[5] = {&B.XS, &B.XP, &B.PSI, reinterpret_cast<void **>(&B.FLD),
                     reinterpret_cast<void **>(&B.MOM)};
-  size_t bytes[5] = {2 * B.nXS * B.esize, 2 * B.nXP * B.xsize, 2 * B.nPSI * B.esize,
+  const size_t pc = B.pop_copies();
+  size_t bytes[5] = {pc * B.nXS * B.esize, pc * B.nXP * B.xsize, 2 * B.nPSI * B.esize,
                      2 * B.nFLD * sizeof(double), 2 * B.nMOM * sizeof(float)};
   for (int i = 0; i < (neq(x) ? 5 : 4); ++i) {
     if (hipMalloc(ptrs[i], bytes[i]) != hipSuccess) {
@@ -472,12 +487,14 @@ int run_steps(tpl_ctx *x, const Buffers &B, int nx, int ny, int *cur,
   }
   for (long long i = 0; i < n; ++i) {
     if (timed) HIPCHK(hipEventRecord(e0, x->stream));
+    const int ip = B.inplace ? (x->ip_odd ? 2 : 1) : 0;
     if (B.esize == 4)
       HIPCHK(launch_step<float>(p, B.half<float>(*cur), B.half<float>(1 - *cur), ref,
-                                x->qtab_d, x->stream, B.xsize == 2));
+                                x->qtab_d, x->stream, B.xsize == 2, ip));
     else
       HIPCHK(launch_step<double>(p, B.half<double>(*cur), B.half<double>(1 - *cur), ref,
-                                 x->qtab_d, x->stream));
+                                 x->qtab_d, x->stream, false, ip));
+    if (B.inplace) x->ip_odd ^= 1;
     if (timed) {
       HIPCHK(hipEventRecord(e1, x->stream));
       HIPCHK(hipEventSynchronize(e1));
@@ -495,14 +512,19 @@ int run_steps(tpl_ctx *x, const Buffers &B, int nx, int ny, int *cur,
 // fastest (every shape computes bitwise the same step).  The timed launches
 // read the current half and write the other without swapping, so repeating
 // them changes nothing; the first launch of each shape is a warm-up.
+constexpr int kTuneShapes = 6;
+const int kTuneCand[kTuneShapes][3] = {{1, 1, 0}, {4, 1, 1}, {2, 2, 1},
+                                       {8, 1, 0}, {8, 1, 1}, {4, 2, 1}};
+
 int tune_groups(tpl_ctx *x) {
+  if (x->buf.inplace) return TPL_OK;  // timed on real steps (tune_groups_inplace)
   x->tuned = true;
   x->wg_tuned = 0;
   StepParams p0 = make_step_params(x, x->c.nx, x->c.ny, x->c.qsplit);
   if (p0.qs != 1 || p0.wg != 0 || x->c.group_x * x->c.group_y > 1) return TPL_OK;
   const Buffers &B = x->buf;
   const bool neq = B.xsize == 2;  // one wave per SIMD: at most 4 waves per group
-  const int cand[][3] = {{1, 1, 0}, {4, 1, 1}, {2, 2, 1}, {8, 1, 0}, {8, 1, 1}, {4, 2, 1}};
+  const auto &cand = kTuneCand;
   const StepRef ref =
       B.esize == 4 ? step_ref(x) : StepRef{nullptr, nullptr, nullptr, nullptr, nullptr};
   hipEvent_t e0, e1;
@@ -538,6 +560,67 @@ int tune_groups(tpl_ctx *x) {
       x->wg_tuned = p.wg;
     }
   }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+// In-place steps cannot be repeated without advancing the state, so the
+// shapes are timed on real steps: a warm-up pair and a timed pair each
+// (every shape computes bitwise the same steps).  Needs kTuneSteps steps;
+// returns the number taken in *done.
+constexpr int kTuneSteps = 4 * kTuneShapes;
+int tune_groups_inplace(tpl_ctx *x, long long *done) {
+  *done = 0;
+  x->tuned = true;
+  x->wg_tuned = 0;
+  const StepParams p0 = make_step_params(x, x->c.nx, x->c.ny, x->c.qsplit);
+  if (p0.wg != 0 || x->c.group_x * x->c.group_y > 1) return TPL_OK;
+  const Buffers &B = x->buf;
+  const StepRef ref =
+      B.esize == 4 ? step_ref(x) : StepRef{nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 0.f;
+  int rc = TPL_OK, best_wg = 0;
+  for (const auto &c : kTuneCand) {
+    StepParams p = p0;
+    if (c[0] * c[1] > 1 && !set_group(p, c[0], c[1], c[2])) continue;
+    auto launch = [&]() {
+      const int ip = x->ip_odd ? 2 : 1;
+      const hipError_t e =
+          B.esize == 4
+              ? launch_step<float>(p, B.half<float>(x->cur), B.half<float>(1 - x->cur), ref,
+                                   x->qtab_d, x->stream, false, ip)
+              : launch_step<double>(p, B.half<double>(x->cur), B.half<double>(1 - x->cur), ref,
+                                    x->qtab_d, x->stream, false, ip);
+      if (e == hipSuccess) {  // a real step
+        x->ip_odd ^= 1;
+        x->cur = 1 - x->cur;
+        ++*done;
+      }
+      return e;
+    };
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e0, x->stream);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, x->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      rc = fail(TPL_EHIP, std::string("tile-group tuning: ") + hipGetErrorString(e));
+      break;
+    }
+    x->tune_ms += ms * 2.0;
+    if (best == 0.f || ms < best) {
+      best = ms;
+      best_wg = p.wg;
+    }
+  }
+  x->wg_tuned = best_wg;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return rc;
@@ -635,6 +718,7 @@ int prepare_state(tpl_ctx *x) {
     }
   }
   x->cur = 0;
+  x->ip_odd = 0;
   x->step = 0;
   x->inited = false;
   return TPL_OK;
@@ -740,6 +824,17 @@ int check_ready(const tpl_ctx *x) {
   return TPL_OK;
 }
 
+// Calls that read or write populations need them in their plain order,
+// which in-place streaming holds after an even number of steps.
+int check_populations(const tpl_ctx *x) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  if (x->ip_odd)
+    return fail(TPL_ESTATE, "in-place streaming holds the populations in streamed order after "
+                            "an odd number of steps: advance one more step first");
+  return TPL_OK;
+}
+
 struct Key {
   const char *name;
   double Config::*dbl;
@@ -759,6 +854,7 @@ const Key kKeys[] = {
     {"drift_cap", &Config::drift_cap, nullptr, nullptr},
     {"drift_relax", &Config::drift_relax, nullptr, nullptr},
     {"qe_model", nullptr, &Config::qe_model, nullptr},
+    {"inplace", nullptr, &Config::inplace, nullptr},
     {"precision", nullptr, &Config::precision, nullptr},
     {"pert_modes", nullptr, &Config::pert_modes, nullptr},
     {"pre_steps", nullptr, nullptr, &Config::pre_steps},
@@ -858,6 +954,7 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
   // BF16 form: XP records carry the remainders and the 5 FP32 moments
   const double ms = 0.0;
   const double xq = x->c.precision == TPL_BF16NEQ ? 70.0 : 25.0 * xs;  // XP bytes per (r, Q)
+  const double pc = x->c.inplace ? 1.0 : 2.0;  // population arrays
   struct {
     const char *n;
     double v;
@@ -870,10 +967,11 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
       {"R", d.R}, {"DQ", d.DQ}, {"F0", d.F0}, {"kappa", d.kappa},
       {"meq", d.meq}, {"Sc", d.Sc}, {"rhoS0", d.rhoS0}, {"rhoP0", d.rhoP0},
       {"step", (double)x->step},
-      {"bytes_XS", 2.0 * es * 9 * N}, {"bytes_XP", 2.0 * xq * d.nqd * N},
+      {"bytes_XS", pc * es * 9 * N}, {"bytes_XP", pc * xq * d.nqd * N},
       {"bytes_PSI", 2.0 * es * d.nqd * N}, {"bytes_FLD", 16.0 * NF * N},
       {"bytes_MOM", 2.0 * ms * d.nqd * N},
-      {"bytes_state", 2.0 * N * (es * (9 + d.nqd) + xq * d.nqd + ms * d.nqd + 8.0 * NF)},
+      {"bytes_state",
+       N * (pc * (es * 9 + xq * d.nqd) + 2.0 * (es * d.nqd + ms * d.nqd + 8.0 * NF))},
       // algorithmic HBM bytes of one step: populations read + written,
       // lagged psi written + read, lagged per-node fields written + read
       // (BF16 form: remainders and FP32 fluxes read + written once)
@@ -885,6 +983,7 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
       {"group_y_used", (double)((x->wg_used >> 8) & 255)},
       {"group_sync_used", (double)((x->wg_used >> 16) & 1)},
       {"tune_ms", x->tune_ms},
+      {"inplace_odd", (double)x->ip_odd},
   };
   for (auto &kv : vals)
     if (std::strcmp(kv.n, key) == 0) {
@@ -911,7 +1010,10 @@ int tpl_adopt_buffers(tpl_ctx *x, void *const *dptrs, const size_t *bytes, int n
   B.nPSI = state_elems(x, 2);
   B.nFLD = state_elems(x, 3);
   B.esize = elem_size(x);
-  const size_t need[4] = {2 * B.nXS * B.esize, 2 * B.nXP * B.esize, 2 * B.nPSI * B.esize,
+  B.xsize = B.esize;
+  B.inplace = x->c.inplace != 0;
+  const size_t pc = B.pop_copies();
+  const size_t need[4] = {pc * B.nXS * B.esize, pc * B.nXP * B.esize, 2 * B.nPSI * B.esize,
                           2 * B.nFLD * sizeof(double)};
   for (int i = 0; i < 4; ++i) {
     if (!dptrs[i] || bytes[i] < need[i])
@@ -951,8 +1053,15 @@ int tpl_step(tpl_ctx *x, int64_t n) {
   int rc = check_ready(x);
   if (rc) return rc;
   if (n < 0) return fail(TPL_EINVAL, "n must be >= 0");
-  if (!x->tuned && x->c.autotune && n > 0) {
+  if (!x->tuned && x->c.autotune && n > 0 && !x->buf.inplace) {
     rc = tune_groups(x);
+    if (rc) return rc;
+  }
+  if (!x->tuned && x->c.autotune && x->buf.inplace && !x->mlp && n >= kTuneSteps) {
+    long long done = 0;
+    rc = tune_groups_inplace(x, &done);
+    x->step += done;
+    n -= done;
     if (rc) return rc;
   }
   {
@@ -1084,7 +1193,7 @@ int tpl_diagnostics(tpl_ctx *x, tpl_diag *out) {
 
 int tpl_get_window(tpl_ctx *x, int x0, int y0, int w, int h, double *XS,
                    double *XP, double *psi, double *U) {
-  int rc = check_ready(x);
+  int rc = check_populations(x);
   if (rc) return rc;
   if (w < 1 || h < 1) return fail(TPL_EINVAL, "window must be non-empty");
   const size_t nqd = x->d.nqd, wh = (size_t)w * h;
@@ -1157,14 +1266,14 @@ static int array_from_host(tpl_ctx *x, void *dst, int planes, const float *ref,
 }
 
 int tpl_get_state(tpl_ctx *x, double *XS, double *XP, double *psi, double *U) {
-  int rc = check_ready(x);
+  int rc = (XS || XP) ? check_populations(x) : check_ready(x);
   if (rc) return rc;
   const size_t N = (size_t)x->c.nx * x->c.ny;
   const int nqd = x->d.nqd, cur = x->cur;
   const RefView r = ref_view(x);
-  const size_t es = x->buf.esize;
-  const char *XSd = static_cast<const char *>(x->buf.XS) + cur * x->buf.nXS * es;
-  const char *XPd = static_cast<const char *>(x->buf.XP) + cur * x->buf.nXP * x->buf.xsize;
+  const size_t es = x->buf.esize, hp = x->buf.pop_half(cur);
+  const char *XSd = static_cast<const char *>(x->buf.XS) + hp * x->buf.nXS * es;
+  const char *XPd = static_cast<const char *>(x->buf.XP) + hp * x->buf.nXP * x->buf.xsize;
   const char *PSd = static_cast<const char *>(x->buf.PSI) + cur * x->buf.nPSI * es;
   FloatView fv;
   if (XP && neq(x)) {
@@ -1183,14 +1292,14 @@ int tpl_get_state(tpl_ctx *x, double *XS, double *XP, double *psi, double *U) {
 
 int tpl_set_state(tpl_ctx *x, const double *XS, const double *XP,
                   const double *psi, const double *U) {
-  int rc = check_ready(x);
+  int rc = check_populations(x);  // the node fields are refreshed from the populations
   if (rc) return rc;
   const size_t N = (size_t)x->c.nx * x->c.ny;
   const int nqd = x->d.nqd, cur = x->cur;
   const RefView r = ref_view(x);
-  const size_t es = x->buf.esize;
-  char *XSd = static_cast<char *>(x->buf.XS) + cur * x->buf.nXS * es;
-  char *XPd = static_cast<char *>(x->buf.XP) + cur * x->buf.nXP * x->buf.xsize;
+  const size_t es = x->buf.esize, hp = x->buf.pop_half(cur);
+  char *XSd = static_cast<char *>(x->buf.XS) + hp * x->buf.nXS * es;
+  char *XPd = static_cast<char *>(x->buf.XP) + hp * x->buf.nXP * x->buf.xsize;
   char *PSd = static_cast<char *>(x->buf.PSI) + cur * x->buf.nPSI * es;
   if (XS && (rc = array_from_host(x, XSd, 9, r.XS, XS))) return rc;
   if (neq(x) && XP) {
@@ -1246,15 +1355,15 @@ static const char kMagic[8] = {'T', 'P', 'L', 'C', 'K', 'P', 'T', '1'};
 // current half in storage precision (XS, XP, PSI, FLD) and, for the FP32
 // form, the FP64 reference.
 int tpl_save(tpl_ctx *x, const char *path) {
-  int rc = check_ready(x);
+  int rc = check_populations(x);
   if (rc) return rc;
   if (!path) return fail(TPL_EINVAL, "null path");
   FILE *f = std::fopen(path, "wb");
   if (!f) return fail(TPL_EINVAL, std::string("cannot open ") + path);
   HIPCHK(hipStreamSynchronize(x->stream));
-  const size_t es = x->buf.esize, xs = x->buf.xsize, cur = x->cur;
-  const void *src[6] = {static_cast<const char *>(x->buf.XS) + cur * x->buf.nXS * es,
-                        static_cast<const char *>(x->buf.XP) + cur * x->buf.nXP * xs,
+  const size_t es = x->buf.esize, xs = x->buf.xsize, cur = x->cur, hp = x->buf.pop_half(x->cur);
+  const void *src[6] = {static_cast<const char *>(x->buf.XS) + hp * x->buf.nXS * es,
+                        static_cast<const char *>(x->buf.XP) + hp * x->buf.nXP * xs,
                         static_cast<const char *>(x->buf.PSI) + cur * x->buf.nPSI * es,
                         x->buf.FLD + cur * x->buf.nFLD, x->ref,
                         x->buf.MOM ? x->buf.MOM + cur * x->buf.nMOM : nullptr};
@@ -1291,9 +1400,9 @@ int tpl_load(tpl_ctx *x, const char *path) {
     std::fclose(f);
     return fail(TPL_EINVAL, "checkpoint does not match this context");
   }
-  const size_t es = x->buf.esize, xs = x->buf.xsize, cur = x->cur;
-  void *dst[6] = {static_cast<char *>(x->buf.XS) + cur * x->buf.nXS * es,
-                  static_cast<char *>(x->buf.XP) + cur * x->buf.nXP * xs,
+  const size_t es = x->buf.esize, xs = x->buf.xsize, cur = x->cur, hp = x->buf.pop_half(x->cur);
+  void *dst[6] = {static_cast<char *>(x->buf.XS) + hp * x->buf.nXS * es,
+                  static_cast<char *>(x->buf.XP) + hp * x->buf.nXP * xs,
                   static_cast<char *>(x->buf.PSI) + cur * x->buf.nPSI * es,
                   x->buf.FLD + cur * x->buf.nFLD, x->ref,
                   x->buf.MOM ? x->buf.MOM + cur * x->buf.nMOM : nullptr};
@@ -1318,6 +1427,7 @@ int tpl_load(tpl_ctx *x, const char *path) {
     HIPCHK(hipStreamSynchronize(x->stream));
   }
   x->step = step;
+  x->ip_odd = 0;  // a checkpoint holds the populations in plain order
   return TPL_OK;
 }
 
@@ -1395,8 +1505,8 @@ InstDev inst_record(tpl_ctx *x, const Buffers &B, int nx, int ny, int qs, int it
   r.p.tiles_per_xcd = 0;
   r.p.wg = 0;
   for (int h = 0; h < 2; ++h) {
-    r.XS[h] = static_cast<char *>(B.XS) + h * B.nXS * B.esize;
-    r.XP[h] = static_cast<char *>(B.XP) + h * B.nXP * B.esize;
+    r.XS[h] = static_cast<char *>(B.XS) + B.pop_half(h) * B.nXS * B.esize;
+    r.XP[h] = static_cast<char *>(B.XP) + B.pop_half(h) * B.nXP * B.esize;
     r.PSI[h] = static_cast<char *>(B.PSI) + h * B.nPSI * B.esize;
     r.FLD[h] = B.FLD + h * B.nFLD;
   }
@@ -1755,6 +1865,8 @@ int tpl_batch_set_param(tpl_batch *b, const char *key, double value) {
       return TPL_OK;
     }
   if (!strcmp(key, "precision")) return fail(TPL_EINVAL, "precision is fixed at tpl_batch_create");
+  if (!strcmp(key, "inplace"))
+    return fail(TPL_EINVAL, "batched instances keep two population arrays");
   if (b->inited) return fail(TPL_ESTATE, "instance parameters are fixed after tpl_batch_init");
   for (tpl_ctx *x : b->inst) {
     const int rc = tpl_set_param(x, key, value);
@@ -2268,8 +2380,8 @@ void tpl_mlp_destroy(tpl_mlp *m) {
 }
 
 int tpl_restrict(const tpl_ctx *fine, tpl_ctx *coarse) {
-  int rc = check_ready(fine);
-  if (!rc) rc = check_ready(coarse);
+  int rc = check_populations(fine);
+  if (!rc) rc = check_populations(coarse);
   if (rc) return rc;
   const int nxf = fine->c.nx, nyf = fine->c.ny, nxc = coarse->c.nx, nyc = coarse->c.ny;
   if (nxc < 1 || nyc < 1 || nxf % nxc || nyf % nyc || nxf / nxc != nyf / nyc)

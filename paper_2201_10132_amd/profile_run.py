@@ -3,7 +3,8 @@
 Runs, in one process: a plain device-to-device copy of a known size (the
 calibration for the HBM byte counters), then the 1024 x 1024, NQ = 16 FP64
 workload for a few steps (short base-state run, since only the step kernel
-is measured), or with --batch N the first N instances of the seeded batched
+is measured; other sizes, one population array and a fixed tile group by
+option), or with --batch N the first N instances of the seeded batched
 sweep (FP32, NQ = 6) stepped together with a fixed launch shape (one
 Q-slice, groups of 4 tiles: the autotuner's usual pick; plain launches, no
 graph, so that every dispatch is the measured step).  Usage
@@ -30,6 +31,12 @@ def main():
     ap.add_argument("--qsplit", type=int, default=1, help="Q-slices of the batched step")
     ap.add_argument("--group", type=int, default=4, help="tiles per workgroup of the batched step")
     ap.add_argument("--batch-nq", type=int, default=6, help="Q points per axis of the batched sweep")
+    ap.add_argument("--periods", type=int, default=4)
+    ap.add_argument("--inplace", type=int, default=0, help="1: one population array")
+    ap.add_argument("--group-x", type=int, default=0,
+                    help="tile group of the single-lattice step (0: the autotuner's choice)")
+    ap.add_argument("--group-y", type=int, default=1)
+    ap.add_argument("--group-sync", type=int, default=1)
     args = ap.parse_args()
     import torch
     import paper_2201_10132_amd as P
@@ -52,10 +59,18 @@ def main():
               f"copy_bytes={8 * n}", flush=True)
         b.close()
         return
-    t = P.Tpl(args.nx, args.ny, 60.0, 1.0, 0.7, periods=4, nq=args.nq, pre_steps=100,
+    t = P.Tpl(args.nx, args.ny, 60.0, 1.0, 0.7, periods=args.periods, nq=args.nq, pre_steps=100,
               pert_modes=1)
     if args.precision:
         t.set_param("precision", args.precision)
+    if args.inplace:
+        t.set_param("inplace", 1)
+    if args.group_x:
+        t.set_param("autotune", 0)
+        t.set_param("group_y", 1)
+        t.set_param("group_x", args.group_x)
+        t.set_param("group_y", args.group_y)
+        t.set_param("group_sync", args.group_sync)
     t.init(seed=0, perturbation=1e-4)
     t.step(args.steps)
     print(f"bytes_per_step={t.query('bytes_per_step'):.0f} copy_bytes={8 * n}", flush=True)

@@ -220,10 +220,16 @@ class Tpl:
         _check(lib().tpl_diagnostics(self._h, C.byref(d)))
         return {n: getattr(d, n) for n in DIAG_NAMES}
 
-    def get_state(self):
+    def get_state(self, populations=True):
+        """XS, XP, psi, U as FP64 arrays; populations=False skips XS and XP
+        (those need the plain population order that in-place streaming holds
+        after an even number of steps)."""
         nqd = self.nqd
-        XS = np.zeros((9, self.ny, self.nx)); XP = np.zeros((25, nqd, self.ny, self.nx))
         psi = np.zeros((nqd, self.ny, self.nx)); U = np.zeros((2, self.ny, self.nx))
+        if not populations:
+            _check(lib().tpl_get_state(self._h, None, None, _dptr(psi), _dptr(U)))
+            return dict(psi=psi, U=U)
+        XS = np.zeros((9, self.ny, self.nx)); XP = np.zeros((25, nqd, self.ny, self.nx))
         _check(lib().tpl_get_state(self._h, _dptr(XS), _dptr(XP), _dptr(psi), _dptr(U)))
         return dict(XS=XS, XP=XP, psi=psi, U=U)
 

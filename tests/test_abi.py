@@ -192,3 +192,43 @@ def test_qe_model_parameters():
     with pytest.raises(P.TplError):
         t.set_param("qe_model", 3)
     t.close()
+
+
+def test_inplace_storage_knob():
+    """In-place streaming: one population array (half the XS and XP bytes,
+    same algorithmic bytes per step); FP64 and FP32 only, nx a multiple of
+    64, not for batches; population calls need an initialised context."""
+    t = P.Tpl(128, 64, 60.0, 1.0, 0.7, periods=2, nq=8)
+    two = {k: t.query(k) for k in ("bytes_XS", "bytes_XP", "bytes_PSI", "bytes_FLD",
+                                   "bytes_state", "bytes_per_step")}
+    t.set_param("inplace", 1)
+    assert t.query("inplace") == 1 and t.query("inplace_odd") == 0
+    assert t.query("bytes_XS") == two["bytes_XS"] / 2
+    assert t.query("bytes_XP") == two["bytes_XP"] / 2
+    for k in ("bytes_PSI", "bytes_FLD", "bytes_per_step"):
+        assert t.query(k) == two[k]
+    assert t.query("bytes_state") == two["bytes_state"] - (two["bytes_XS"] + two["bytes_XP"]) / 2
+    t.set_param("precision", P.TPL_FP32)
+    with pytest.raises(P.TplError) as e:
+        t.set_param("precision", P.TPL_BF16NEQ)
+    assert e.value.code == P.tpl.TPL_EINVAL
+    with pytest.raises(P.TplError):
+        t.set_param("inplace", 2)
+    with pytest.raises(P.TplError) as e:
+        t.get_state()
+    assert e.value.code == P.tpl.TPL_ESTATE  # not initialised
+    t.close()
+    u = P.Tpl(96, 64, 60.0, 1.0, 0.7, periods=2, nq=8)
+    with pytest.raises(P.TplError) as e:
+        u.set_param("inplace", 1)
+    assert "multiple of 64" in str(e.value)
+    u.close()
+    v = P.Tpl(128, 64, 60.0, 1.0, 0.7, periods=2, nq=8, precision=P.TPL_BF16NEQ)
+    with pytest.raises(P.TplError):
+        v.set_param("inplace", 1)
+    v.close()
+    b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8)])
+    with pytest.raises(P.TplError) as e:
+        b.set_param("inplace", 1)
+    assert "two population arrays" in str(e.value)
+    b.close()
