@@ -438,6 +438,12 @@ def measure_inplace(torch, forms, args) -> dict:
         e["tune_ms"] = m["tune_ms"]
         if nq == w3["nq"] and ref is not None:
             e["speed_vs_two_array"] = round(m["mlups"] / ref["mlups"], 3)
+        if nq == 8:  # counters of the two alternating kernels, one launch each on average
+            tb = [traffic_bytes(os.path.join(ROOT, "profiles", f"k_step_inplace_{k}_fp64_"
+                                             "kolmogorov4096_nq8_traffic.txt"))
+                  for k in ("pull", "local")]
+            if None not in tb:
+                e["roofline"]["traffic"] = round(sum(tb) / 2)
         res[f"fp64_4096x4096_nq{nq}"] = e
     return res
 
