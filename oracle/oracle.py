@@ -40,7 +40,7 @@ class _Config(C.Structure):
                 ("force_scale", C.c_double), ("lambda_set", C.c_double),
                 ("ny_param", C.c_int), ("y_offset", C.c_int), ("x_offset", C.c_int),
                 ("nx_param", C.c_int), ("drift_cap", C.c_double), ("drift_relax", C.c_double),
-                ("qe_model", C.c_int)]
+                ("qe_model", C.c_int), ("gradients", C.c_int)]
 
 
 _DERIVED = ["kf", "l", "nu", "nuS", "lambda", "G", "tau1S", "tau2S", "tau1P", "tau2P",
@@ -126,7 +126,7 @@ def splitmix64_next(state: int):
 DEFAULTS = dict(nq=16, periods=1, Re=20.0, Wi=0.5, beta=0.8, u0=0.05, phi=0.01,
                 spring=0, b=25.0, tau_drag=0.0, tau_ratio_p=1.0, force_scale=1.0,
                 lambda_set=0.0, ny_param=0, y_offset=0, x_offset=0, nx_param=0, drift_cap=0.1,
-                drift_relax=1.0, qe_model=1)
+                drift_relax=1.0, qe_model=1, gradients=0)
 
 DIAG_NAMES = ["step", "mass_S", "mass_P", "mom_x", "mom_y", "amplitude",
               "enstrophy", "qrms", "min_psi"]

@@ -240,6 +240,10 @@ static int derive(orc_sim *s, char *err) {
     if (err) snprintf(err, 256, "qe_model must be 1 or 2");
     return -1;
   }
+  if (c->gradients != 0 && c->gradients != 1) {
+    if (err) snprintf(err, 256, "gradients must be 0 or 1");
+    return -1;
+  }
   if (c->tau_ratio_p > 1.0 || c->tau_ratio_p <= 0.0) {
     if (err) snprintf(err, 256, "tau_ratio_p must be in (0,1]");
     return -1;
@@ -408,6 +412,50 @@ void orc_polymer_qe2(const orc_sim *s, double psi, const double J[4], const doub
 }
 
 /* ------------------------------------------------------------------------ */
+/* The g-moments the mixture velocity needs (densities, momenta, solvent
+ * second moments, the Q-sum S of the spring terms) and the mixture velocity
+ * itself (see orc_collide_node). */
+static void mixture(const orc_sim *s, const double *gS, const double *gP, const double *sq,
+                    const double Fb[2], double *rhoS_out, double JSg[2], double PSg[3],
+                    double *rhoP_out, double JPg[2], double U[2]) {
+  const orc_derived *p = &s->p;
+  const int nqd = s->nqd;
+  const int m2 = s->c.qe_model == 2;
+  const double tJS = m2 ? p->tau1S : p->tau2S, tJP = m2 ? p->tau1P : p->tau2P;
+  /* solvent moments of g */
+  double rhoS = 0;
+  JSg[0] = JSg[1] = 0;
+  PSg[0] = PSg[1] = PSg[2] = 0;
+  for (int i = 0; i < 9; ++i) {
+    rhoS += gS[i];
+    JSg[0] += C9[i][0] * gS[i];
+    JSg[1] += C9[i][1] * gS[i];
+    PSg[0] += C9[i][0] * C9[i][0] * gS[i];
+    PSg[1] += C9[i][0] * C9[i][1] * gS[i];
+    PSg[2] += C9[i][1] * C9[i][1] * gS[i];
+  }
+  /* polymer moments of g at every Q-node and their Q-sums */
+  double rhoP = 0, S[2] = {0, 0};
+  JPg[0] = JPg[1] = 0;
+  for (int q = 0; q < nqd; ++q) {
+    const double *g = gP + 25 * q;
+    for (int k = 0; k < 25; ++k) {
+      rhoP += g[k];
+      JPg[0] += s->cp[k][0] * g[k];
+      JPg[1] += s->cp[k][1] * g[k];
+    }
+    S[0] += sq[2 * q];
+    S[1] += sq[2 * q + 1];
+  }
+  /* mixture velocity */
+  double aS = 1.0 / (2.0 * tJS + 1.0), aP = 1.0 / (2.0 * tJP + 1.0);
+  double den = rhoS * aS + rhoP * aP;
+  for (int a = 0; a < 2; ++a)
+    U[a] = ((JSg[a] + 0.5 * Fb[a]) * aS + (JPg[a] + S[a] / (2.0 * tJP)) * aP) / den;
+  *rhoS_out = rhoS;
+  *rhoP_out = rhoP;
+}
+
 /* Steps 4-7 at one r-node.
  *
  * Two quasi-equilibrium models (Sec. V):
@@ -436,33 +484,9 @@ void orc_collide_node(const orc_sim *s, const double *gS, const double *gP,
   const int nqd = s->nqd;
   const int m2 = s->c.qe_model == 2;
   const double tJS = m2 ? p->tau1S : p->tau2S, tJP = m2 ? p->tau1P : p->tau2P;
-  /* solvent moments of g */
-  double rhoS = 0, JSg[2] = {0, 0}, PSg[3] = {0, 0, 0};
-  for (int i = 0; i < 9; ++i) {
-    rhoS += gS[i];
-    JSg[0] += C9[i][0] * gS[i];
-    JSg[1] += C9[i][1] * gS[i];
-    PSg[0] += C9[i][0] * C9[i][0] * gS[i];
-    PSg[1] += C9[i][0] * C9[i][1] * gS[i];
-    PSg[2] += C9[i][1] * C9[i][1] * gS[i];
-  }
-  /* polymer moments of g at every Q-node and their Q-sums */
-  double rhoP = 0, JPg[2] = {0, 0}, S[2] = {0, 0};
-  for (int q = 0; q < nqd; ++q) {
-    const double *g = gP + 25 * q;
-    for (int k = 0; k < 25; ++k) {
-      rhoP += g[k];
-      JPg[0] += s->cp[k][0] * g[k];
-      JPg[1] += s->cp[k][1] * g[k];
-    }
-    S[0] += sq[2 * q];
-    S[1] += sq[2 * q + 1];
-  }
-  /* mixture velocity */
-  double aS = 1.0 / (2.0 * tJS + 1.0), aP = 1.0 / (2.0 * tJP + 1.0);
-  double den = rhoS * aS + rhoP * aP;
-  for (int a = 0; a < 2; ++a)
-    U[a] = ((JSg[a] + 0.5 * Fb[a]) * aS + (JPg[a] + S[a] / (2.0 * tJP)) * aP) / den;
+  double rhoS, JSg[2], PSg[3], rhoP, JPg[2];
+  mixture(s, gS, gP, sq, Fb, &rhoS, JSg, PSg, &rhoP, JPg, U);
+  const double aS = 1.0 / (2.0 * tJS + 1.0), aP = 1.0 / (2.0 * tJP + 1.0);
 
   /* solvent: target momentum rho_S U + tJ_S F (the body force by a shift of
    * the equilibrium velocity) */
@@ -584,12 +608,45 @@ static double body_force_x(const orc_sim *s, int y) {
   return s->p.F0 * sin(s->p.kf * (double)(y + s->c.y_offset));
 }
 
-/* One time step: stream; then, per r-node, the lagged non-local terms and
- * the collision; then record the observables as the next step's lag. */
-static void step_once(orc_sim *s) {
-  stream(s);
+/* Spring terms of J^r_eq at node (x, y) from the recorded psi: first-order
+ * Taylor expansion of sum_nu (F_nu/zeta) psi(r - R_nu, Q) (Sec. III/V),
+ * s = kappa Fhat(Q) [Q . grad psi(r, Q)]. */
+static void spring_terms(const orc_sim *s, int x, int y, double *sq) {
+  const int nqd = s->nqd;
+  for (int q = 0; q < nqd; ++q) {
+    double gx = ddx(s, s->psi, nqd, q, x, y);
+    double gy = ddy(s, s->psi, nqd, q, x, y);
+    double qg = s->Q[2 * q] * gx + s->Q[2 * q + 1] * gy;
+    sq[2 * q] = s->p.kappa * s->Fh[2 * q] * qg;
+    sq[2 * q + 1] = s->p.kappa * s->Fh[2 * q + 1] * qg;
+  }
+}
+
+static void body_force(const orc_sim *s, int y, size_t n, double Fb[2]) {
+  Fb[0] = body_force_x(s, y);
+  Fb[1] = 0.0;
+  if (s->src) {
+    Fb[0] += s->src[2 * n];
+    Fb[1] += s->src[2 * n + 1];
+  }
+}
+
+/* Same-step gradients (the reading that takes the gradients at the current
+ * time level): replace the recorded psi and U by those of the pulled
+ * populations of this step, psi^n(r, Q) = sum_k g_k and U^n the mixture
+ * velocity with the spring terms of grad psi^n, before any node collides. */
+static void current_observables(orc_sim *s) {
   const int nx = s->nx, ny = s->ny, nqd = s->nqd;
-  const double kappa = s->p.kappa;
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      size_t n = nid(s, x, y);
+      for (int q = 0; q < nqd; ++q) {
+        double ps = 0;
+        for (int k = 0; k < 25; ++k) ps += s->GP[(n * nqd + q) * 25 + k];
+        s->psi[n * nqd + q] = ps;
+      }
+    }
 #pragma omp parallel
   {
     double *sq = malloc(sizeof(double) * 2 * nqd);
@@ -597,24 +654,36 @@ static void step_once(orc_sim *s) {
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         size_t n = nid(s, x, y);
-        /* lagged velocity gradient K_ab = d_b U_a of U^{n-1} */
+        double Fb[2], rhoS, JSg[2], PSg[3], rhoP, JPg[2];
+        spring_terms(s, x, y, sq);
+        body_force(s, y, n, Fb);
+        mixture(s, s->GS + 9 * n, s->GP + n * nqd * 25, sq, Fb, &rhoS, JSg, PSg, &rhoP, JPg,
+                s->U + 2 * n);
+      }
+    free(sq);
+  }
+}
+
+/* One time step: stream; then, per r-node, the non-local terms (from the
+ * recorded observables: the previous step's, or with same-step gradients
+ * this step's) and the collision; then record the observables. */
+static void step_once(orc_sim *s) {
+  stream(s);
+  if (s->c.gradients == 1) current_observables(s);
+  const int nx = s->nx, ny = s->ny, nqd = s->nqd;
+#pragma omp parallel
+  {
+    double *sq = malloc(sizeof(double) * 2 * nqd);
+#pragma omp for schedule(static)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        size_t n = nid(s, x, y);
+        /* velocity gradient K_ab = d_b U_a of the recorded U */
         double K[4] = {ddx(s, s->U, 2, 0, x, y), ddy(s, s->U, 2, 0, x, y),
                        ddx(s, s->U, 2, 1, x, y), ddy(s, s->U, 2, 1, x, y)};
-        /* spring term of J^r_eq, first-order Taylor expansion of
-         * sum_nu (F_nu/zeta) psi(r - R_nu, Q) (Sec. III/V):
-         * s = kappa Fhat(Q) [Q . grad psi^{n-1}(r, Q)] */
-        for (int q = 0; q < nqd; ++q) {
-          double gx = ddx(s, s->psi, nqd, q, x, y);
-          double gy = ddy(s, s->psi, nqd, q, x, y);
-          double qg = s->Q[2 * q] * gx + s->Q[2 * q + 1] * gy;
-          sq[2 * q] = kappa * s->Fh[2 * q] * qg;
-          sq[2 * q + 1] = kappa * s->Fh[2 * q + 1] * qg;
-        }
-        double Fb[2] = {body_force_x(s, y), 0.0};
-        if (s->src) {
-          Fb[0] += s->src[2 * n];
-          Fb[1] += s->src[2 * n + 1];
-        }
+        spring_terms(s, x, y, sq);
+        double Fb[2];
+        body_force(s, y, n, Fb);
         double Un[2];
         orc_collide_node(s, s->GS + 9 * n, s->GP + n * nqd * 25, K, sq, Fb,
                          s->XS + 9 * n, s->XP + n * nqd * 25, Un);

@@ -24,6 +24,9 @@
  *   step (polymer, Q)                  -> Hookean relaxation time lambda
  *   step (coupling, forcing, spring)   -> laminar Oldroyd-B closed form
  *   step (conservation)                -> mass and momentum invariants
+ *   same-step gradients                -> independence of the lagged fields;
+ *                                         the laminar closed form and the
+ *                                         invariants as above
  *   perturb                            -> prescribed RMS amplitude
  *   splitmix64                         -> published test vectors
  *   FENE runs                          -> parity unpinned beyond the above
@@ -60,6 +63,10 @@ typedef struct {
   double drift_relax;  /* > 0: also cap it at drift_relax (2 - omega_P)        */
   int qe_model;        /* 1: component-momentum quasi-equilibria (Sec. V (i));
                         * 2: stress-tensor quasi-equilibria (Sec. V (ii))      */
+  int gradients;       /* time level of the velocity gradient and of the
+                        * spring term's psi gradient, which the paper leaves
+                        * open: 0 = the previous step's observables (lagged);
+                        * 1 = the current step's, from the pulled populations */
 } orc_config;
 
 /* Derived lattice parameters (step 0 of the scheme contract). */

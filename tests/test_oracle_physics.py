@@ -11,6 +11,9 @@ P9     forced laminar Kolmogorov state with Hookean dumbbells against the
        Oldroyd-B closed form (Sec. VII forcing; Sec. III elastic stress).
 P12    x-invariance: with no perturbation the amplitude stays at round-off.
 P14    the parameter mapping gives the paper's Schmidt-number range (Sec. VII).
+Same-step gradients (the reading of the gradients' time level that takes
+this step's observables): the invariants and the laminar closed form as
+above, and a step that ignores the recorded fields.
 """
 import numpy as np
 import pytest
@@ -37,9 +40,10 @@ def _abs_momentum(sim):
     return np.sqrt((J ** 2).sum(0)).sum()
 
 
+@pytest.mark.parametrize("gradients", [0, 1])
 @pytest.mark.parametrize("spring", [0, 1])
-def test_conservation_on_lattice(spring):
-    sim = oracle.OracleSim(16, 16, nq=6, spring=spring)
+def test_conservation_on_lattice(spring, gradients):
+    sim = oracle.OracleSim(16, 16, nq=6, spring=spring, gradients=gradients)
     sim.base_state(300)
     sim.perturb(seed=3, amp=0.05, multimode=True)
     d0 = sim.diagnostics()
@@ -127,7 +131,8 @@ def test_conformation_relaxation_time():
     assert e[0] > e[1] > e[2]
 
 
-def test_laminar_oldroyd_b_profile():
+@pytest.mark.parametrize("gradients", [0, 1])
+def test_laminar_oldroyd_b_profile(gradients):
     """Hookean laminar state: U = U_L sin ky with
     U_L = F0 / (k^2 [eta_s + eta_pk + G lambda / (1 + lambda D k^2)]),
     C_xy = lambda U_L k cos(ky) / (1 + lambda D k^2),
@@ -135,7 +140,8 @@ def test_laminar_oldroyd_b_profile():
     eta_s = rho_S c_s^2 tau1_S, eta_pk = rho_P c_s^2 tau1_P (kinetic part of the
     polymer populations), D = c_s^2 tau2_P (r-diffusion)."""
     ny = 64
-    sim = oracle.OracleSim(1, ny, nq=16, spring=1, Re=5.0, Wi=0.5, beta=0.8, periods=1)
+    sim = oracle.OracleSim(1, ny, nq=16, spring=1, Re=5.0, Wi=0.5, beta=0.8, periods=1,
+                           gradients=gradients)
     d = sim.derived()
     sim.rest()
     sim.step(int(12 * max(d["l"] ** 2 / d["nu"], d["lambda"])))
@@ -251,3 +257,42 @@ def test_stiff_fene_diverges_without_the_relative_cap():
     m0 = o.diagnostics()["min_psi"]
     o.step(8000)
     assert healthy(o.diagnostics(), 2 * m0)
+
+
+def test_same_step_gradients_use_this_steps_observables():
+    """With same-step gradients a step ignores the recorded psi and U: two
+    states that differ only there step to the same populations, and to the
+    populations a lagged step reaches when the recorded fields are replaced
+    by the observables this step produces.  The lagged step does depend on
+    them."""
+    def sim(gradients):
+        o = oracle.OracleSim(8, 8, nq=6, spring=0, gradients=gradients, periods=1)
+        o.base_state(100)
+        o.perturb(seed=1, amp=0.05, multimode=True)
+        o.step(3)
+        return o
+
+    def with_lag(o, psi, U):
+        st = o.get_state()
+        o.set_state(XS=st["XS"], XP=st["XP"], psi=psi, U=U)
+        return o
+
+    a = sim(1)
+    st = a.get_state()
+    noisy = with_lag(sim(1), st["psi"] * (1 + inputs.normal(5, st["psi"].shape, 0.1)),
+                     inputs.normal(6, st["U"].shape, 1e-3))
+    a.step(1); noisy.step(1)
+    ra, rn = a.get_state(), noisy.get_state()
+    for k in ra:
+        assert np.array_equal(ra[k], rn[k]), k
+    lag_sim = oracle.OracleSim(8, 8, nq=6, spring=0, gradients=0, periods=1)
+    lag_sim.set_state(XS=st["XS"], XP=st["XP"], psi=ra["psi"], U=ra["U"])
+    lag_sim.step(1)
+    rl = lag_sim.get_state()
+    for k in ("XS", "XP"):
+        assert np.array_equal(ra[k], rl[k]), k
+    b = sim(0)
+    stb = b.get_state()
+    other = with_lag(sim(0), stb["psi"], inputs.normal(6, stb["U"].shape, 1e-3))
+    b.step(1); other.step(1)
+    assert not np.array_equal(b.get_state()["XP"], other.get_state()["XP"])
