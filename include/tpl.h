@@ -145,6 +145,12 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *                 diagnostics and the amplitude are available after every
  *                 step.  The autotuner times its shapes on the first
  *                 tpl_step of at least 24 steps, as real steps
+ *   gradients 0   time level of the velocity gradient and of the spring
+ *                 term's psi gradient (the paper leaves it open): 0 = the
+ *                 previous step's observables (one pass); 1 = this step's,
+ *                 formed from the pulled populations before the step (three
+ *                 more launches, about 1.5x the bytes; FP64 and FP32 forms,
+ *                 not for batches)
  *   pert_modes 1  0 = single x-mode, 1 = multimode perturbation
  *   pre_steps -1  base-state column steps (-1 = 5 max(l^2/nu, lambda))
  *   qsplit 0      Q-slices per r-tile in the step kernel: 0 (automatic),
@@ -281,8 +287,8 @@ tpl_batch *tpl_batch_create(const tpl_instance *inst, int n, int precision);
  *   graph_steps 20 steps captured per HIP graph (< 2: plain launches)
  *   time_kernels 0 1 = time tpl_batch_step with HIP events (kernel_ms)
  * Any other key is a tpl_set_param key applied to every instance before
- * tpl_batch_init (TPL_ESTATE afterwards; precision and inplace are
- * rejected). */
+ * tpl_batch_init (TPL_ESTATE afterwards; precision, inplace and gradients
+ * are rejected). */
 int tpl_batch_set_param(tpl_batch *b, const char *key, double value);
 
 /* Keys: the launch keys above and instances, active (not flagged unstable),

@@ -111,6 +111,12 @@ template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
                        StepRef ref, const QNode *qtab, hipStream_t s, bool neq = false,
                        int ip = 0);
+// Same-step gradients: overwrite the read half's PSI, M and U with this
+// step's psi^n, M^n and U^n (three launches) before launch_step.  ip as there
+// (the pull of the step that follows); FP64 and FP32 forms.
+template <typename T>
+hipError_t launch_same_step_fields(const StepParams &p, StateT<T> a, StepRef ref,
+                                   const QNode *qtab, hipStream_t s, int ip = 0);
 // BF16 non-equilibrium form <-> FP32 deviations from the reference, node by
 // node: dev [25][nqd][N] = w_k (m0 + 3 (v_k . J)) + n_k (decode), and the
 // inverse (encode: writes MOM and n).

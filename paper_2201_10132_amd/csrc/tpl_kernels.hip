@@ -197,6 +197,18 @@ __device__ __forceinline__ void neq_encode(const double d[25], uint16_t nb[25], 
 // are wave-uniform (scalar loads).
 // One 64-node tile of one lattice (all qs slices of the workgroup take part).
 // red: LDS of qs * 12 * 64 doubles.
+// Mixture velocity: the velocity at which the momentum exchange of the two
+// species cancels (Sec. IV/V), from their g-momenta, the body force and the
+// Q-sum S of the spring term, weighted by 1 / (2 tJ + 1) per species.
+__device__ __forceinline__ void mixture_velocity(const StepParams &p, double rhoS, double JSx,
+                                                 double JSy, double rhoP, double JPx, double JPy,
+                                                 double Sx, double Sy, double Fbx, double Fby,
+                                                 double &Ux, double &Uy) {
+  const double den = rhoS * p.aS + rhoP * p.aP;
+  Ux = ((JSx + 0.5 * Fbx) * p.aS + (JPx + Sx / (2.0 * p.tJP)) * p.aP) / den;
+  Uy = ((JSy + 0.5 * Fby) * p.aS + (JPy + Sy / (2.0 * p.tJP)) * p.aP) / den;
+}
+
 // In-place streaming (IP != 0; one population array, a == b for XS and XP;
 // the AA pattern of Bailey et al., "Accelerating lattice Boltzmann fluid flow
 // simulations using graphics processors", ICPP 2009, with the Q-disk
@@ -297,9 +309,8 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
     Fby = p.src[N + r];
   }
   // ---- mixture velocity: exchange of the two species cancels
-  const double den = rhoS * p.aS + rhoP * p.aP;
-  const double Ux = ((JSx + 0.5 * Fbx) * p.aS + (JPx + Sx / (2.0 * p.tJP)) * p.aP) / den;
-  const double Uy = ((JSy + 0.5 * Fby) * p.aS + (JPy + Sy / (2.0 * p.tJP)) * p.aP) / den;
+  double Ux, Uy;
+  mixture_velocity(p, rhoS, JSx, JSy, rhoP, JPx, JPy, Sx, Sy, Fbx, Fby, Ux, Uy);
   const bool writer = (slice == 0) && active;
 
   // ---- solvent collision (slice 0 writes)
@@ -753,6 +764,123 @@ template hipError_t launch_step<double>(const StepParams &, StateT<double>, Stat
                                         StepRef, const QNode *, hipStream_t, bool, int);
 template hipError_t launch_step<float>(const StepParams &, StateT<float>, StateT<float>,
                                        StepRef, const QNode *, hipStream_t, bool, int);
+
+// Same-step gradients: before the step, the read half's recorded psi, M and
+// U are replaced by this step's (the step then reads them where it would
+// read the previous step's): psi^n(r, Q) of the pulled populations, one
+// thread per (r, Q)-node; M^n = sum_Q psi^n Q Fhat^T per r-node; U^n, the
+// mixture velocity with the spring-stress divergence of M^n, per r-node.
+// ip selects the pull of the in-place steps as in step_tile.
+template <typename T>
+__global__ void k_pre_psi(StepParams p, StateT<T> a, const float *__restrict__ rpull,
+                          const float *__restrict__ rpsi, const QNode *__restrict__ qtab, int ip) {
+  constexpr bool F32 = std::is_same<T, float>::value;
+  constexpr uint32_t SZ = sizeof(T);
+  const long long N = p.N;
+  const long long rr = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rr >= N) return;
+  const int r = (int)rr, q = blockIdx.y, nx = p.nx, ny = p.ny, nqd = p.nqd;
+  const int y = r / nx, x = r - y * nx;
+  const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+  const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
+  const QNode CONSTANT_AS &qn = cst(qtab)[q];
+  double psi = 0.0;
+#pragma unroll
+  for (int k = 0; k < 25; ++k) {
+    const int d = pdir(k);
+    const int sx = C9X[d] == 1 ? xm : (C9X[d] == -1 ? xp : x);
+    const int sy = C9Y[d] == 1 ? ym : (C9Y[d] == -1 ? yp : y);
+    const T *pl = ip == 2 ? a.XP + (size_t)(krev(k) * nqd + q) * N : a.XP + (size_t)qn.plane[k] * N;
+    const uint32_t off = SZ * (uint32_t)(ip == 2 ? r : sy * nx + sx);
+    const double ref = F32 ? (double)rpull[((size_t)y * nqd + q) * 25 + k] : 0.0;
+    psi += full(ldo(pl, off), ref);
+  }
+  sto(a.PSI + (size_t)q * N, SZ * (uint32_t)r,
+      stored<T>(psi, F32 ? (double)rpsi[(size_t)y * nqd + q] : 0.0));
+}
+
+template <typename T>
+__global__ void k_pre_m(StepParams p, StateT<T> a, const float *__restrict__ rpsi,
+                        const QNode *__restrict__ qtab) {
+  constexpr bool F32 = std::is_same<T, float>::value;
+  const long long N = p.N;
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  const int y = (int)(r / p.nx);
+  double Mxx = 0.0, Mxy = 0.0, Myy = 0.0;
+  for (int q = 0; q < p.nqd; ++q) {
+    const double psi = full(a.PSI[(size_t)q * N + r], F32 ? (double)rpsi[(size_t)y * p.nqd + q] : 0.0);
+    const QNode CONSTANT_AS &qn = cst(qtab)[q];
+    Mxx += psi * qn.qx * qn.fx;
+    Mxy += psi * qn.qx * qn.fy;
+    Myy += psi * qn.qy * qn.fy;
+  }
+  a.FLD[(size_t)F_MXX * N + r] = Mxx;
+  a.FLD[(size_t)F_MXY * N + r] = Mxy;
+  a.FLD[(size_t)F_MYY * N + r] = Myy;
+}
+
+template <typename T>
+__global__ void k_pre_u(StepParams p, StateT<T> a, const float *__restrict__ rspull, int ip) {
+  constexpr bool F32 = std::is_same<T, float>::value;
+  const long long N = p.N;
+  const long long rr = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rr >= N) return;
+  const int r = (int)rr, nx = p.nx, ny = p.ny;
+  const int y = r / nx, x = r - y * nx;
+  const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+  const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
+  const double *G = a.FLD;
+  double rhoS = 0.0, JSx = 0.0, JSy = 0.0, rhoP = 0.0, JPx = 0.0, JPy = 0.0;
+#pragma unroll
+  for (int d = 0; d < 9; ++d) {
+    const int sx = C9X[d] == 1 ? xm : (C9X[d] == -1 ? xp : x);
+    const int sy = C9Y[d] == 1 ? ym : (C9Y[d] == -1 ? yp : y);
+    const size_t src = (size_t)sy * nx + sx;
+    const size_t sp = ip == 2 ? (size_t)rev9(d) * N + r : (size_t)d * N + src;
+    const double g = full(a.XS[sp], F32 ? (double)rspull[(size_t)y * 9 + d] : 0.0);
+    rhoS += g;
+    if (C9X[d]) JSx += C9X[d] * g;
+    if (C9Y[d]) JSy += C9Y[d] * g;
+    const double m = G[(size_t)(F_M0 + d) * N + src];
+    rhoP += m;
+    if (C9X[d]) JPx += C9X[d] * m;
+    if (C9Y[d]) JPy += C9Y[d] * m;
+  }
+  auto dX = [&](int f) {
+    return 0.5 * (G[(size_t)f * N + (size_t)y * nx + xp] - G[(size_t)f * N + (size_t)y * nx + xm]);
+  };
+  auto dY = [&](int f) {
+    return 0.5 * (G[(size_t)f * N + (size_t)yp * nx + x] - G[(size_t)f * N + (size_t)ym * nx + x]);
+  };
+  const double Sx = p.kappa * (dX(F_MXX) + dY(F_MXY));
+  const double Sy = p.kappa * (dX(F_MXY) + dY(F_MYY));
+  double Fbx = p.F0 * sin(p.kf * (double)(y + p.y0)), Fby = 0.0;
+  if (p.src != nullptr) {
+    Fbx += p.src[r];
+    Fby = p.src[N + r];
+  }
+  double Ux, Uy;
+  mixture_velocity(p, rhoS, JSx, JSy, rhoP, JPx, JPy, Sx, Sy, Fbx, Fby, Ux, Uy);
+  a.FLD[(size_t)F_UX * N + r] = Ux;
+  a.FLD[(size_t)F_UY * N + r] = Uy;
+}
+
+template <typename T>
+hipError_t launch_same_step_fields(const StepParams &p, StateT<T> a, StepRef ref,
+                                   const QNode *qtab, hipStream_t s, int ip) {
+  if (ip < 0 || ip > 2 || p.nqd < 1 || p.nqd > 65535) return hipErrorInvalidValue;
+  const unsigned nb = (unsigned)((p.N + 255) / 256);
+  hipLaunchKernelGGL(k_pre_psi<T>, dim3(nb, (unsigned)p.nqd), dim3(256), 0, s, p, a, ref.pull,
+                     ref.psi, qtab, ip);
+  hipLaunchKernelGGL(k_pre_m<T>, dim3(nb), dim3(256), 0, s, p, a, ref.psi, qtab);
+  hipLaunchKernelGGL(k_pre_u<T>, dim3(nb), dim3(256), 0, s, p, a, ref.spull, ip);
+  return hipGetLastError();
+}
+template hipError_t launch_same_step_fields<double>(const StepParams &, StateT<double>, StepRef,
+                                                    const QNode *, hipStream_t, int);
+template hipError_t launch_same_step_fields<float>(const StepParams &, StateT<float>, StepRef,
+                                                   const QNode *, hipStream_t, int);
 
 // BF16 non-equilibrium form: node-local conversions to and from FP32
 // deviations (auxiliary paths: initialisation, state exchange, diagnostics).

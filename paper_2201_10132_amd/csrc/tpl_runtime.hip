@@ -45,6 +45,7 @@ struct Config {
   int group_x = 1, group_y = 1, group_sync = 0, autotune = 1;
   int qe_model = 1;
   int inplace = 0;  // one population array, streamed in place
+  int gradients = 0;  // 0: lagged (previous step's) gradients; 1: same-step
 };
 
 struct Derived {
@@ -74,6 +75,9 @@ int derive(const Config &c, Derived &d) {
     return fail(TPL_EINVAL, "in-place streaming is for the FP64 and FP32 forms");
   if (c.inplace && c.nx % 64)
     return fail(TPL_EINVAL, "in-place streaming needs nx a multiple of 64");
+  if (c.gradients != 0 && c.gradients != 1) return fail(TPL_EINVAL, "gradients must be 0 or 1");
+  if (c.gradients && c.precision == TPL_BF16NEQ)
+    return fail(TPL_EINVAL, "same-step gradients are for the FP64 and FP32 forms");
   // the step kernel addresses a plane with 32-bit byte offsets: 8 N < 2^32
   if ((long long)c.nx * c.ny >= (1LL << 29)) return fail(TPL_EINVAL, "lattice too large");
 
@@ -466,6 +470,27 @@ int upload_tables(tpl_ctx *x) {
 // both produce the same base state).
 constexpr int kColumnQs = 8;
 
+// One step of the lattice in B read from half cur: with same-step gradients
+// the three field launches, then the step (ip: the in-place step kind).
+hipError_t enqueue_step(const tpl_ctx *x, const Buffers &B, const StepParams &p,
+                        const StepRef &ref, int cur, int ip) {
+  hipError_t e = hipSuccess;
+  if (B.esize == 4) {
+    if (x->c.gradients) e = launch_same_step_fields<float>(p, B.half<float>(cur), ref, x->qtab_d,
+                                                           x->stream, ip);
+    if (e == hipSuccess)
+      e = launch_step<float>(p, B.half<float>(cur), B.half<float>(1 - cur), ref, x->qtab_d,
+                             x->stream, B.xsize == 2, ip);
+  } else {
+    if (x->c.gradients) e = launch_same_step_fields<double>(p, B.half<double>(cur), ref,
+                                                            x->qtab_d, x->stream, ip);
+    if (e == hipSuccess)
+      e = launch_step<double>(p, B.half<double>(cur), B.half<double>(1 - cur), ref, x->qtab_d,
+                              x->stream, false, ip);
+  }
+  return e;
+}
+
 // Enqueue n steps of an nx x ny lattice held in B (halves *cur and 1-*cur)
 // with qs_req Q-slices (0: automatic).  B's element size selects the FP64 or
 // the FP32 step.
@@ -488,12 +513,7 @@ int run_steps(tpl_ctx *x, const Buffers &B, int nx, int ny, int *cur,
   for (long long i = 0; i < n; ++i) {
     if (timed) HIPCHK(hipEventRecord(e0, x->stream));
     const int ip = B.inplace ? (x->ip_odd ? 2 : 1) : 0;
-    if (B.esize == 4)
-      HIPCHK(launch_step<float>(p, B.half<float>(*cur), B.half<float>(1 - *cur), ref,
-                                x->qtab_d, x->stream, B.xsize == 2, ip));
-    else
-      HIPCHK(launch_step<double>(p, B.half<double>(*cur), B.half<double>(1 - *cur), ref,
-                                 x->qtab_d, x->stream, false, ip));
+    HIPCHK(enqueue_step(x, B, p, ref, *cur, ip));
     if (B.inplace) x->ip_odd ^= 1;
     if (timed) {
       HIPCHK(hipEventRecord(e1, x->stream));
@@ -588,13 +608,7 @@ int tune_groups_inplace(tpl_ctx *x, long long *done) {
     StepParams p = p0;
     if (c[0] * c[1] > 1 && !set_group(p, c[0], c[1], c[2])) continue;
     auto launch = [&]() {
-      const int ip = x->ip_odd ? 2 : 1;
-      const hipError_t e =
-          B.esize == 4
-              ? launch_step<float>(p, B.half<float>(x->cur), B.half<float>(1 - x->cur), ref,
-                                   x->qtab_d, x->stream, false, ip)
-              : launch_step<double>(p, B.half<double>(x->cur), B.half<double>(1 - x->cur), ref,
-                                    x->qtab_d, x->stream, false, ip);
+      const hipError_t e = enqueue_step(x, B, p, ref, x->cur, x->ip_odd ? 2 : 1);
       if (e == hipSuccess) {  // a real step
         x->ip_odd ^= 1;
         x->cur = 1 - x->cur;
@@ -855,6 +869,7 @@ const Key kKeys[] = {
     {"drift_relax", &Config::drift_relax, nullptr, nullptr},
     {"qe_model", nullptr, &Config::qe_model, nullptr},
     {"inplace", nullptr, &Config::inplace, nullptr},
+    {"gradients", nullptr, &Config::gradients, nullptr},
     {"precision", nullptr, &Config::precision, nullptr},
     {"pert_modes", nullptr, &Config::pert_modes, nullptr},
     {"pre_steps", nullptr, nullptr, &Config::pre_steps},
@@ -974,9 +989,12 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
        N * (pc * (es * 9 + xq * d.nqd) + 2.0 * (es * d.nqd + ms * d.nqd + 8.0 * NF))},
       // algorithmic HBM bytes of one step: populations read + written,
       // lagged psi written + read, lagged per-node fields written + read
-      // (BF16 form: remainders and FP32 fluxes read + written once)
+      // (BF16 form: remainders and FP32 fluxes read + written once); same-step
+      // gradients add a second read of the polymer populations, psi written
+      // and read, the solvent read and 17 FP64 field values per node
       {"bytes_per_step",
-       N * (2.0 * es * (9 + d.nqd) + 2.0 * (xq + ms) * d.nqd + 8.0 * 2.0 * NF)},
+       N * (2.0 * es * (9 + d.nqd) + 2.0 * (xq + ms) * d.nqd + 8.0 * 2.0 * NF) +
+           (x->c.gradients ? N * (xq * d.nqd + 2.0 * es * d.nqd + 9.0 * es + 136.0) : 0.0)},
       {"kernel_ms", x->kernel_ms}, {"kernel_launches", (double)x->kernel_launches},
       {"qsplit_used", (double)x->qs_used},
       {"group_x_used", (double)(x->wg_used & 255)},
@@ -1867,6 +1885,8 @@ int tpl_batch_set_param(tpl_batch *b, const char *key, double value) {
   if (!strcmp(key, "precision")) return fail(TPL_EINVAL, "precision is fixed at tpl_batch_create");
   if (!strcmp(key, "inplace"))
     return fail(TPL_EINVAL, "batched instances keep two population arrays");
+  if (!strcmp(key, "gradients"))
+    return fail(TPL_EINVAL, "the batched step takes lagged gradients");
   if (b->inited) return fail(TPL_ESTATE, "instance parameters are fixed after tpl_batch_init");
   for (tpl_ctx *x : b->inst) {
     const int rc = tpl_set_param(x, key, value);

@@ -232,3 +232,24 @@ def test_inplace_storage_knob():
         b.set_param("inplace", 1)
     assert "two population arrays" in str(e.value)
     b.close()
+
+
+def test_same_step_gradients_knob():
+    """Same-step gradients: a parameter before init; its three extra
+    launches add a second population read, psi written and read, the
+    solvent read and 17 FP64 values per node to the algorithmic bytes."""
+    t = P.Tpl(128, 64, 60.0, 1.0, 0.7, periods=2, nq=8)
+    N, nqd = 128 * 64, t.nqd
+    b0 = t.query("bytes_per_step")
+    t.set_param("gradients", 1)
+    assert t.query("bytes_per_step") == b0 + N * (200 * nqd + 16 * nqd + 72 + 136)
+    with pytest.raises(P.TplError):
+        t.set_param("gradients", 2)
+    with pytest.raises(P.TplError):
+        t.set_param("precision", P.TPL_BF16NEQ)
+    t.set_param("inplace", 1)  # both together are allowed
+    t.close()
+    b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8)])
+    with pytest.raises(P.TplError):
+        b.set_param("gradients", 1)
+    b.close()
