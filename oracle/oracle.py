@@ -40,7 +40,7 @@ class _Config(C.Structure):
                 ("force_scale", C.c_double), ("lambda_set", C.c_double),
                 ("ny_param", C.c_int), ("y_offset", C.c_int), ("x_offset", C.c_int),
                 ("nx_param", C.c_int), ("drift_cap", C.c_double), ("drift_relax", C.c_double),
-                ("qe_model", C.c_int), ("gradients", C.c_int)]
+                ("qe_model", C.c_int), ("gradients", C.c_int), ("spring_shift", C.c_int)]
 
 
 _DERIVED = ["kf", "l", "nu", "nuS", "lambda", "G", "tau1S", "tau2S", "tau1P", "tau2P",
@@ -91,6 +91,7 @@ def _L():
         lib.orc_solvent_qe2.argtypes = [C.c_double, dp, dp, dp]
         lib.orc_polymer_qe2.argtypes = [C.c_void_p, C.c_double, dp, dp, dp]
         lib.orc_collide_node.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, dp, dp]
+        lib.orc_spring_terms.argtypes = [C.c_void_p, C.c_int, C.c_int, dp]
         lib.orc_set_threads.restype = None
         lib.orc_set_threads.argtypes = [C.c_int]
         lib.orc_max_threads.restype = C.c_int
@@ -126,7 +127,7 @@ def splitmix64_next(state: int):
 DEFAULTS = dict(nq=16, periods=1, Re=20.0, Wi=0.5, beta=0.8, u0=0.05, phi=0.01,
                 spring=0, b=25.0, tau_drag=0.0, tau_ratio_p=1.0, force_scale=1.0,
                 lambda_set=0.0, ny_param=0, y_offset=0, x_offset=0, nx_param=0, drift_cap=0.1,
-                drift_relax=1.0, qe_model=1, gradients=0)
+                drift_relax=1.0, qe_model=1, gradients=0, spring_shift=0)
 
 DIAG_NAMES = ["step", "mass_S", "mass_P", "mom_x", "mom_y", "amplitude",
               "enstrophy", "qrms", "min_psi"]
@@ -220,6 +221,12 @@ class OracleSim:
     def observables(self) -> np.ndarray:
         out = np.zeros((10, self.ny, self.nx))
         _L().orc_observables(self._h, _ptr(out))
+        return out
+
+    def spring_terms(self, x: int, y: int) -> np.ndarray:
+        """Spring terms [nqd][2] of J^r_eq at node (x, y) from the recorded psi."""
+        out = np.zeros((self.nqd, 2))
+        _L().orc_spring_terms(self._h, int(x), int(y), _ptr(out))
         return out
 
     def set_source(self, F=None):

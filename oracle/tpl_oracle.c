@@ -244,6 +244,10 @@ static int derive(orc_sim *s, char *err) {
     if (err) snprintf(err, 256, "gradients must be 0 or 1");
     return -1;
   }
+  if (c->spring_shift != 0 && c->spring_shift != 1) {
+    if (err) snprintf(err, 256, "spring_shift must be 0 or 1");
+    return -1;
+  }
   if (c->tau_ratio_p > 1.0 || c->tau_ratio_p <= 0.0) {
     if (err) snprintf(err, 256, "tau_ratio_p must be in (0,1]");
     return -1;
@@ -608,19 +612,45 @@ static double body_force_x(const orc_sim *s, int y) {
   return s->p.F0 * sin(s->p.kf * (double)(y + s->c.y_offset));
 }
 
-/* Spring terms of J^r_eq at node (x, y) from the recorded psi: first-order
- * Taylor expansion of sum_nu (F_nu/zeta) psi(r - R_nu, Q) (Sec. III/V),
- * s = kappa Fhat(Q) [Q . grad psi(r, Q)]. */
+/* Spring terms of J^r_eq at node (x, y) from the recorded psi, the lattice
+ * form of sum_nu (F_nu/zeta) psi(r - R_nu, Q) (Sec. III/V) with the beads at
+ * R = -+Q/2 and F_1 = -F_2 = F: s = kappa Fhat(Q) [psi(r + Q/2) - psi(r - Q/2)],
+ * or its first-order Taylor expansion kappa Fhat(Q) [Q . grad psi(r, Q)]. */
+/* psi(X, Y, q) at a real position by bilinear interpolation between the four
+ * surrounding nodes, periodic in both directions.  The weights sum to one and
+ * do not depend on the node, so the lattice sum of the interpolated field
+ * equals that of psi (sum-preserving). */
+static double psi_at(const orc_sim *s, double X, double Y, int q) {
+  const double fx0 = floor(X), fy0 = floor(Y);
+  const double fx = X - fx0, fy = Y - fy0;
+  const int x0 = wrap((int)fx0, s->nx), x1 = wrap((int)fx0 + 1, s->nx);
+  const int y0 = wrap((int)fy0, s->ny), y1 = wrap((int)fy0 + 1, s->ny);
+  const int nqd = s->nqd;
+  return (1.0 - fx) * (1.0 - fy) * s->psi[nid(s, x0, y0) * nqd + q] +
+         fx * (1.0 - fy) * s->psi[nid(s, x1, y0) * nqd + q] +
+         (1.0 - fx) * fy * s->psi[nid(s, x0, y1) * nqd + q] +
+         fx * fy * s->psi[nid(s, x1, y1) * nqd + q];
+}
+
 static void spring_terms(const orc_sim *s, int x, int y, double *sq) {
   const int nqd = s->nqd;
   for (int q = 0; q < nqd; ++q) {
-    double gx = ddx(s, s->psi, nqd, q, x, y);
-    double gy = ddy(s, s->psi, nqd, q, x, y);
-    double qg = s->Q[2 * q] * gx + s->Q[2 * q + 1] * gy;
+    const double Qx = s->Q[2 * q], Qy = s->Q[2 * q + 1];
+    double qg;
+    if (s->c.spring_shift) {
+      /* the two beads at r -+ Q/2 (Sec. V): psi(r + Q/2) - psi(r - Q/2) */
+      qg = psi_at(s, x + 0.5 * Qx, y + 0.5 * Qy, q) - psi_at(s, x - 0.5 * Qx, y - 0.5 * Qy, q);
+    } else {
+      double gx = ddx(s, s->psi, nqd, q, x, y);
+      double gy = ddy(s, s->psi, nqd, q, x, y);
+      qg = Qx * gx + Qy * gy;
+    }
     sq[2 * q] = s->p.kappa * s->Fh[2 * q] * qg;
     sq[2 * q + 1] = s->p.kappa * s->Fh[2 * q + 1] * qg;
   }
 }
+
+void orc_spring_terms(const orc_sim *s, int x, int y, double *sq) { spring_terms(s, x, y, sq); }
 
 static void body_force(const orc_sim *s, int y, size_t n, double Fb[2]) {
   Fb[0] = body_force_x(s, y);

@@ -24,6 +24,9 @@
  *   step (polymer, Q)                  -> Hookean relaxation time lambda
  *   step (coupling, forcing, spring)   -> laminar Oldroyd-B closed form
  *   step (conservation)                -> mass and momentum invariants
+ *   non-local spring shift             -> lattice sums (momentum), the
+ *                                         Fourier symbol of interpolation,
+ *                                         Taylor limit at long wavelength
  *   same-step gradients                -> independence of the lagged fields;
  *                                         the laminar closed form and the
  *                                         invariants as above
@@ -67,6 +70,12 @@ typedef struct {
                         * spring term's psi gradient, which the paper leaves
                         * open: 0 = the previous step's observables (lagged);
                         * 1 = the current step's, from the pulled populations */
+  int spring_shift;    /* form of the spring term of J^r_eq (Sec. V):
+                        * 0 = first-order Taylor expansion,
+                        *     kappa Fhat(Q) (Q . grad psi(r, Q));
+                        * 1 = the non-local shift itself,
+                        *     kappa Fhat(Q) [psi(r + Q/2, Q) - psi(r - Q/2, Q)],
+                        *     psi at r +- Q/2 by periodic bilinear interpolation */
 } orc_config;
 
 /* Derived lattice parameters (step 0 of the scheme contract). */
@@ -137,6 +146,9 @@ void orc_diagnostics(const orc_sim *s, double *out);
 void orc_solvent_eq(double rho, double ux, double uy, double *out9);
 void orc_polymer_eq(const orc_sim *s, double psi, const double Jr[2],
                     const double JQ[2], double *out25);
+/* Spring terms sq[nqd][2] of J^r_eq at node (x, y) from the recorded psi
+ * (the form spring_shift selects). */
+void orc_spring_terms(const orc_sim *s, int x, int y, double *sq);
 /* One collision at one r-node from pulled populations gS[9], gP[nqd][25]
  * with lagged velocity gradient K[4] = (dUx/dx, dUx/dy, dUy/dx, dUy/dy),
  * spring terms sq[nqd][2] and body force Fb[2]; writes post-collision

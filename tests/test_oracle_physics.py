@@ -296,3 +296,61 @@ def test_same_step_gradients_use_this_steps_observables():
     other = with_lag(sim(0), stb["psi"], inputs.normal(6, stb["U"].shape, 1e-3))
     b.step(1); other.step(1)
     assert not np.array_equal(b.get_state()["XP"], other.get_state()["XP"])
+
+
+def _interp_symbol(k, a):
+    """Fourier symbol of periodic bilinear interpolation at offset a along one
+    axis: value at x + a of exp(i k x) sampled on the nodes, divided by
+    exp(i k x) (a = n + f: (1 - f) e^{i k n} + f e^{i k (n + 1)})."""
+    n = np.floor(a)
+    f = a - n
+    return (1 - f) * np.exp(1j * k * n) + f * np.exp(1j * k * (n + 1))
+
+
+@pytest.mark.parametrize("shift", [0, 1])
+def test_spring_term_fourier_symbol(shift):
+    """For psi(r, Q) = p_Q + A_Q cos(k . r + phi) the spring term is a
+    closed form of k: kappa Fhat(Q) Re{A_Q e^{i(k.r + phi)} sigma(k, Q)} with
+    sigma = i (Q_x sin k_x + Q_y sin k_y) for the Taylor form (central
+    differences) and sigma = S(Q/2) - S(-Q/2), S the product of the axes'
+    interpolation symbols, for the shifted form.  At long wavelength both
+    tend to i k . Q."""
+    nx, ny = 24, 20
+    o = oracle.OracleSim(nx, ny, nq=8, spring=1, spring_shift=shift, periods=1)
+    t, d, nqd = o.tables(), o.derived(), o.nqd
+    Q, Fh = t["Q"], t["Fhat"]
+    kx, ky, phi = 2 * np.pi * 3 / nx, 2 * np.pi * 2 / ny, 0.4
+    A = 1e-3 * (1 + np.arange(nqd) / nqd)
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    psi = t["peq"][:, None, None] + A[:, None, None] * np.cos(kx * X + ky * Y + phi)[None]
+    st = o.get_state()
+    o.set_state(XS=st["XS"], XP=st["XP"], psi=psi, U=st["U"])
+    for (x, y) in [(0, 0), (5, 7), (23, 19), (11, 3)]:
+        got = o.spring_terms(x, y)
+        if shift:
+            sig = (_interp_symbol(kx, Q[:, 0] / 2) * _interp_symbol(ky, Q[:, 1] / 2)
+                   - _interp_symbol(kx, -Q[:, 0] / 2) * _interp_symbol(ky, -Q[:, 1] / 2))
+        else:
+            sig = 1j * (Q[:, 0] * np.sin(kx) + Q[:, 1] * np.sin(ky))
+        diff = np.real(A * np.exp(1j * (kx * x + ky * y + phi)) * sig)
+        want = d["kappa"] * Fh * diff[:, None]
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max(), (x, y)
+    # long wavelength: shifted and Taylor forms agree to second order
+    k = 2 * np.pi / 4096
+    s1 = (_interp_symbol(k, Q[:, 0] / 2) - _interp_symbol(k, -Q[:, 0] / 2))
+    assert np.abs(s1 - 1j * k * Q[:, 0]).max() < 0.5 * (k * 8) ** 2 * k * 8
+
+
+@pytest.mark.parametrize("spring", [0, 1])
+def test_conservation_with_shifted_spring_term(spring):
+    sim = oracle.OracleSim(16, 16, nq=6, spring=spring, spring_shift=1)
+    sim.base_state(300)
+    sim.perturb(seed=3, amp=0.05, multimode=True)
+    d0 = sim.diagnostics()
+    pabs = _abs_momentum(sim)
+    sim.step(200)
+    d1 = sim.diagnostics()
+    assert abs(d1["mass_S"] / d0["mass_S"] - 1) < 1e-13
+    assert abs(d1["mass_P"] / d0["mass_P"] - 1) < 1e-13
+    for c in ("mom_x", "mom_y"):
+        assert abs(d1[c] - d0[c]) < 1e-12 * pabs
