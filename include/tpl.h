@@ -151,6 +151,13 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *                 formed from the pulled populations before the step (three
  *                 more launches, about 1.5x the bytes; FP64 and FP32 forms,
  *                 not for batches)
+ *   spring_shift 0  form of the spring term of the imposed polymer flux
+ *                 (Sec. V, the force times psi at the two beads): 0 = its
+ *                 first-order Taylor form kappa Fhat (Q . grad psi); 1 = the
+ *                 shift itself, kappa Fhat [psi(r + Q/2) - psi(r - Q/2)] with
+ *                 psi between nodes by periodic bilinear interpolation (one
+ *                 more launch sums it over Q); two-array FP64 and FP32 storage
+ *                 with lagged gradients, not for batches
  *   pert_modes 1  0 = single x-mode, 1 = multimode perturbation
  *   pre_steps -1  base-state column steps (-1 = 5 max(l^2/nu, lambda))
  *   qsplit 0      Q-slices per r-tile in the step kernel: 0 (automatic),
@@ -287,8 +294,8 @@ tpl_batch *tpl_batch_create(const tpl_instance *inst, int n, int precision);
  *   graph_steps 20 steps captured per HIP graph (< 2: plain launches)
  *   time_kernels 0 1 = time tpl_batch_step with HIP events (kernel_ms)
  * Any other key is a tpl_set_param key applied to every instance before
- * tpl_batch_init (TPL_ESTATE afterwards; precision, inplace and gradients
- * are rejected). */
+ * tpl_batch_init (TPL_ESTATE afterwards; precision, inplace, gradients and
+ * spring_shift are rejected). */
 int tpl_batch_set_param(tpl_batch *b, const char *key, double value);
 
 /* Keys: the launch keys above and instances, active (not flagged unstable),

@@ -47,7 +47,7 @@ struct StepParams {
   int wg;               // tile groups (qs == 1 only): tiles along x in bits 0-7,
                         // rows in bits 8-15, bit 16: barrier per Q-node; 0 = off
   int qe;               // quasi-equilibrium model: 1 component momenta, 2 stresses
-  int pad;
+  int shift;            // spring term: 0 Taylor form, 1 psi at r +- Q/2 (interpolated)
   long long N;  // nx * ny
   double aS, aP;         // 1 / (2 tJ + 1) per species
   double tJS, tJP;       // momentum relaxation time: tau2 (model 1), tau1 (model 2)
@@ -111,6 +111,12 @@ template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
                        StepRef ref, const QNode *qtab, hipStream_t s, bool neq = false,
                        int ip = 0);
+// Non-local spring term: S = kappa sum_Q Fhat [psi(r + Q/2) - psi(r - Q/2)]
+// of the read half's psi (bilinear interpolation, periodic) into its FLD
+// slots F_MXX (S_x) and F_MXY (S_y), where the step with p.shift reads it.
+template <typename T>
+hipError_t launch_spring_sum(const StepParams &p, StateT<T> a, StepRef ref, const QNode *qtab,
+                             hipStream_t s);
 // Same-step gradients: overwrite the read half's PSI, M and U with this
 // step's psi^n, M^n and U^n (three launches) before launch_step.  ip as there
 // (the pull of the step that follows); FP64 and FP32 forms.

@@ -197,6 +197,39 @@ __device__ __forceinline__ void neq_encode(const double d[25], uint16_t nb[25], 
 // are wave-uniform (scalar loads).
 // One 64-node tile of one lattice (all qs slices of the workgroup take part).
 // red: LDS of qs * 12 * 64 doubles.
+// Non-local spring term: psi(r + Q/2) - psi(r - Q/2) of one Q-node's plane P
+// (stored T, FP32 reference rpq(row)) at node (x, y), each side by bilinear
+// interpolation between its four surrounding nodes, periodic.  The Q-node's
+// offsets are wave-uniform; the wrap loops run at most NQ/4 + 1 times (a
+// narrow lattice such as the one-column base-state run wraps more than once).
+__device__ __forceinline__ int wrap_to(int v, int n) {
+  while (v < 0) v += n;
+  while (v >= n) v -= n;
+  return v;
+}
+template <typename T, typename RefRow>
+__device__ __forceinline__ double spring_shift_diff(const T *P, int x, int y, int nx, int ny,
+                                                   double qx, double qy, RefRow rpq) {
+  const double ax = 0.5 * qx, ay = 0.5 * qy;
+  const double flx = floor(ax), fly = floor(ay);
+  const double fx = ax - flx, fy = ay - fly;
+  const int ix = (int)flx, iy = (int)fly;
+  auto at = [&](int xx, int yy) {
+    return full(ldo(P, (uint32_t)sizeof(T) * (uint32_t)(yy * nx + xx)), rpq(yy));
+  };
+  // + side: floor(Q/2) and the next node; - side: floor(-Q/2) = -floor(Q/2) - 1
+  // (Q/2 is never an integer: Q-nodes sit at half-integers), weights swapped
+  const int xp0 = wrap_to(x + ix, nx), xp1 = wrap_to(x + ix + 1, nx);
+  const int yp0 = wrap_to(y + iy, ny), yp1 = wrap_to(y + iy + 1, ny);
+  const int xm0 = wrap_to(x - ix - 1, nx), xm1 = wrap_to(x - ix, nx);
+  const int ym0 = wrap_to(y - iy - 1, ny), ym1 = wrap_to(y - iy, ny);
+  const double vp = (1.0 - fx) * (1.0 - fy) * at(xp0, yp0) + fx * (1.0 - fy) * at(xp1, yp0) +
+                    (1.0 - fx) * fy * at(xp0, yp1) + fx * fy * at(xp1, yp1);
+  const double vm = fx * fy * at(xm0, ym0) + (1.0 - fx) * fy * at(xm1, ym0) +
+                    fx * (1.0 - fy) * at(xm0, ym1) + (1.0 - fx) * (1.0 - fy) * at(xm1, ym1);
+  return vp - vm;
+}
+
 // Mixture velocity: the velocity at which the momentum exchange of the two
 // species cancels (Sec. IV/V), from their g-momenta, the body force and the
 // Q-sum S of the spring term, weighted by 1 / (2 tJ + 1) per species.
@@ -226,7 +259,8 @@ __device__ __forceinline__ void mixture_velocity(const StepParams &p, double rho
 // solvent follows the same maps with the D2Q9 set.  Every wave of a
 // workgroup owns its own nodes (one Q-slice), and the per-node fields and
 // lagged psi stay double-buffered.
-template <typename T, bool ROWTILE, bool NEQ = false, bool QE2 = false, int IP = 0>
+template <typename T, bool ROWTILE, bool NEQ = false, bool QE2 = false, int IP = 0,
+          bool SHIFT = false>
 __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &a,
                                           const StateT<T> &b, const float *__restrict__ rpull,
                                           const float *__restrict__ rstore,
@@ -301,8 +335,10 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   auto dX = [&](int f) { return 0.5 * (ldo(fplane(a.FLD, f), fE) - ldo(fplane(a.FLD, f), fW)); };
   auto dY = [&](int f) { return 0.5 * (ldo(fplane(a.FLD, f), fN) - ldo(fplane(a.FLD, f), fS)); };
   const double Kxx = dX(F_UX), Kxy = dY(F_UX), Kyx = dX(F_UY), Kyy = dY(F_UY);
-  const double Sx = p.kappa * (dX(F_MXX) + dY(F_MXY));
-  const double Sy = p.kappa * (dX(F_MXY) + dY(F_MYY));
+  // Q-sum of the spring terms: the divergence of the lagged M (Taylor form),
+  // or summed from the shifted psi by a launch before the step
+  const double Sx = SHIFT ? ldo(fplane(a.FLD, F_MXX), fR) : p.kappa * (dX(F_MXX) + dY(F_MXY));
+  const double Sy = SHIFT ? ldo(fplane(a.FLD, F_MXY), fR) : p.kappa * (dX(F_MXY) + dY(F_MYY));
   double Fbx = p.F0 * sin(p.kf * (double)(y + p.y0)), Fby = 0.0;
   if (p.src != nullptr) {  // extra body force (a learned correction's source)
     Fbx += p.src[r];
@@ -455,12 +491,18 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
             if (PV[k][a] && PV[k][b2]) P2[a][b2] += PV[k][a] * PV[k][b2] * g[k];
       }
     }
-    // spring term: kappa Fhat (Q . grad psi^{n-1})
+    // spring term: kappa Fhat (Q . grad psi^{n-1}), or with the shift
+    // kappa Fhat [psi^{n-1}(r + Q/2) - psi^{n-1}(r - Q/2)]
     const T *P = plane(a.PSI, q);
-    const double pE = full(ldo(P, oE), rpq(y, q)), pW = full(ldo(P, oW), rpq(y, q));
-    const double pN = full(ldo(P, oN), rpq(yp, q)), pS = full(ldo(P, oS), rpq(ym, q));
-    const double gx = 0.5 * (pE - pW), gy = 0.5 * (pN - pS);
-    const double qg = qn.qx * gx + qn.qy * gy;
+    double qg;
+    if constexpr (SHIFT) {
+      qg = spring_shift_diff(P, x, y, nx, ny, qn.qx, qn.qy, [&](int row) { return rpq(row, q); });
+    } else {
+      const double pE = full(ldo(P, oE), rpq(y, q)), pW = full(ldo(P, oW), rpq(y, q));
+      const double pN = full(ldo(P, oN), rpq(yp, q)), pS = full(ldo(P, oS), rpq(ym, q));
+      const double gx = 0.5 * (pE - pW), gy = 0.5 * (pN - pS);
+      qg = qn.qx * gx + qn.qy * gy;
+    }
     const double sx = p.kappa * qn.fx * qg, sy = p.kappa * qn.fy * qg;
     // imposed fluxes and moment inversion
     const double Erx = psi * Ux + sx, Ery = psi * Uy + sy;
@@ -591,7 +633,8 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   if (p.qs > 1) __syncthreads();  // red is reused by the workgroup's next tile
 }
 
-template <typename T, int MAXT, bool ROWTILE, bool NEQ = false, bool QE2 = false, int IP = 0>
+template <typename T, int MAXT, bool ROWTILE, bool NEQ = false, bool QE2 = false, int IP = 0,
+          bool SHIFT = false>
 __global__ void __launch_bounds__(MAXT)
     k_step(StepParams p, StateT<T> a, StateT<T> b, const float *__restrict__ rpull,
            const float *__restrict__ rstore, const float *__restrict__ rpsi,
@@ -612,8 +655,8 @@ __global__ void __launch_bounds__(MAXT)
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     tile = ((grp / gpr) * gy + w / gx) * tpr + (grp % gpr) * gx + w % gx;
   }
-  step_tile<T, ROWTILE, NEQ, QE2, IP>(p, a, b, rpull, rstore, rpsi, rspull, rsstore, qtab,
-                                      tile, red);
+  step_tile<T, ROWTILE, NEQ, QE2, IP, SHIFT>(p, a, b, rpull, rstore, rpsi, rspull, rsstore,
+                                             qtab, tile, red);
 }
 
 
@@ -657,7 +700,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)
 #undef TPL_LD
     pp.wg = 0;
     pp.qe = 1;
-    pp.pad = 0;
+    pp.shift = 0;
     pp.pS = pp.pP = 0.0;
     const int rd = parity ^ d.cur0;
     const StateT<T> a{static_cast<T *>(d.XS[rd]), static_cast<T *>(d.XP[rd]),
@@ -710,6 +753,25 @@ hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
   if (p.qe != 1 && p.qe != 2) return hipErrorInvalidValue;
   const dim3 g(grid), blk(64 * p.qs * gsize);
 #define TPL_STEP_ARGS p, a, b, r.pull, r.store, r.psi, r.spull, r.sstore, qtab
+  if (p.shift != 0 && p.shift != 1) return hipErrorInvalidValue;
+  if (p.shift) {
+    // non-local spring term: two arrays, FP64 and FP32 storage
+    if (neq || ip != 0) return hipErrorInvalidValue;
+#define TPL_STEP_SH(MAXT, RT)                                                                 \
+  if (p.qe == 2)                                                                             \
+    hipLaunchKernelGGL((k_step<T, MAXT, RT, false, true, 0, true>), g, blk, lds, s,          \
+                       TPL_STEP_ARGS);                                                       \
+  else                                                                                       \
+    hipLaunchKernelGGL((k_step<T, MAXT, RT, false, false, 0, true>), g, blk, lds, s,         \
+                       TPL_STEP_ARGS);
+    if (p.qs * gsize <= 4) {
+      if (rowtile) { TPL_STEP_SH(256, true) } else { TPL_STEP_SH(256, false) }
+    } else {
+      if (rowtile) { TPL_STEP_SH(512, true) } else { TPL_STEP_SH(512, false) }
+    }
+#undef TPL_STEP_SH
+    return hipGetLastError();
+  }
   if (ip != 0) {
     // in place: one population array, whole tiles, one Q-slice
     if (ip != 1 && ip != 2) return hipErrorInvalidValue;
@@ -865,6 +927,41 @@ __global__ void k_pre_u(StepParams p, StateT<T> a, const float *__restrict__ rsp
   a.FLD[(size_t)F_UX * N + r] = Ux;
   a.FLD[(size_t)F_UY * N + r] = Uy;
 }
+
+template <typename T>
+__global__ void k_spring_sum(StepParams p, StateT<T> a, const float *__restrict__ rpsi,
+                             const QNode *__restrict__ qtab) {
+  constexpr bool F32 = std::is_same<T, float>::value;
+  const long long N = p.N;
+  const long long rr = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rr >= N) return;
+  const int r = (int)rr, nx = p.nx, ny = p.ny, nqd = p.nqd;
+  const int y = r / nx, x = r - y * nx;
+  double Sx = 0.0, Sy = 0.0;
+  for (int q = 0; q < nqd; ++q) {
+    const QNode CONSTANT_AS &qn = cst(qtab)[q];
+    const double d = spring_shift_diff(a.PSI + (size_t)q * N, x, y, nx, ny, qn.qx, qn.qy,
+                                       [&](int row) {
+                                         return F32 ? (double)rpsi[(size_t)row * nqd + q] : 0.0;
+                                       });
+    Sx += p.kappa * qn.fx * d;
+    Sy += p.kappa * qn.fy * d;
+  }
+  a.FLD[(size_t)F_MXX * N + r] = Sx;
+  a.FLD[(size_t)F_MXY * N + r] = Sy;
+}
+
+template <typename T>
+hipError_t launch_spring_sum(const StepParams &p, StateT<T> a, StepRef ref, const QNode *qtab,
+                             hipStream_t s) {
+  const unsigned nb = (unsigned)((p.N + 255) / 256);
+  hipLaunchKernelGGL(k_spring_sum<T>, dim3(nb), dim3(256), 0, s, p, a, ref.psi, qtab);
+  return hipGetLastError();
+}
+template hipError_t launch_spring_sum<double>(const StepParams &, StateT<double>, StepRef,
+                                              const QNode *, hipStream_t);
+template hipError_t launch_spring_sum<float>(const StepParams &, StateT<float>, StepRef,
+                                             const QNode *, hipStream_t);
 
 template <typename T>
 hipError_t launch_same_step_fields(const StepParams &p, StateT<T> a, StepRef ref,

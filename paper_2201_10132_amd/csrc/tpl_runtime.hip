@@ -46,6 +46,7 @@ struct Config {
   int qe_model = 1;
   int inplace = 0;  // one population array, streamed in place
   int gradients = 0;  // 0: lagged (previous step's) gradients; 1: same-step
+  int spring_shift = 0;  // spring term: 0 Taylor form, 1 psi at r +- Q/2
 };
 
 struct Derived {
@@ -78,6 +79,11 @@ int derive(const Config &c, Derived &d) {
   if (c.gradients != 0 && c.gradients != 1) return fail(TPL_EINVAL, "gradients must be 0 or 1");
   if (c.gradients && c.precision == TPL_BF16NEQ)
     return fail(TPL_EINVAL, "same-step gradients are for the FP64 and FP32 forms");
+  if (c.spring_shift != 0 && c.spring_shift != 1)
+    return fail(TPL_EINVAL, "spring_shift must be 0 or 1");
+  if (c.spring_shift && (c.precision == TPL_BF16NEQ || c.inplace || c.gradients))
+    return fail(TPL_EINVAL, "the shifted spring term is for two-array FP64 and FP32 storage "
+                            "with lagged gradients");
   // the step kernel addresses a plane with 32-bit byte offsets: 8 N < 2^32
   if ((long long)c.nx * c.ny >= (1LL << 29)) return fail(TPL_EINVAL, "lattice too large");
 
@@ -318,6 +324,7 @@ StepParams make_step_params(const tpl_ctx *x, int nx, int ny, int qs_req) {
   p.y0 = 0;
   const bool m2 = x->c.qe_model == 2;
   p.qe = m2 ? 2 : 1;
+  p.shift = x->c.spring_shift;
   p.tJS = m2 ? d.tau1S : d.tau2S;
   p.tJP = m2 ? d.tau1P : d.tau2P;
   p.aS = 1.0 / (2.0 * p.tJS + 1.0);
@@ -471,19 +478,24 @@ int upload_tables(tpl_ctx *x) {
 constexpr int kColumnQs = 8;
 
 // One step of the lattice in B read from half cur: with same-step gradients
-// the three field launches, then the step (ip: the in-place step kind).
+// the three field launches, with the shifted spring term its Q-sum, then the
+// step (ip: the in-place step kind).
 hipError_t enqueue_step(const tpl_ctx *x, const Buffers &B, const StepParams &p,
                         const StepRef &ref, int cur, int ip) {
   hipError_t e = hipSuccess;
   if (B.esize == 4) {
     if (x->c.gradients) e = launch_same_step_fields<float>(p, B.half<float>(cur), ref, x->qtab_d,
                                                            x->stream, ip);
+    if (e == hipSuccess && p.shift)
+      e = launch_spring_sum<float>(p, B.half<float>(cur), ref, x->qtab_d, x->stream);
     if (e == hipSuccess)
       e = launch_step<float>(p, B.half<float>(cur), B.half<float>(1 - cur), ref, x->qtab_d,
                              x->stream, B.xsize == 2, ip);
   } else {
     if (x->c.gradients) e = launch_same_step_fields<double>(p, B.half<double>(cur), ref,
                                                             x->qtab_d, x->stream, ip);
+    if (e == hipSuccess && p.shift)
+      e = launch_spring_sum<double>(p, B.half<double>(cur), ref, x->qtab_d, x->stream);
     if (e == hipSuccess)
       e = launch_step<double>(p, B.half<double>(cur), B.half<double>(1 - cur), ref, x->qtab_d,
                               x->stream, false, ip);
@@ -870,6 +882,7 @@ const Key kKeys[] = {
     {"qe_model", nullptr, &Config::qe_model, nullptr},
     {"inplace", nullptr, &Config::inplace, nullptr},
     {"gradients", nullptr, &Config::gradients, nullptr},
+    {"spring_shift", nullptr, &Config::spring_shift, nullptr},
     {"precision", nullptr, &Config::precision, nullptr},
     {"pert_modes", nullptr, &Config::pert_modes, nullptr},
     {"pre_steps", nullptr, nullptr, &Config::pre_steps},
@@ -991,10 +1004,13 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
       // lagged psi written + read, lagged per-node fields written + read
       // (BF16 form: remainders and FP32 fluxes read + written once); same-step
       // gradients add a second read of the polymer populations, psi written
-      // and read, the solvent read and 17 FP64 field values per node
+      // and read, the solvent read and 17 FP64 field values per node; the
+      // shifted spring term a second read of psi and its Q-sum written (the
+      // step reads the sum where it would read M)
       {"bytes_per_step",
        N * (2.0 * es * (9 + d.nqd) + 2.0 * (xq + ms) * d.nqd + 8.0 * 2.0 * NF) +
-           (x->c.gradients ? N * (xq * d.nqd + 2.0 * es * d.nqd + 9.0 * es + 136.0) : 0.0)},
+           (x->c.gradients ? N * (xq * d.nqd + 2.0 * es * d.nqd + 9.0 * es + 136.0) : 0.0) +
+           (x->c.spring_shift ? N * (es * d.nqd + 16.0) : 0.0)},
       {"kernel_ms", x->kernel_ms}, {"kernel_launches", (double)x->kernel_launches},
       {"qsplit_used", (double)x->qs_used},
       {"group_x_used", (double)(x->wg_used & 255)},
@@ -1887,6 +1903,8 @@ int tpl_batch_set_param(tpl_batch *b, const char *key, double value) {
     return fail(TPL_EINVAL, "batched instances keep two population arrays");
   if (!strcmp(key, "gradients"))
     return fail(TPL_EINVAL, "the batched step takes lagged gradients");
+  if (!strcmp(key, "spring_shift"))
+    return fail(TPL_EINVAL, "the batched step takes the Taylor spring term");
   if (b->inited) return fail(TPL_ESTATE, "instance parameters are fixed after tpl_batch_init");
   for (tpl_ctx *x : b->inst) {
     const int rc = tpl_set_param(x, key, value);

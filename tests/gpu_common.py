@@ -7,7 +7,7 @@ import paper_2201_10132_amd as P
 
 LIB_KEYS = ("nq", "spring", "b", "phi", "tau_drag", "tau_ratio_p", "force_scale",
             "drift_cap", "drift_relax", "qe_model", "pre_steps", "qsplit", "pert_modes",
-            "inplace", "gradients")
+            "inplace", "gradients", "spring_shift")
 
 
 def make_pair(nx, ny, Re, Wi, beta, periods, u0=0.05, **kw):

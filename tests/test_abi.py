@@ -253,3 +253,21 @@ def test_same_step_gradients_knob():
     with pytest.raises(P.TplError):
         b.set_param("gradients", 1)
     b.close()
+
+
+def test_spring_shift_knob():
+    t = P.Tpl(128, 64, 60.0, 1.0, 0.7, periods=2, nq=8)
+    N, nqd = 128 * 64, t.nqd
+    b0 = t.query("bytes_per_step")
+    t.set_param("spring_shift", 1)
+    assert t.query("bytes_per_step") == b0 + N * (8 * nqd + 16)
+    for k, v in (("inplace", 1), ("gradients", 1), ("precision", P.TPL_BF16NEQ),
+                 ("spring_shift", 2)):
+        with pytest.raises(P.TplError):
+            t.set_param(k, v)
+    t.set_param("precision", P.TPL_FP32)
+    t.close()
+    b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8)])
+    with pytest.raises(P.TplError):
+        b.set_param("spring_shift", 1)
+    b.close()
