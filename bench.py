@@ -176,6 +176,13 @@ def main():
         e["speed_vs_lagged"] = e.pop("speedup_vs_fp64")
         e["amplitude_rel_diff_vs_lagged"] = e.pop("amplitude_rel_err_vs_fp64")
         out["same_step_gradients"] = {"fp64_1024x1024_nq16": e}
+        # the spring term from psi at the beads (interpolated) instead of its
+        # Taylor form: one more launch sums it over Q
+        e = form_entry(measure(torch, w, 0, args.steps, args.warmup, args.pre_steps,
+                               spring_shift=1), main64)
+        e["speed_vs_taylor"] = e.pop("speedup_vs_fp64")
+        e["amplitude_rel_diff_vs_taylor"] = e.pop("amplitude_rel_err_vs_fp64")
+        out["spring_shift"] = {"fp64_1024x1024_nq16": e}
     if not args.no_forms:
         # the stress-tensor quasi-equilibrium model (Sec. V model (ii)): same
         # bytes, second moments added to the arithmetic; drag time tau1_S =
@@ -396,19 +403,21 @@ def measure_growth(torch, w, pre_steps, steps, every=100):
     squares over samples every `every` steps from steps/4 on), of the same
     seeded run stored in FP64, FP32 and BF16 non-equilibrium form; the
     storage forms' error is stated against the FP64 run.  The same FP64 run
-    with same-step gradients shows what the gradients' time level changes."""
+    with same-step gradients, and with the shifted spring term, shows what
+    those readings change."""
     import numpy as np
     import paper_2201_10132_amd as P
 
     n_fit = steps // 4
     out = {"workload": f"kolmogorov_{w['nx']}x{w['ny']}_nq{w['nq']}", "steps": steps,
            "sample_every": every, "fit_window": [n_fit, steps], "gamma": {}, "amplitude_end": {}}
-    runs = (("fp64", P.TPL_FP64, 0), ("fp32", P.TPL_FP32, 0), ("bf16neq", P.TPL_BF16NEQ, 0),
-            ("fp64_same_step", P.TPL_FP64, 1))
-    for name, prec, grad in runs:
+    runs = (("fp64", P.TPL_FP64, {}), ("fp32", P.TPL_FP32, {}), ("bf16neq", P.TPL_BF16NEQ, {}),
+            ("fp64_same_step", P.TPL_FP64, {"gradients": 1}),
+            ("fp64_spring_shift", P.TPL_FP64, {"spring_shift": 1}))
+    for name, prec, opt in runs:
         t = P.Tpl(w["nx"], w["ny"], w["Re"], w["Wi"], w["beta"], periods=w["periods"],
                   nq=w["nq"], spring=w["spring"], pre_steps=pre_steps, pert_modes=1,
-                  precision=prec, gradients=grad)
+                  precision=prec, **opt)
         t.init(seed=w["seed"], perturbation=w["perturbation"])
         ns, amps = [0], [t.amplitude()]
         t0 = time.perf_counter()
@@ -430,6 +439,7 @@ def measure_growth(torch, w, pre_steps, steps, every=100):
                                     for k in ("fp32", "bf16neq")}
     # not an error: another reading of the scheme
     out["same_step_gamma_rel_diff"] = abs(out["gamma"]["fp64_same_step"] / g64 - 1)
+    out["spring_shift_gamma_rel_diff"] = abs(out["gamma"]["fp64_spring_shift"] / g64 - 1)
     return out
 
 

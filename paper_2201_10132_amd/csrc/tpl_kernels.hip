@@ -928,17 +928,25 @@ __global__ void k_pre_u(StepParams p, StateT<T> a, const float *__restrict__ rsp
   a.FLD[(size_t)F_UY * N + r] = Uy;
 }
 
+// One 64-node tile per workgroup, kSpringSlices waves each summing every
+// kSpringSlices-th Q-node; the slices' partial sums are added in slice order
+// (the same order for every lattice, so results do not depend on its size).
+constexpr int kSpringSlices = 8;
 template <typename T>
-__global__ void k_spring_sum(StepParams p, StateT<T> a, const float *__restrict__ rpsi,
-                             const QNode *__restrict__ qtab) {
+__global__ void __launch_bounds__(64 * kSpringSlices)
+    k_spring_sum(StepParams p, StateT<T> a, const float *__restrict__ rpsi,
+                 const QNode *__restrict__ qtab) {
   constexpr bool F32 = std::is_same<T, float>::value;
+  __shared__ double part[kSpringSlices][2][64];
   const long long N = p.N;
-  const long long rr = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (rr >= N) return;
-  const int r = (int)rr, nx = p.nx, ny = p.ny, nqd = p.nqd;
+  const int lane = threadIdx.x & 63;
+  const int slice = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long long rr = (long long)blockIdx.x * 64 + lane;
+  const int r = (int)(rr < N ? rr : N - 1);
+  const int nx = p.nx, ny = p.ny, nqd = p.nqd;
   const int y = r / nx, x = r - y * nx;
   double Sx = 0.0, Sy = 0.0;
-  for (int q = 0; q < nqd; ++q) {
+  for (int q = slice; q < nqd; q += kSpringSlices) {
     const QNode CONSTANT_AS &qn = cst(qtab)[q];
     const double d = spring_shift_diff(a.PSI + (size_t)q * N, x, y, nx, ny, qn.qx, qn.qy,
                                        [&](int row) {
@@ -947,15 +955,25 @@ __global__ void k_spring_sum(StepParams p, StateT<T> a, const float *__restrict_
     Sx += p.kappa * qn.fx * d;
     Sy += p.kappa * qn.fy * d;
   }
-  a.FLD[(size_t)F_MXX * N + r] = Sx;
-  a.FLD[(size_t)F_MXY * N + r] = Sy;
+  part[slice][0][lane] = Sx;
+  part[slice][1][lane] = Sy;
+  __syncthreads();
+  if (slice == 0 && rr < N) {
+    for (int s2 = 1; s2 < kSpringSlices; ++s2) {
+      Sx += part[s2][0][lane];
+      Sy += part[s2][1][lane];
+    }
+    a.FLD[(size_t)F_MXX * N + r] = Sx;
+    a.FLD[(size_t)F_MXY * N + r] = Sy;
+  }
 }
 
 template <typename T>
 hipError_t launch_spring_sum(const StepParams &p, StateT<T> a, StepRef ref, const QNode *qtab,
                              hipStream_t s) {
-  const unsigned nb = (unsigned)((p.N + 255) / 256);
-  hipLaunchKernelGGL(k_spring_sum<T>, dim3(nb), dim3(256), 0, s, p, a, ref.psi, qtab);
+  const unsigned nb = (unsigned)((p.N + 63) / 64);
+  hipLaunchKernelGGL(k_spring_sum<T>, dim3(nb), dim3(64 * kSpringSlices), 0, s, p, a, ref.psi,
+                     qtab);
   return hipGetLastError();
 }
 template hipError_t launch_spring_sum<double>(const StepParams &, StateT<double>, StepRef,

@@ -99,3 +99,16 @@ def test_shift_differs_from_taylor_form_slightly():
     (ma, aa), (mb, ab) = run(0), run(1)
     assert not np.array_equal(ma, mb)
     assert abs(ab / aa - 1) < 2e-2
+
+
+def test_kolmogorov72_driver_with_shift():
+    """The paper's cell driven as separate contexts with the shifted spring
+    term (a short run at a small Q-grid)."""
+    from paper_2201_10132_amd import kolmogorov72 as K
+
+    res = K.run(t_end=1.0, every=0.5, nq=8, progress=False, spring_shift=1)
+    assert len(res["t"]) == 3 and res["unstable"] == [False, False, False]
+    for i in range(3):
+        assert np.all(np.isfinite(res["enstrophy"][i])) and res["enstrophy"][i][-1] > 0
+    rows = K.summary(res)
+    assert [r["Wi"] for r in rows] == list(K.WIS)
