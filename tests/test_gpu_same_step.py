@@ -95,3 +95,40 @@ def test_same_step_differs_from_lagged_only_slightly():
     (ma, aa), (mb, ab) = run(0), run(1)
     assert not np.array_equal(ma, mb)
     assert abs(ab / aa - 1) < 1e-2
+
+
+def test_same_step_fullsize_sampled_node_parity():
+    """The benchmark's 1024^2 NQ 16 workload with same-step gradients, in the
+    launch configuration the benchmark uses: one step's update of sampled
+    nodes against the oracle on the 7 x 7 window around each (this step's psi
+    and U at the neighbours reach three nodes out), and conservation."""
+    import oracle
+    from tests.gpu_common import FLOOR
+
+    NX = NY = 1024
+    prm = dict(Re=60.0, Wi=1.0, beta=0.7, periods=4)
+    print("same-step fullsize: init 1024x1024 nq=16", flush=True)
+    t = P.Tpl(NX, NY, prm["Re"], prm["Wi"], prm["beta"], periods=prm["periods"], nq=16,
+              pre_steps=200, pert_modes=1, gradients=1)
+    t.init(seed=0, perturbation=1e-4)
+    t.step(2)
+    d0 = t.diagnostics()
+    samples = [(0, 0), (1023, 1023), (511, 300), (64, 511)]
+    wins = {s: t.get_window(s[0] - 3, s[1] - 3, 7, 7) for s in samples}
+    t.step(1)
+    d1 = t.diagnostics()
+    for (x, y), w in wins.items():
+        print(f"same-step fullsize: node ({x},{y})", flush=True)
+        o = oracle.OracleSim(7, 7, nq=16, ny_param=NY, y_offset=y - 3, gradients=1, **prm)
+        o.set_state(XS=w["XS"], XP=w["XP"], psi=w["psi"], U=w["U"])
+        o.step(1)
+        want = o.get_state()
+        got = t.get_window(x, y, 1, 1)
+        for k in ("XS", "XP", "psi", "U"):
+            assert max_rel(got[k][..., 0, 0], want[k][..., 3, 3], FLOOR[k]) < 1e-14, (k, x, y)
+    assert abs(d1["mass_S"] / d0["mass_S"] - 1) < 1e-13
+    assert abs(d1["mass_P"] / d0["mass_P"] - 1) < 1e-13
+    scale = d0["mass_S"] * 0.05
+    assert abs(d1["mom_x"] - d0["mom_x"]) < 1e-13 * scale
+    assert abs(d1["mom_y"] - d0["mom_y"]) < 1e-13 * scale
+    t.close()

@@ -112,3 +112,40 @@ def test_kolmogorov72_driver_with_shift():
         assert np.all(np.isfinite(res["enstrophy"][i])) and res["enstrophy"][i][-1] > 0
     rows = K.summary(res)
     assert [r["Wi"] for r in rows] == list(K.WIS)
+
+
+def test_shift_fullsize_sampled_node_parity():
+    """The benchmark's 1024^2 NQ 16 workload with the shifted spring term, in
+    the benchmark's launch configuration: one step's update of sampled nodes
+    against the oracle on the 11 x 11 window around each (the beads of the
+    largest Q-nodes sit up to five nodes away), and conservation."""
+    import oracle
+    from tests.gpu_common import FLOOR
+
+    NX = NY = 1024
+    prm = dict(Re=60.0, Wi=1.0, beta=0.7, periods=4)
+    print("shift fullsize: init 1024x1024 nq=16", flush=True)
+    t = P.Tpl(NX, NY, prm["Re"], prm["Wi"], prm["beta"], periods=prm["periods"], nq=16,
+              pre_steps=200, pert_modes=1, spring_shift=1)
+    t.init(seed=0, perturbation=1e-4)
+    t.step(2)
+    d0 = t.diagnostics()
+    samples = [(0, 0), (1023, 1023), (511, 300), (64, 511)]
+    wins = {s: t.get_window(s[0] - 5, s[1] - 5, 11, 11) for s in samples}
+    t.step(1)
+    d1 = t.diagnostics()
+    for (x, y), w in wins.items():
+        print(f"shift fullsize: node ({x},{y})", flush=True)
+        o = oracle.OracleSim(11, 11, nq=16, ny_param=NY, y_offset=y - 5, spring_shift=1, **prm)
+        o.set_state(XS=w["XS"], XP=w["XP"], psi=w["psi"], U=w["U"])
+        o.step(1)
+        want = o.get_state()
+        got = t.get_window(x, y, 1, 1)
+        for k in ("XS", "XP", "psi", "U"):
+            assert max_rel(got[k][..., 0, 0], want[k][..., 5, 5], FLOOR[k]) < 1e-14, (k, x, y)
+    assert abs(d1["mass_S"] / d0["mass_S"] - 1) < 1e-13
+    assert abs(d1["mass_P"] / d0["mass_P"] - 1) < 1e-13
+    scale = d0["mass_S"] * 0.05
+    assert abs(d1["mom_x"] - d0["mom_x"]) < 1e-13 * scale
+    assert abs(d1["mom_y"] - d0["mom_y"]) < 1e-13 * scale
+    t.close()
