@@ -212,6 +212,13 @@ def main():
             bt = out["batched"]
             if tb is not None:
                 bt["roofline"]["traffic"] = round(tb * bt["bytes_active_fraction"])
+        if args.batch_instances == BATCH["instances"] and not args.no_inplace:
+            out["batched_inplace"] = {
+                f"fp32_nq{nq}": measure_batch_inplace(torch, nq, max(5, args.steps // 2),
+                                                      args.warmup, args.pre_steps)
+                for nq in (BATCH["nq"], 10)}
+            e = out["batched_inplace"][f"fp32_nq{BATCH['nq']}"]
+            e["speed_vs_two_array"] = round(e["mlups"] / out["batched"]["mlups"], 3)
         if "precision_forms" in out:  # (ii) plain FP64 lattice at the sweep's NQ
             ref = out["precision_forms"][f"fp64_1024x1024_nq{BATCH['nq']}"]["mlups"]
             out["batched"]["speedup_vs_fp64_plain_matched_nq"] = round(
@@ -326,6 +333,47 @@ def measure_batch(torch, n, steps, warmup, pre_steps, obo_steps) -> dict:
     print(f"# batch {n} instances: init {init_s:.1f} s, {kernel_ms:.3f} ms/step, "
           f"qsplit={res['qsplit']} group={res['group']} grid={res['grid']}, one-by-one "
           f"{res['one_by_one_mlups']} MLUPS", file=sys.stderr, flush=True)
+    b.close()
+    return res
+
+
+def measure_batch_inplace(torch, nq, steps, warmup, pre_steps) -> dict:
+    """The batched sweep with every instance streamed in place (one
+    population array each): at the sweep's NQ beside the two-array batch,
+    and at NQ 10, where two arrays (404 GB) would not fit one GPU."""
+    import paper_2201_10132_amd as P
+    from tests import inputs
+
+    insts = inputs.c4_instances(BATCH["instances"])
+    stream = torch.cuda.Stream()
+    b = P.Batch(insts, precision=BATCH["precision"], nq=nq, pre_steps=pre_steps,
+                time_kernels=1, inplace=1)
+    b.set_stream(stream.cuda_stream)
+    t0 = time.perf_counter()
+    b.init()
+    init_s = time.perf_counter() - t0
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    wall = time.perf_counter() - t0
+    kernel_ms = b.query("kernel_ms")
+    nodes = b.query("nodes")
+    state = b.query("bytes_state")
+    pop = sum(b.instance(i).query("bytes_XS") + b.instance(i).query("bytes_XP")
+              for i in range(len(insts)))
+    res = {"workload": f"kolmogorov_batch_{len(insts)}_seeded_fp32_nq{nq}_inplace",
+           "nq": nq, "nqd": int(b.instance(0).nqd), "steps": steps,
+           "mlups": round(nodes * steps / wall / 1e6, 3), "ms_per_step": round(wall / steps * 1e3, 4),
+           "kernel_ms": round(kernel_ms, 4),
+           "roofline": roofline(dict(bytes_step=b.query("bytes_per_step"), kernel_ms=kernel_ms),
+                                None),
+           "bytes_state_gb": round(state / 1e9, 1),
+           "two_array_bytes_state_gb": round((state + pop) / 1e9, 1),
+           "group": int(b.query("group_used")), "grid": int(b.query("grid_used")),
+           "init_s": round(init_s, 2), "unstable": int(b.query("unstable"))}
+    print(f"# batch in place nq={nq}: init {init_s:.1f} s, {kernel_ms:.3f} ms/step, "
+          f"state {res['bytes_state_gb']} GB", file=sys.stderr, flush=True)
     b.close()
     return res
 

@@ -136,7 +136,8 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *                 own locations; results are bitwise those of the
  *                 two-array step.  Halves the population memory.  FP64 and
  *                 FP32 only, nx a multiple of 64, one Q-slice (qsplit is
- *                 ignored), not for batches.  After an odd number of steps
+ *                 ignored); a batch sets it for all its instances
+ *                 (tpl_batch_set_param).  After an odd number of steps
  *                 the populations are held in streamed order: the calls
  *                 that read or write populations (tpl_get_state with XS or
  *                 XP, tpl_set_state, tpl_get_window, tpl_get_populations,
@@ -294,8 +295,13 @@ tpl_batch *tpl_batch_create(const tpl_instance *inst, int n, int precision);
  *   graph_steps 20 steps captured per HIP graph (< 2: plain launches)
  *   time_kernels 0 1 = time tpl_batch_step with HIP events (kernel_ms)
  * Any other key is a tpl_set_param key applied to every instance before
- * tpl_batch_init (TPL_ESTATE afterwards; precision, inplace, gradients and
- * spring_shift are rejected). */
+ * tpl_batch_init (TPL_ESTATE afterwards; precision, gradients and
+ * spring_shift are rejected).  inplace 1 streams every instance in place
+ * (each nx a multiple of 64; set here, not per instance): one Q-slice,
+ * groups of `group` tiles (4 unless set), the shape not timed (an in-place
+ * launch advances the state); graphs are captured per step-count parity;
+ * an instance stepped on its own blocks tpl_batch_step (TPL_ESTATE) until
+ * it is back at the batch's step parity. */
 int tpl_batch_set_param(tpl_batch *b, const char *key, double value);
 
 /* Keys: the launch keys above and instances, active (not flagged unstable),

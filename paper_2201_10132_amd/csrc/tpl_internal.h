@@ -140,9 +140,12 @@ hipError_t launch_step_ref(int nqd, int ny, const QNode *qtab, RefView ref,
 hipError_t launch_tile_dev(int planes, int nx, int ny, const double *col,
                            const float *ref, float *dst, hipStream_t s);
 // group > 1 (qs == 1 only): consecutive items per workgroup, one wave each.
+// ip = 1, 2: the in-place step kinds (every instance in place; qs == 1,
+// whole tiles), 0: two arrays.
 template <typename T>
 hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs, int grid,
-                             bool rowtile, int parity, hipStream_t s, int group = 1);
+                             bool rowtile, int parity, hipStream_t s, int group = 1,
+                             int ip = 0);
 hipError_t launch_rest(int nqd, long long N, double rhoS0, double rhoP0,
                        const double *peq, StateView a, hipStream_t s);
 template <typename T>

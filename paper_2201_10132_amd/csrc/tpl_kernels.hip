@@ -418,9 +418,17 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
     const QNode CONSTANT_AS &qn = cst(qtab)[q];  // scalar loads
     double g[25];
     if constexpr (IP == 2) {
+      // plane order, each base one plane stride past the last; the stride is
+      // kept opaque so that the 25 bases are not hoisted out of the Q-loop
+      // (held across it they spill scalar registers, and the spills
+      // serialise the loads)
+      uint64_t stride = (uint64_t)nqd * (uint64_t)N * SZ;
+      asm volatile("" : "+s"(stride));
+      const char *pb = reinterpret_cast<const char *>(uni(a.XP + (size_t)q * N));
 #pragma unroll
-      for (int k = 0; k < 25; ++k)
-        g[k] = full(ldo(plane(a.XP, (long long)krev(k) * nqd + q), oR), rq(rpull, y, q, k));
+      for (int j = 0; j < 25; ++j)
+        g[krev(j)] = full(ldo(reinterpret_cast<const T *>(pb + (size_t)j * stride), oR),
+                          rq(rpull, y, q, krev(j)));
     } else if constexpr (!NEQ) {
 #pragma unroll
       for (int k = 0; k < 25; ++k)
@@ -566,9 +574,15 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
     }
     if (active) {
       if constexpr (IP == 1) {
+        // the source planes are read again here rather than held across the
+        // collision (25 bases in scalar registers spill and serialise the
+        // loads); the empty asm keeps the compiler from reusing the earlier
+        // reads
+        const QNode GLOBAL_AS &qs2 = *(const QNode GLOBAL_AS *)(qtab + q);
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int k = 0; k < 25; ++k)
-          sto(wplane(b.XP, qn.plane[krev(k)]), osrc[pdir(krev(k))],
+          sto(wplane(b.XP, qs2.plane[krev(k)]), osrc[pdir(krev(k))],
               stored<T>(g[k], rq(rstore, y, q, k)));
         sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
       } else if constexpr (!NEQ) {
@@ -667,8 +681,8 @@ __global__ void __launch_bounds__(MAXT)
 // With group > 1 (one Q-slice) a workgroup takes `group` consecutive items,
 // one wave each, so that neighbouring tiles' overlapping stencil reads meet
 // in the caches; units of `group` items are what the grid and the XCD
-// mapping count.
-template <typename T, int MAXT, bool ROWTILE>
+// mapping count.  IP != 0: every instance streams in place (step_tile).
+template <typename T, int MAXT, bool ROWTILE, int IP = 0>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)))
     k_step_batch(const InstDev *__restrict__ inst, int ninst, int nitems, int items_per_xcd,
                  int parity, int group) {
@@ -707,19 +721,33 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)
                       static_cast<T *>(d.PSI[rd]), d.FLD[rd]};
     const StateT<T> b{static_cast<T *>(d.XS[rd ^ 1]), static_cast<T *>(d.XP[rd ^ 1]),
                       static_cast<T *>(d.PSI[rd ^ 1]), d.FLD[rd ^ 1]};
-    step_tile<T, ROWTILE>(pp, a, b, d.rpull, d.rstore, d.rpsi, d.rspull, d.rsstore, d.qtab,
-                          item - d.item0, red);
+    step_tile<T, ROWTILE, false, false, IP>(pp, a, b, d.rpull, d.rstore, d.rpsi, d.rspull,
+                                            d.rsstore, d.qtab, item - d.item0, red);
   }
 }
 
 template <typename T>
 hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs, int grid,
-                             bool rowtile, int parity, hipStream_t s, int group) {
+                             bool rowtile, int parity, hipStream_t s, int group, int ip) {
   if (group < 1 || (group > 1 && qs != 1) || qs * group > 8) return hipErrorInvalidValue;
   const size_t lds = qs > 1 ? (size_t)qs * 12 * 64 * sizeof(double) : 0;
   const int nunits = (nitems + group - 1) / group;
   const int per_xcd = (grid % 8 == 0 && nunits >= 64) ? (nunits + 7) / 8 : 0;
   const dim3 g(grid), blk(64 * qs * group);
+  if (ip != 0) {
+    // in place: whole tiles (nx a multiple of 64 for every instance), one Q-slice
+    if ((ip != 1 && ip != 2) || qs != 1 || !rowtile) return hipErrorInvalidValue;
+#define TPL_BATCH_IP(MAXT, IP)                                                          \
+  hipLaunchKernelGGL((k_step_batch<T, MAXT, true, IP>), g, blk, lds, s, inst, ninst, nitems, \
+                     per_xcd, parity, group)
+    if (group <= 4) {
+      if (ip == 1) TPL_BATCH_IP(256, 1); else TPL_BATCH_IP(256, 2);
+    } else {
+      if (ip == 1) TPL_BATCH_IP(512, 1); else TPL_BATCH_IP(512, 2);
+    }
+#undef TPL_BATCH_IP
+    return hipGetLastError();
+  }
   if (qs * group <= 4) {
     if (rowtile)
       hipLaunchKernelGGL((k_step_batch<T, 256, true>), g, blk, lds, s, inst, ninst, nitems,
@@ -738,9 +766,9 @@ hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs,
   return hipGetLastError();
 }
 template hipError_t launch_step_batch<double>(const InstDev *, int, int, int, int, bool, int,
-                                              hipStream_t, int);
+                                              hipStream_t, int, int);
 template hipError_t launch_step_batch<float>(const InstDev *, int, int, int, int, bool, int,
-                                             hipStream_t, int);
+                                             hipStream_t, int, int);
 
 template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,

@@ -1513,6 +1513,9 @@ struct tpl_batch {
   // captured graph: graph_steps launches with parities 0, 1, 0, 1, ...
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
+  // in-place streaming of every instance: the step kind alternates with the
+  // batch's step count (ip_odd), which the captured graph starts from (graph_ip)
+  int inplace = 0, ip_odd = 0, graph_ip = 0;
   double *scratch = nullptr;
   int scratch_n = 0;
   double kernel_ms = 0.0, tune_ms = 0.0;
@@ -1574,19 +1577,23 @@ int upload_table(tpl_batch *b, const std::vector<InstDev> &tab) {
   return TPL_OK;
 }
 
+// inplace: the instances' own lattices, streamed in place when the batch is
+// (the base-state columns always keep two arrays).
 hipError_t batch_launch(const tpl_batch *b, int esize, int ninst, int nitems, int qs, int grid,
-                        bool rowtile, int parity, int group) {
+                        bool rowtile, int parity, int group, bool inplace = true) {
+  const int ip = (inplace && b->inplace) ? (((b->ip_odd + parity) & 1) ? 2 : 1) : 0;
   return esize == 4 ? launch_step_batch<float>(b->tab_d, ninst, nitems, qs, grid, rowtile, parity,
-                                               b->stream, group)
+                                               b->stream, group, ip)
                     : launch_step_batch<double>(b->tab_d, ninst, nitems, qs, grid, rowtile,
-                                                parity, b->stream, group);
+                                                parity, b->stream, group, ip);
 }
 
 // Enqueue n launches of the uploaded table with parities p0, p0^1, ...
 int batch_run(tpl_batch *b, int esize, int ninst, int nitems, int qs, int grid, bool rowtile,
-              int p0, long long n, int group = 1) {
+              int p0, long long n, int group = 1, bool inplace = true) {
   for (long long i = 0; i < n; ++i)
-    HIPCHK(batch_launch(b, esize, ninst, nitems, qs, grid, rowtile, (int)((p0 + i) & 1), group));
+    HIPCHK(batch_launch(b, esize, ninst, nitems, qs, grid, rowtile, (int)((p0 + i) & 1), group,
+                        inplace));
   return TPL_OK;
 }
 
@@ -1633,7 +1640,7 @@ int batch_columns(tpl_batch *b) {
     }
     rc = upload_table(b, tab);
     if (rc) break;
-    rc = batch_run(b, 8, (int)tab.size(), items, qs, items, false, 0, k);
+    rc = batch_run(b, 8, (int)tab.size(), items, qs, items, false, 0, k, 1, false);
     if (rc) break;
     for (int i = 0; i < n; ++i)
       if (rem[i] > 0) {
@@ -1711,6 +1718,17 @@ int choose_shape(tpl_batch *b) {
     return fail(TPL_EINVAL, "group must be 0 (tuned), 1, 2, 4 or 8");
   if (b->group > 1 && b->qsplit > 1)
     return fail(TPL_EINVAL, "item groups need one Q-slice (qsplit 0 or 1)");
+  if (b->inplace) {
+    // in place a launch advances the state, so shapes cannot be timed by
+    // repeating it: one Q-slice, groups of `group` tiles (4 unless set)
+    if (b->qsplit > 1) return fail(TPL_EINVAL, "in-place streaming needs one Q-slice (qsplit 0 or 1)");
+    const int grp = b->group > 0 ? b->group : 4;
+    b->qs_used = 1;
+    b->group_used = grp;
+    const int rc = build_main_table(b, 1);
+    b->grid_used = b->grid > 0 ? b->grid : batch_units(b, grp);
+    return rc;
+  }
   int rc0 = build_main_table(b, qs_list[0]);  // sets nitems
   if (rc0) return rc0;
   if (!b->autotune) {
@@ -1799,6 +1817,7 @@ int capture_graph(tpl_batch *b) {
   }
   if (e != hipSuccess) return fail(TPL_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
   b->graph = g;
+  b->graph_ip = b->ip_odd;
   HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
   return TPL_OK;
 }
@@ -1899,8 +1918,20 @@ int tpl_batch_set_param(tpl_batch *b, const char *key, double value) {
       return TPL_OK;
     }
   if (!strcmp(key, "precision")) return fail(TPL_EINVAL, "precision is fixed at tpl_batch_create");
-  if (!strcmp(key, "inplace"))
-    return fail(TPL_EINVAL, "batched instances keep two population arrays");
+  if (!strcmp(key, "inplace")) {
+    if (b->inited) return fail(TPL_ESTATE, "inplace is fixed after tpl_batch_init");
+    if (value != 0 && value != 1) return fail(TPL_EINVAL, "inplace must be 0 or 1");
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+      const int rc = tpl_set_param(b->inst[i], key, value);
+      if (rc) {  // leave every instance as it was
+        const std::string msg = g_err;
+        for (size_t j = 0; j < i; ++j) (void)tpl_set_param(b->inst[j], key, b->inplace);
+        return fail(rc, msg);
+      }
+    }
+    b->inplace = (int)value;
+    return TPL_OK;
+  }
   if (!strcmp(key, "gradients"))
     return fail(TPL_EINVAL, "the batched step takes lagged gradients");
   if (!strcmp(key, "spring_shift"))
@@ -1964,9 +1995,14 @@ int tpl_batch_set_stream(tpl_batch *b, void *hip_stream) {
 
 int tpl_batch_init(tpl_batch *b) {
   if (!b) return fail(TPL_EINVAL, "null batch");
-  for (tpl_ctx *x : b->inst)
+  for (tpl_ctx *x : b->inst) {
     if (x->c.qe_model != 1)
       return fail(TPL_EINVAL, "the batched step runs the component-momentum model (qe_model 1)");
+    if (x->c.gradients || x->c.spring_shift)
+      return fail(TPL_EINVAL, "the batched step takes lagged gradients and the Taylor spring term");
+    if (x->c.inplace != b->inplace)
+      return fail(TPL_EINVAL, "in-place streaming is set for the whole batch (tpl_batch_set_param)");
+  }
   b->inited = false;
   drop_graph(b);
   if (!b->stream) {  // the batch's own stream, made on first use
@@ -1993,6 +2029,7 @@ int tpl_batch_init(tpl_batch *b) {
   b->unstable.assign(b->inst.size(), 0);
   b->rowtile = true;
   for (tpl_ctx *x : b->inst) b->rowtile = b->rowtile && (x->c.nx % 64 == 0);
+  b->ip_odd = 0;
   b->step = 0;
   b->kernel_ms = 0.0;
   b->kernel_steps = 0;
@@ -2008,6 +2045,9 @@ int tpl_batch_step(tpl_batch *b, int64_t n) {
   // instances may have been stepped on their own: refresh the halves read
   for (size_t j = 0, i = 0; i < b->inst.size(); ++i) {
     if (b->unstable[i]) continue;
+    if (b->inplace && b->inst[i]->ip_odd != b->ip_odd)
+      return fail(TPL_ESTATE, "in place, every instance must be at the batch's step parity "
+                              "(instance " + std::to_string(i) + " was stepped on its own)");
     if (b->tab[j].cur0 != b->inst[i]->cur) {
       b->tab[j].cur0 = b->inst[i]->cur;
       b->tab_dirty = true;
@@ -2021,6 +2061,7 @@ int tpl_batch_step(tpl_batch *b, int64_t n) {
     b->tab_dirty = false;
   }
   const int esize = batch_esize(b), G = b->graph_steps & ~1;
+  if (b->gexec && b->inplace && b->graph_ip != b->ip_odd) drop_graph(b);  // other step kind first
   if (G >= 2 && n >= G && !b->gexec) {
     rc = capture_graph(b);
     if (rc) return rc;
@@ -2050,8 +2091,10 @@ int tpl_batch_step(tpl_batch *b, int64_t n) {
   for (size_t i = 0; i < b->inst.size(); ++i) {
     if (b->unstable[i]) continue;
     b->inst[i]->cur ^= (int)(n & 1);
+    if (b->inplace) b->inst[i]->ip_odd ^= (int)(n & 1);
     b->inst[i]->step += n;
   }
+  if (b->inplace) b->ip_odd ^= (int)(n & 1);
   b->step += n;
   int newly = 0;
   rc = batch_check(b, &newly);

@@ -228,9 +228,17 @@ def test_inplace_storage_knob():
         v.set_param("inplace", 1)
     v.close()
     b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8)])
+    b.set_param("inplace", 1)  # forwarded to every instance
+    assert b.instance(0).query("inplace") == 1
+    with pytest.raises(P.TplError):
+        b.set_param("inplace", 2)
+    b.close()
+    b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8),
+                 dict(nx=96, ny=64, Re=20.0, Wi=0.5, beta=0.8)])
     with pytest.raises(P.TplError) as e:
-        b.set_param("inplace", 1)
-    assert "two population arrays" in str(e.value)
+        b.set_param("inplace", 1)  # an instance whose nx is not a multiple of 64
+    assert "multiple of 64" in str(e.value)
+    assert b.instance(0).query("inplace") == 0  # the others left as they were
     b.close()
 
 

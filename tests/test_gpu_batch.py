@@ -238,3 +238,50 @@ def test_batch_errors():
     assert b.query("qsplit_used") == 2 and b.query("group") == 0
     b.step(2)
     b.close()
+
+
+@pytest.mark.parametrize("precision", [P.TPL_FP64, P.TPL_FP32], ids=["fp64", "fp32"])
+def test_batch_in_place_matches_two_arrays(precision):
+    """Every instance streamed in place: the same states as the two-array
+    batch in the same launch shape, bitwise, after even step counts, and the
+    same per-node fields after odd ones; graph replays across step-count
+    parities (a graph captured at one parity is re-captured at the other);
+    population reads refused at odd parity; an instance stepped on its own
+    blocks the batch until it is back at the batch's parity."""
+    def make(inplace):
+        b = P.Batch(ROWS, precision=precision, nq=6, pre_steps=40, qsplit=1, group=4,
+                    autotune=0, graph_steps=4, inplace=inplace)
+        b.init()
+        return b
+    a, b = make(0), make(1)
+    assert b.query("qsplit_used") == 1 and b.query("group_used") == 4
+    assert b.query("bytes_state") < a.query("bytes_state")
+    total = 0
+    for n in (5, 4, 9, 2, 1, 1):
+        a.step(n); b.step(n)
+        total += n
+        print(f"in-place batch: step {total}", flush=True)
+        for i in range(len(ROWS)):
+            ta, tb = a.instance(i), b.instance(i)
+            assert np.array_equal(ta.moments(), tb.moments()), (total, i)
+            assert tb.query("inplace_odd") == total % 2
+            if total % 2 == 0:
+                sa, sb = ta.get_state(), tb.get_state()
+                for k in sa:
+                    assert np.array_equal(sa[k], sb[k]), (total, i, k)
+            else:
+                with pytest.raises(P.TplError):
+                    tb.get_state()
+    b.instance(0).step(1)
+    with pytest.raises(P.TplError) as e:
+        b.step(2)
+    assert "parity" in str(e.value)
+    b.instance(0).step(1)
+    a.instance(0).set_param("qsplit", 1)  # its own launches: one Q-slice, as in place
+    a.instance(0).step(2)
+    a.step(2); b.step(2)
+    for i in range(len(ROWS)):
+        sa, sb = a.instance(i).get_state(), b.instance(i).get_state()
+        for k in sa:
+            assert np.array_equal(sa[k], sb[k]), ("after own steps", i, k)
+    a.close(); b.close()
