@@ -586,9 +586,15 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
               stored<T>(g[k], rq(rstore, y, q, k)));
         sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
       } else if constexpr (!NEQ) {
+        // plane bases one stride apart, the stride opaque so that they are
+        // not hoisted out of the Q-loop (as for the node-local in-place reads)
+        uint64_t stride = (uint64_t)nqd * (uint64_t)N * SZ;
+        asm volatile("" : "+s"(stride));
+        char *pw = reinterpret_cast<char *>(uni(b.XP + (size_t)q * N));
 #pragma unroll
         for (int k = 0; k < 25; ++k)
-          sto(wplane(b.XP, (long long)k * nqd + q), oR, stored<T>(g[k], rq(rstore, y, q, k)));
+          sto(reinterpret_cast<T *>(pw + (size_t)k * stride), oR,
+              stored<T>(g[k], rq(rstore, y, q, k)));
         sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
       } else {
         // deviations -> BF16 remainders and FP32 moments
