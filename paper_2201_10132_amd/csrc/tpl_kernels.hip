@@ -154,7 +154,8 @@ __device__ __forceinline__ double neq_lin(int k, double ps, const double J[4], d
 }
 // Encode the deviations d[25] of one (r, Q)-node: BF16 remainders nb[25] and
 // the stored moments m[5] (m0, Jrx, Jry, JQx, JQy) as FP32.
-__device__ __forceinline__ void neq_encode(const double d[25], uint16_t nb[25], float m[5]) {
+template <typename D>  // float (the step) or double (conversions)
+__device__ __forceinline__ void neq_encode(const D d[25], uint16_t nb[25], float m[5]) {
   double m0 = 0.0, J[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < 25; ++k) {
@@ -416,7 +417,15 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   for (int q = slice; q < nqd; q += p.qs) {
     if (qsync) __syncthreads();  // keep the group's waves on the same Q-node
     const QNode CONSTANT_AS &qn = cst(qtab)[q];  // scalar loads
-    double g[25];
+    // the Q-node's 25 populations: FP64 values, or for the BF16 form their
+    // FP32 deviations from the pull reference (the collision's result: from
+    // the store reference), which halves the registers they hold
+    using GT = std::conditional_t<NEQ, float, double>;
+    GT g[25];
+    auto G = [&](int k) -> double {
+      if constexpr (NEQ) return rq(rpull, y, q, k) + (double)g[k];
+      else return g[k];
+    };
     if constexpr (IP == 2) {
       // plane order, each base one plane stride past the last; the stride is
       // kept opaque so that the 25 bases are not hoisted out of the Q-loop
@@ -475,8 +484,8 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
 #pragma unroll
           for (int c = 0; c < 4; ++c)
             if (PV[k][c]) J[c] = (double)lj[k - k0][j++];
-          g[k] = rq(rpull, y, q, k) + neq_lin(k, (double)lm0[k - k0], J, bb ? -1.0 : 1.0) +
-                 from_bf16((uint16_t)ln[k - k0]);
+          g[k] = (float)(neq_lin(k, (double)lm0[k - k0], J, bb ? -1.0 : 1.0) +
+                         from_bf16((uint16_t)ln[k - k0]));
         }
       };
       pull(std::integral_constant<int, 0>{}, std::integral_constant<int, 13>{});
@@ -486,17 +495,18 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
     double P2[4][4] = {};  // model 2: second moments sum xi_a xi_b g (a <= b)
 #pragma unroll
     for (int k = 0; k < 25; ++k) {
-      psi += g[k];
-      if (PV[k][0]) Jrx += PV[k][0] * g[k];
-      if (PV[k][1]) Jry += PV[k][1] * g[k];
-      if (PV[k][2]) JQx += PV[k][2] * g[k];
-      if (PV[k][3]) JQy += PV[k][3] * g[k];
+      const double gk = G(k);
+      psi += gk;
+      if (PV[k][0]) Jrx += PV[k][0] * gk;
+      if (PV[k][1]) Jry += PV[k][1] * gk;
+      if (PV[k][2]) JQx += PV[k][2] * gk;
+      if (PV[k][3]) JQy += PV[k][3] * gk;
       if constexpr (QE2) {
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int b2 = a; b2 < 4; ++b2)
-            if (PV[k][a] && PV[k][b2]) P2[a][b2] += PV[k][a] * PV[k][b2] * g[k];
+            if (PV[k][a] && PV[k][b2]) P2[a][b2] += PV[k][a] * PV[k][b2] * gk;
       }
     }
     // spring term: kappa Fhat (Q . grad psi^{n-1}), or with the shift
@@ -569,8 +579,10 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
           t += hw * hk;
         }
       }
-      g[k] = p.c1P * g[k] + t;  // post-collision population
-      mg[pdir(k)] += g[k];
+      const double go = p.c1P * G(k) + t;  // post-collision population
+      mg[pdir(k)] += go;
+      if constexpr (NEQ) g[k] = (float)(go - rq(rstore, y, q, k));
+      else g[k] = go;
     }
     if (active) {
       if constexpr (IP == 1) {
@@ -599,8 +611,6 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
       } else {
         // deviations -> BF16 remainders and FP32 moments
         sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
-#pragma unroll
-        for (int k = 0; k < 25; ++k) g[k] -= rq(rstore, y, q, k);
         uint16_t nb[25];
         float m[5];
         neq_encode(g, nb, m);
