@@ -1714,10 +1714,10 @@ int choose_shape(tpl_batch *b) {
     qs_list[0] = q;
     nqs = 1;
   }
-  if (b->group != 0 && b->group != 1 && b->group != 2 && b->group != 4 && b->group != 8)
-    return fail(TPL_EINVAL, "group must be 0 (tuned), 1, 2, 4 or 8");
   if (b->group > 1 && b->qsplit > 1)
     return fail(TPL_EINVAL, "item groups need one Q-slice (qsplit 0 or 1)");
+  if (b->group != 0 && b->group != 1 && b->group != 2 && b->group != 4 && b->group != 8)
+    return fail(TPL_EINVAL, "group must be 0 (tuned), 1, 2, 4 or 8");
   if (b->inplace) {
     // in place a launch advances the state, so shapes cannot be timed by
     // repeating it: one Q-slice, groups of `group` tiles (4 unless set)
