@@ -158,7 +158,7 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *                 shift itself, kappa Fhat [psi(r + Q/2) - psi(r - Q/2)] with
  *                 psi between nodes by periodic bilinear interpolation (one
  *                 more launch sums it over Q); two-array FP64 and FP32 storage
- *                 with lagged gradients, not for batches
+ *                 with lagged gradients; a batch sets it for all instances
  *   pert_modes 1  0 = single x-mode, 1 = multimode perturbation
  *   pre_steps -1  base-state column steps (-1 = 5 max(l^2/nu, lambda))
  *   qsplit 0      Q-slices per r-tile in the step kernel: 0 (automatic),
@@ -295,8 +295,10 @@ tpl_batch *tpl_batch_create(const tpl_instance *inst, int n, int precision);
  *   graph_steps 20 steps captured per HIP graph (< 2: plain launches)
  *   time_kernels 0 1 = time tpl_batch_step with HIP events (kernel_ms)
  * Any other key is a tpl_set_param key applied to every instance before
- * tpl_batch_init (TPL_ESTATE afterwards; precision, gradients and
- * spring_shift are rejected).  inplace 1 streams every instance in place
+ * tpl_batch_init (TPL_ESTATE afterwards; precision and gradients are
+ * rejected).  spring_shift 1 takes the shifted spring term for every
+ * instance (a batched launch forms its Q-sums before each step).  inplace 1
+ * streams every instance in place
  * (each nx a multiple of 64; set here, not per instance): one Q-slice,
  * groups of `group` tiles (4 unless set), the shape not timed (an in-place
  * launch advances the state); graphs are captured per step-count parity;

@@ -145,7 +145,12 @@ hipError_t launch_tile_dev(int planes, int nx, int ny, const double *col,
 template <typename T>
 hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs, int grid,
                              bool rowtile, int parity, hipStream_t s, int group = 1,
-                             int ip = 0);
+                             int ip = 0, bool shift = false);
+// The shifted spring term's Q-sum for every item of a batch (before
+// launch_step_batch with shift; grid workgroups of eight waves walk the items).
+template <typename T>
+hipError_t launch_spring_sum_batch(const InstDev *inst, int ninst, int nitems, int grid,
+                                   int parity, hipStream_t s);
 hipError_t launch_rest(int nqd, long long N, double rhoS0, double rhoP0,
                        const double *peq, StateView a, hipStream_t s);
 template <typename T>

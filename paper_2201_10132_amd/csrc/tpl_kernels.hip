@@ -697,8 +697,9 @@ __global__ void __launch_bounds__(MAXT)
 // With group > 1 (one Q-slice) a workgroup takes `group` consecutive items,
 // one wave each, so that neighbouring tiles' overlapping stencil reads meet
 // in the caches; units of `group` items are what the grid and the XCD
-// mapping count.  IP != 0: every instance streams in place (step_tile).
-template <typename T, int MAXT, bool ROWTILE, int IP = 0>
+// mapping count.  IP != 0: every instance streams in place (step_tile);
+// SHIFT: the shifted spring term, its Q-sum formed by k_spring_sum_batch.
+template <typename T, int MAXT, bool ROWTILE, int IP = 0, bool SHIFT = false>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)))
     k_step_batch(const InstDev *__restrict__ inst, int ninst, int nitems, int items_per_xcd,
                  int parity, int group) {
@@ -737,19 +738,35 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)
                       static_cast<T *>(d.PSI[rd]), d.FLD[rd]};
     const StateT<T> b{static_cast<T *>(d.XS[rd ^ 1]), static_cast<T *>(d.XP[rd ^ 1]),
                       static_cast<T *>(d.PSI[rd ^ 1]), d.FLD[rd ^ 1]};
-    step_tile<T, ROWTILE, false, false, IP>(pp, a, b, d.rpull, d.rstore, d.rpsi, d.rspull,
-                                            d.rsstore, d.qtab, item - d.item0, red);
+    step_tile<T, ROWTILE, false, false, IP, SHIFT>(pp, a, b, d.rpull, d.rstore, d.rpsi,
+                                                   d.rspull, d.rsstore, d.qtab, item - d.item0,
+                                                   red);
   }
 }
 
 template <typename T>
 hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs, int grid,
-                             bool rowtile, int parity, hipStream_t s, int group, int ip) {
+                             bool rowtile, int parity, hipStream_t s, int group, int ip,
+                             bool shift) {
   if (group < 1 || (group > 1 && qs != 1) || qs * group > 8) return hipErrorInvalidValue;
   const size_t lds = qs > 1 ? (size_t)qs * 12 * 64 * sizeof(double) : 0;
   const int nunits = (nitems + group - 1) / group;
   const int per_xcd = (grid % 8 == 0 && nunits >= 64) ? (nunits + 7) / 8 : 0;
   const dim3 g(grid), blk(64 * qs * group);
+  if (shift) {
+    // the shifted spring term: two arrays
+    if (ip != 0) return hipErrorInvalidValue;
+#define TPL_BATCH_SH(MAXT, RT)                                                          \
+  hipLaunchKernelGGL((k_step_batch<T, MAXT, RT, 0, true>), g, blk, lds, s, inst, ninst, nitems, \
+                     per_xcd, parity, group)
+    if (qs * group <= 4) {
+      if (rowtile) TPL_BATCH_SH(256, true); else TPL_BATCH_SH(256, false);
+    } else {
+      if (rowtile) TPL_BATCH_SH(512, true); else TPL_BATCH_SH(512, false);
+    }
+#undef TPL_BATCH_SH
+    return hipGetLastError();
+  }
   if (ip != 0) {
     // in place: whole tiles (nx a multiple of 64 for every instance), one Q-slice
     if ((ip != 1 && ip != 2) || qs != 1 || !rowtile) return hipErrorInvalidValue;
@@ -782,9 +799,9 @@ hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs,
   return hipGetLastError();
 }
 template hipError_t launch_step_batch<double>(const InstDev *, int, int, int, int, bool, int,
-                                              hipStream_t, int, int);
+                                              hipStream_t, int, int, bool);
 template hipError_t launch_step_batch<float>(const InstDev *, int, int, int, int, bool, int,
-                                             hipStream_t, int, int);
+                                             hipStream_t, int, int, bool);
 
 template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
@@ -1024,6 +1041,72 @@ template hipError_t launch_spring_sum<double>(const StepParams &, StateT<double>
                                               const QNode *, hipStream_t);
 template hipError_t launch_spring_sum<float>(const StepParams &, StateT<float>, StepRef,
                                              const QNode *, hipStream_t);
+
+// The same Q-sum for every item (64-node tile) of a batch, the read half of
+// each instance chosen by parity as in k_step_batch.
+template <typename T>
+__global__ void __launch_bounds__(64 * kSpringSlices)
+    k_spring_sum_batch(const InstDev *__restrict__ inst, int ninst, int nitems, int parity) {
+  constexpr bool F32 = std::is_same<T, float>::value;
+  __shared__ double part[kSpringSlices][2][64];
+  const int lane = threadIdx.x & 63;
+  const int slice = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const InstDev CONSTANT_AS *ci = cst(inst);
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    int lo = 0, hi = ninst - 1;  // last instance with item0 <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ci[mid].item0 <= item) lo = mid; else hi = mid - 1;
+    }
+    const InstDev CONSTANT_AS &d = ci[lo];
+    const long long N = d.p.N;
+    const int nx = d.p.nx, ny = d.p.ny, nqd = d.p.nqd;
+    const double kappa = d.p.kappa;
+    const int rd = parity ^ d.cur0;
+    const T *PSI = static_cast<const T *>(d.PSI[rd]);
+    double *FLD = d.FLD[rd];
+    const float *rpsi = d.rpsi;
+    const QNode *qtab = d.qtab;
+    const long long rr = (long long)(item - d.item0) * 64 + lane;
+    const int r = (int)(rr < N ? rr : N - 1);
+    const int y = r / nx, x = r - y * nx;
+    double Sx = 0.0, Sy = 0.0;
+    for (int q = slice; q < nqd; q += kSpringSlices) {
+      const QNode CONSTANT_AS &qn = cst(qtab)[q];
+      const double dd = spring_shift_diff(PSI + (size_t)q * N, x, y, nx, ny, qn.qx, qn.qy,
+                                          [&](int row) {
+                                            return F32 ? (double)rpsi[(size_t)row * nqd + q] : 0.0;
+                                          });
+      Sx += kappa * qn.fx * dd;
+      Sy += kappa * qn.fy * dd;
+    }
+    part[slice][0][lane] = Sx;
+    part[slice][1][lane] = Sy;
+    __syncthreads();
+    if (slice == 0 && rr < N) {
+      for (int s2 = 1; s2 < kSpringSlices; ++s2) {
+        Sx += part[s2][0][lane];
+        Sy += part[s2][1][lane];
+      }
+      FLD[(size_t)F_MXX * N + r] = Sx;
+      FLD[(size_t)F_MXY * N + r] = Sy;
+    }
+    __syncthreads();  // part is reused by the next item
+  }
+}
+
+template <typename T>
+hipError_t launch_spring_sum_batch(const InstDev *inst, int ninst, int nitems, int grid,
+                                   int parity, hipStream_t s) {
+  if (grid < 1 || nitems < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_spring_sum_batch<T>, dim3(grid), dim3(64 * kSpringSlices), 0, s, inst,
+                     ninst, nitems, parity);
+  return hipGetLastError();
+}
+template hipError_t launch_spring_sum_batch<double>(const InstDev *, int, int, int, int,
+                                                    hipStream_t);
+template hipError_t launch_spring_sum_batch<float>(const InstDev *, int, int, int, int,
+                                                   hipStream_t);
 
 template <typename T>
 hipError_t launch_same_step_fields(const StepParams &p, StateT<T> a, StepRef ref,

@@ -1516,6 +1516,7 @@ struct tpl_batch {
   // in-place streaming of every instance: the step kind alternates with the
   // batch's step count (ip_odd), which the captured graph starts from (graph_ip)
   int inplace = 0, ip_odd = 0, graph_ip = 0;
+  int spring_shift = 0;  // the shifted spring term for every instance
   double *scratch = nullptr;
   int scratch_n = 0;
   double kernel_ms = 0.0, tune_ms = 0.0;
@@ -1582,10 +1583,19 @@ int upload_table(tpl_batch *b, const std::vector<InstDev> &tab) {
 hipError_t batch_launch(const tpl_batch *b, int esize, int ninst, int nitems, int qs, int grid,
                         bool rowtile, int parity, int group, bool inplace = true) {
   const int ip = (inplace && b->inplace) ? (((b->ip_odd + parity) & 1) ? 2 : 1) : 0;
+  const bool sh = b->spring_shift != 0;  // base-state columns as well
+  if (sh) {
+    const int sg = nitems < 4096 ? nitems : 4096;
+    const hipError_t e =
+        esize == 4 ? launch_spring_sum_batch<float>(b->tab_d, ninst, nitems, sg, parity, b->stream)
+                   : launch_spring_sum_batch<double>(b->tab_d, ninst, nitems, sg, parity,
+                                                     b->stream);
+    if (e != hipSuccess) return e;
+  }
   return esize == 4 ? launch_step_batch<float>(b->tab_d, ninst, nitems, qs, grid, rowtile, parity,
-                                               b->stream, group, ip)
+                                               b->stream, group, ip, sh)
                     : launch_step_batch<double>(b->tab_d, ninst, nitems, qs, grid, rowtile,
-                                                parity, b->stream, group, ip);
+                                                parity, b->stream, group, ip, sh);
 }
 
 // Enqueue n launches of the uploaded table with parities p0, p0^1, ...
@@ -1918,24 +1928,25 @@ int tpl_batch_set_param(tpl_batch *b, const char *key, double value) {
       return TPL_OK;
     }
   if (!strcmp(key, "precision")) return fail(TPL_EINVAL, "precision is fixed at tpl_batch_create");
-  if (!strcmp(key, "inplace")) {
-    if (b->inited) return fail(TPL_ESTATE, "inplace is fixed after tpl_batch_init");
-    if (value != 0 && value != 1) return fail(TPL_EINVAL, "inplace must be 0 or 1");
+  if (!strcmp(key, "inplace") || !strcmp(key, "spring_shift")) {
+    // set for the whole batch: every instance or none
+    int &field = !strcmp(key, "inplace") ? b->inplace : b->spring_shift;
+    if (b->inited) return fail(TPL_ESTATE, std::string(key) + " is fixed after tpl_batch_init");
+    if (value != 0 && value != 1) return fail(TPL_EINVAL, std::string(key) + " must be 0 or 1");
     for (size_t i = 0; i < b->inst.size(); ++i) {
       const int rc = tpl_set_param(b->inst[i], key, value);
       if (rc) {  // leave every instance as it was
         const std::string msg = g_err;
-        for (size_t j = 0; j < i; ++j) (void)tpl_set_param(b->inst[j], key, b->inplace);
+        for (size_t j = 0; j < i; ++j) (void)tpl_set_param(b->inst[j], key, field);
         return fail(rc, msg);
       }
     }
-    b->inplace = (int)value;
+    field = (int)value;
     return TPL_OK;
   }
   if (!strcmp(key, "gradients"))
     return fail(TPL_EINVAL, "the batched step takes lagged gradients");
-  if (!strcmp(key, "spring_shift"))
-    return fail(TPL_EINVAL, "the batched step takes the Taylor spring term");
+
   if (b->inited) return fail(TPL_ESTATE, "instance parameters are fixed after tpl_batch_init");
   for (tpl_ctx *x : b->inst) {
     const int rc = tpl_set_param(x, key, value);
@@ -1998,10 +2009,10 @@ int tpl_batch_init(tpl_batch *b) {
   for (tpl_ctx *x : b->inst) {
     if (x->c.qe_model != 1)
       return fail(TPL_EINVAL, "the batched step runs the component-momentum model (qe_model 1)");
-    if (x->c.gradients || x->c.spring_shift)
-      return fail(TPL_EINVAL, "the batched step takes lagged gradients and the Taylor spring term");
-    if (x->c.inplace != b->inplace)
-      return fail(TPL_EINVAL, "in-place streaming is set for the whole batch (tpl_batch_set_param)");
+    if (x->c.gradients) return fail(TPL_EINVAL, "the batched step takes lagged gradients");
+    if (x->c.inplace != b->inplace || x->c.spring_shift != b->spring_shift)
+      return fail(TPL_EINVAL, "inplace and spring_shift are set for the whole batch "
+                              "(tpl_batch_set_param)");
   }
   b->inited = false;
   drop_graph(b);

@@ -276,6 +276,9 @@ def test_spring_shift_knob():
     t.set_param("precision", P.TPL_FP32)
     t.close()
     b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8)])
+    b.set_param("spring_shift", 1)  # forwarded to every instance
+    assert b.instance(0).query("spring_shift") == 1
     with pytest.raises(P.TplError):
-        b.set_param("spring_shift", 1)
+        b.set_param("inplace", 1)  # not with the shifted spring term
+    assert b.instance(0).query("inplace") == 0
     b.close()

@@ -285,3 +285,30 @@ def test_batch_in_place_matches_two_arrays(precision):
         for k in sa:
             assert np.array_equal(sa[k], sb[k]), ("after own steps", i, k)
     a.close(); b.close()
+
+
+@pytest.mark.parametrize("insts", [MIXED, ROWS], ids=["mixed", "rows"])
+def test_batch_shifted_spring_matches_single_contexts(insts):
+    """The shifted spring term in the batched step (its Q-sums formed by a
+    batched launch, also for the base-state columns): every instance equals
+    a context of its own with the same option and Q-slice count, bitwise,
+    through graph replays; and the oracle on the first instance."""
+    b = P.Batch(insts, nq=6, pre_steps=30, autotune=0, qsplit=1, group=1, graph_steps=4,
+                spring_shift=1)
+    b.init()
+    b.step(9)
+    for i, d in enumerate(insts):
+        print(f"shifted batch: instance {i}", flush=True)
+        t = _single(d, P.TPL_FP64, nq=6, pre_steps=30, qsplit=1, autotune=0, spring_shift=1)
+        t.step(9)
+        diff = _states_equal(b.instance(i).get_state(), t.get_state())
+        assert all(v == 0.0 for v in diff.values()), (i, diff)
+        t.close()
+    d = insts[0]
+    o = oracle.OracleSim(d["nx"], d["ny"], nq=6, Re=d["Re"], Wi=d["Wi"], beta=d["beta"],
+                         periods=d["periods"], spring_shift=1)
+    o.base_state(30)
+    o.perturb(d["seed"], d["perturbation"], True)
+    o.step(9)
+    compare_states(b.instance(0).get_state(), o.get_state(), 1e-12)
+    b.close()

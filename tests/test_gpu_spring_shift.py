@@ -101,9 +101,10 @@ def test_shift_differs_from_taylor_form_slightly():
     assert abs(ab / aa - 1) < 2e-2
 
 
-def test_kolmogorov72_driver_with_shift():
-    """The paper's cell driven as separate contexts with the shifted spring
-    term (a short run at a small Q-grid)."""
+def test_kolmogorov72_driver_with_shift_and_as_separate_contexts():
+    """The paper's cell with the shifted spring term, batched, and as
+    separate contexts (the driver's path for options the batched step does
+    not take): the two agree bitwise (a short run at a small Q-grid)."""
     from paper_2201_10132_amd import kolmogorov72 as K
 
     res = K.run(t_end=1.0, every=0.5, nq=8, progress=False, spring_shift=1)
@@ -112,6 +113,19 @@ def test_kolmogorov72_driver_with_shift():
         assert np.all(np.isfinite(res["enstrophy"][i])) and res["enstrophy"][i][-1] > 0
     rows = K.summary(res)
     assert [r["Wi"] for r in rows] == list(K.WIS)
+    cells = K._Cells([dict(K.CELL, Wi=w, seed=0, perturbation=1e-3) for w in K.WIS],
+                     precision=P.TPL_FP64, nq=8, pre_steps=0, spring_shift=1)
+    batch = P.Batch([dict(K.CELL, Wi=w, seed=0, perturbation=1e-3) for w in K.WIS],
+                    precision=P.TPL_FP64, nq=8, pre_steps=0, spring_shift=1, autotune=0,
+                    qsplit=8)
+    cells.init(); batch.init()
+    for t in cells.cells:
+        t.set_param("qsplit", 8)
+        t.set_param("autotune", 0)
+    cells.step(30); batch.step(30)
+    for i in range(3):
+        assert cells.instance(i).diagnostics() == batch.instance(i).diagnostics(), i
+    cells.close(); batch.close()
 
 
 def test_shift_fullsize_sampled_node_parity():
