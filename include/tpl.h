@@ -150,8 +150,8 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *                 term's psi gradient (the paper leaves it open): 0 = the
  *                 previous step's observables (one pass); 1 = this step's,
  *                 formed from the pulled populations before the step (three
- *                 more launches, about 1.5x the bytes; FP64 and FP32 forms,
- *                 not for batches)
+ *                 more launches, about 1.5x the bytes; FP64 and FP32 forms;
+ *                 a batch sets it for all instances)
  *   spring_shift 0  form of the spring term of the imposed polymer flux
  *                 (Sec. V, the force times psi at the two beads): 0 = its
  *                 first-order Taylor form kappa Fhat (Q . grad psi); 1 = the
@@ -295,9 +295,14 @@ tpl_batch *tpl_batch_create(const tpl_instance *inst, int n, int precision);
  *   graph_steps 20 steps captured per HIP graph (< 2: plain launches)
  *   time_kernels 0 1 = time tpl_batch_step with HIP events (kernel_ms)
  * Any other key is a tpl_set_param key applied to every instance before
- * tpl_batch_init (TPL_ESTATE afterwards; precision and gradients are
- * rejected).  spring_shift 1 takes the shifted spring term for every
- * instance (a batched launch forms its Q-sums before each step).  inplace 1
+ * tpl_batch_init (TPL_ESTATE afterwards; precision is rejected).
+ * spring_shift 1 takes the shifted spring term for every instance (a
+ * batched launch forms its Q-sums before each step); gradients 1 takes
+ * same-step gradients for every instance (three batched launches form this
+ * step's psi, M and U before each step).  These and inplace are set for the
+ * whole batch: a value an instance refuses leaves every instance as it was
+ * (the error returned), and tpl_batch_init returns TPL_EINVAL if an
+ * instance's own setting differs from the batch's.  inplace 1
  * streams every instance in place
  * (each nx a multiple of 64; set here, not per instance): one Q-slice,
  * groups of `group` tiles (4 unless set), the shape not timed (an in-place

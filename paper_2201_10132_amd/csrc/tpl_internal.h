@@ -123,6 +123,11 @@ hipError_t launch_spring_sum(const StepParams &p, StateT<T> a, StepRef ref, cons
 template <typename T>
 hipError_t launch_same_step_fields(const StepParams &p, StateT<T> a, StepRef ref,
                                    const QNode *qtab, hipStream_t s, int ip = 0);
+// The same for every item of a batch (before launch_step_batch; nqd: the
+// batch's Q-nodes per r-node).
+template <typename T>
+hipError_t launch_same_step_fields_batch(const InstDev *inst, int ninst, int nitems, int nqd,
+                                         int parity, int ip, hipStream_t s);
 // BF16 non-equilibrium form <-> FP32 deviations from the reference, node by
 // node: dev [25][nqd][N] = w_k (m0 + 3 (v_k . J)) + n_k (decode), and the
 // inverse (encode: writes MOM and n).

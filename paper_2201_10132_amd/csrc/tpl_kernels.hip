@@ -895,14 +895,13 @@ template hipError_t launch_step<float>(const StepParams &, StateT<float>, StateT
 // mixture velocity with the spring-stress divergence of M^n, per r-node.
 // ip selects the pull of the in-place steps as in step_tile.
 template <typename T>
-__global__ void k_pre_psi(StepParams p, StateT<T> a, const float *__restrict__ rpull,
-                          const float *__restrict__ rpsi, const QNode *__restrict__ qtab, int ip) {
+__device__ __forceinline__ void pre_psi_node(const StepParams &p, const StateT<T> &a,
+                                             const float *rpull, const float *rpsi,
+                                             const QNode *qtab, int ip, int r, int q) {
   constexpr bool F32 = std::is_same<T, float>::value;
   constexpr uint32_t SZ = sizeof(T);
   const long long N = p.N;
-  const long long rr = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (rr >= N) return;
-  const int r = (int)rr, q = blockIdx.y, nx = p.nx, ny = p.ny, nqd = p.nqd;
+  const int nx = p.nx, ny = p.ny, nqd = p.nqd;
   const int y = r / nx, x = r - y * nx;
   const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
   const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
@@ -923,13 +922,11 @@ __global__ void k_pre_psi(StepParams p, StateT<T> a, const float *__restrict__ r
 }
 
 template <typename T>
-__global__ void k_pre_m(StepParams p, StateT<T> a, const float *__restrict__ rpsi,
-                        const QNode *__restrict__ qtab) {
+__device__ __forceinline__ void pre_m_node(const StepParams &p, const StateT<T> &a,
+                                           const float *rpsi, const QNode *qtab, int r) {
   constexpr bool F32 = std::is_same<T, float>::value;
   const long long N = p.N;
-  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= N) return;
-  const int y = (int)(r / p.nx);
+  const int y = r / p.nx;
   double Mxx = 0.0, Mxy = 0.0, Myy = 0.0;
   for (int q = 0; q < p.nqd; ++q) {
     const double psi = full(a.PSI[(size_t)q * N + r], F32 ? (double)rpsi[(size_t)y * p.nqd + q] : 0.0);
@@ -944,12 +941,11 @@ __global__ void k_pre_m(StepParams p, StateT<T> a, const float *__restrict__ rps
 }
 
 template <typename T>
-__global__ void k_pre_u(StepParams p, StateT<T> a, const float *__restrict__ rspull, int ip) {
+__device__ __forceinline__ void pre_u_node(const StepParams &p, const StateT<T> &a,
+                                           const float *rspull, int ip, int r) {
   constexpr bool F32 = std::is_same<T, float>::value;
   const long long N = p.N;
-  const long long rr = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (rr >= N) return;
-  const int r = (int)rr, nx = p.nx, ny = p.ny;
+  const int nx = p.nx, ny = p.ny;
   const int y = r / nx, x = r - y * nx;
   const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
   const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
@@ -988,6 +984,103 @@ __global__ void k_pre_u(StepParams p, StateT<T> a, const float *__restrict__ rsp
   a.FLD[(size_t)F_UX * N + r] = Ux;
   a.FLD[(size_t)F_UY * N + r] = Uy;
 }
+
+template <typename T>
+__global__ void k_pre_psi(StepParams p, StateT<T> a, const float *__restrict__ rpull,
+                          const float *__restrict__ rpsi, const QNode *__restrict__ qtab, int ip) {
+  const long long rr = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rr >= p.N) return;
+  pre_psi_node<T>(p, a, rpull, rpsi, qtab, ip, (int)rr, blockIdx.y);
+}
+
+template <typename T>
+__global__ void k_pre_m(StepParams p, StateT<T> a, const float *__restrict__ rpsi,
+                        const QNode *__restrict__ qtab) {
+  const long long rr = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rr >= p.N) return;
+  pre_m_node<T>(p, a, rpsi, qtab, (int)rr);
+}
+
+template <typename T>
+__global__ void k_pre_u(StepParams p, StateT<T> a, const float *__restrict__ rspull, int ip) {
+  const long long rr = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rr >= p.N) return;
+  pre_u_node<T>(p, a, rspull, ip, (int)rr);
+}
+
+// The same three passes over every item (64-node tile) of a batch; the read
+// half of each instance chosen by parity as in k_step_batch.  One wave per
+// item (and Q-node for the psi pass), items walked with the grid's stride.
+__device__ __forceinline__ int batch_instance(const InstDev CONSTANT_AS *ci, int ninst,
+                                              int item) {
+  int lo = 0, hi = ninst - 1;  // last instance with item0 <= item
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ci[mid].item0 <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+template <typename T>
+__device__ __forceinline__ StateT<T> batch_half(const InstDev &d, int h) {
+  return StateT<T>{static_cast<T *>(d.XS[h]), static_cast<T *>(d.XP[h]),
+                   static_cast<T *>(d.PSI[h]), d.FLD[h]};
+}
+
+template <typename T>
+__global__ void k_pre_psi_batch(const InstDev *__restrict__ inst, int ninst, int nitems,
+                                int parity, int ip) {
+  const InstDev CONSTANT_AS *ci = cst(inst);
+  const int q = blockIdx.y;
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const InstDev &d = inst[batch_instance(ci, ninst, item)];
+    const StepParams pp = d.p;
+    if (q >= pp.nqd) continue;
+    const long long rr = (long long)(item - d.item0) * 64 + threadIdx.x;
+    if (rr < pp.N)
+      pre_psi_node<T>(pp, batch_half<T>(d, parity ^ d.cur0), d.rpull, d.rpsi, d.qtab, ip,
+                      (int)rr, q);
+  }
+}
+
+template <typename T>
+__global__ void k_pre_m_batch(const InstDev *__restrict__ inst, int ninst, int nitems,
+                              int parity) {
+  const InstDev CONSTANT_AS *ci = cst(inst);
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const InstDev &d = inst[batch_instance(ci, ninst, item)];
+    const StepParams pp = d.p;
+    const long long rr = (long long)(item - d.item0) * 64 + threadIdx.x;
+    if (rr < pp.N) pre_m_node<T>(pp, batch_half<T>(d, parity ^ d.cur0), d.rpsi, d.qtab, (int)rr);
+  }
+}
+
+template <typename T>
+__global__ void k_pre_u_batch(const InstDev *__restrict__ inst, int ninst, int nitems,
+                              int parity, int ip) {
+  const InstDev CONSTANT_AS *ci = cst(inst);
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const InstDev &d = inst[batch_instance(ci, ninst, item)];
+    const StepParams pp = d.p;
+    const long long rr = (long long)(item - d.item0) * 64 + threadIdx.x;
+    if (rr < pp.N) pre_u_node<T>(pp, batch_half<T>(d, parity ^ d.cur0), d.rspull, ip, (int)rr);
+  }
+}
+
+template <typename T>
+hipError_t launch_same_step_fields_batch(const InstDev *inst, int ninst, int nitems, int nqd,
+                                         int parity, int ip, hipStream_t s) {
+  if (ip < 0 || ip > 2 || nitems < 1 || nqd < 1 || nqd > 65535) return hipErrorInvalidValue;
+  const unsigned g = (unsigned)(nitems < 16384 ? nitems : 16384);
+  hipLaunchKernelGGL(k_pre_psi_batch<T>, dim3(g, (unsigned)nqd), dim3(64), 0, s, inst, ninst,
+                     nitems, parity, ip);
+  hipLaunchKernelGGL(k_pre_m_batch<T>, dim3(g), dim3(64), 0, s, inst, ninst, nitems, parity);
+  hipLaunchKernelGGL(k_pre_u_batch<T>, dim3(g), dim3(64), 0, s, inst, ninst, nitems, parity, ip);
+  return hipGetLastError();
+}
+template hipError_t launch_same_step_fields_batch<double>(const InstDev *, int, int, int, int, int,
+                                                          hipStream_t);
+template hipError_t launch_same_step_fields_batch<float>(const InstDev *, int, int, int, int, int,
+                                                         hipStream_t);
 
 // One 64-node tile per workgroup, kSpringSlices waves each summing every
 // kSpringSlices-th Q-node; the slices' partial sums are added in slice order

@@ -1517,6 +1517,7 @@ struct tpl_batch {
   // batch's step count (ip_odd), which the captured graph starts from (graph_ip)
   int inplace = 0, ip_odd = 0, graph_ip = 0;
   int spring_shift = 0;  // the shifted spring term for every instance
+  int gradients = 0;     // same-step gradients for every instance
   double *scratch = nullptr;
   int scratch_n = 0;
   double kernel_ms = 0.0, tune_ms = 0.0;
@@ -1584,6 +1585,16 @@ hipError_t batch_launch(const tpl_batch *b, int esize, int ninst, int nitems, in
                         bool rowtile, int parity, int group, bool inplace = true) {
   const int ip = (inplace && b->inplace) ? (((b->ip_odd + parity) & 1) ? 2 : 1) : 0;
   const bool sh = b->spring_shift != 0;  // base-state columns as well
+  if (b->gradients) {  // base-state columns as well
+    int nqd = 1;  // Q-nodes per r-node, the largest of the instances
+    for (const tpl_ctx *x : b->inst) nqd = x->d.nqd > nqd ? x->d.nqd : nqd;
+    const hipError_t e =
+        esize == 4 ? launch_same_step_fields_batch<float>(b->tab_d, ninst, nitems, nqd, parity, ip,
+                                                          b->stream)
+                   : launch_same_step_fields_batch<double>(b->tab_d, ninst, nitems, nqd, parity,
+                                                           ip, b->stream);
+    if (e != hipSuccess) return e;
+  }
   if (sh) {
     const int sg = nitems < 4096 ? nitems : 4096;
     const hipError_t e =
@@ -1928,9 +1939,11 @@ int tpl_batch_set_param(tpl_batch *b, const char *key, double value) {
       return TPL_OK;
     }
   if (!strcmp(key, "precision")) return fail(TPL_EINVAL, "precision is fixed at tpl_batch_create");
-  if (!strcmp(key, "inplace") || !strcmp(key, "spring_shift")) {
+  if (!strcmp(key, "inplace") || !strcmp(key, "spring_shift") || !strcmp(key, "gradients")) {
     // set for the whole batch: every instance or none
-    int &field = !strcmp(key, "inplace") ? b->inplace : b->spring_shift;
+    int &field = !strcmp(key, "inplace")        ? b->inplace
+                 : !strcmp(key, "spring_shift") ? b->spring_shift
+                                                : b->gradients;
     if (b->inited) return fail(TPL_ESTATE, std::string(key) + " is fixed after tpl_batch_init");
     if (value != 0 && value != 1) return fail(TPL_EINVAL, std::string(key) + " must be 0 or 1");
     for (size_t i = 0; i < b->inst.size(); ++i) {
@@ -1944,9 +1957,6 @@ int tpl_batch_set_param(tpl_batch *b, const char *key, double value) {
     field = (int)value;
     return TPL_OK;
   }
-  if (!strcmp(key, "gradients"))
-    return fail(TPL_EINVAL, "the batched step takes lagged gradients");
-
   if (b->inited) return fail(TPL_ESTATE, "instance parameters are fixed after tpl_batch_init");
   for (tpl_ctx *x : b->inst) {
     const int rc = tpl_set_param(x, key, value);
@@ -2009,9 +2019,9 @@ int tpl_batch_init(tpl_batch *b) {
   for (tpl_ctx *x : b->inst) {
     if (x->c.qe_model != 1)
       return fail(TPL_EINVAL, "the batched step runs the component-momentum model (qe_model 1)");
-    if (x->c.gradients) return fail(TPL_EINVAL, "the batched step takes lagged gradients");
-    if (x->c.inplace != b->inplace || x->c.spring_shift != b->spring_shift)
-      return fail(TPL_EINVAL, "inplace and spring_shift are set for the whole batch "
+    if (x->c.inplace != b->inplace || x->c.spring_shift != b->spring_shift ||
+        x->c.gradients != b->gradients)
+      return fail(TPL_EINVAL, "inplace, spring_shift and gradients are set for the whole batch "
                               "(tpl_batch_set_param)");
   }
   b->inited = false;

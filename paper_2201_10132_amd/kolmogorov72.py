@@ -16,8 +16,8 @@ these are qualitative checks.
 With --spring-shift the spring term is the shift itself, psi at the two
 beads r +- Q/2, instead of its first-order Taylor form: the dumbbells here
 span a sizeable part of the forcing wavelength (sigma k = 1.1), where the
-two differ.  Options the batched step does not take (same-step gradients)
-run the three cells as separate contexts.
+two differ.  Options the batched step does not take (the component-stress
+quasi-equilibria, qe_model 2) run the three cells as separate contexts.
 
 Usage: python -m paper_2201_10132_amd.kolmogorov72 [--t-end 2000] [--spring-shift] [--out file.json]
 """
@@ -86,7 +86,7 @@ def run(t_end=2000.0, every=1.0, wis=WIS, nq=32, seed=0, perturbation=1e-3,
     `every` convective times.  Returns dict(t, enstrophy[w], qrms[w],
     amplitude[w], unstable[w])."""
     insts = [dict(CELL, Wi=w, seed=seed, perturbation=perturbation) for w in wis]
-    cls = _Cells if params.get("gradients") else Batch
+    cls = _Cells if params.get("qe_model", 1) != 1 else Batch
     b = cls(insts, precision=precision, nq=nq, pre_steps=0, **params)
     b.init()
     tc = convective_steps()

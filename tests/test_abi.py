@@ -257,9 +257,21 @@ def test_same_step_gradients_knob():
         t.set_param("precision", P.TPL_BF16NEQ)
     t.set_param("inplace", 1)  # both together are allowed
     t.close()
-    b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8)])
-    with pytest.raises(P.TplError):
+    b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8),
+                 dict(nx=32, ny=16, Re=20.0, Wi=0.5, beta=0.8)])
+    b.instance(1).set_param("spring_shift", 1)
+    with pytest.raises(P.TplError):  # refused by the second: the first left as it was
         b.set_param("gradients", 1)
+    assert [b.instance(i).query("gradients") for i in range(2)] == [0, 0]
+    with pytest.raises(P.TplError):  # the instances' options differ from the batch's
+        b.init()
+    b.close()
+    b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8)])
+    b.set_param("gradients", 1)  # forwarded to every instance
+    assert b.instance(0).query("gradients") == 1
+    with pytest.raises(P.TplError):
+        b.set_param("spring_shift", 1)  # not with same-step gradients
+    b.set_param("gradients", 0)
     b.close()
 
 

@@ -312,3 +312,36 @@ def test_batch_shifted_spring_matches_single_contexts(insts):
     o.step(9)
     compare_states(b.instance(0).get_state(), o.get_state(), 1e-12)
     b.close()
+
+
+@pytest.mark.parametrize("insts,precision,inplace",
+                         [(MIXED, P.TPL_FP64, 0), (ROWS, P.TPL_FP32, 0), (ROWS, P.TPL_FP64, 1)],
+                         ids=["mixed-fp64", "rows-fp32", "rows-fp64-inplace"])
+def test_batch_same_step_gradients_match_single_contexts(insts, precision, inplace):
+    """Same-step gradients in the batched step (the three field passes
+    batched too, also for the base-state columns): every instance equals a
+    context of its own with the same options and Q-slice count, bitwise,
+    through graph replays, also streamed in place; and the oracle on the
+    first instance (FP64)."""
+    group = 4 if inplace else 1
+    b = P.Batch(insts, precision=precision, nq=6, pre_steps=30, autotune=0, qsplit=1,
+                group=group, graph_steps=4, gradients=1, inplace=inplace)
+    b.init()
+    b.step(10)
+    for i, d in enumerate(insts):
+        print(f"same-step batch: instance {i}", flush=True)
+        t = _single(d, precision, nq=6, pre_steps=30, qsplit=1, autotune=0, gradients=1,
+                    inplace=inplace)
+        t.step(10)
+        diff = _states_equal(b.instance(i).get_state(), t.get_state())
+        assert all(v == 0.0 for v in diff.values()), (i, diff)
+        t.close()
+    if precision == P.TPL_FP64:
+        d = insts[0]
+        o = oracle.OracleSim(d["nx"], d["ny"], nq=6, Re=d["Re"], Wi=d["Wi"], beta=d["beta"],
+                             periods=d["periods"], gradients=1)
+        o.base_state(30)
+        o.perturb(d["seed"], d["perturbation"], True)
+        o.step(10)
+        compare_states(b.instance(0).get_state(), o.get_state(), 1e-12)
+    b.close()
