@@ -157,8 +157,10 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *                 first-order Taylor form kappa Fhat (Q . grad psi); 1 = the
  *                 shift itself, kappa Fhat [psi(r + Q/2) - psi(r - Q/2)] with
  *                 psi between nodes by periodic bilinear interpolation (one
- *                 more launch sums it over Q); two-array FP64 and FP32 storage
- *                 with lagged gradients; a batch sets it for all instances
+ *                 more launch sums it over Q); FP64 and FP32 forms, in place
+ *                 or not; with gradients 1 the sum is taken over this step's
+ *                 psi and replaces the M pass; a batch sets it for all
+ *                 instances
  *   pert_modes 1  0 = single x-mode, 1 = multimode perturbation
  *   pre_steps -1  base-state column steps (-1 = 5 max(l^2/nu, lambda))
  *   qsplit 0      Q-slices per r-tile in the step kernel: 0 (automatic),

@@ -119,15 +119,17 @@ hipError_t launch_spring_sum(const StepParams &p, StateT<T> a, StepRef ref, cons
                              hipStream_t s);
 // Same-step gradients: overwrite the read half's PSI, M and U with this
 // step's psi^n, M^n and U^n (three launches) before launch_step.  ip as there
-// (the pull of the step that follows); FP64 and FP32 forms.
+// (the pull of the step that follows); FP64 and FP32 forms.  With p.shift the
+// M pass is replaced by the spring-sum pass over psi^n (launch_spring_sum),
+// whose Q-sum the velocity pass and the step read.
 template <typename T>
 hipError_t launch_same_step_fields(const StepParams &p, StateT<T> a, StepRef ref,
                                    const QNode *qtab, hipStream_t s, int ip = 0);
 // The same for every item of a batch (before launch_step_batch; nqd: the
-// batch's Q-nodes per r-node).
+// batch's Q-nodes per r-node; shift: the batch's shifted spring term).
 template <typename T>
 hipError_t launch_same_step_fields_batch(const InstDev *inst, int ninst, int nitems, int nqd,
-                                         int parity, int ip, hipStream_t s);
+                                         int parity, int ip, bool shift, hipStream_t s);
 // BF16 non-equilibrium form <-> FP32 deviations from the reference, node by
 // node: dev [25][nqd][N] = w_k (m0 + 3 (v_k . J)) + n_k (decode), and the
 // inverse (encode: writes MOM and n).

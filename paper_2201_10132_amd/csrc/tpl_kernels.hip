@@ -753,9 +753,22 @@ hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs,
   const int nunits = (nitems + group - 1) / group;
   const int per_xcd = (grid % 8 == 0 && nunits >= 64) ? (nunits + 7) / 8 : 0;
   const dim3 g(grid), blk(64 * qs * group);
+  if (shift && ip != 0) {
+    // the shifted spring term streamed in place: whole tiles, one Q-slice
+    if ((ip != 1 && ip != 2) || qs != 1 || !rowtile) return hipErrorInvalidValue;
+#define TPL_BATCH_IPSH(MAXT, IP)                                                            \
+  hipLaunchKernelGGL((k_step_batch<T, MAXT, true, IP, true>), g, blk, lds, s, inst, ninst, \
+                     nitems, per_xcd, parity, group)
+    if (group <= 4) {
+      if (ip == 1) TPL_BATCH_IPSH(256, 1); else TPL_BATCH_IPSH(256, 2);
+    } else {
+      if (ip == 1) TPL_BATCH_IPSH(512, 1); else TPL_BATCH_IPSH(512, 2);
+    }
+#undef TPL_BATCH_IPSH
+    return hipGetLastError();
+  }
   if (shift) {
-    // the shifted spring term: two arrays
-    if (ip != 0) return hipErrorInvalidValue;
+    // the shifted spring term, two arrays
 #define TPL_BATCH_SH(MAXT, RT)                                                          \
   hipLaunchKernelGGL((k_step_batch<T, MAXT, RT, 0, true>), g, blk, lds, s, inst, ninst, nitems, \
                      per_xcd, parity, group)
@@ -815,9 +828,28 @@ hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
   const dim3 g(grid), blk(64 * p.qs * gsize);
 #define TPL_STEP_ARGS p, a, b, r.pull, r.store, r.psi, r.spull, r.sstore, qtab
   if (p.shift != 0 && p.shift != 1) return hipErrorInvalidValue;
+  if (p.shift && ip != 0) {
+    // shifted spring term streamed in place: whole tiles, one Q-slice
+    if (ip != 1 && ip != 2) return hipErrorInvalidValue;
+    if (neq || !rowtile || p.qs != 1 || a.XS != b.XS || a.XP != b.XP) return hipErrorInvalidValue;
+#define TPL_STEP_IPSH(QE2, IP)                                                          \
+  if (gsize <= 4)                                                                       \
+    hipLaunchKernelGGL((k_step<T, 256, true, false, QE2, IP, true>), g, blk, lds, s,    \
+                       TPL_STEP_ARGS);                                                  \
+  else                                                                                  \
+    hipLaunchKernelGGL((k_step<T, 512, true, false, QE2, IP, true>), g, blk, lds, s,    \
+                       TPL_STEP_ARGS);
+    if (p.qe == 2) {
+      if (ip == 1) { TPL_STEP_IPSH(true, 1) } else { TPL_STEP_IPSH(true, 2) }
+    } else {
+      if (ip == 1) { TPL_STEP_IPSH(false, 1) } else { TPL_STEP_IPSH(false, 2) }
+    }
+#undef TPL_STEP_IPSH
+    return hipGetLastError();
+  }
   if (p.shift) {
-    // non-local spring term: two arrays, FP64 and FP32 storage
-    if (neq || ip != 0) return hipErrorInvalidValue;
+    // non-local spring term, two arrays: FP64 and FP32 storage
+    if (neq) return hipErrorInvalidValue;
 #define TPL_STEP_SH(MAXT, RT)                                                                 \
   if (p.qe == 2)                                                                             \
     hipLaunchKernelGGL((k_step<T, MAXT, RT, false, true, 0, true>), g, blk, lds, s,          \
@@ -972,8 +1004,10 @@ __device__ __forceinline__ void pre_u_node(const StepParams &p, const StateT<T> 
   auto dY = [&](int f) {
     return 0.5 * (G[(size_t)f * N + (size_t)yp * nx + x] - G[(size_t)f * N + (size_t)ym * nx + x]);
   };
-  const double Sx = p.kappa * (dX(F_MXX) + dY(F_MXY));
-  const double Sy = p.kappa * (dX(F_MXY) + dY(F_MYY));
+  // Taylor form: kappa div M of this step's M; shifted form: the Q-sum the
+  // spring-sum pass formed from this step's psi (F_MXX, F_MXY slots)
+  const double Sx = p.shift ? G[(size_t)F_MXX * N + r] : p.kappa * (dX(F_MXX) + dY(F_MXY));
+  const double Sy = p.shift ? G[(size_t)F_MXY * N + r] : p.kappa * (dX(F_MXY) + dY(F_MYY));
   double Fbx = p.F0 * sin(p.kf * (double)(y + p.y0)), Fby = 0.0;
   if (p.src != nullptr) {
     Fbx += p.src[r];
@@ -1067,20 +1101,30 @@ __global__ void k_pre_u_batch(const InstDev *__restrict__ inst, int ninst, int n
 }
 
 template <typename T>
+hipError_t launch_spring_sum_batch(const InstDev *inst, int ninst, int nitems, int grid,
+                                   int parity, hipStream_t s);
+
+template <typename T>
 hipError_t launch_same_step_fields_batch(const InstDev *inst, int ninst, int nitems, int nqd,
-                                         int parity, int ip, hipStream_t s) {
+                                         int parity, int ip, bool shift, hipStream_t s) {
   if (ip < 0 || ip > 2 || nitems < 1 || nqd < 1 || nqd > 65535) return hipErrorInvalidValue;
   const unsigned g = (unsigned)(nitems < 16384 ? nitems : 16384);
   hipLaunchKernelGGL(k_pre_psi_batch<T>, dim3(g, (unsigned)nqd), dim3(64), 0, s, inst, ninst,
                      nitems, parity, ip);
-  hipLaunchKernelGGL(k_pre_m_batch<T>, dim3(g), dim3(64), 0, s, inst, ninst, nitems, parity);
+  if (shift) {  // the Q-sum of the shifted spring term of this step's psi
+    const hipError_t e =
+        launch_spring_sum_batch<T>(inst, ninst, nitems, nitems < 4096 ? nitems : 4096, parity, s);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_pre_m_batch<T>, dim3(g), dim3(64), 0, s, inst, ninst, nitems, parity);
+  }
   hipLaunchKernelGGL(k_pre_u_batch<T>, dim3(g), dim3(64), 0, s, inst, ninst, nitems, parity, ip);
   return hipGetLastError();
 }
 template hipError_t launch_same_step_fields_batch<double>(const InstDev *, int, int, int, int, int,
-                                                          hipStream_t);
+                                                          bool, hipStream_t);
 template hipError_t launch_same_step_fields_batch<float>(const InstDev *, int, int, int, int, int,
-                                                         hipStream_t);
+                                                         bool, hipStream_t);
 
 // One 64-node tile per workgroup, kSpringSlices waves each summing every
 // kSpringSlices-th Q-node; the slices' partial sums are added in slice order
@@ -1208,7 +1252,12 @@ hipError_t launch_same_step_fields(const StepParams &p, StateT<T> a, StepRef ref
   const unsigned nb = (unsigned)((p.N + 255) / 256);
   hipLaunchKernelGGL(k_pre_psi<T>, dim3(nb, (unsigned)p.nqd), dim3(256), 0, s, p, a, ref.pull,
                      ref.psi, qtab, ip);
-  hipLaunchKernelGGL(k_pre_m<T>, dim3(nb), dim3(256), 0, s, p, a, ref.psi, qtab);
+  if (p.shift) {  // the Q-sum of the shifted spring term of this step's psi
+    const hipError_t e = launch_spring_sum<T>(p, a, ref, qtab, s);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_pre_m<T>, dim3(nb), dim3(256), 0, s, p, a, ref.psi, qtab);
+  }
   hipLaunchKernelGGL(k_pre_u<T>, dim3(nb), dim3(256), 0, s, p, a, ref.spull, ip);
   return hipGetLastError();
 }

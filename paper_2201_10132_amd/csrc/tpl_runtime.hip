@@ -81,9 +81,8 @@ int derive(const Config &c, Derived &d) {
     return fail(TPL_EINVAL, "same-step gradients are for the FP64 and FP32 forms");
   if (c.spring_shift != 0 && c.spring_shift != 1)
     return fail(TPL_EINVAL, "spring_shift must be 0 or 1");
-  if (c.spring_shift && (c.precision == TPL_BF16NEQ || c.inplace || c.gradients))
-    return fail(TPL_EINVAL, "the shifted spring term is for two-array FP64 and FP32 storage "
-                            "with lagged gradients");
+  if (c.spring_shift && c.precision == TPL_BF16NEQ)
+    return fail(TPL_EINVAL, "the shifted spring term is for the FP64 and FP32 forms");
   // the step kernel addresses a plane with 32-bit byte offsets: 8 N < 2^32
   if ((long long)c.nx * c.ny >= (1LL << 29)) return fail(TPL_EINVAL, "lattice too large");
 
@@ -486,7 +485,7 @@ hipError_t enqueue_step(const tpl_ctx *x, const Buffers &B, const StepParams &p,
   if (B.esize == 4) {
     if (x->c.gradients) e = launch_same_step_fields<float>(p, B.half<float>(cur), ref, x->qtab_d,
                                                            x->stream, ip);
-    if (e == hipSuccess && p.shift)
+    if (e == hipSuccess && p.shift && !x->c.gradients)
       e = launch_spring_sum<float>(p, B.half<float>(cur), ref, x->qtab_d, x->stream);
     if (e == hipSuccess)
       e = launch_step<float>(p, B.half<float>(cur), B.half<float>(1 - cur), ref, x->qtab_d,
@@ -494,7 +493,7 @@ hipError_t enqueue_step(const tpl_ctx *x, const Buffers &B, const StepParams &p,
   } else {
     if (x->c.gradients) e = launch_same_step_fields<double>(p, B.half<double>(cur), ref,
                                                             x->qtab_d, x->stream, ip);
-    if (e == hipSuccess && p.shift)
+    if (e == hipSuccess && p.shift && !x->c.gradients)
       e = launch_spring_sum<double>(p, B.half<double>(cur), ref, x->qtab_d, x->stream);
     if (e == hipSuccess)
       e = launch_step<double>(p, B.half<double>(cur), B.half<double>(1 - cur), ref, x->qtab_d,
@@ -1006,10 +1005,15 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
       // gradients add a second read of the polymer populations, psi written
       // and read, the solvent read and 17 FP64 field values per node; the
       // shifted spring term a second read of psi and its Q-sum written (the
-      // step reads the sum where it would read M)
+      // step reads the sum where it would read M); both together: the M pass
+      // is the spring-sum pass, and the velocity pass reads the sum (13
+      // values per node instead of 17, psi read once less)
       {"bytes_per_step",
        N * (2.0 * es * (9 + d.nqd) + 2.0 * (xq + ms) * d.nqd + 8.0 * 2.0 * NF) +
-           (x->c.gradients ? N * (xq * d.nqd + 2.0 * es * d.nqd + 9.0 * es + 136.0) : 0.0) +
+           (x->c.gradients ? N * (xq * d.nqd + 9.0 * es +
+                                  (x->c.spring_shift ? es * d.nqd + 104.0
+                                                     : 2.0 * es * d.nqd + 136.0))
+                           : 0.0) +
            (x->c.spring_shift ? N * (es * d.nqd + 16.0) : 0.0)},
       {"kernel_ms", x->kernel_ms}, {"kernel_launches", (double)x->kernel_launches},
       {"qsplit_used", (double)x->qs_used},
@@ -1590,12 +1594,12 @@ hipError_t batch_launch(const tpl_batch *b, int esize, int ninst, int nitems, in
     for (const tpl_ctx *x : b->inst) nqd = x->d.nqd > nqd ? x->d.nqd : nqd;
     const hipError_t e =
         esize == 4 ? launch_same_step_fields_batch<float>(b->tab_d, ninst, nitems, nqd, parity, ip,
-                                                          b->stream)
+                                                          sh, b->stream)
                    : launch_same_step_fields_batch<double>(b->tab_d, ninst, nitems, nqd, parity,
-                                                           ip, b->stream);
+                                                           ip, sh, b->stream);
     if (e != hipSuccess) return e;
   }
-  if (sh) {
+  if (sh && !b->gradients) {  // (with same-step gradients formed above)
     const int sg = nitems < 4096 ? nitems : 4096;
     const hipError_t e =
         esize == 4 ? launch_spring_sum_batch<float>(b->tab_d, ninst, nitems, sg, parity, b->stream)

@@ -260,18 +260,14 @@ def test_same_step_gradients_knob():
     b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8),
                  dict(nx=32, ny=16, Re=20.0, Wi=0.5, beta=0.8)])
     b.instance(1).set_param("spring_shift", 1)
-    with pytest.raises(P.TplError):  # refused by the second: the first left as it was
-        b.set_param("gradients", 1)
-    assert [b.instance(i).query("gradients") for i in range(2)] == [0, 0]
     with pytest.raises(P.TplError):  # the instances' options differ from the batch's
         b.init()
-    b.close()
-    b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8)])
+    b.instance(1).set_param("spring_shift", 0)
+    b.instance(1).set_param("qe_model", 2)
     b.set_param("gradients", 1)  # forwarded to every instance
-    assert b.instance(0).query("gradients") == 1
-    with pytest.raises(P.TplError):
-        b.set_param("spring_shift", 1)  # not with same-step gradients
-    b.set_param("gradients", 0)
+    assert [b.instance(i).query("gradients") for i in range(2)] == [1, 1]
+    with pytest.raises(P.TplError):  # the batched step runs model (i) only
+        b.init()
     b.close()
 
 
@@ -281,16 +277,21 @@ def test_spring_shift_knob():
     b0 = t.query("bytes_per_step")
     t.set_param("spring_shift", 1)
     assert t.query("bytes_per_step") == b0 + N * (8 * nqd + 16)
-    for k, v in (("inplace", 1), ("gradients", 1), ("precision", P.TPL_BF16NEQ),
-                 ("spring_shift", 2)):
+    for k, v in (("precision", P.TPL_BF16NEQ), ("spring_shift", 2)):
         with pytest.raises(P.TplError):
             t.set_param(k, v)
+    # with same-step gradients the M pass is the spring-sum pass: psi read
+    # once less and 13 field values per node instead of 17
+    t.set_param("gradients", 1)
+    assert t.query("bytes_per_step") == b0 + N * (8 * nqd + 16) + N * (200 * nqd + 8 * nqd
+                                                                       + 72 + 104)
+    t.set_param("inplace", 1)
     t.set_param("precision", P.TPL_FP32)
     t.close()
     b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8)])
     b.set_param("spring_shift", 1)  # forwarded to every instance
     assert b.instance(0).query("spring_shift") == 1
-    with pytest.raises(P.TplError):
-        b.set_param("inplace", 1)  # not with the shifted spring term
-    assert b.instance(0).query("inplace") == 0
+    b.set_param("inplace", 1)
+    b.set_param("gradients", 1)
+    assert b.instance(0).query("inplace") == 1 and b.instance(0).query("gradients") == 1
     b.close()

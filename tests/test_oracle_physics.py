@@ -341,9 +341,10 @@ def test_spring_term_fourier_symbol(shift):
     assert np.abs(s1 - 1j * k * Q[:, 0]).max() < 0.5 * (k * 8) ** 2 * k * 8
 
 
+@pytest.mark.parametrize("gradients", [0, 1])
 @pytest.mark.parametrize("spring", [0, 1])
-def test_conservation_with_shifted_spring_term(spring):
-    sim = oracle.OracleSim(16, 16, nq=6, spring=spring, spring_shift=1)
+def test_conservation_with_shifted_spring_term(spring, gradients):
+    sim = oracle.OracleSim(16, 16, nq=6, spring=spring, spring_shift=1, gradients=gradients)
     sim.base_state(300)
     sim.perturb(seed=3, amp=0.05, multimode=True)
     d0 = sim.diagnostics()
@@ -354,3 +355,33 @@ def test_conservation_with_shifted_spring_term(spring):
     assert abs(d1["mass_P"] / d0["mass_P"] - 1) < 1e-13
     for c in ("mom_x", "mom_y"):
         assert abs(d1[c] - d0[c]) < 1e-12 * pabs
+
+
+def test_shift_with_same_step_gradients_on_uniform_polymer():
+    """Polymer populations uniform in r (solvent sheared): this step's psi
+    is uniform, so the shifted and the Taylor spring terms both vanish and
+    one same-step step gives the same state in both forms; after a second
+    step, once psi varies, the two differ."""
+    nx, ny = 8, 8
+    states = []
+    for shift in (0, 1):
+        sim = oracle.OracleSim(nx, ny, nq=6, Wi=0.8, spring_shift=shift, gradients=1)
+        t = sim.tables(); d = sim.derived()
+        y = np.arange(ny)
+        u = 1e-2 * np.sin(2 * np.pi * y / ny)
+        XS = np.stack([oracle.OracleSim.solvent_eq(d["rhoS0"], uj, 0.0) for uj in u], axis=1)
+        XS = np.repeat(XS[:, :, None], nx, axis=2)
+        psi0 = d["rhoP0"] * t["peq"]
+        XP = np.broadcast_to((t["wP"][:, None] * psi0[None, :])[:, :, None, None],
+                             (25, sim.nqd, ny, nx)).copy()
+        U = np.zeros((2, ny, nx)); U[0] = u[:, None]
+        psi = np.broadcast_to(psi0[:, None, None], (sim.nqd, ny, nx)).copy()
+        sim.set_state(XS=XS, XP=XP, psi=psi, U=U)
+        sim.step(1)
+        one = sim.get_state()
+        sim.step(1)
+        states.append((one, sim.get_state()))
+    for k in ("XS", "XP", "psi", "U"):
+        a, b = states[0][0][k], states[1][0][k]
+        assert np.abs(a - b).max() <= 1e-15 * max(np.abs(a).max(), 1e-3), k
+    assert np.abs(states[0][1]["XP"] - states[1][1]["XP"]).max() > 0
