@@ -220,10 +220,24 @@ __device__ __forceinline__ double spring_shift_diff(const T *P, int x, int y, in
   };
   // + side: floor(Q/2) and the next node; - side: floor(-Q/2) = -floor(Q/2) - 1
   // (Q/2 is never an integer: Q-nodes sit at half-integers), weights swapped
-  const int xp0 = wrap_to(x + ix, nx), xp1 = wrap_to(x + ix + 1, nx);
-  const int yp0 = wrap_to(y + iy, ny), yp1 = wrap_to(y + iy + 1, ny);
-  const int xm0 = wrap_to(x - ix - 1, nx), xm1 = wrap_to(x - ix, nx);
-  const int ym0 = wrap_to(y - iy - 1, ny), ym1 = wrap_to(y - iy, ny);
+  int xp0, xp1, yp0, yp1, xm0, xm1, ym0, ym1;
+  if ((ix < 0 ? -ix : ix) + 2 <= nx && (iy < 0 ? -iy : iy) + 2 <= ny) {
+    // offsets shorter than the lattice (wave-uniform test): every index lies
+    // in [-n, 2n), one conditional add or subtract wraps it
+    auto wr = [](int v, int n) {
+      v = v < 0 ? v + n : v;
+      return v >= n ? v - n : v;
+    };
+    xp0 = wr(x + ix, nx); xp1 = wr(x + ix + 1, nx);
+    yp0 = wr(y + iy, ny); yp1 = wr(y + iy + 1, ny);
+    xm0 = wr(x - ix - 1, nx); xm1 = wr(x - ix, nx);
+    ym0 = wr(y - iy - 1, ny); ym1 = wr(y - iy, ny);
+  } else {
+    xp0 = wrap_to(x + ix, nx); xp1 = wrap_to(x + ix + 1, nx);
+    yp0 = wrap_to(y + iy, ny); yp1 = wrap_to(y + iy + 1, ny);
+    xm0 = wrap_to(x - ix - 1, nx); xm1 = wrap_to(x - ix, nx);
+    ym0 = wrap_to(y - iy - 1, ny); ym1 = wrap_to(y - iy, ny);
+  }
   const double vp = (1.0 - fx) * (1.0 - fy) * at(xp0, yp0) + fx * (1.0 - fy) * at(xp1, yp0) +
                     (1.0 - fx) * fy * at(xp0, yp1) + fx * fy * at(xp1, yp1);
   const double vm = fx * fy * at(xm0, ym0) + (1.0 - fx) * fy * at(xm1, ym0) +
@@ -1144,6 +1158,7 @@ __global__ void __launch_bounds__(64 * kSpringSlices)
   const int nx = p.nx, ny = p.ny, nqd = p.nqd;
   const int y = r / nx, x = r - y * nx;
   double Sx = 0.0, Sy = 0.0;
+#pragma unroll 2
   for (int q = slice; q < nqd; q += kSpringSlices) {
     const QNode CONSTANT_AS &qn = cst(qtab)[q];
     const double d = spring_shift_diff(a.PSI + (size_t)q * N, x, y, nx, ny, qn.qx, qn.qy,
@@ -1208,6 +1223,7 @@ __global__ void __launch_bounds__(64 * kSpringSlices)
     const int r = (int)(rr < N ? rr : N - 1);
     const int y = r / nx, x = r - y * nx;
     double Sx = 0.0, Sy = 0.0;
+#pragma unroll 2
     for (int q = slice; q < nqd; q += kSpringSlices) {
       const QNode CONSTANT_AS &qn = cst(qtab)[q];
       const double dd = spring_shift_diff(PSI + (size_t)q * N, x, y, nx, ny, qn.qx, qn.qy,

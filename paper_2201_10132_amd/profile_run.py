@@ -33,6 +33,8 @@ def main():
     ap.add_argument("--batch-nq", type=int, default=6, help="Q points per axis of the batched sweep")
     ap.add_argument("--periods", type=int, default=4)
     ap.add_argument("--inplace", type=int, default=0, help="1: one population array")
+    ap.add_argument("--spring-shift", type=int, default=0, help="1: the shifted spring term")
+    ap.add_argument("--gradients", type=int, default=0, help="1: same-step gradients")
     ap.add_argument("--group-x", type=int, default=0,
                     help="tile group of the single-lattice step (0: the autotuner's choice)")
     ap.add_argument("--group-y", type=int, default=1)
@@ -65,6 +67,10 @@ def main():
         t.set_param("precision", args.precision)
     if args.inplace:
         t.set_param("inplace", 1)
+    if args.spring_shift:
+        t.set_param("spring_shift", 1)
+    if args.gradients:
+        t.set_param("gradients", 1)
     if args.group_x:
         t.set_param("autotune", 0)
         t.set_param("group_y", 1)
