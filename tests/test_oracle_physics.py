@@ -385,3 +385,33 @@ def test_shift_with_same_step_gradients_on_uniform_polymer():
         a, b = states[0][0][k], states[1][0][k]
         assert np.abs(a - b).max() <= 1e-15 * max(np.abs(a).max(), 1e-3), k
     assert np.abs(states[0][1]["XP"] - states[1][1]["XP"]).max() > 0
+
+
+def _fene_rest_qrms(drift_cap, nq=32, lam=28.6479, steps=1500):
+    """RMS extension / R of a FENE polymer at rest (no flow, no forcing) after
+    many relaxation times, and that of the sampled FENE rest distribution."""
+    o = oracle.OracleSim(1, 8, nq=nq, Re=3.5, Wi=0.1, beta=0.5, periods=2, u0=0.01,
+                         force_scale=0.0, drift_cap=drift_cap, lambda_set=lam)
+    d, t = o.derived(), o.tables()
+    q2 = (t["Q"] ** 2).sum(1)
+    R = np.sqrt(25.0) * d["sigma"]
+    o.base_state(0)
+    o.step(steps)
+    psi = o.get_state()["psi"][:, 0, 0]
+    return (np.sqrt((psi * q2).sum() / psi.sum()) / R, np.sqrt((t["peq"] * q2).sum()) / R,
+            d["tau2P"])
+
+
+def test_fene_rest_distribution_is_kept_with_a_loose_drift_cap():
+    """The FENE rest distribution (1 - Q^2/R^2)^(b/2) balances Q-diffusion and
+    the spring drift: at rest the lattice keeps its RMS extension when the
+    drift is not capped, or capped at 0.2 per step (the 72^2 experiment's
+    reading); at tau2_P = 0.54 (its Wi = 0.1 cell) a cap of 0.1 binds two
+    sigma out and inflates the extension by more than 10 %."""
+    free, eq, tau2 = _fene_rest_qrms(0.0)
+    assert abs(tau2 - 0.536) < 1e-3
+    assert abs(free / eq - 1) < 3e-3
+    loose, _, _ = _fene_rest_qrms(0.2)
+    assert abs(loose / eq - 1) < 1e-2
+    tight, _, _ = _fene_rest_qrms(0.1)
+    assert tight / eq - 1 > 0.1
