@@ -117,7 +117,12 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *   tau_ratio_p 1 polymer tau1 / tau2
  *   force_scale 1 multiplies F0
  *   lambda 0      > 0: polymer relaxation time in steps instead of Wi l / u0
- *   drift_cap 0.1 cap on the Q-drift D_Q |F/kT| per step (0 = none)
+ *   drift_cap 0.1 cap on the Q-drift D_Q |F/kT| per step (0 = none); it
+ *                 keeps the linear Q-space equilibrium positive near the
+ *                 FENE singularity.  Where tau2_P is large (about 0.5) it
+ *                 binds inside the bulk of the FENE rest distribution and
+ *                 stretches it; up to about 0.3 (below c_s^2 = 1/3) the
+ *                 equilibrium stays positive
  *   drift_relax 1 also cap that drift at drift_relax (2 - omega_P), the
  *                 damping rate of the polymer's non-conserved moments,
  *                 omega_P = 2 / (2 tau1_P + 1) (0 = none)
