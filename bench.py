@@ -105,7 +105,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the lattice would shard as y-slabs; see DESIGN.md)", file=sys.stderr)
+              "(the lattice would shard as y-slabs, one per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch
