@@ -131,7 +131,9 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *                 tau2_S = tau_drag, D_Q = c_s^2 tau2_P); 2 = component
  *                 stresses quasi-conserved (viscosity c_s^2 tau2_S, drag time
  *                 tau1_S = tau_drag <= tau2_S, D_Q = c_s^2 tau1_P,
- *                 tau2_P = tau1_P / tau_ratio_p); not for batches
+ *                 tau2_P = tau1_P / tau_ratio_p); in a batch every
+ *                 instance takes the same model, model (ii) with
+ *                 spring_shift 0
  *   precision 0   TPL_FP64, TPL_FP32 or TPL_BF16NEQ population storage
  *   inplace 0     1 = one population array instead of two, streamed in place
  *                 (Sec. VI streaming and Q-disk bounce-back, by the AA

@@ -148,11 +148,12 @@ hipError_t launch_tile_dev(int planes, int nx, int ny, const double *col,
                            const float *ref, float *dst, hipStream_t s);
 // group > 1 (qs == 1 only): consecutive items per workgroup, one wave each.
 // ip = 1, 2: the in-place step kinds (every instance in place; qs == 1,
-// whole tiles), 0: two arrays.
+// whole tiles), 0: two arrays.  qe2: every instance runs model (ii) (the
+// stress quasi-equilibria; not with shift).
 template <typename T>
 hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs, int grid,
                              bool rowtile, int parity, hipStream_t s, int group = 1,
-                             int ip = 0, bool shift = false);
+                             int ip = 0, bool shift = false, bool qe2 = false);
 // The shifted spring term's Q-sum for every item of a batch (before
 // launch_step_batch with shift; grid workgroups of eight waves walk the items).
 template <typename T>

@@ -713,7 +713,8 @@ __global__ void __launch_bounds__(MAXT)
 // in the caches; units of `group` items are what the grid and the XCD
 // mapping count.  IP != 0: every instance streams in place (step_tile);
 // SHIFT: the shifted spring term, its Q-sum formed by k_spring_sum_batch.
-template <typename T, int MAXT, bool ROWTILE, int IP = 0, bool SHIFT = false>
+// QE2: the stress quasi-equilibria (model (ii)) for every instance.
+template <typename T, int MAXT, bool ROWTILE, int IP = 0, bool SHIFT = false, bool QE2 = false>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)))
     k_step_batch(const InstDev *__restrict__ inst, int ninst, int nitems, int items_per_xcd,
                  int parity, int group) {
@@ -744,15 +745,20 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)
     TPL_LD(F0) TPL_LD(kf) TPL_LD(src)
 #undef TPL_LD
     pp.wg = 0;
-    pp.qe = 1;
+    pp.qe = QE2 ? 2 : 1;
     pp.shift = 0;
-    pp.pS = pp.pP = 0.0;
+    if constexpr (QE2) {
+      pp.pS = d.p.pS;
+      pp.pP = d.p.pP;
+    } else {
+      pp.pS = pp.pP = 0.0;
+    }
     const int rd = parity ^ d.cur0;
     const StateT<T> a{static_cast<T *>(d.XS[rd]), static_cast<T *>(d.XP[rd]),
                       static_cast<T *>(d.PSI[rd]), d.FLD[rd]};
     const StateT<T> b{static_cast<T *>(d.XS[rd ^ 1]), static_cast<T *>(d.XP[rd ^ 1]),
                       static_cast<T *>(d.PSI[rd ^ 1]), d.FLD[rd ^ 1]};
-    step_tile<T, ROWTILE, false, false, IP, SHIFT>(pp, a, b, d.rpull, d.rstore, d.rpsi,
+    step_tile<T, ROWTILE, false, QE2, IP, SHIFT>(pp, a, b, d.rpull, d.rstore, d.rpsi,
                                                    d.rspull, d.rsstore, d.qtab, item - d.item0,
                                                    red);
   }
@@ -761,12 +767,39 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)
 template <typename T>
 hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs, int grid,
                              bool rowtile, int parity, hipStream_t s, int group, int ip,
-                             bool shift) {
+                             bool shift, bool qe2) {
   if (group < 1 || (group > 1 && qs != 1) || qs * group > 8) return hipErrorInvalidValue;
   const size_t lds = qs > 1 ? (size_t)qs * 12 * 64 * sizeof(double) : 0;
   const int nunits = (nitems + group - 1) / group;
   const int per_xcd = (grid % 8 == 0 && nunits >= 64) ? (nunits + 7) / 8 : 0;
   const dim3 g(grid), blk(64 * qs * group);
+  if (qe2) {
+    // model (ii): two arrays or in place, Taylor form of the spring term
+    if (shift) return hipErrorInvalidValue;
+    if (ip != 0) {
+      if ((ip != 1 && ip != 2) || qs != 1 || !rowtile) return hipErrorInvalidValue;
+#define TPL_BATCH_IP2(MAXT, IP)                                                               \
+  hipLaunchKernelGGL((k_step_batch<T, MAXT, true, IP, false, true>), g, blk, lds, s, inst,   \
+                     ninst, nitems, per_xcd, parity, group)
+      if (group <= 4) {
+        if (ip == 1) TPL_BATCH_IP2(256, 1); else TPL_BATCH_IP2(256, 2);
+      } else {
+        if (ip == 1) TPL_BATCH_IP2(512, 1); else TPL_BATCH_IP2(512, 2);
+      }
+#undef TPL_BATCH_IP2
+      return hipGetLastError();
+    }
+#define TPL_BATCH_QE2(MAXT, RT)                                                               \
+  hipLaunchKernelGGL((k_step_batch<T, MAXT, RT, 0, false, true>), g, blk, lds, s, inst, ninst, \
+                     nitems, per_xcd, parity, group)
+    if (qs * group <= 4) {
+      if (rowtile) TPL_BATCH_QE2(256, true); else TPL_BATCH_QE2(256, false);
+    } else {
+      if (rowtile) TPL_BATCH_QE2(512, true); else TPL_BATCH_QE2(512, false);
+    }
+#undef TPL_BATCH_QE2
+    return hipGetLastError();
+  }
   if (shift && ip != 0) {
     // the shifted spring term streamed in place: whole tiles, one Q-slice
     if ((ip != 1 && ip != 2) || qs != 1 || !rowtile) return hipErrorInvalidValue;
@@ -826,9 +859,9 @@ hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs,
   return hipGetLastError();
 }
 template hipError_t launch_step_batch<double>(const InstDev *, int, int, int, int, bool, int,
-                                              hipStream_t, int, int, bool);
+                                              hipStream_t, int, int, bool, bool);
 template hipError_t launch_step_batch<float>(const InstDev *, int, int, int, int, bool, int,
-                                             hipStream_t, int, int, bool);
+                                             hipStream_t, int, int, bool, bool);
 
 template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,

@@ -1522,6 +1522,7 @@ struct tpl_batch {
   int inplace = 0, ip_odd = 0, graph_ip = 0;
   int spring_shift = 0;  // the shifted spring term for every instance
   int gradients = 0;     // same-step gradients for every instance
+  bool qe2 = false;      // model (ii) for every instance (set at tpl_batch_init)
   double *scratch = nullptr;
   int scratch_n = 0;
   double kernel_ms = 0.0, tune_ms = 0.0;
@@ -1608,9 +1609,9 @@ hipError_t batch_launch(const tpl_batch *b, int esize, int ninst, int nitems, in
     if (e != hipSuccess) return e;
   }
   return esize == 4 ? launch_step_batch<float>(b->tab_d, ninst, nitems, qs, grid, rowtile, parity,
-                                               b->stream, group, ip, sh)
+                                               b->stream, group, ip, sh, b->qe2)
                     : launch_step_batch<double>(b->tab_d, ninst, nitems, qs, grid, rowtile,
-                                                parity, b->stream, group, ip, sh);
+                                                parity, b->stream, group, ip, sh, b->qe2);
 }
 
 // Enqueue n launches of the uploaded table with parities p0, p0^1, ...
@@ -2021,13 +2022,16 @@ int tpl_batch_set_stream(tpl_batch *b, void *hip_stream) {
 int tpl_batch_init(tpl_batch *b) {
   if (!b) return fail(TPL_EINVAL, "null batch");
   for (tpl_ctx *x : b->inst) {
-    if (x->c.qe_model != 1)
-      return fail(TPL_EINVAL, "the batched step runs the component-momentum model (qe_model 1)");
+    if (x->c.qe_model != b->inst[0]->c.qe_model)
+      return fail(TPL_EINVAL, "the instances of a batch share one qe_model");
+    if (x->c.qe_model == 2 && x->c.spring_shift)
+      return fail(TPL_EINVAL, "the batched step runs model (ii) with the Taylor spring term");
     if (x->c.inplace != b->inplace || x->c.spring_shift != b->spring_shift ||
         x->c.gradients != b->gradients)
       return fail(TPL_EINVAL, "inplace, spring_shift and gradients are set for the whole batch "
                               "(tpl_batch_set_param)");
   }
+  b->qe2 = !b->inst.empty() && b->inst[0]->c.qe_model == 2;
   b->inited = false;
   drop_graph(b);
   if (!b->stream) {  // the batch's own stream, made on first use

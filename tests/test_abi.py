@@ -266,7 +266,7 @@ def test_same_step_gradients_knob():
     b.instance(1).set_param("qe_model", 2)
     b.set_param("gradients", 1)  # forwarded to every instance
     assert [b.instance(i).query("gradients") for i in range(2)] == [1, 1]
-    with pytest.raises(P.TplError):  # the batched step runs model (i) only
+    with pytest.raises(P.TplError):  # the instances of a batch share one model
         b.init()
     b.close()
 
@@ -294,4 +294,24 @@ def test_spring_shift_knob():
     b.set_param("inplace", 1)
     b.set_param("gradients", 1)
     assert b.instance(0).query("inplace") == 1 and b.instance(0).query("gradients") == 1
+    b.close()
+
+
+def test_batch_model2_rules():
+    """A batch runs one quasi-equilibrium model for all its instances, and
+    model (ii) with the Taylor form of the spring term; both are checked
+    before anything is allocated."""
+    from tests import inputs
+    b = P.Batch(inputs.c4_instances(2), precision=1, nq=4, pre_steps=10)
+    b.instance(1).set_param("qe_model", 2)
+    b.instance(1).set_param("tau_drag", 1e-3)
+    with pytest.raises(P.TplError) as e:
+        b.init()
+    assert "qe_model" in str(e.value)
+    b.close()
+    b = P.Batch(inputs.c4_instances(2), precision=1, nq=4, pre_steps=10, qe_model=2,
+                tau_drag=1e-3, spring_shift=1)
+    with pytest.raises(P.TplError) as e:
+        b.init()
+    assert "Taylor" in str(e.value)
     b.close()

@@ -345,3 +345,45 @@ def test_batch_same_step_gradients_match_single_contexts(insts, precision, inpla
         o.step(10)
         compare_states(b.instance(0).get_state(), o.get_state(), 1e-12)
     b.close()
+
+
+def _model2_params(d):
+    nuS = oracle.OracleSim(d["nx"], d["ny"], Re=d["Re"], Wi=d["Wi"], beta=d["beta"],
+                           periods=d["periods"]).derived()["nuS"]
+    return dict(qe_model=2, tau_drag=0.5 * nuS * 3.0)
+
+
+@pytest.mark.parametrize("insts,precision,inplace",
+                         [(MIXED, P.TPL_FP64, 0), (ROWS, P.TPL_FP32, 0), (ROWS, P.TPL_FP64, 1)],
+                         ids=["mixed-fp64", "rows-fp32", "rows-fp64-inplace"])
+def test_batch_model2_matches_single_contexts(insts, precision, inplace):
+    """Model (ii) (stress quasi-equilibria) in the batched step, each instance
+    with its own drag time: every instance equals a context of its own with
+    the same options and Q-slice count, bitwise, through graph replays and
+    the base-state columns, also in place; and the oracle on the first
+    instance (FP64)."""
+    extra = [_model2_params(d) for d in insts]
+    b = P.Batch(insts, precision=precision, nq=6, pre_steps=30, autotune=0, qsplit=1,
+                group=4 if inplace else 1, graph_steps=4, inplace=inplace)
+    for i, e in enumerate(extra):
+        for k, v in e.items():
+            b.instance(i).set_param(k, v)
+    b.init()
+    b.step(10)
+    for i, d in enumerate(insts):
+        print(f"model (ii) batch: instance {i}", flush=True)
+        t = _single(d, precision, nq=6, pre_steps=30, qsplit=1, autotune=0, inplace=inplace,
+                    **extra[i])
+        t.step(10)
+        diff = _states_equal(b.instance(i).get_state(), t.get_state())
+        assert all(v == 0.0 for v in diff.values()), (i, diff)
+        t.close()
+    if precision == P.TPL_FP64:
+        d = insts[0]
+        o = oracle.OracleSim(d["nx"], d["ny"], nq=6, Re=d["Re"], Wi=d["Wi"], beta=d["beta"],
+                             periods=d["periods"], **extra[0])
+        o.base_state(30)
+        o.perturb(d["seed"], d["perturbation"], True)
+        o.step(10)
+        compare_states(b.instance(0).get_state(), o.get_state(), 1e-12)
+    b.close()

@@ -110,12 +110,3 @@ def test_model2_tile_groups_bitwise():
     a, b = run(None), run((4, 2))
     for k in a:
         assert np.array_equal(a[k], b[k]), k
-
-
-def test_batch_rejects_model2():
-    from tests import inputs
-    b = P.Batch(inputs.c4_instances(2), precision=1, nq=4, pre_steps=10, qe_model=2,
-                tau_drag=1e-3)
-    with pytest.raises(P.TplError):
-        b.init()
-    b.close()
