@@ -278,7 +278,7 @@ def measure_batch(torch, n, steps, warmup, pre_steps, obo_steps) -> dict:
     import math
 
     import paper_2201_10132_amd as P
-    from tests import inputs
+    from paper_2201_10132_amd import inputs
 
     insts = inputs.c4_instances(n)
     stream = torch.cuda.Stream()
@@ -342,7 +342,7 @@ def measure_batch_inplace(torch, nq, steps, warmup, pre_steps) -> dict:
     population array each): at the sweep's NQ beside the two-array batch,
     and at NQ 10, where two arrays (404 GB) would not fit one GPU."""
     import paper_2201_10132_amd as P
-    from tests import inputs
+    from paper_2201_10132_amd import inputs
 
     insts = inputs.c4_instances(BATCH["instances"])
     stream = torch.cuda.Stream()
@@ -391,7 +391,7 @@ def measure_learned(torch, pre_steps) -> dict:
     coarse steps), a 256^2 coarse lattice (4x restriction), 40 epochs of
     Adam; judged on held-out seeds 2000-2003 over 400 fine steps."""
     import paper_2201_10132_amd.learned as LL
-    from tests import inputs
+    from paper_2201_10132_amd import inputs
 
     c = LEARNED
     t0 = time.perf_counter()

@@ -106,7 +106,8 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
 
 /* Set a parameter before tpl_init (TPL_ESTATE afterwards, except for the
  * launch/timing knobs qsplit, group_x, group_y, group_sync, autotune and
- * time_kernels, which may be set at any time and change no result;
+ * time_kernels and the health-check knobs diag_every and psi_floor, which
+ * may be set at any time and change no result;
  * TPL_EINVAL for an unknown key or a value out of range).  Keys and defaults:
  *   nq 16         Q points per axis (even, 4..48)
  *   spring 0      0 = FENE (Warner), 1 = Hookean
@@ -117,12 +118,13 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *   tau_ratio_p 1 polymer tau1 / tau2
  *   force_scale 1 multiplies F0
  *   lambda 0      > 0: polymer relaxation time in steps instead of Wi l / u0
- *   drift_cap 0.1 cap on the Q-drift D_Q |F/kT| per step (0 = none); it
+ *   drift_cap 0.2 cap on the Q-drift D_Q |F/kT| per step (0 = none); it
  *                 keeps the linear Q-space equilibrium positive near the
- *                 FENE singularity.  Where tau2_P is large (about 0.5) it
- *                 binds inside the bulk of the FENE rest distribution and
- *                 stretches it; up to about 0.3 (below c_s^2 = 1/3) the
- *                 equilibrium stays positive
+ *                 FENE singularity, which needs a drift below c_s^2 = 1/3
+ *                 per step less the flow term K Q; 0.2 leaves that room.
+ *                 A tighter cap binds inside the bulk of the FENE rest
+ *                 distribution where tau2_P is large (0.1 stretches it by
+ *                 18 % at tau2_P = 0.54)
  *   drift_relax 1 also cap that drift at drift_relax (2 - omega_P), the
  *                 damping rate of the polymer's non-conserved moments,
  *                 omega_P = 2 / (2 tau1_P + 1) (0 = none)
@@ -183,6 +185,14 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *                 the full lattice (a few idempotent launches; tune_ms) and
  *                 keep the fastest; every shape gives bitwise the same step
  *   time_kernels 0  1 = time every step-kernel launch with HIP events
+ *   diag_every 0  tpl_step checks the state's health every diag_every steps
+ *                 (0: once, after its last step) and stops at the first
+ *                 failed check (see tpl_step)
+ *   psi_floor 0.1 tolerance of that check on the polymer density: the state
+ *                 fails if min psi < -psi_floor max psi over all (r, Q)-nodes.
+ *                 The linear Q-space equilibrium does not keep psi positive:
+ *                 in healthy FENE runs the outermost Q-nodes hold psi down to
+ *                 about -1e-2 max psi; a diverging run goes far below
  * Any parameter also fixes the derived values read by tpl_query. */
 int tpl_set_param(tpl_ctx *ctx, const char *key, double value);
 
@@ -218,8 +228,13 @@ int tpl_adopt_buffers(tpl_ctx *ctx, void *const *dptrs, const size_t *bytes,
 int tpl_init(tpl_ctx *ctx, uint64_t seed, double perturbation);
 
 /* Advance n >= 0 time steps.  Enqueued on the bound stream; synchronises
- * before returning.  Returns TPL_EUNSTABLE if the mixture velocity holds a
- * NaN or Inf afterwards. */
+ * before returning.  After every diag_every steps (after the last step if
+ * diag_every is 0) a health check reads the mixture velocity and psi of
+ * every (r, Q)-node: if any is NaN or Inf, or min psi < -psi_floor max psi
+ * (psi is a density of dumbbell configurations, Sec. VI.B), the call returns
+ * TPL_EUNSTABLE at once, with the state and the step counter (tpl_query key
+ * step) of that check and the cause in tpl_last_error; the state is not
+ * rolled back (tpl_save / tpl_load restore a checkpoint). */
 int tpl_step(tpl_ctx *ctx, int64_t n);
 
 /* Observables of the last completed step (step 0 = the initial state), SoA
@@ -339,10 +354,11 @@ int tpl_batch_set_stream(tpl_batch *b, void *hip_stream);
  * 12 bytes per node of working memory).  Synchronises before returning. */
 int tpl_batch_init(tpl_batch *b);
 
-/* Advance every active instance n >= 0 steps, then check each for NaN/Inf:
- * an instance that diverged is flagged (tpl_batch_status), dropped from
- * later launches and keeps its last state; the others go on.  Returns TPL_OK
- * unless a call fails.  Synchronises before returning. */
+/* Advance every active instance n >= 0 steps, then check each as tpl_step
+ * does (NaN/Inf, psi below -psi_floor max psi of that instance): an instance
+ * that fails is flagged (tpl_batch_status), dropped from later launches and
+ * keeps its last state; the others go on.  Returns TPL_OK unless a call
+ * fails.  Synchronises before returning. */
 int tpl_batch_step(tpl_batch *b, int64_t n);
 
 /* tpl_perturbation_amplitude of every instance (NaN for an unstable one);

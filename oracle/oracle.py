@@ -126,7 +126,7 @@ def splitmix64_next(state: int):
 
 DEFAULTS = dict(nq=16, periods=1, Re=20.0, Wi=0.5, beta=0.8, u0=0.05, phi=0.01,
                 spring=0, b=25.0, tau_drag=0.0, tau_ratio_p=1.0, force_scale=1.0,
-                lambda_set=0.0, ny_param=0, y_offset=0, x_offset=0, nx_param=0, drift_cap=0.1,
+                lambda_set=0.0, ny_param=0, y_offset=0, x_offset=0, nx_param=0, drift_cap=0.2,
                 drift_relax=1.0, qe_model=1, gradients=0, spring_shift=0)
 
 DIAG_NAMES = ["step", "mass_S", "mass_P", "mom_x", "mom_y", "amplitude",

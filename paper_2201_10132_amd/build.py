@@ -1,9 +1,12 @@
-"""Build libtpl.so (the HIP library behind include/tpl.h) for gfx950, in-tree."""
+"""Build libtpl.so (the HIP library behind include/tpl.h) for gfx950, in-tree.
+
+Each source is compiled to an object in parallel, then linked."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -11,7 +14,7 @@ LIB = os.path.join(HERE, "libtpl.so")
 SOURCES = ["tpl_runtime.hip", "tpl_kernels.hip", "tpl_learned.hip"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
@@ -20,12 +23,24 @@ HIPCC_FLAGS = [
 
 def build(extra_flags=None, out=LIB, verbose=False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = out + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *(extra_flags or []), "-o", tmp,
-           *[os.path.join(CSRC, s) for s in SOURCES]]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd, cwd=CSRC)
+    with tempfile.TemporaryDirectory(prefix="tplbuild") as tmpd:
+        procs, objs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpd, os.path.splitext(src)[0] + ".o")
+            cmd = [hipcc, *HIPCC_FLAGS, *(extra_flags or []), "-c", "-o", obj,
+                   os.path.join(CSRC, src)]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((cmd, subprocess.Popen(cmd, cwd=CSRC)))
+            objs.append(obj)
+        failed = [cmd for cmd, p in procs if p.wait() != 0]
+        if failed:
+            raise subprocess.CalledProcessError(1, failed[0])
+        tmp = out + ".tmp"
+        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd, cwd=CSRC)
     os.replace(tmp, out)
     return out
 

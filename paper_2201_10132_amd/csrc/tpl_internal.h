@@ -191,8 +191,12 @@ hipError_t launch_observables(int nqd, int nx, int ny, const QNode *qtab,
                               double inv_s2, double G, double mref,
                               StateT<T> a, RefView ref, double *out,
                               hipStream_t s);
-hipError_t launch_nan_check(long long N, const double *FLD, double *partial,
-                            int *nblocks, hipStream_t s);
+// Health of a state: out[0] = number of non-finite mixture velocities and
+// polymer densities, out[1] / out[2] = smallest / largest psi.  partial holds
+// 3 kHealthBlocks doubles.
+template <typename T>
+hipError_t launch_health(int nx, int ny, int nqd, StateT<T> a, RefView ref,
+                         double *partial, double *out, hipStream_t s);
 template <typename T>
 hipError_t launch_window(int nx, int ny, int nqd, int x0, int y0, int w, int h,
                          StateT<T> a, RefView ref, double *dst, hipStream_t s);
@@ -242,5 +246,7 @@ hipError_t launch_restrict(int planes, int nxf, int nyf, int m, const T *src, do
                            hipStream_t s);
 
 constexpr int kDiagComp = 8;  // massS massP momx momy enstrophy psiQ2 psi minpsi
+constexpr int kDiagBlocks = 1024;   // workgroups of the diagnostics reduction
+constexpr int kHealthBlocks = 1024;  // workgroups of the health check
 
 }  // namespace tplk

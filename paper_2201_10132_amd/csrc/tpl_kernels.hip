@@ -1597,26 +1597,51 @@ hipError_t launch_from_f64(int nx, int ny, int planes, const double *src,
   return hipGetLastError();
 }
 
-// Block-wide sum of one double (256 threads), fixed order.
-__device__ double block_sum256(double v, double *sh) {
-  sh[threadIdx.x] = v;
+// Workgroup reductions of one double per thread.  Each wavefront folds its
+// 64 lanes with cross-lane exchanges in a fixed butterfly order (every lane
+// ends with bitwise the same value, since a + b == b + a), then the
+// wavefront results are combined in wavefront order.  Deterministic; the
+// result is returned to every thread.  sh holds at least blockDim.x / 64
+// doubles.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ double block_sum(double v, double *sh) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double out = sh[0];
+  double out = sh[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) out += sh[w];
   __syncthreads();
   return out;
 }
-__device__ double block_min256(double v, double *sh) {
-  sh[threadIdx.x] = v;
+__device__ double block_min(double v, double *sh) {
+  v = wave_min(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + w]);
-    __syncthreads();
-  }
-  const double out = sh[0];
+  double out = sh[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) out = fmin(out, sh[w]);
+  __syncthreads();
+  return out;
+}
+__device__ double block_max(double v, double *sh) {
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double out = sh[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) out = fmax(out, sh[w]);
   __syncthreads();
   return out;
 }
@@ -1630,7 +1655,7 @@ __global__ void k_perturb_field(int nx, int ny, int x0, int y0, int NX, int NY,
                                 double amp_u0, int multimode,
                                 double *__restrict__ du,
                                 double *__restrict__ partial) {
-  __shared__ double sh[256];
+  __shared__ double sh[16];
   const long long N = (long long)nx * ny;
   const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
   double ux = 0.0, uy = 0.0;
@@ -1652,7 +1677,7 @@ __global__ void k_perturb_field(int nx, int ny, int x0, int y0, int NX, int NY,
     du[r] = ux;
     du[N + r] = uy;
   }
-  const double tot = block_sum256(ux * ux + uy * uy, sh);
+  const double tot = block_sum(ux * ux + uy * uy, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
@@ -1729,11 +1754,11 @@ template hipError_t launch_perturb_apply<float>(int, int, int, const double *,
 // out[c] = sum_i partial[i*ncomp + c] (one workgroup, fixed order).
 __global__ void k_sum(const double *__restrict__ partial, int n, int ncomp,
                       double *__restrict__ out) {
-  __shared__ double sh[256];
+  __shared__ double sh[16];
   for (int c = 0; c < ncomp; ++c) {
     double v = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) v += partial[(size_t)i * ncomp + c];
-    const double t = block_sum256(v, sh);
+    const double t = block_sum(v, sh);
     if (threadIdx.x == 0) out[c] = t;
   }
 }
@@ -1747,7 +1772,7 @@ hipError_t launch_sum(const double *partial, int n, int ncomp, double *out,
 // partial[y] = sum_x |U - <U>_x(y)|^2, one workgroup per row.
 __global__ void k_amplitude_rows(int nx, int ny, const double *__restrict__ FLD,
                                  double *__restrict__ partial) {
-  __shared__ double sh[256];
+  __shared__ double sh[16];
   const long long N = (long long)nx * ny;
   const int y = blockIdx.x;
   const double *ux = FLD + (size_t)F_UX * N + (size_t)y * nx;
@@ -1757,14 +1782,14 @@ __global__ void k_amplitude_rows(int nx, int ny, const double *__restrict__ FLD,
     sx += ux[x];
     sy += uy[x];
   }
-  const double mx = block_sum256(sx, sh) / nx;
-  const double my = block_sum256(sy, sh) / nx;
+  const double mx = block_sum(sx, sh) / nx;
+  const double my = block_sum(sy, sh) / nx;
   double acc = 0.0;
   for (int x = threadIdx.x; x < nx; x += 256) {
     const double dx = ux[x] - mx, dy = uy[x] - my;
     acc += dx * dx + dy * dy;
   }
-  const double t = block_sum256(acc, sh);
+  const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[y] = t;
 }
 
@@ -1780,7 +1805,7 @@ hipError_t launch_amplitude_rows(int nx, int ny, const double *FLD,
 template <typename T>
 __global__ void k_diag(int nx, int ny, int nqd, const QNode *__restrict__ qtab,
                        StateT<T> a, RefView ref, double *__restrict__ partial) {
-  __shared__ double sh[256];
+  __shared__ double sh[16];
   constexpr bool F32 = std::is_same<T, float>::value;
   const long long N = (long long)nx * ny;
   double v[kDiagComp] = {0, 0, 0, 0, 0, 0, 0, 1e300};
@@ -1813,10 +1838,10 @@ __global__ void k_diag(int nx, int ny, int nqd, const QNode *__restrict__ qtab,
     }
   }
   for (int c = 0; c < kDiagComp - 1; ++c) {
-    const double t = block_sum256(v[c], sh);
+    const double t = block_sum(v[c], sh);
     if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kDiagComp + c] = t;
   }
-  const double mn = block_min256(v[7], sh);
+  const double mn = block_min(v[7], sh);
   if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kDiagComp + 7] = mn;
 }
 
@@ -1826,7 +1851,7 @@ hipError_t launch_diag(int nx, int ny, int nqd, const QNode *qtab,
                        hipStream_t s) {
   const long long N = (long long)nx * ny;
   long long nb = (N + 255) / 256;
-  if (nb > 1024) nb = 1024;
+  if (nb > kDiagBlocks) nb = kDiagBlocks;
   *nblocks = (int)nb;
   hipLaunchKernelGGL(k_diag<T>, dim3((unsigned)nb), dim3(256), 0, s, nx, ny, nqd,
                      qtab, a, ref, partial);
@@ -1839,14 +1864,14 @@ template hipError_t launch_diag<float>(int, int, int, const QNode *, StateT<floa
 
 __global__ void k_diag_final(const double *__restrict__ partial, int n,
                              double *__restrict__ out) {
-  __shared__ double sh[256];
+  __shared__ double sh[16];
   for (int c = 0; c < kDiagComp; ++c) {
     double v = (c == kDiagComp - 1) ? 1e300 : 0.0;
     for (int i = threadIdx.x; i < n; i += 256) {
       const double p = partial[(size_t)i * kDiagComp + c];
       v = (c == kDiagComp - 1) ? fmin(v, p) : v + p;
     }
-    const double t = (c == kDiagComp - 1) ? block_min256(v, sh) : block_sum256(v, sh);
+    const double t = (c == kDiagComp - 1) ? block_min(v, sh) : block_sum(v, sh);
     if (threadIdx.x == 0) out[c] = t;
   }
 }
@@ -1908,30 +1933,75 @@ template hipError_t launch_observables<float>(int, int, int, const QNode *, doub
                                               double, StateT<float>, RefView, double *,
                                               hipStream_t);
 
-// Count non-finite mixture-velocity entries per workgroup into partial[], as
-// doubles, so that the generic sum kernel can reduce them.
-__global__ void k_nan_check(long long N, const double *__restrict__ FLD,
-                            double *__restrict__ partial) {
-  __shared__ double sh[256];
-  double bad = 0.0;
+// Health of a state, per workgroup into partial[3 block + c]: the number of
+// non-finite mixture velocities and polymer densities (c = 0), and the
+// smallest and largest polymer density psi over all (r, Q)-nodes (c = 1, 2).
+// psi is a density of dumbbell configurations (Sec. VI.B): a run whose psi
+// goes negative beyond round-off has lost positivity.
+template <typename T>
+__global__ void k_health(int nx, int ny, int nqd, StateT<T> a, RefView ref,
+                         double *__restrict__ partial) {
+  __shared__ double sh[16];
+  constexpr bool F32 = std::is_same<T, float>::value;
+  const long long N = (long long)nx * ny;
+  double bad = 0.0, mn = 1e300, mx = -1e300;
   for (long long r = (long long)blockIdx.x * 256 + threadIdx.x; r < N;
        r += (long long)gridDim.x * 256) {
-    const double ux = FLD[(size_t)F_UX * N + r], uy = FLD[(size_t)F_UY * N + r];
+    const double ux = a.FLD[(size_t)F_UX * N + r], uy = a.FLD[(size_t)F_UY * N + r];
     if (!isfinite(ux) || !isfinite(uy)) bad += 1.0;
+    const int y = (int)(r / nx);
+    for (int q = 0; q < nqd; ++q) {
+      const double ps = full(a.PSI[(size_t)q * N + r],
+                             F32 ? (double)ref.PSI[(size_t)q * ny + y] : 0.0);
+      if (!isfinite(ps)) bad += 1.0;
+      mn = fmin(mn, ps);
+      mx = fmax(mx, ps);
+    }
   }
-  const double t = block_sum256(bad, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  const double b = block_sum(bad, sh);
+  const double lo = block_min(mn, sh);
+  const double hi = block_max(mx, sh);
+  if (threadIdx.x == 0) {
+    partial[3 * (size_t)blockIdx.x] = b;
+    partial[3 * (size_t)blockIdx.x + 1] = lo;
+    partial[3 * (size_t)blockIdx.x + 2] = hi;
+  }
 }
 
-hipError_t launch_nan_check(long long N, const double *FLD, double *partial,
-                            int *nblocks, hipStream_t s) {
+__global__ void k_health_final(const double *__restrict__ partial, int n,
+                               double *__restrict__ out) {
+  __shared__ double sh[16];
+  double b = 0.0, mn = 1e300, mx = -1e300;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    b += partial[3 * (size_t)i];
+    mn = fmin(mn, partial[3 * (size_t)i + 1]);
+    mx = fmax(mx, partial[3 * (size_t)i + 2]);
+  }
+  b = block_sum(b, sh);
+  mn = block_min(mn, sh);
+  mx = block_max(mx, sh);
+  if (threadIdx.x == 0) {
+    out[0] = b;
+    out[1] = mn;
+    out[2] = mx;
+  }
+}
+
+template <typename T>
+hipError_t launch_health(int nx, int ny, int nqd, StateT<T> a, RefView ref,
+                         double *partial, double *out, hipStream_t s) {
+  const long long N = (long long)nx * ny;
   long long nb = (N + 255) / 256;
-  if (nb > 1024) nb = 1024;
-  *nblocks = (int)nb;
-  hipLaunchKernelGGL(k_nan_check, dim3((unsigned)nb), dim3(256), 0, s, N, FLD,
+  if (nb > kHealthBlocks) nb = kHealthBlocks;
+  hipLaunchKernelGGL(k_health<T>, dim3((unsigned)nb), dim3(256), 0, s, nx, ny, nqd, a, ref,
                      partial);
+  hipLaunchKernelGGL(k_health_final, dim3(1), dim3(256), 0, s, partial, (int)nb, out);
   return hipGetLastError();
 }
+template hipError_t launch_health<double>(int, int, int, StateT<double>, RefView, double *,
+                                          double *, hipStream_t);
+template hipError_t launch_health<float>(int, int, int, StateT<float>, RefView, double *,
+                                         double *, hipStream_t);
 
 // Gather a w x h window (periodic wrap) of XS, XP, PSI and U into
 // dst[plane][h][w] with planes 9 | 25 nqd | nqd | 2, as full FP64 values.

@@ -39,7 +39,7 @@ struct Config {
   double Re = 0, Wi = 0, beta = 1, u0 = 0.05;
   int nq = 16, spring = 0, precision = TPL_FP64, pert_modes = 1;
   double b = 25.0, phi = 0.01, tau_drag = 0.0, tau_ratio_p = 1.0;
-  double force_scale = 1.0, lambda_set = 0.0, drift_cap = 0.1, drift_relax = 1.0;
+  double force_scale = 1.0, lambda_set = 0.0, drift_cap = 0.2, drift_relax = 1.0;
   long long pre_steps = -1;
   int qsplit = 0, time_kernels = 0;
   int group_x = 1, group_y = 1, group_sync = 0, autotune = 1;
@@ -47,6 +47,8 @@ struct Config {
   int inplace = 0;  // one population array, streamed in place
   int gradients = 0;  // 0: lagged (previous step's) gradients; 1: same-step
   int spring_shift = 0;  // spring term: 0 Taylor form, 1 psi at r +- Q/2
+  long long diag_every = 0;  // health check every k steps of tpl_step (0: at its end)
+  double psi_floor = 0.1;    // unstable if min psi < -psi_floor max psi
 };
 
 struct Derived {
@@ -893,11 +895,146 @@ const Key kKeys[] = {
     {"autotune", nullptr, &Config::autotune, nullptr},
     {"u0", &Config::u0, nullptr, nullptr},
     {"periods", nullptr, &Config::periods, nullptr},
+    {"diag_every", nullptr, nullptr, &Config::diag_every},
+    {"psi_floor", &Config::psi_floor, nullptr, nullptr},
 };
 
 }  // namespace
 
 int learned_source(tpl_ctx *x);  // attached correction -> x->src_d (below)
+
+namespace {
+
+// Device doubles that the diagnostics need as working memory: the
+// reduction's partials and result, then the amplitude's row sums and total.
+size_t diag_scratch_doubles(int ny) {
+  return (size_t)kDiagBlocks * kDiagComp + kDiagComp + (size_t)ny + 1;
+}
+
+// A(n) with device working memory w of at least ny + 1 doubles.
+double amplitude_with(tpl_ctx *x, double *w) {
+  const int nx = x->c.nx, ny = x->c.ny;
+  if (launch_amplitude_rows(nx, ny, x->buf.half64(x->cur).FLD, w, x->stream) != hipSuccess ||
+      launch_sum(w, ny, 1, w + ny, x->stream) != hipSuccess) {
+    fail(TPL_EHIP, "amplitude kernels failed");
+    return NAN;
+  }
+  double tot = 0.0;
+  if (hipMemcpyAsync(&tot, w + ny, sizeof(double), hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
+      hipStreamSynchronize(x->stream) != hipSuccess) {
+    fail(TPL_EHIP, "amplitude copy failed");
+    return NAN;
+  }
+  return std::sqrt(tot / ((double)nx * ny)) / x->c.u0;
+}
+
+// tpl_diagnostics with device working memory w of diag_scratch_doubles(ny)
+// doubles (the BF16 form also decodes its populations into a buffer of its
+// own).
+int diagnostics_with(tpl_ctx *x, double *w, tpl_diag *out) {
+  int rc;
+  int nb = 0;
+  FloatView fv;
+  if (fp32(x) && (rc = float_view(x, x->cur, fv))) return rc;
+  if (fp32(x))
+    HIPCHK(launch_diag<float>(x->c.nx, x->c.ny, x->d.nqd, x->qtab_d, fv.v, ref_view(x), w, &nb,
+                              x->stream));
+  else
+    HIPCHK(launch_diag<double>(x->c.nx, x->c.ny, x->d.nqd, x->qtab_d, x->buf.half64(x->cur),
+                               ref_view(x), w, &nb, x->stream));
+  double *res = w + (size_t)kDiagBlocks * kDiagComp;
+  HIPCHK(launch_diag_final(w, nb, res, x->stream));
+  double h[kDiagComp];
+  HIPCHK(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, x->stream));
+  HIPCHK(hipStreamSynchronize(x->stream));
+  const double amp = amplitude_with(x, res + kDiagComp);
+  out->step = (double)x->step;
+  out->mass_S = h[0];
+  out->mass_P = h[1];
+  out->mom_x = h[2];
+  out->mom_y = h[3];
+  out->amplitude = amp;
+  out->enstrophy = h[4];
+  out->qrms = h[6] > 0 ? std::sqrt(h[5] / h[6]) / x->d.R : 0.0;
+  out->min_psi = h[7];
+  return TPL_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// n steps of the current launch shape (a new source from an attached
+// correction before each step).
+int advance(tpl_ctx *x, int64_t n) {
+  int rc;
+  if (x->mlp) {
+    for (int64_t i = 0; i < n; ++i) {
+      rc = learned_source(x);
+      if (rc) return rc;
+      if (!(x->last_drift <= x->drift_bound)) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "correction rejected before step %lld: max |F|/rho = %.3e u0 "
+                 "exceeds the drift bound %.3e u0", x->step + 1, x->last_drift, x->drift_bound);
+        return fail(TPL_EREJECTED, msg);
+      }
+      rc = run_steps(x, x->buf, x->c.nx, x->c.ny, &x->cur, 1, x->c.time_kernels != 0,
+                     x->c.qsplit);
+      if (rc) return rc;
+      x->step += 1;
+    }
+    return TPL_OK;
+  }
+  if (n == 0) return TPL_OK;
+  rc = run_steps(x, x->buf, x->c.nx, x->c.ny, &x->cur, n, x->c.time_kernels != 0, x->c.qsplit);
+  if (rc) return rc;
+  x->step += n;
+  return TPL_OK;
+}
+
+// Health of the current state (non-finite U or psi, min and max psi) into
+// out[3]; partial and out are device arrays (3 kHealthBlocks and 3 doubles).
+int health(tpl_ctx *x, double *partial, double *dout, hipStream_t s, double out[3]) {
+  if (fp32(x))
+    HIPCHK(launch_health<float>(x->c.nx, x->c.ny, x->d.nqd, x->buf.half<float>(x->cur),
+                                ref_view(x), partial, dout, s));
+  else
+    HIPCHK(launch_health<double>(x->c.nx, x->c.ny, x->d.nqd, x->buf.half64(x->cur),
+                                 ref_view(x), partial, dout, s));
+  if (out) {
+    HIPCHK(hipMemcpyAsync(out, dout, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return TPL_OK;
+}
+
+// TPL_EUNSTABLE (with the step and the cause) if the state holds NaN/Inf or
+// psi below -psi_floor max psi.
+int judge_health(const tpl_ctx *x, const double h[3]) {
+  char msg[200];
+  if (h[0] != 0.0) {
+    snprintf(msg, sizeof msg, "state not finite after step %lld (%.0f non-finite values of U "
+             "and psi)", x->step, h[0]);
+    return fail(TPL_EUNSTABLE, msg);
+  }
+  if (h[1] < -x->c.psi_floor * h[2]) {
+    snprintf(msg, sizeof msg, "polymer density negative after step %lld: min psi %.3e < "
+             "-%.3g max psi (max %.3e)", x->step, h[1], x->c.psi_floor, h[2]);
+    return fail(TPL_EUNSTABLE, msg);
+  }
+  return TPL_OK;
+}
+
+int check_health(tpl_ctx *x) {
+  int rc = ensure_scratch(x, 3 * (size_t)kHealthBlocks + 3);
+  if (rc) return rc;
+  double h[3];
+  rc = health(x, x->scratch, x->scratch + 3 * (size_t)kHealthBlocks, x->stream, h);
+  if (rc) return rc;
+  return judge_health(x, h);
+}
+
+}  // namespace
 
 // ===========================================================================
 // C ABI
@@ -931,7 +1068,8 @@ int tpl_set_param(tpl_ctx *x, const char *key, double v) {
   if (!x || !key) return fail(TPL_EINVAL, "null argument");
   // launch and timing knobs change no state and may be set at any time
   const bool runtime_knob = !std::strcmp(key, "qsplit") || !std::strcmp(key, "time_kernels") ||
-                            !std::strncmp(key, "group_", 6) || !std::strcmp(key, "autotune");
+                            !std::strncmp(key, "group_", 6) || !std::strcmp(key, "autotune") ||
+                            !std::strcmp(key, "diag_every") || !std::strcmp(key, "psi_floor");
   if (x->inited && !runtime_knob)
     return fail(TPL_ESTATE, "parameters are fixed after tpl_init");
   Config c = x->c;
@@ -944,7 +1082,10 @@ int tpl_set_param(tpl_ctx *x, const char *key, double v) {
       if (v != std::floor(v)) return fail(TPL_EINVAL, std::string(key) + " must be an integer");
       c.*(k.in) = (int)v;
     }
-    if (k.ll) c.*(k.ll) = (long long)v;
+    if (k.ll) {
+      if (v != std::floor(v)) return fail(TPL_EINVAL, std::string(key) + " must be an integer");
+      c.*(k.ll) = (long long)v;
+    }
   }
   if (!found) return fail(TPL_EINVAL, std::string("unknown parameter ") + key);
   if (c.spring != 0 && c.spring != 1) return fail(TPL_EINVAL, "spring must be 0 or 1");
@@ -955,6 +1096,8 @@ int tpl_set_param(tpl_ctx *x, const char *key, double v) {
     return fail(TPL_EINVAL, "group_x * group_y must be in [1,8]");
   if (!(c.drift_cap >= 0)) return fail(TPL_EINVAL, "drift_cap must be >= 0");
   if (!(c.drift_relax >= 0)) return fail(TPL_EINVAL, "drift_relax must be >= 0");
+  if (c.diag_every < 0) return fail(TPL_EINVAL, "diag_every must be >= 0");
+  if (!(c.psi_floor >= 0)) return fail(TPL_EINVAL, "psi_floor must be >= 0");
   if (runtime_knob) {
     x->c = c;
     return TPL_OK;
@@ -1107,41 +1250,18 @@ int tpl_step(tpl_ctx *x, int64_t n) {
     x->qs_used = p.qs;
     x->wg_used = p.wg;
   }
-  if (x->mlp) {  // learned correction: a new source before every step
-    for (int64_t i = 0; i < n; ++i) {
-      rc = learned_source(x);
-      if (rc) return rc;
-      if (!(x->last_drift <= x->drift_bound)) {
-        char msg[160];
-        snprintf(msg, sizeof msg, "correction rejected before step %lld: max |F|/rho = %.3e u0 "
-                 "exceeds the drift bound %.3e u0", x->step + 1, x->last_drift, x->drift_bound);
-        return fail(TPL_EREJECTED, msg);
-      }
-      rc = run_steps(x, x->buf, x->c.nx, x->c.ny, &x->cur, 1, x->c.time_kernels != 0,
-                     x->c.qsplit);
-      if (rc) return rc;
-      x->step += 1;
-    }
-  } else {
-    rc = run_steps(x, x->buf, x->c.nx, x->c.ny, &x->cur, n, x->c.time_kernels != 0,
-                   x->c.qsplit);
+  // advance in chunks of diag_every steps (all n if 0), checking the state's
+  // health after each chunk; a failed check stops the call there
+  int64_t done = 0;
+  do {
+    const int64_t chunk = x->c.diag_every > 0 ? std::min<int64_t>(x->c.diag_every, n - done)
+                                              : n - done;
+    rc = advance(x, chunk);
     if (rc) return rc;
-    x->step += n;
-  }
-  // divergence check on the mixture velocity
-  const long long N = (long long)x->c.nx * x->c.ny;
-  rc = ensure_scratch(x, 1024 + 1);
-  if (rc) return rc;
-  int nb = 0;
-  HIPCHK(launch_nan_check(N, x->buf.half64(x->cur).FLD, x->scratch, &nb, x->stream));
-  HIPCHK(launch_sum(x->scratch, nb, 1, x->scratch + 1024, x->stream));
-  double bad = 0.0;
-  HIPCHK(hipMemcpyAsync(&bad, x->scratch + 1024, sizeof(double), hipMemcpyDeviceToHost,
-                        x->stream));
-  HIPCHK(hipStreamSynchronize(x->stream));
-  if (bad != 0.0)
-    return fail(TPL_EUNSTABLE, "mixture velocity is not finite at " +
-                                   std::to_string((long long)bad) + " nodes");
+    done += chunk;
+    rc = check_health(x);
+    if (rc) return rc;
+  } while (done < n);
   return TPL_OK;
 }
 
@@ -1180,53 +1300,17 @@ int tpl_moments(tpl_ctx *x, double *out, size_t len) {
 
 double tpl_perturbation_amplitude(tpl_ctx *x) {
   if (check_ready(x)) return NAN;
-  const int nx = x->c.nx, ny = x->c.ny;
-  if (ensure_scratch(x, (size_t)ny + 1)) return NAN;
-  if (launch_amplitude_rows(nx, ny, x->buf.half64(x->cur).FLD, x->scratch, x->stream) != hipSuccess ||
-      launch_sum(x->scratch, ny, 1, x->scratch + ny, x->stream) != hipSuccess) {
-    fail(TPL_EHIP, "amplitude kernels failed");
-    return NAN;
-  }
-  double tot = 0.0;
-  if (hipMemcpyAsync(&tot, x->scratch + ny, sizeof(double), hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
-      hipStreamSynchronize(x->stream) != hipSuccess) {
-    fail(TPL_EHIP, "amplitude copy failed");
-    return NAN;
-  }
-  return std::sqrt(tot / ((double)nx * ny)) / x->c.u0;
+  if (ensure_scratch(x, (size_t)x->c.ny + 1)) return NAN;
+  return amplitude_with(x, x->scratch);
 }
 
 int tpl_diagnostics(tpl_ctx *x, tpl_diag *out) {
   int rc = check_ready(x);
   if (rc) return rc;
   if (!out) return fail(TPL_EINVAL, "null output");
-  rc = ensure_scratch(x, (size_t)1024 * kDiagComp + kDiagComp);
+  rc = ensure_scratch(x, diag_scratch_doubles(x->c.ny));
   if (rc) return rc;
-  int nb = 0;
-  FloatView fv;
-  if (fp32(x) && (rc = float_view(x, x->cur, fv))) return rc;
-  if (fp32(x))
-    HIPCHK(launch_diag<float>(x->c.nx, x->c.ny, x->d.nqd, x->qtab_d, fv.v, ref_view(x),
-                              x->scratch, &nb, x->stream));
-  else
-    HIPCHK(launch_diag<double>(x->c.nx, x->c.ny, x->d.nqd, x->qtab_d, x->buf.half64(x->cur),
-                               ref_view(x), x->scratch, &nb, x->stream));
-  double *res = x->scratch + (size_t)1024 * kDiagComp;
-  HIPCHK(launch_diag_final(x->scratch, nb, res, x->stream));
-  double h[kDiagComp];
-  HIPCHK(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, x->stream));
-  HIPCHK(hipStreamSynchronize(x->stream));
-  const double amp = tpl_perturbation_amplitude(x);
-  out->step = (double)x->step;
-  out->mass_S = h[0];
-  out->mass_P = h[1];
-  out->mom_x = h[2];
-  out->mom_y = h[3];
-  out->amplitude = amp;
-  out->enstrophy = h[4];
-  out->qrms = h[6] > 0 ? std::sqrt(h[5] / h[6]) / x->d.R : 0.0;
-  out->min_psi = h[7];
-  return TPL_OK;
+  return diagnostics_with(x, x->scratch, out);
 }
 
 int tpl_get_window(tpl_ctx *x, int x0, int y0, int w, int h, double *XS,
@@ -1848,29 +1932,28 @@ int capture_graph(tpl_batch *b) {
   return TPL_OK;
 }
 
-// NaN/Inf check of every active instance's mixture velocity; newly unstable
+// Health check of every active instance (NaN/Inf in U or psi, psi below
+// -psi_floor max psi, as tpl_step judges a context); newly unstable
 // instances are flagged and dropped from the table.
 int batch_check(tpl_batch *b, int *newly) {
   *newly = 0;
   const int n = (int)b->inst.size();
-  int rc = batch_scratch(b, n);
+  int rc = batch_scratch(b, 3 * n);
   if (rc) return rc;
   for (int i = 0; i < n; ++i) {
     if (b->unstable[i]) continue;
     tpl_ctx *x = b->inst[i];
-    rc = ensure_scratch(x, 1024);
+    rc = ensure_scratch(x, 3 * (size_t)kHealthBlocks);
     if (rc) return rc;
-    int nb = 0;
-    HIPCHK(launch_nan_check((long long)x->c.nx * x->c.ny, x->buf.half64(x->cur).FLD, x->scratch,
-                            &nb, b->stream));
-    HIPCHK(launch_sum(x->scratch, nb, 1, b->scratch + i, b->stream));
+    rc = health(x, x->scratch, b->scratch + 3 * i, b->stream, nullptr);
+    if (rc) return rc;
   }
-  std::vector<double> bad(n, 0.0);
-  HIPCHK(hipMemcpyAsync(bad.data(), b->scratch, sizeof(double) * n, hipMemcpyDeviceToHost,
+  std::vector<double> h(3 * n, 0.0);
+  HIPCHK(hipMemcpyAsync(h.data(), b->scratch, sizeof(double) * 3 * n, hipMemcpyDeviceToHost,
                         b->stream));
   HIPCHK(hipStreamSynchronize(b->stream));
   for (int i = 0; i < n; ++i)
-    if (!b->unstable[i] && bad[i] != 0.0) {
+    if (!b->unstable[i] && judge_health(b->inst[i], &h[3 * i]) != TPL_OK) {
       b->unstable[i] = 1;
       ++*newly;
     }

@@ -38,12 +38,13 @@ from .tpl import TPL_FP64, Batch, Tpl, TplError
 # the run diverges within two convective times, at 0.01 it spans 29 steps
 CELL = dict(nx=72, ny=72, periods=4, Re=3.5, beta=0.5, u0=0.01)
 WIS = (0.1, 2.5, 5.0)
-# Cap on the Q-drift D_Q |F/kT| per step: 0.2 instead of the library's 0.1.
-# At Wi = 0.1 (tau2_P = 0.54) the 0.1 cap already binds two sigma out, where
-# the FENE rest distribution is 11 % of its peak, and the rest extension
-# settles 18 % above the FENE value; at 0.2 it is within 1 %, and the linear
-# Q-space equilibrium stays positive (drift below c_s^2 = 1/3 per step, with
-# room for the flow term).  The elastic cells (tau2_P <= 0.02) are unaffected.
+# Cap on the Q-drift D_Q |F/kT| per step (the library's default, 0.2).  At
+# Wi = 0.1 (tau2_P = 0.54) a cap of 0.1 would already bind two sigma out,
+# where the FENE rest distribution is 11 % of its peak, and the rest
+# extension would settle 18 % above the FENE value; at 0.2 it is within 1 %,
+# and the linear Q-space equilibrium stays positive (drift below c_s^2 = 1/3
+# per step, with room for the flow term).  The elastic cells (tau2_P <= 0.02)
+# do not reach it.
 DRIFT_CAP = 0.2
 
 

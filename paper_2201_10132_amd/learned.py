@@ -234,8 +234,7 @@ def main():
     1000, held-out seeds from 2000, parameters drawn as in the plan)."""
     import torch
 
-    sys.path.insert(0, __file__.rsplit("/", 2)[0])
-    from tests import inputs
+    from . import inputs
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--trajectories", type=int, default=64)

@@ -315,3 +315,15 @@ def test_batch_model2_rules():
         b.init()
     assert "Taylor" in str(e.value)
     b.close()
+
+
+def test_health_check_knobs():
+    t = P.Tpl(16, 16, 20.0, 0.5, 0.8)
+    assert t.query("diag_every") == 0 and t.query("psi_floor") == 0.1
+    t.set_param("diag_every", 5)
+    t.set_param("psi_floor", 0.0)
+    assert t.query("diag_every") == 5 and t.query("psi_floor") == 0.0
+    for k, v in (("diag_every", -1), ("psi_floor", -0.5), ("diag_every", 1.5)):
+        with pytest.raises(P.TplError):
+            t.set_param(k, v)
+    t.close()

@@ -224,12 +224,14 @@ def _stiff_fene(relax, nq=8):
 
 def test_fene_drift_caps_in_the_force_table():
     """Every Q-node's drift D_Q |Fhat| stays within both caps: the absolute
-    0.1 per step and 2 - omega_P (omega_P = 2 / (2 tau1_P + 1)); the caps
-    only bind where the continuous FENE force exceeds them."""
+    drift_cap per step (0.2 by default) and 2 - omega_P (omega_P =
+    2 / (2 tau1_P + 1)); the caps only bind where the continuous FENE force
+    exceeds them."""
     for kw in (dict(Re=60.0, Wi=1.0, beta=0.7, ny_param=256), dict(Re=20.0, Wi=0.5, beta=0.8)):
         o = oracle.OracleSim(8, 8, nq=16, periods=1, **kw)
         d, t = o.derived(), o.tables()
-        cap = min(0.1, 2.0 - 2.0 / (2.0 * d["tau1P"] + 1.0))
+        assert o.cfg["drift_cap"] == 0.2
+        cap = min(0.2, 2.0 - 2.0 / (2.0 * d["tau1P"] + 1.0))
         Q, F = t["Q"], t["Fhat"]
         drift = d["DQ"] * np.hypot(F[:, 0], F[:, 1])
         assert drift.max() <= cap * (1 + 1e-12)
