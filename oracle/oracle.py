@@ -72,6 +72,8 @@ def _L():
         lib.orc_get_tables.argtypes = [C.c_void_p, ip, dp, ip, dp, dp, dp, ip, ip, dp]
         lib.orc_rest.argtypes = [C.c_void_p]
         lib.orc_base_state.argtypes = [C.c_void_p, C.c_long]
+        lib.orc_analytic_state.restype = C.c_int
+        lib.orc_analytic_state.argtypes = [C.c_void_p]
         lib.orc_default_prerun.restype = C.c_long
         lib.orc_default_prerun.argtypes = [C.c_void_p]
         lib.orc_perturb.argtypes = [C.c_void_p, C.c_uint64, C.c_double, C.c_int]
@@ -182,6 +184,11 @@ class OracleSim:
 
     def base_state(self, npre: int = -1):
         _L().orc_base_state(self._h, int(npre))
+
+    def analytic_state(self):
+        """Hookean laminar Kolmogorov state in closed form (model 1, Wi > 0)."""
+        if _L().orc_analytic_state(self._h) != 0:
+            raise ValueError("the analytic state needs Hookean springs, qe_model 1 and Wi > 0")
 
     def default_prerun(self) -> int:
         return int(_L().orc_default_prerun(self._h))

@@ -777,6 +777,70 @@ void orc_rest(orc_sim *s) {
   s->nstep = 0;
 }
 
+/* Analytic initial state (Hookean springs, component-momentum model, Wi > 0):
+ * the forced laminar Kolmogorov state of Hookean dumbbells, the Oldroyd-B
+ * profile with the stress diffusion of the polymer populations, on every
+ * column (Sec. VII forcing; Sec. V imposed fluxes; App. A Smoluchowski limit).
+ *   U_x = U_L sin(k y), U_L = F0 / (k^2 [eta_s + eta_pk + G lambda / (1 + lambda D k^2)])
+ *   with eta_s = rho_S c_s^2 tau1_S, eta_pk = rho_P c_s^2 tau1_P, D = c_s^2 tau2_P;
+ *   conformation c_xy = lambda U_L k cos(k y) / (1 + lambda D k^2),
+ *   c_xx = 1 + lambda^2 U_L^2 k^2 / (1 + lambda D k^2) [1 + cos(2 k y) / (1 + 4 lambda D k^2)],
+ *   c_yy = 1;
+ *   psi(y, Q) proportional to exp(-Q^T (sigma^2 c)^-1 Q / 2) over the disk,
+ *   summing to rho_P;
+ * the solvent at its equilibrium about U, the polymer at its equilibrium
+ * with the imposed fluxes J^r = psi U and J^Q = psi (K Q - D_Q Fhat),
+ * K_xy = dU_x/dy.  Returns -1 (state unchanged) for other configurations. */
+int orc_analytic_state(orc_sim *s) {
+  if (s->c.spring != 1 || s->c.qe_model != 1 || !(s->p.G > 0.0)) return -1;
+  const int nqd = s->nqd;
+  const double k = s->p.kf, lam = s->p.lambda, G = s->p.G;
+  const double D = CS2 * s->p.tau2P;
+  const double etas = s->p.rhoS0 * CS2 * s->p.tau1S, etap = s->p.rhoP0 * CS2 * s->p.tau1P;
+  const double a = 1.0 + lam * D * k * k;
+  const double UL = s->p.F0 / (k * k * (etas + etap + G * lam / a));
+  const double s2 = s->p.sigma * s->p.sigma;
+  double *w = malloc(sizeof(double) * (size_t)nqd);
+  for (int y = 0; y < s->ny; ++y) {
+    const double Y = (double)(y + s->c.y_offset);
+    const double ux = UL * sin(k * Y), Kxy = UL * k * cos(k * Y);
+    const double cxy = lam * UL * k * cos(k * Y) / a;
+    const double cxx = 1.0 + lam * lam * UL * UL * k * k / a *
+                                 (1.0 + cos(2.0 * k * Y) / (1.0 + 4.0 * lam * D * k * k));
+    const double cyy = 1.0;
+    /* inverse of sigma^2 c */
+    const double det = s2 * s2 * (cxx * cyy - cxy * cxy);
+    const double ixx = s2 * cyy / det, ixy = -s2 * cxy / det, iyy = s2 * cxx / det;
+    double tot = 0.0;
+    for (int q = 0; q < nqd; ++q) {
+      const double qx = s->Q[2 * q], qy = s->Q[2 * q + 1];
+      w[q] = exp(-0.5 * (ixx * qx * qx + 2.0 * ixy * qx * qy + iyy * qy * qy));
+      tot += w[q];
+    }
+    double feq[9];
+    orc_solvent_eq(s->p.rhoS0, ux, 0.0, feq);
+    for (int x = 0; x < s->nx; ++x) {
+      const size_t n = nid(s, x, y);
+      for (int i = 0; i < 9; ++i) s->XS[9 * n + i] = feq[i];
+      for (int q = 0; q < nqd; ++q) {
+        const double psi = s->p.rhoP0 * w[q] / tot;
+        const double qy = s->Q[2 * q + 1];
+        const double Jr[2] = {psi * ux, 0.0};
+        const double JQ[2] = {psi * (Kxy * qy - s->p.DQ * s->Fh[2 * q]),
+                              psi * (-s->p.DQ * s->Fh[2 * q + 1])};
+        orc_polymer_eq(s, psi, Jr, JQ, s->XP + (n * nqd + q) * 25);
+        s->psi[n * nqd + q] = psi;
+      }
+      s->U[2 * n] = ux;
+      s->U[2 * n + 1] = 0.0;
+    }
+  }
+  free(w);
+  record_densities(s);
+  s->nstep = 0;
+  return 0;
+}
+
 long orc_default_prerun(const orc_sim *s) {
   double t = s->p.l * s->p.l / s->p.nu;
   if (s->p.lambda > t) t = s->p.lambda;

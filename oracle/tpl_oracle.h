@@ -104,6 +104,9 @@ void orc_get_tables(const orc_sim *s, int *cS, double *wS, int *cP,
 /* Initial states (step 8). */
 void orc_rest(orc_sim *s);
 void orc_base_state(orc_sim *s, long npre); /* npre < 0: default length */
+/* Hookean laminar Kolmogorov state in closed form (model 1, Wi > 0); -1 and
+ * nothing changed otherwise. */
+int orc_analytic_state(orc_sim *s);
 long orc_default_prerun(const orc_sim *s);
 void orc_perturb(orc_sim *s, uint64_t seed, double amp, int multimode);
 

@@ -417,3 +417,28 @@ def test_fene_rest_distribution_is_kept_with_a_loose_drift_cap():
     assert abs(loose / eq - 1) < 1e-2
     tight, _, _ = _fene_rest_qrms(0.1)
     assert tight / eq - 1 > 0.1
+
+
+def test_analytic_hookean_state_is_the_laminar_steady_state():
+    """The closed-form Hookean laminar state (the analytic initial state)
+    against the scheme's own steady state: started from it, a column keeps
+    its velocity amplitude and conformation within the closed form's
+    accuracy (P9), and both agree with the long pre-run's."""
+    ny = 64
+    kw = dict(nq=16, spring=1, Re=5.0, Wi=0.5, beta=0.8, periods=1)
+    a = oracle.OracleSim(1, ny, **kw)
+    d = a.derived()
+    a.analytic_state()
+    o0 = a.observables()
+    y = np.arange(ny); k = d["kf"]
+    U0 = _sin_amp(o0[1, :, 0], k, y)
+    a.step(int(2 * max(d["l"] ** 2 / d["nu"], d["lambda"])))
+    o1 = a.observables()
+    assert abs(_sin_amp(o1[1, :, 0], k, y) / U0 - 1) < 3e-3
+    assert np.abs(o1[5] - o0[5]).max() < 5e-3 * np.abs(o0[5]).max()
+    assert np.abs((o1[4] - o1[6]) - (o0[4] - o0[6])).max() < 1e-2 * np.abs(o0[4] - o0[6]).max()
+    b = oracle.OracleSim(1, ny, **kw)
+    b.base_state(int(12 * max(d["l"] ** 2 / d["nu"], d["lambda"])))
+    assert abs(_sin_amp(b.observables()[1, :, 0], k, y) / U0 - 1) < 3e-3
+    with pytest.raises(ValueError):
+        oracle.OracleSim(1, ny, **dict(kw, spring=0)).analytic_state()
