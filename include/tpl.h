@@ -253,6 +253,18 @@ double tpl_perturbation_amplitude(tpl_ctx *ctx);
 /* FP64 totals and extremes of the current state (see tpl_diag). */
 int tpl_diagnostics(tpl_ctx *ctx, tpl_diag *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the values
+ * of tpl_diagnostics, computed by the same kernels in a static working array
+ * of the library (one per GPU, held until the process ends, about 0.6 MB)
+ * instead of the context's lazily allocated buffer.  Calls no hipMalloc or
+ * hipFree.  The calling thread's current device must be the context's.
+ * TPL_EINVAL for a lattice of more than 65536 rows or the TPL_BF16NEQ form
+ * (which decodes into a buffer of its own).  Every call on a GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (other threads, other
+ * streams) race and must be serialised by the caller. */
+int tpl_diagnostics_noalloc(tpl_ctx *ctx, tpl_diag *out);
+
 /* Whole-lattice state exchange in the canonical layouts, as doubles.  Any
  * pointer may be NULL (that array is skipped).  tpl_set_state requires a
  * context after tpl_init; it replaces populations, the lagged psi and U and

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -960,6 +961,39 @@ int diagnostics_with(tpl_ctx *x, double *w, tpl_diag *out) {
   return TPL_OK;
 }
 
+// Working memory of tpl_diagnostics_noalloc, one copy per GPU for the
+// life of the process: the diagnostics' partial sums and result and the
+// amplitude's row sums, for lattices of at most kNoAllocRows rows.  Every
+// call on a GPU reuses it (each call writes every value it later reads, so
+// nothing needs clearing); calls that overlap on one GPU race.  Host code
+// uses only its device address from noalloc_scratch(), never the name.
+constexpr int kNoAllocRows = 1 << 16;
+constexpr size_t kNoAllocDoubles = (size_t)kDiagBlocks * kDiagComp + kDiagComp + kNoAllocRows + 1;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double *g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's copy of scratch (looked up once per
+// device, with that device current).
+int noalloc_scratch(double **p) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(TPL_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(TPL_EHIP, std::string("hipGetSymbolAddress of the static working memory: ") +
+                                hipGetErrorString(e));
+    g_noalloc_ptr[dev] = static_cast<double *>(ptr);
+  }
+  *p = g_noalloc_ptr[dev];
+  return TPL_OK;
+}
+
 }  // namespace
 
 namespace {
@@ -1311,6 +1345,23 @@ int tpl_diagnostics(tpl_ctx *x, tpl_diag *out) {
   rc = ensure_scratch(x, diag_scratch_doubles(x->c.ny));
   if (rc) return rc;
   return diagnostics_with(x, x->scratch, out);
+}
+
+int tpl_diagnostics_noalloc(tpl_ctx *x, tpl_diag *out) {
+  int rc = check_ready(x);
+  if (rc) return rc;
+  if (!out) return fail(TPL_EINVAL, "null output");
+  if (neq(x))
+    return fail(TPL_EINVAL, "tpl_diagnostics_noalloc: the BF16 form decodes into a buffer "
+                            "it would have to allocate");
+  if (x->c.ny > kNoAllocRows)
+    return fail(TPL_EINVAL, "tpl_diagnostics_noalloc: ny = " + std::to_string(x->c.ny) +
+                                " exceeds the static working memory (at most " +
+                                std::to_string(kNoAllocRows) + " rows)");
+  double *w = nullptr;
+  rc = noalloc_scratch(&w);
+  if (rc) return rc;
+  return diagnostics_with(x, w, out);
 }
 
 int tpl_get_window(tpl_ctx *x, int x0, int y0, int w, int h, double *XS,

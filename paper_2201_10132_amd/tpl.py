@@ -76,6 +76,7 @@ def lib():
         "tpl_moments_device": (C.c_int, [vp, vp, C.c_size_t]),
         "tpl_perturbation_amplitude": (C.c_double, [vp]),
         "tpl_diagnostics": (C.c_int, [vp, C.POINTER(tpl_diag)]),
+        "tpl_diagnostics_noalloc": (C.c_int, [vp, C.POINTER(tpl_diag)]),
         "tpl_get_state": (C.c_int, [vp, dp, dp, dp, dp]),
         "tpl_set_state": (C.c_int, [vp, dp, dp, dp, dp]),
         "tpl_get_window": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp]),
@@ -218,6 +219,13 @@ class Tpl:
     def diagnostics(self) -> dict:
         d = tpl_diag()
         _check(lib().tpl_diagnostics(self._h, C.byref(d)))
+        return {n: getattr(d, n) for n in DIAG_NAMES}
+
+    def diagnostics_noalloc(self) -> dict:
+        """tpl_diagnostics_noalloc: the same values, computed in the
+        library's static working memory (no device allocation)."""
+        d = tpl_diag()
+        _check(lib().tpl_diagnostics_noalloc(self._h, C.byref(d)))
         return {n: getattr(d, n) for n in DIAG_NAMES}
 
     def get_state(self, populations=True):
