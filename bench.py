@@ -152,8 +152,8 @@ def main():
         forms[f"fp32_1024x1024_nq{nq}"] = form_entry(f32q, f64q)
         # BF16 non-equilibrium form (precision 2)
         b16 = measure(torch, w, 2, args.steps, args.warmup, args.pre_steps)
-        forms["bf16neq_1024x1024_nq16"] = form_entry(b16, main64)
-        forms["bf16neq_1024x1024_nq16"]["speedup_vs_fp32"] = round(b16["mlups"] / f32["mlups"], 3)
+        forms["bf16_1024x1024_nq16"] = form_entry(b16, main64)
+        forms["bf16_1024x1024_nq16"]["speedup_vs_fp32"] = round(b16["mlups"] / f32["mlups"], 3)
         # the large precision-form workload, each form against the FP64 run
         w3 = WORKLOAD_FP32_LARGE
         tag = f"4096x4096_nq{w3['nq']}"
@@ -163,8 +163,8 @@ def main():
         f32l = measure(torch, w3, 1, n3, args.warmup, args.pre_steps)
         forms[f"fp32_{tag}"] = form_entry(f32l, f64l)
         b16l = measure(torch, w3, 2, n3, args.warmup, args.pre_steps)
-        forms[f"bf16neq_{tag}"] = form_entry(b16l, f64l)
-        forms[f"bf16neq_{tag}"]["speedup_vs_fp32"] = round(b16l["mlups"] / f32l["mlups"], 3)
+        forms[f"bf16_{tag}"] = form_entry(b16l, f64l)
+        forms[f"bf16_{tag}"]["speedup_vs_fp32"] = round(b16l["mlups"] / f32l["mlups"], 3)
         out["precision_forms"] = forms
     if not args.no_inplace:
         out["inplace"] = measure_inplace(torch, out.get("precision_forms"), args)
@@ -459,7 +459,7 @@ def measure_growth(torch, w, pre_steps, steps, every=100):
     n_fit = steps // 4
     out = {"workload": f"kolmogorov_{w['nx']}x{w['ny']}_nq{w['nq']}", "steps": steps,
            "sample_every": every, "fit_window": [n_fit, steps], "gamma": {}, "amplitude_end": {}}
-    runs = (("fp64", P.TPL_FP64, {}), ("fp32", P.TPL_FP32, {}), ("bf16neq", P.TPL_BF16NEQ, {}),
+    runs = (("fp64", P.TPL_FP64, {}), ("fp32", P.TPL_FP32, {}), ("bf16", P.TPL_BF16, {}),
             ("fp64_same_step", P.TPL_FP64, {"gradients": 1}),
             ("fp64_spring_shift", P.TPL_FP64, {"spring_shift": 1}))
     for name, prec, opt in runs:
@@ -482,9 +482,9 @@ def measure_growth(torch, w, pre_steps, steps, every=100):
         print(f"# growth {name}: gamma {out['gamma'][name]:.6e}, A(0) {amps[0]:.4e}, "
               f"A({steps}) {amps[-1]:.4e}, {wall:.1f} s", file=sys.stderr, flush=True)
     g64 = out["gamma"]["fp64"]
-    out["gamma_rel_err"] = {k: abs(out["gamma"][k] / g64 - 1) for k in ("fp32", "bf16neq")}
+    out["gamma_rel_err"] = {k: abs(out["gamma"][k] / g64 - 1) for k in ("fp32", "bf16")}
     out["amplitude_end_rel_err"] = {k: abs(out["amplitude_end"][k] / out["amplitude_end"]["fp64"] - 1)
-                                    for k in ("fp32", "bf16neq")}
+                                    for k in ("fp32", "bf16")}
     # not an error: another reading of the scheme
     out["same_step_gamma_rel_diff"] = abs(out["gamma"]["fp64_same_step"] / g64 - 1)
     out["spring_shift_gamma_rel_diff"] = abs(out["gamma"]["fp64_spring_shift"] / g64 - 1)

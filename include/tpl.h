@@ -58,15 +58,15 @@ enum {
  *   TPL_FP64     FP64 values
  *   TPL_FP32     FP32 deviations from an x-invariant FP32 reference (the
  *                base state), FP64 per-node fields
- *   TPL_BF16NEQ  solvent and psi as TPL_FP32; each polymer (r, Q)-node stores
- *                FP32 moments of its deviations (density and the fluxes
- *                J^r, J^Q) and, per population, the BF16 remainder after the
- *                linear equilibrium of those moments; the moments are stored
- *                net of the rounded remainders' moments, so density and
- *                fluxes are exact to FP32 (74 bytes per (r, Q)-node against
- *                104 (FP32) and 208 (FP64)); needs nx ny even and
- *                70 nx ny < 2^32; bytes_XP counts remainders and moments */
-enum { TPL_FP64 = 0, TPL_FP32 = 1, TPL_BF16NEQ = 2 };
+ *   TPL_BF16     solvent and psi as TPL_FP32; the polymer populations as the
+ *                BF16 rounding (nearest even, 8 significant bits) of their
+ *                deviation from the same reference (54 bytes per (r, Q)-node
+ *                against 104 for FP32 and 208 for FP64).  Its error is set by
+ *                the size of the deviations: small near the reference (a
+ *                perturbed, converged base state), large where the state has
+ *                moved far from it (a base state still spinning up)
+ */
+enum { TPL_FP64 = 0, TPL_FP32 = 1, TPL_BF16 = 2 };
 enum { TPL_SOLVENT = 0, TPL_POLYMER = 1 };
 
 #define TPL_NFIELDS 10
@@ -136,7 +136,7 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *                 tau2_P = tau1_P / tau_ratio_p); in a batch every
  *                 instance takes the same model, model (ii) with
  *                 spring_shift 0
- *   precision 0   TPL_FP64, TPL_FP32 or TPL_BF16NEQ population storage
+ *   precision 0   TPL_FP64, TPL_FP32 or TPL_BF16 population storage
  *   inplace 0     1 = one population array instead of two, streamed in place
  *                 (Sec. VI streaming and Q-disk bounce-back, by the AA
  *                 pattern of Bailey et al., ICPP 2009): steps alternate
@@ -215,7 +215,7 @@ int tpl_set_stream(tpl_ctx *ctx, void *hip_stream);
  * bytes[i] bytes, 256-byte aligned, for i = 0..3 in the order returned by
  * tpl_query keys bytes_XS, bytes_XP, bytes_PSI, bytes_FLD (each holds the
  * double-buffered array; XS and XP hold one array with inplace 1).  The
- * caller keeps ownership.  Not available for TPL_BF16NEQ (TPL_EINVAL). */
+ * caller keeps ownership. */
 int tpl_adopt_buffers(tpl_ctx *ctx, void *const *dptrs, const size_t *bytes,
                       int n);
 
@@ -259,7 +259,7 @@ int tpl_diagnostics(tpl_ctx *ctx, tpl_diag *out);
  * of the library (one per GPU, held until the process ends, about 0.6 MB)
  * instead of the context's lazily allocated buffer.  Calls no hipMalloc or
  * hipFree.  The calling thread's current device must be the context's.
- * TPL_EINVAL for a lattice of more than 65536 rows or the TPL_BF16NEQ form
+ * TPL_EINVAL for a lattice of more than 65536 rows or the TPL_BF16 form
  * (which decodes into a buffer of its own).  Every call on a GPU shares that
  * GPU's array: calls that overlap in time on one GPU (other threads, other
  * streams) race and must be serialised by the caller. */

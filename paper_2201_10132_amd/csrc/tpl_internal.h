@@ -64,9 +64,8 @@ template <typename T>
 struct StateT {
   T *XS, *XP, *PSI;
   double *FLD;
-  // BF16 non-equilibrium form: XP holds one 70 N-byte record per Q-node:
-  // the BF16 (uint16) remainders [25][N], then the FP32 moments [5][N]
-  // (m0, J^r_x, J^r_y, J^Q_x, J^Q_y).  MOM is unused (kept null).
+  // BF16 form: XP holds [25][nqd][N] BF16 (uint16) deviations.  MOM is
+  // unused (kept null).
   float *MOM;
 };
 using StateView = StateT<double>;
@@ -130,12 +129,12 @@ hipError_t launch_same_step_fields(const StepParams &p, StateT<T> a, StepRef ref
 template <typename T>
 hipError_t launch_same_step_fields_batch(const InstDev *inst, int ninst, int nitems, int nqd,
                                          int parity, int ip, bool shift, hipStream_t s);
-// BF16 non-equilibrium form <-> FP32 deviations from the reference, node by
-// node: dev [25][nqd][N] = w_k (m0 + 3 (v_k . J)) + n_k (decode), and the
-// inverse (encode: writes MOM and n).
-hipError_t launch_neq_decode(int nqd, long long N, StateT<float> a, float *dev, hipStream_t s);
-hipError_t launch_neq_encode(int nqd, long long N, const float *dev, StateT<float> a,
-                             hipStream_t s);
+// BF16 form <-> FP32 deviations from the reference: dev [25][nqd][N] =
+// the stored BF16 values of XP (decode), and the rounding of dev to BF16
+// into XP (encode).
+hipError_t launch_bf16_decode(int nqd, long long N, StateT<float> a, float *dev, hipStream_t s);
+hipError_t launch_bf16_encode(int nqd, long long N, const float *dev, StateT<float> a,
+                              hipStream_t s);
 // Build the FP32 form's reference from the FP64 column state (ref = the
 // column rounded to FP32) and the step kernel's regrouped tables.
 hipError_t launch_make_ref(int nqd, int ny, StateView col, float *ref,

@@ -128,13 +128,10 @@ __device__ __forceinline__ double stored<double>(double v, double) { return v; }
 template <>
 __device__ __forceinline__ float stored<float>(double v, double ref) { return (float)(v - ref); }
 
-// BF16 non-equilibrium form: a polymer population is its reference value
-// plus the linear equilibrium of its node's FP32 deviation moments
-// (m0, J^r, J^Q) plus a BF16 remainder n.  The stored moments are the node's
-// exact deviation moments minus those of its rounded remainders, so that the
-// reconstructed populations carry the exact density and fluxes (to FP32) and
-// the rounding touches only higher moments.  BF16 keeps FP32's exponent
-// range, so the remainder needs no scaling.
+// BF16 form: a polymer population is stored as the BF16 rounding (nearest
+// even) of its deviation from the FP32 reference, the x-invariant base state;
+// solvent and psi keep FP32 deviations.  BF16 has FP32's exponent range, so
+// the deviations need no scaling.
 __device__ __forceinline__ uint16_t to_bf16(double v) {
   uint32_t u = __float_as_uint((float)v);
   u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
@@ -142,41 +139,6 @@ __device__ __forceinline__ uint16_t to_bf16(double v) {
 }
 __device__ __forceinline__ double from_bf16(uint16_t b) {
   return (double)__uint_as_float(((uint32_t)b) << 16);
-}
-// w_k (m0 + 3 (v_k . J)) with J = (Jrx, Jry, JQx, JQy); sq = -1 flips the
-// Q-velocity (the stored population of a bounced-back pull is k*)
-__device__ __forceinline__ double neq_lin(int k, double ps, const double J[4], double sq) {
-  double t = ps;
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-    if (PV[k][c]) t += 3.0 * (c < 2 ? 1.0 : sq) * PV[k][c] * J[c];
-  return (k == 0 ? 1.0 / 3.0 : 1.0 / 36.0) * t;
-}
-// Encode the deviations d[25] of one (r, Q)-node: BF16 remainders nb[25] and
-// the stored moments m[5] (m0, Jrx, Jry, JQx, JQy) as FP32.
-template <typename D>  // float (the step) or double (conversions)
-__device__ __forceinline__ void neq_encode(const D d[25], uint16_t nb[25], float m[5]) {
-  double m0 = 0.0, J[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < 25; ++k) {
-    m0 += d[k];
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (PV[k][c]) J[c] += PV[k][c] * d[k];
-  }
-  double s0 = 0.0, sJ[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < 25; ++k) {
-    nb[k] = to_bf16(d[k] - neq_lin(k, m0, J, 1.0));
-    const double r = from_bf16(nb[k]);
-    s0 += r;
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (PV[k][c]) sJ[c] += PV[k][c] * r;
-  }
-  m[0] = (float)(m0 - s0);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) m[1 + c] = (float)(J[c] - sJ[c]);
 }
 
 // ---------------------------------------------------------------------------
@@ -274,7 +236,7 @@ __device__ __forceinline__ void mixture_velocity(const StepParams &p, double rho
 // solvent follows the same maps with the D2Q9 set.  Every wave of a
 // workgroup owns its own nodes (one Q-slice), and the per-node fields and
 // lagged psi stay double-buffered.
-template <typename T, bool ROWTILE, bool NEQ = false, bool QE2 = false, int IP = 0,
+template <typename T, bool ROWTILE, bool B16 = false, bool QE2 = false, int IP = 0,
           bool SHIFT = false>
 __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &a,
                                           const StateT<T> &b, const float *__restrict__ rpull,
@@ -434,10 +396,10 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
     // the Q-node's 25 populations: FP64 values, or for the BF16 form their
     // FP32 deviations from the pull reference (the collision's result: from
     // the store reference), which halves the registers they hold
-    using GT = std::conditional_t<NEQ, float, double>;
+    using GT = std::conditional_t<B16, float, double>;
     GT g[25];
     auto G = [&](int k) -> double {
-      if constexpr (NEQ) return rq(rpull, y, q, k) + (double)g[k];
+      if constexpr (B16) return rq(rpull, y, q, k) + (double)g[k];
       else return g[k];
     };
     if constexpr (IP == 2) {
@@ -452,58 +414,17 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
       for (int j = 0; j < 25; ++j)
         g[krev(j)] = full(ldo(reinterpret_cast<const T *>(pb + (size_t)j * stride), oR),
                           rq(rpull, y, q, krev(j)));
-    } else if constexpr (!NEQ) {
+    } else if constexpr (!B16) {
 #pragma unroll
       for (int k = 0; k < 25; ++k)
         g[k] = full(ldo(plane(a.XP, qn.plane[k]), osrc[pdir(k)]), rq(rpull, y, q, k));
     } else {
-      // source population: the source node's moments and remainder.  One
-      // Q-node's record holds its 25 remainder planes (BF16) then its 5
-      // moment planes (FP32), so the nine Q-neighbours' records are nine
-      // bases and every load is a 32-bit offset from one of them.  Loads are
-      // issued in two batches, each in full before its values are used;
-      // remainders are read as aligned dwords (16-bit loads into register
-      // halves would chain one load behind the other).
-      const char *rec[9];
-      const uint32_t n2 = 2u * (uint32_t)N, n4 = 4u * (uint32_t)N, mo = 50u * (uint32_t)N;
+      // BF16 form: the 25 pulled deviations, 16 bits each, at half the byte
+      // offsets of the FP32 planes
+      const uint16_t *xp = reinterpret_cast<const uint16_t *>(a.XP);
 #pragma unroll
-      for (int d = 0; d < 9; ++d) {
-        const int qq = qn.qnb[d] >= 0 ? qn.qnb[d] : q;
-        rec[d] = uni(reinterpret_cast<const char *>(a.XP) + (size_t)qq * 70 * N);
-      }
-      auto pull = [&](auto K0, auto K1) {
-        constexpr int k0 = decltype(K0)::value, k1 = decltype(K1)::value;
-        float lm0[k1 - k0], lj[k1 - k0][2];
-        uint32_t ln[k1 - k0];
-#pragma unroll
-        for (int k = k0; k < k1; ++k) {
-          const int d = dir9(PV[k][2], PV[k][3]);
-          const bool bb = qn.qnb[d] < 0;
-          const uint32_t o = osrc[pdir(k)];
-          const uint32_t on = (uint32_t)(bb ? kstar(k) : k) * n2 + (o >> 1);
-          const uint32_t *rw = reinterpret_cast<const uint32_t *>(rec[d]);
-          const float *rf = reinterpret_cast<const float *>(rec[d]);
-          ln[k - k0] = ldo(rw, on & ~3u) >> ((on & 2u) * 8u);
-          lm0[k - k0] = ldo(rf, mo + o);
-          int j = 0;
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-            if (PV[k][c]) lj[k - k0][j++] = ldo(rf, mo + (uint32_t)(c + 1) * n4 + o);
-        }
-#pragma unroll
-        for (int k = k0; k < k1; ++k) {
-          const bool bb = qn.qnb[dir9(PV[k][2], PV[k][3])] < 0;
-          double J[4] = {0.0, 0.0, 0.0, 0.0};
-          int j = 0;
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-            if (PV[k][c]) J[c] = (double)lj[k - k0][j++];
-          g[k] = (float)(neq_lin(k, (double)lm0[k - k0], J, bb ? -1.0 : 1.0) +
-                         from_bf16((uint16_t)ln[k - k0]));
-        }
-      };
-      pull(std::integral_constant<int, 0>{}, std::integral_constant<int, 13>{});
-      pull(std::integral_constant<int, 13>{}, std::integral_constant<int, 25>{});
+      for (int k = 0; k < 25; ++k)
+        g[k] = (float)from_bf16(ldo(uni(xp + (size_t)qn.plane[k] * N), osrc[pdir(k)] >> 1));
     }
     double psi = 0.0, Jrx = 0.0, Jry = 0.0, JQx = 0.0, JQy = 0.0;
     double P2[4][4] = {};  // model 2: second moments sum xi_a xi_b g (a <= b)
@@ -595,7 +516,7 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
       }
       const double go = p.c1P * G(k) + t;  // post-collision population
       mg[pdir(k)] += go;
-      if constexpr (NEQ) g[k] = (float)(go - rq(rstore, y, q, k));
+      if constexpr (B16) g[k] = (float)(go - rq(rstore, y, q, k));
       else g[k] = go;
     }
     if (active) {
@@ -611,7 +532,7 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
           sto(wplane(b.XP, qs2.plane[krev(k)]), osrc[pdir(krev(k))],
               stored<T>(g[k], rq(rstore, y, q, k)));
         sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
-      } else if constexpr (!NEQ) {
+      } else if constexpr (!B16) {
         // plane bases one stride apart, the stride opaque so that they are
         // not hoisted out of the Q-loop (as for the node-local in-place reads)
         uint64_t stride = (uint64_t)nqd * (uint64_t)N * SZ;
@@ -623,19 +544,15 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
               stored<T>(g[k], rq(rstore, y, q, k)));
         sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
       } else {
-        // deviations -> BF16 remainders and FP32 moments
+        // BF16 form: the 25 deviations (from the store reference) rounded to
+        // 16 bits, plane stride opaque as above
         sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
-        uint16_t nb[25];
-        float m[5];
-        neq_encode(g, nb, m);
-        char *rw = uni(reinterpret_cast<char *>(b.XP) + (size_t)q * 70 * N);
-        const uint32_t n2 = 2u * (uint32_t)N, n4 = 4u * (uint32_t)N, mo = 50u * (uint32_t)N;
-#pragma unroll
-        for (int c = 0; c < 5; ++c)
-          sto(reinterpret_cast<float *>(rw), mo + (uint32_t)c * n4 + oR, m[c]);
+        uint64_t stride = (uint64_t)nqd * (uint64_t)N * 2u;
+        asm volatile("" : "+s"(stride));
+        char *pw = reinterpret_cast<char *>(uni(reinterpret_cast<uint16_t *>(b.XP) + (size_t)q * N));
 #pragma unroll
         for (int k = 0; k < 25; ++k)
-          sto(reinterpret_cast<uint16_t *>(rw), (uint32_t)k * n2 + (oR >> 1), nb[k]);
+          sto(reinterpret_cast<uint16_t *>(pw + (size_t)k * stride), oR >> 1, to_bf16(g[k]));
       }
     }
     Mxx += psi * qn.qx * qn.fx;
@@ -677,7 +594,7 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
   if (p.qs > 1) __syncthreads();  // red is reused by the workgroup's next tile
 }
 
-template <typename T, int MAXT, bool ROWTILE, bool NEQ = false, bool QE2 = false, int IP = 0,
+template <typename T, int MAXT, bool ROWTILE, bool B16 = false, bool QE2 = false, int IP = 0,
           bool SHIFT = false>
 __global__ void __launch_bounds__(MAXT)
     k_step(StepParams p, StateT<T> a, StateT<T> b, const float *__restrict__ rpull,
@@ -699,7 +616,7 @@ __global__ void __launch_bounds__(MAXT)
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     tile = ((grp / gpr) * gy + w / gx) * tpr + (grp % gpr) * gx + w % gx;
   }
-  step_tile<T, ROWTILE, NEQ, QE2, IP, SHIFT>(p, a, b, rpull, rstore, rpsi, rspull, rsstore,
+  step_tile<T, ROWTILE, B16, QE2, IP, SHIFT>(p, a, b, rpull, rstore, rpsi, rspull, rsstore,
                                              qtab, tile, red);
 }
 
@@ -865,7 +782,7 @@ template hipError_t launch_step_batch<float>(const InstDev *, int, int, int, int
 
 template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
-                       StepRef r, const QNode *qtab, hipStream_t s, bool neq, int ip) {
+                       StepRef r, const QNode *qtab, hipStream_t s, bool b16, int ip) {
   const int gsize = p.wg ? (p.wg & 255) * ((p.wg >> 8) & 255) : 1;
   const int grid = p.tiles_per_xcd > 0 ? 8 * p.tiles_per_xcd : p.ntiles / gsize;
   const size_t lds = p.qs > 1 ? (size_t)p.qs * 12 * 64 * sizeof(double) : 0;
@@ -878,7 +795,7 @@ hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
   if (p.shift && ip != 0) {
     // shifted spring term streamed in place: whole tiles, one Q-slice
     if (ip != 1 && ip != 2) return hipErrorInvalidValue;
-    if (neq || !rowtile || p.qs != 1 || a.XS != b.XS || a.XP != b.XP) return hipErrorInvalidValue;
+    if (b16 || !rowtile || p.qs != 1 || a.XS != b.XS || a.XP != b.XP) return hipErrorInvalidValue;
 #define TPL_STEP_IPSH(QE2, IP)                                                          \
   if (gsize <= 4)                                                                       \
     hipLaunchKernelGGL((k_step<T, 256, true, false, QE2, IP, true>), g, blk, lds, s,    \
@@ -896,7 +813,7 @@ hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
   }
   if (p.shift) {
     // non-local spring term, two arrays: FP64 and FP32 storage
-    if (neq) return hipErrorInvalidValue;
+    if (b16) return hipErrorInvalidValue;
 #define TPL_STEP_SH(MAXT, RT)                                                                 \
   if (p.qe == 2)                                                                             \
     hipLaunchKernelGGL((k_step<T, MAXT, RT, false, true, 0, true>), g, blk, lds, s,          \
@@ -915,7 +832,7 @@ hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
   if (ip != 0) {
     // in place: one population array, whole tiles, one Q-slice
     if (ip != 1 && ip != 2) return hipErrorInvalidValue;
-    if (neq || !rowtile || p.qs != 1 || a.XS != b.XS || a.XP != b.XP) return hipErrorInvalidValue;
+    if (b16 || !rowtile || p.qs != 1 || a.XS != b.XS || a.XP != b.XP) return hipErrorInvalidValue;
 #define TPL_STEP_IP(QE2, IP)                                                           \
   if (gsize <= 4)                                                                      \
     hipLaunchKernelGGL((k_step<T, 256, true, false, QE2, IP>), g, blk, lds, s, TPL_STEP_ARGS); \
@@ -929,32 +846,32 @@ hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
 #undef TPL_STEP_IP
     return hipGetLastError();
   }
-#define TPL_STEP_LAUNCH2(NEQ, QE2)                                                    \
+#define TPL_STEP_LAUNCH2(B16, QE2)                                                    \
   if (p.qs * gsize <= 4) {                                                            \
     if (rowtile)                                                                      \
-      hipLaunchKernelGGL((k_step<T, 256, true, NEQ, QE2>), g, blk, lds, s, TPL_STEP_ARGS);  \
+      hipLaunchKernelGGL((k_step<T, 256, true, B16, QE2>), g, blk, lds, s, TPL_STEP_ARGS);  \
     else                                                                              \
-      hipLaunchKernelGGL((k_step<T, 256, false, NEQ, QE2>), g, blk, lds, s, TPL_STEP_ARGS); \
+      hipLaunchKernelGGL((k_step<T, 256, false, B16, QE2>), g, blk, lds, s, TPL_STEP_ARGS); \
   } else {                                                                            \
     if (rowtile)                                                                      \
-      hipLaunchKernelGGL((k_step<T, 512, true, NEQ, QE2>), g, blk, lds, s, TPL_STEP_ARGS);  \
+      hipLaunchKernelGGL((k_step<T, 512, true, B16, QE2>), g, blk, lds, s, TPL_STEP_ARGS);  \
     else                                                                              \
-      hipLaunchKernelGGL((k_step<T, 512, false, NEQ, QE2>), g, blk, lds, s, TPL_STEP_ARGS); \
+      hipLaunchKernelGGL((k_step<T, 512, false, B16, QE2>), g, blk, lds, s, TPL_STEP_ARGS); \
   }
-#define TPL_STEP_LAUNCH(NEQ)     \
+#define TPL_STEP_LAUNCH(B16)     \
   if (p.qe == 2) {               \
-    TPL_STEP_LAUNCH2(NEQ, true)  \
+    TPL_STEP_LAUNCH2(B16, true)  \
   } else {                       \
-    TPL_STEP_LAUNCH2(NEQ, false) \
+    TPL_STEP_LAUNCH2(B16, false) \
   }
   if constexpr (std::is_same<T, float>::value) {
-    if (neq) {
+    if (b16) {
       TPL_STEP_LAUNCH(true)
     } else {
       TPL_STEP_LAUNCH(false)
     }
   } else {
-    if (neq) return hipErrorInvalidValue;
+    if (b16) return hipErrorInvalidValue;
     TPL_STEP_LAUNCH(false)
   }
 #undef TPL_STEP_LAUNCH
@@ -1315,58 +1232,31 @@ template hipError_t launch_same_step_fields<double>(const StepParams &, StateT<d
 template hipError_t launch_same_step_fields<float>(const StepParams &, StateT<float>, StepRef,
                                                    const QNode *, hipStream_t, int);
 
-// BF16 non-equilibrium form: node-local conversions to and from FP32
-// deviations (auxiliary paths: initialisation, state exchange, diagnostics).
-__global__ void k_neq_decode(int nqd, long long N, StateT<float> a, float *__restrict__ dev) {
+// BF16 form: conversions of the polymer populations to and from FP32
+// deviations, elementwise over [25][nqd][N] (auxiliary paths: initialisation,
+// state exchange, diagnostics).
+__global__ void k_bf16_decode(long long n, const uint16_t *__restrict__ src,
+                              float *__restrict__ dev) {
   const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N * nqd) return;
-  const int q = (int)(j / N);
-  const long long r = j - (long long)q * N;
-  const char *rec = reinterpret_cast<const char *>(a.XP) + (size_t)q * 70 * N;
-  const uint16_t *n = reinterpret_cast<const uint16_t *>(rec);
-  const float *mom = reinterpret_cast<const float *>(rec + 50 * N);
-  double J[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) J[c] = (double)mom[(size_t)(c + 1) * N + r];
-  const double m0 = (double)mom[r];
-#pragma unroll
-  for (int k = 0; k < 25; ++k)
-    dev[(size_t)(k * nqd + q) * N + r] =
-        (float)(neq_lin(k, m0, J, 1.0) + from_bf16(n[(size_t)k * N + r]));
+  if (j < n) dev[j] = (float)from_bf16(src[j]);
+}
+__global__ void k_bf16_encode(long long n, const float *__restrict__ dev,
+                              uint16_t *__restrict__ dst) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) dst[j] = to_bf16(dev[j]);
 }
 
-__global__ void k_neq_encode(int nqd, long long N, const float *__restrict__ dev,
-                             StateT<float> a) {
-  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N * nqd) return;
-  const int q = (int)(j / N);
-  const long long r = j - (long long)q * N;
-  double d[25];
-#pragma unroll
-  for (int k = 0; k < 25; ++k) d[k] = (double)dev[(size_t)(k * nqd + q) * N + r];
-  uint16_t nb[25];
-  float m[5];
-  neq_encode(d, nb, m);
-  char *rec = reinterpret_cast<char *>(a.XP) + (size_t)q * 70 * N;
-  float *mom = reinterpret_cast<float *>(rec + 50 * N);
-  uint16_t *nr = reinterpret_cast<uint16_t *>(rec);
-#pragma unroll
-  for (int c = 0; c < 5; ++c) mom[(size_t)c * N + r] = m[c];
-#pragma unroll
-  for (int k = 0; k < 25; ++k) nr[(size_t)k * N + r] = nb[k];
-}
-
-hipError_t launch_neq_decode(int nqd, long long N, StateT<float> a, float *dev, hipStream_t s) {
-  const long long n = N * nqd;
-  hipLaunchKernelGGL(k_neq_decode, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nqd, N, a,
-                     dev);
+hipError_t launch_bf16_decode(int nqd, long long N, StateT<float> a, float *dev, hipStream_t s) {
+  const long long n = 25 * N * nqd;
+  hipLaunchKernelGGL(k_bf16_decode, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                     reinterpret_cast<const uint16_t *>(a.XP), dev);
   return hipGetLastError();
 }
-hipError_t launch_neq_encode(int nqd, long long N, const float *dev, StateT<float> a,
-                             hipStream_t s) {
-  const long long n = N * nqd;
-  hipLaunchKernelGGL(k_neq_encode, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nqd, N,
-                     dev, a);
+hipError_t launch_bf16_encode(int nqd, long long N, const float *dev, StateT<float> a,
+                              hipStream_t s) {
+  const long long n = 25 * N * nqd;
+  hipLaunchKernelGGL(k_bf16_encode, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, dev,
+                     reinterpret_cast<uint16_t *>(a.XP));
   return hipGetLastError();
 }
 

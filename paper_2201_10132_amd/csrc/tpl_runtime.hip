@@ -75,16 +75,16 @@ int derive(const Config &c, Derived &d) {
     return fail(TPL_EINVAL, "tau_ratio_p must be in (0,1] (tau1 <= tau2)");
   if (c.qe_model != 1 && c.qe_model != 2) return fail(TPL_EINVAL, "qe_model must be 1 or 2");
   if (c.inplace != 0 && c.inplace != 1) return fail(TPL_EINVAL, "inplace must be 0 or 1");
-  if (c.inplace && c.precision == TPL_BF16NEQ)
+  if (c.inplace && c.precision == TPL_BF16)
     return fail(TPL_EINVAL, "in-place streaming is for the FP64 and FP32 forms");
   if (c.inplace && c.nx % 64)
     return fail(TPL_EINVAL, "in-place streaming needs nx a multiple of 64");
   if (c.gradients != 0 && c.gradients != 1) return fail(TPL_EINVAL, "gradients must be 0 or 1");
-  if (c.gradients && c.precision == TPL_BF16NEQ)
+  if (c.gradients && c.precision == TPL_BF16)
     return fail(TPL_EINVAL, "same-step gradients are for the FP64 and FP32 forms");
   if (c.spring_shift != 0 && c.spring_shift != 1)
     return fail(TPL_EINVAL, "spring_shift must be 0 or 1");
-  if (c.spring_shift && c.precision == TPL_BF16NEQ)
+  if (c.spring_shift && c.precision == TPL_BF16)
     return fail(TPL_EINVAL, "the shifted spring term is for the FP64 and FP32 forms");
   // the step kernel addresses a plane with 32-bit byte offsets: 8 N < 2^32
   if ((long long)c.nx * c.ny >= (1LL << 29)) return fail(TPL_EINVAL, "lattice too large");
@@ -206,17 +206,12 @@ int derive(const Config &c, Derived &d) {
   // the polymer flux relaxes with tau2_P (model 1) or tau1_P (model 2)
   const double tJ = c.qe_model == 2 ? d.tau1P : d.tau2P;
   d.kappa = d.rhoP0 > 0 ? d.G * tJ / (d.rhoP0 * d.meq) : 0.0;
-  // the BF16 form addresses one Q-node's 25 remainder planes (and 5 moment
-  // planes) with 32-bit offsets and reads remainders as aligned dwords
-  if (c.precision == TPL_BF16NEQ && (70LL * c.nx * c.ny >= (1LL << 32) || (c.nx * c.ny) % 2))
-    return fail(TPL_EINVAL, "the BF16 form needs nx ny even and 70 nx ny < 2^32");
   return TPL_OK;
 }
 
 // Double-buffered state.  XS and PSI hold elements of esize bytes (8: FP64
 // values, 4: FP32 deviations from the reference), XP elements of xsize bytes
-// (8, 4, or 2: the BF16 remainders of the BF16 non-equilibrium form, whose
-// FP32 deviation fluxes are in MOM); FLD is FP64.  With in-place streaming
+// (8, 4, or 2: the BF16 deviations of the BF16 form); FLD is FP64.  With in-place streaming
 // both halves share one XS and one XP array.
 struct Buffers {
   void *XS = nullptr, *XP = nullptr, *PSI = nullptr;
@@ -367,7 +362,7 @@ size_t xp_size(const tpl_ctx *x) {
 }
 // FP32 reference forms (FP32 storage and the BF16 non-equilibrium form)
 bool fp32(const tpl_ctx *x) { return x->c.precision != TPL_FP64; }
-bool neq(const tpl_ctx *x) { return x->c.precision == TPL_BF16NEQ; }
+bool bf16(const tpl_ctx *x) { return x->c.precision == TPL_BF16; }
 
 int alloc_state(tpl_ctx *x) {
   if (x->buf.XS) return TPL_OK;
@@ -377,7 +372,6 @@ int alloc_state(tpl_ctx *x) {
   B.nPSI = state_elems(x, 2);
   B.nFLD = state_elems(x, 3);
   B.nMOM = 0;
-  if (neq(x)) B.nXP = 35 * B.nPSI;  // per Q-node: 25 BF16 + 5 FP32 planes (70 N bytes)
   B.esize = elem_size(x);
   B.xsize = xp_size(x);
   B.inplace = x->c.inplace != 0;
@@ -386,7 +380,7 @@ int alloc_state(tpl_ctx *x) {
   const size_t pc = B.pop_copies();
   size_t bytes[5] = {pc * B.nXS * B.esize, pc * B.nXP * B.xsize, 2 * B.nPSI * B.esize,
                      2 * B.nFLD * sizeof(double), 2 * B.nMOM * sizeof(float)};
-  for (int i = 0; i < (neq(x) ? 5 : 4); ++i) {
+  for (int i = 0; i < 4; ++i) {
     if (hipMalloc(ptrs[i], bytes[i]) != hipSuccess) {
       (void)hipGetLastError();
       for (int j = 0; j < i; ++j) {
@@ -442,21 +436,21 @@ struct FloatView {
 };
 int float_view(tpl_ctx *x, int h, FloatView &fv) {
   fv.v = x->buf.half<float>(h);
-  if (!neq(x)) return TPL_OK;
+  if (!bf16(x)) return TPL_OK;
   const long long N = (long long)x->c.nx * x->c.ny;
   if (hipMalloc(&fv.tmp, 25 * (size_t)x->d.nqd * N * sizeof(float)) != hipSuccess) {
     (void)hipGetLastError();
     fv.tmp = nullptr;
     return fail(TPL_ENOMEM, "decode buffer allocation failed");
   }
-  HIPCHK(launch_neq_decode(x->d.nqd, N, fv.v, fv.tmp, x->stream));
+  HIPCHK(launch_bf16_decode(x->d.nqd, N, fv.v, fv.tmp, x->stream));
   fv.v.XP = fv.tmp;
   return TPL_OK;
 }
 int float_writeback(tpl_ctx *x, int h, FloatView &fv) {
-  if (!neq(x)) return TPL_OK;
+  if (!bf16(x)) return TPL_OK;
   const long long N = (long long)x->c.nx * x->c.ny;
-  HIPCHK(launch_neq_encode(x->d.nqd, N, fv.tmp, x->buf.half<float>(h), x->stream));
+  HIPCHK(launch_bf16_encode(x->d.nqd, N, fv.tmp, x->buf.half<float>(h), x->stream));
   HIPCHK(hipStreamSynchronize(x->stream));
   return TPL_OK;
 }
@@ -557,7 +551,7 @@ int tune_groups(tpl_ctx *x) {
   StepParams p0 = make_step_params(x, x->c.nx, x->c.ny, x->c.qsplit);
   if (p0.qs != 1 || p0.wg != 0 || x->c.group_x * x->c.group_y > 1) return TPL_OK;
   const Buffers &B = x->buf;
-  const bool neq = B.xsize == 2;  // one wave per SIMD: at most 4 waves per group
+  const bool b16 = B.xsize == 2;
   const auto &cand = kTuneCand;
   const StepRef ref =
       B.esize == 4 ? step_ref(x) : StepRef{nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -568,12 +562,11 @@ int tune_groups(tpl_ctx *x) {
   int rc = TPL_OK;
   for (const auto &c : cand) {
     StepParams p = p0;
-    if (c[0] * c[1] > 1 && (!set_group(p, c[0], c[1], c[2]) || (neq && c[0] * c[1] > 4)))
-      continue;
+    if (c[0] * c[1] > 1 && !set_group(p, c[0], c[1], c[2])) continue;
     auto launch = [&]() {
       return B.esize == 4
                  ? launch_step<float>(p, B.half<float>(x->cur), B.half<float>(1 - x->cur), ref,
-                                      x->qtab_d, x->stream, neq)
+                                      x->qtab_d, x->stream, b16)
                  : launch_step<double>(p, B.half<double>(x->cur), B.half<double>(1 - x->cur),
                                        ref, x->qtab_d, x->stream);
     };
@@ -814,7 +807,7 @@ int seed_from_column(tpl_ctx *x, const StateView &cv) {
     HIPCHK(launch_tile_dev(9, nx, ny, cv.XS, rv.XS, h0.XS, x->stream));
     HIPCHK(launch_tile_dev(d.nqd, nx, ny, cv.PSI, rv.PSI, h0.PSI, x->stream));
     HIPCHK(launch_tile_fields(nx, ny, cv.FLD, h0.FLD, x->stream));
-    if (!neq(x)) {
+    if (!bf16(x)) {
       HIPCHK(launch_tile_dev(25 * d.nqd, nx, ny, cv.XP, rv.XP, h0.XP, x->stream));
     } else {  // FP32 deviations of the column, then their BF16 encoding
       const long long N = (long long)nx * ny;
@@ -824,7 +817,7 @@ int seed_from_column(tpl_ctx *x, const StateView &cv) {
         return fail(TPL_ENOMEM, "encode buffer allocation failed");
       }
       hipError_t e = launch_tile_dev(25 * d.nqd, nx, ny, cv.XP, rv.XP, tmp, x->stream);
-      if (e == hipSuccess) e = launch_neq_encode(d.nqd, N, tmp, h0, x->stream);
+      if (e == hipSuccess) e = launch_bf16_encode(d.nqd, N, tmp, h0, x->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
       (void)hipFree(tmp);
       if (e != hipSuccess) return fail(TPL_EHIP, std::string("encode: ") + hipGetErrorString(e));
@@ -1123,8 +1116,8 @@ int tpl_set_param(tpl_ctx *x, const char *key, double v) {
   }
   if (!found) return fail(TPL_EINVAL, std::string("unknown parameter ") + key);
   if (c.spring != 0 && c.spring != 1) return fail(TPL_EINVAL, "spring must be 0 or 1");
-  if (c.precision != TPL_FP64 && c.precision != TPL_FP32 && c.precision != TPL_BF16NEQ)
-    return fail(TPL_EINVAL, "precision must be TPL_FP64, TPL_FP32 or TPL_BF16NEQ");
+  if (c.precision != TPL_FP64 && c.precision != TPL_FP32 && c.precision != TPL_BF16)
+    return fail(TPL_EINVAL, "precision must be TPL_FP64, TPL_FP32 or TPL_BF16");
   if (c.qsplit < 0 || c.qsplit > 8) return fail(TPL_EINVAL, "qsplit must be in [0,8]");
   if (c.group_x < 1 || c.group_y < 1 || c.group_x * c.group_y > 8)
     return fail(TPL_EINVAL, "group_x * group_y must be in [1,8]");
@@ -1155,9 +1148,8 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
   const double N = (double)x->c.nx * x->c.ny;
   const double es = x->c.precision == TPL_FP64 ? 8.0 : 4.0;
   const double xs = x->c.precision == TPL_FP64 ? 8.0 : x->c.precision == TPL_FP32 ? 4.0 : 2.0;
-  // BF16 form: XP records carry the remainders and the 5 FP32 moments
   const double ms = 0.0;
-  const double xq = x->c.precision == TPL_BF16NEQ ? 70.0 : 25.0 * xs;  // XP bytes per (r, Q)
+  const double xq = 25.0 * xs;  // XP bytes per (r, Q)
   const double pc = x->c.inplace ? 1.0 : 2.0;  // population arrays
   struct {
     const char *n;
@@ -1218,17 +1210,16 @@ int tpl_adopt_buffers(tpl_ctx *x, void *const *dptrs, const size_t *bytes, int n
   if (!x || !dptrs || !bytes) return fail(TPL_EINVAL, "null argument");
   if (x->inited || x->buf.XS) return fail(TPL_ESTATE, "buffers already allocated");
   if (n != 4) return fail(TPL_EINVAL, "expected 4 buffers (XS, XP, PSI, FLD)");
-  if (neq(x)) return fail(TPL_EINVAL, "the BF16 form allocates its own buffers");
   Buffers B;
   B.nXS = state_elems(x, 0);
   B.nXP = state_elems(x, 1);
   B.nPSI = state_elems(x, 2);
   B.nFLD = state_elems(x, 3);
   B.esize = elem_size(x);
-  B.xsize = B.esize;
+  B.xsize = xp_size(x);
   B.inplace = x->c.inplace != 0;
   const size_t pc = B.pop_copies();
-  const size_t need[4] = {pc * B.nXS * B.esize, pc * B.nXP * B.esize, 2 * B.nPSI * B.esize,
+  const size_t need[4] = {pc * B.nXS * B.esize, pc * B.nXP * B.xsize, 2 * B.nPSI * B.esize,
                           2 * B.nFLD * sizeof(double)};
   for (int i = 0; i < 4; ++i) {
     if (!dptrs[i] || bytes[i] < need[i])
@@ -1351,7 +1342,7 @@ int tpl_diagnostics_noalloc(tpl_ctx *x, tpl_diag *out) {
   int rc = check_ready(x);
   if (rc) return rc;
   if (!out) return fail(TPL_EINVAL, "null output");
-  if (neq(x))
+  if (bf16(x))
     return fail(TPL_EINVAL, "tpl_diagnostics_noalloc: the BF16 form decodes into a buffer "
                             "it would have to allocate");
   if (x->c.ny > kNoAllocRows)
@@ -1449,7 +1440,7 @@ int tpl_get_state(tpl_ctx *x, double *XS, double *XP, double *psi, double *U) {
   const char *XPd = static_cast<const char *>(x->buf.XP) + hp * x->buf.nXP * x->buf.xsize;
   const char *PSd = static_cast<const char *>(x->buf.PSI) + cur * x->buf.nPSI * es;
   FloatView fv;
-  if (XP && neq(x)) {
+  if (XP && bf16(x)) {
     if ((rc = float_view(x, cur, fv))) return rc;
     XPd = reinterpret_cast<const char *>(fv.v.XP);
   }
@@ -1475,7 +1466,7 @@ int tpl_set_state(tpl_ctx *x, const double *XS, const double *XP,
   char *XPd = static_cast<char *>(x->buf.XP) + hp * x->buf.nXP * x->buf.xsize;
   char *PSd = static_cast<char *>(x->buf.PSI) + cur * x->buf.nPSI * es;
   if (XS && (rc = array_from_host(x, XSd, 9, r.XS, XS))) return rc;
-  if (neq(x) && XP) {
+  if (bf16(x) && XP) {
     FloatView fv;
     if ((rc = float_view(x, cur, fv))) return rc;
     if (XP && (rc = array_from_host(x, fv.tmp, 25 * nqd, r.XP, XP))) return rc;

@@ -25,7 +25,7 @@ import time
 
 import numpy as np
 
-from .tpl import TPL_BF16NEQ, TPL_FP32, TPL_FP64, Tpl, TplError
+from .tpl import TPL_BF16, TPL_FP32, TPL_FP64, Tpl, TplError
 
 
 def track(nx, ny, periods, Wi, nq, precision, steps, every, pre_steps=3000, perturbation=1e-4,
@@ -104,7 +104,7 @@ def main():
     else:
         steps, nq, every = args.steps or 2000, args.nq or 6, args.every or 100
         res.update(nq=nq, steps=steps, forms={})
-        for name, prec in (("fp64", TPL_FP64), ("fp32", TPL_FP32), ("bf16neq", TPL_BF16NEQ)):
+        for name, prec in (("fp64", TPL_FP64), ("fp32", TPL_FP32), ("bf16", TPL_BF16)):
             r = track(4096, 4096, 16, 1.0, nq, prec, steps, every, pre_steps=args.pre_steps,
                       tag=f"c3 {name}")
             g, win = fit_gamma(r["n"], r["A"], steps // 4)
@@ -112,7 +112,7 @@ def main():
                                       mass_S=r["mass_S"], mass_P=r["mass_P"],
                                       ms_per_step=round(r["wall_s"] / max(1, steps) * 1e3, 2))
         ref = res["forms"]["fp64"]
-        for name in ("fp32", "bf16neq"):
+        for name in ("fp32", "bf16"):
             f = res["forms"][name]
             if f["gamma"] is not None and ref["gamma"] is not None:
                 f["gamma_rel_err"] = abs(f["gamma"] / ref["gamma"] - 1)

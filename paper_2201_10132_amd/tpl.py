@@ -15,7 +15,7 @@ _LIB = os.path.join(_HERE, "libtpl.so")
 
 TPL_OK, TPL_EINVAL, TPL_ENOMEM, TPL_EHIP, TPL_ESTATE, TPL_EUNSTABLE, TPL_EREJECTED = (
     0, -1, -2, -3, -4, -5, -6)
-TPL_FP64, TPL_FP32, TPL_BF16NEQ = 0, 1, 2
+TPL_FP64, TPL_FP32, TPL_BF16 = 0, 1, 2
 TPL_SOLVENT, TPL_POLYMER = 0, 1
 TPL_NFIELDS = 10
 FIELD_NAMES = ["rho", "Ux", "Uy", "rhoP", "Cxx", "Cxy", "Cyy", "tau_xx", "tau_xy", "tau_yy"]

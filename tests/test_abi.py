@@ -145,19 +145,18 @@ def test_batched_sweep_draw():
 
 
 def test_bf16_form_bytes_and_rejections():
-    t = P.Tpl(64, 64, 20.0, 0.5, 0.8, nq=8, precision=P.TPL_BF16NEQ)
+    t = P.Tpl(64, 64, 20.0, 0.5, 0.8, nq=8, precision=P.TPL_BF16)
     N, nqd = 64 * 64, t.nqd
-    # FP32 solvent and psi, BF16 remainders + 5 FP32 moments (74 bytes per (r, Q))
-    assert t.query("bytes_per_step") == N * (2 * 4 * (9 + nqd) + 2 * (2 * 25 + 20) * nqd + 16 * 18)
-    assert t.query("bytes_XP") == 2 * 70 * nqd * N
-    with pytest.raises(P.TplError):
+    # FP32 solvent and psi, BF16 polymer deviations (54 bytes per (r, Q))
+    assert t.query("bytes_per_step") == N * (2 * 4 * (9 + nqd) + 2 * (2 * 25) * nqd + 16 * 18)
+    assert t.query("bytes_XP") == 2 * 2 * 25 * nqd * N
+    with pytest.raises(P.TplError):  # null device pointers
         t.adopt_buffers([0, 0, 0, 0], [1, 1, 1, 1])
     with pytest.raises(P.TplError):
-        P.Batch([dict(nx=16, ny=16, Re=20.0, Wi=0.5, beta=0.8)], precision=P.TPL_BF16NEQ)
+        P.Batch([dict(nx=16, ny=16, Re=20.0, Wi=0.5, beta=0.8)], precision=P.TPL_BF16)
     with pytest.raises(P.TplError):
         t.set_param("precision", 3)
-    with pytest.raises(P.TplError):  # odd node count
-        P.Tpl(13, 9, 20.0, 0.5, 0.8, nq=4, precision=P.TPL_BF16NEQ)
+    P.Tpl(13, 9, 20.0, 0.5, 0.8, nq=4, precision=P.TPL_BF16).close()  # any node count
     t.close()
 
 
@@ -210,7 +209,7 @@ def test_inplace_storage_knob():
     assert t.query("bytes_state") == two["bytes_state"] - (two["bytes_XS"] + two["bytes_XP"]) / 2
     t.set_param("precision", P.TPL_FP32)
     with pytest.raises(P.TplError) as e:
-        t.set_param("precision", P.TPL_BF16NEQ)
+        t.set_param("precision", P.TPL_BF16)
     assert e.value.code == P.tpl.TPL_EINVAL
     with pytest.raises(P.TplError):
         t.set_param("inplace", 2)
@@ -223,7 +222,7 @@ def test_inplace_storage_knob():
         u.set_param("inplace", 1)
     assert "multiple of 64" in str(e.value)
     u.close()
-    v = P.Tpl(128, 64, 60.0, 1.0, 0.7, periods=2, nq=8, precision=P.TPL_BF16NEQ)
+    v = P.Tpl(128, 64, 60.0, 1.0, 0.7, periods=2, nq=8, precision=P.TPL_BF16)
     with pytest.raises(P.TplError):
         v.set_param("inplace", 1)
     v.close()
@@ -254,7 +253,7 @@ def test_same_step_gradients_knob():
     with pytest.raises(P.TplError):
         t.set_param("gradients", 2)
     with pytest.raises(P.TplError):
-        t.set_param("precision", P.TPL_BF16NEQ)
+        t.set_param("precision", P.TPL_BF16)
     t.set_param("inplace", 1)  # both together are allowed
     t.close()
     b = P.Batch([dict(nx=64, ny=64, Re=20.0, Wi=0.5, beta=0.8),
@@ -277,7 +276,7 @@ def test_spring_shift_knob():
     b0 = t.query("bytes_per_step")
     t.set_param("spring_shift", 1)
     assert t.query("bytes_per_step") == b0 + N * (8 * nqd + 16)
-    for k, v in (("precision", P.TPL_BF16NEQ), ("spring_shift", 2)):
+    for k, v in (("precision", P.TPL_BF16), ("spring_shift", 2)):
         with pytest.raises(P.TplError):
             t.set_param(k, v)
     # with same-step gradients the M pass is the spring-sum pass: psi read

@@ -36,13 +36,11 @@ def _run(precision, shape, autotune=0, steps=6):
     return st, used, tune
 
 
-@pytest.mark.parametrize("precision", [P.TPL_FP64, P.TPL_FP32, P.TPL_BF16NEQ])
+@pytest.mark.parametrize("precision", [P.TPL_FP64, P.TPL_FP32, P.TPL_BF16])
 def test_group_shapes_are_bitwise_equal(precision):
     ref, used, _ = _run(precision, None)
     assert used == (0, 0, 0)
     for shape in SHAPES:
-        if precision == P.TPL_BF16NEQ and shape[0] * shape[1] > 4:
-            continue  # that kernel holds one wave per SIMD: at most 4 per group
         print(f"precision {precision} group {shape}", flush=True)
         st, used, _ = _run(precision, shape)
         assert used == shape
@@ -71,7 +69,7 @@ def test_grouped_step_parity_with_oracle():
     assert max_rel(t.moments(), o.observables()) < 1e-13
 
 
-@pytest.mark.parametrize("precision", [P.TPL_FP64, P.TPL_BF16NEQ])
+@pytest.mark.parametrize("precision", [P.TPL_FP64, P.TPL_BF16])
 def test_autotuned_shape_is_bitwise_equal(precision):
     ref, _, _ = _run(precision, None)
     st, used, tune = _run(precision, None, autotune=1)

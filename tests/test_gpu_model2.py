@@ -3,8 +3,8 @@
 
 Tolerances as for model (i): FP64 1e-14 for one step from a random state,
 1e-13 after 100 steps and through init; FP32 within n 2^-24 max|deviation|
-of the oracle (factor 4 margin); BF16 within n (2 2^-9 max|remainder| +
-4 2^-24 max|deviation|) (factor 4).  The drag time tau1_S = tau_drag must
+of the oracle (factor 4 margin); BF16 within n (2^-9 max|polymer deviation|
++ 4 2^-24 max|deviation|) (factor 4).  The drag time tau1_S = tau_drag must
 not exceed the viscous tau2_S = nu_S / c_s^2, so each case takes half of it.
 """
 import numpy as np
@@ -14,7 +14,7 @@ import oracle
 import paper_2201_10132_amd as P
 from tests.gpu_common import compare_states, make_pair, max_rel
 from tests.test_gpu_fp32 import _delta_bound
-from tests.test_gpu_neq import _bound as _neq_bound
+from tests.test_gpu_bf16 import _bound as _bf16_bound
 from tests.test_gpu_parity import _random_state
 
 pytestmark = pytest.mark.gpu
@@ -69,7 +69,7 @@ def test_model2_init_and_run_parity(multimode):
     assert abs(t.amplitude() / o.amplitude() - 1) < 1e-12
 
 
-@pytest.mark.parametrize("precision", [P.TPL_FP32, P.TPL_BF16NEQ])
+@pytest.mark.parametrize("precision", [P.TPL_FP32, P.TPL_BF16])
 def test_model2_storage_forms(precision):
     t, o = _pair(64, 16, 20.0, 0.5, 0.8, 2, nq=6, pre_steps=300, pert_modes=1)
     t.set_param("precision", precision)
@@ -85,7 +85,7 @@ def test_model2_storage_forms(precision):
     if precision == P.TPL_FP32:
         bound = _delta_bound(n, want, base)
     else:
-        b = _neq_bound(n + 1, [want0, want], base)
+        b = _bf16_bound(n + 1, [want0, want], base)
         bound = {k: b for k in ("XS", "XP", "psi")}
     for k in ("XS", "XP", "psi"):
         err = np.abs(got[k] - want[k]).max()
