@@ -171,6 +171,13 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *                 psi and replaces the M pass; a batch sets it for all
  *                 instances
  *   pert_modes 1  0 = single x-mode, 1 = multimode perturbation
+ *   init_mode 0   base state: 0 = the forced x-invariant state reached by a
+ *                 pre-run of the scheme on one column (pre_steps); 1 = the
+ *                 closed-form laminar state of Hookean dumbbells (Oldroyd-B
+ *                 profile with the populations' stress diffusion, both
+ *                 species at their equilibria; Sec. VII forcing, Sec. V
+ *                 fluxes), for spring 1, qe_model 1 and Wi > 0 (TPL_EINVAL
+ *                 from tpl_init otherwise; batches take 0 only)
  *   pre_steps -1  base-state column steps (-1 = 5 max(l^2/nu, lambda))
  *   qsplit 0      Q-slices per r-tile in the step kernel: 0 (automatic),
  *                 1, 2, 4 or 8 (other values round down)

@@ -158,6 +158,16 @@ hipError_t launch_step_batch(const InstDev *inst, int ninst, int nitems, int qs,
 template <typename T>
 hipError_t launch_spring_sum_batch(const InstDev *inst, int ninst, int nitems, int grid,
                                    int parity, hipStream_t s);
+// Closed-form Hookean laminar Kolmogorov column (see k_analytic_column):
+// velocity amplitude UL, forcing wavenumber k, relaxation time lam,
+// Dk2 = lambda D k^2 (stress diffusion D = c_s^2 tau2_P), s2 = sigma^2,
+// densities and the Q-diffusivity D_Q.  Writes XS, XP, PSI and U of col
+// (nx = 1); the other per-node fields follow from launch_refresh.
+struct AnalyticColumn {
+  double UL, k, lam, Dk2, s2, rhoS0, rhoP0, DQ;
+};
+hipError_t launch_analytic_column(int ny, int nqd, const QNode *qtab, AnalyticColumn c,
+                                  StateView col, hipStream_t s);
 hipError_t launch_rest(int nqd, long long N, double rhoS0, double rhoP0,
                        const double *peq, StateView a, hipStream_t s);
 template <typename T>

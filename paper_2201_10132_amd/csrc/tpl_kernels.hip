@@ -1893,6 +1893,68 @@ template hipError_t launch_health<double>(int, int, int, StateT<double>, RefView
 template hipError_t launch_health<float>(int, int, int, StateT<float>, RefView, double *,
                                          double *, hipStream_t);
 
+// Closed-form Hookean laminar Kolmogorov state of one column (nx = 1; one
+// workgroup per row y): the Oldroyd-B profile with the polymer populations'
+// stress diffusion (Sec. VII forcing, Sec. V imposed fluxes),
+//   U_x = UL sin(k y),  c_xy = lambda UL k cos(k y) / (1 + lambda D k^2),
+//   c_xx = 1 + lambda^2 UL^2 k^2 / (1 + lambda D k^2) [1 + cos(2 k y) /
+//          (1 + 4 lambda D k^2)],  c_yy = 1,
+// psi proportional to exp(-Q.(sigma^2 c)^-1 Q / 2) over the disk with the
+// row's sum rho_P0, the solvent at its equilibrium about U and the polymer
+// at its equilibrium with the imposed fluxes J^r = psi U and
+// J^Q = psi (K Q - D_Q Fhat), K_xy = dU_x/dy.  UL comes from the host.
+__global__ void k_analytic_column(int ny, int nqd, const QNode *__restrict__ qtab,
+                                  AnalyticColumn c, StateView col) {
+  __shared__ double sh[16];
+  const int y = blockIdx.x;
+  const double ky = c.k * (double)y;
+  const double ux = c.UL * sin(ky), Kxy = c.UL * c.k * cos(ky);
+  const double cxy = c.lam * c.UL * c.k * cos(ky) / (1.0 + c.Dk2);
+  const double cxx = 1.0 + c.lam * c.lam * c.UL * c.UL * c.k * c.k / (1.0 + c.Dk2) *
+                               (1.0 + cos(2.0 * ky) / (1.0 + 4.0 * c.Dk2));
+  // (sigma^2 c)^-1 with c_yy = 1
+  const double det = c.s2 * c.s2 * (cxx - cxy * cxy);
+  const double ixx = c.s2 / det, ixy = -c.s2 * cxy / det, iyy = c.s2 * cxx / det;
+  auto weight = [&](int q) {
+    const double qx = qtab[q].qx, qy = qtab[q].qy;
+    return exp(-0.5 * (ixx * qx * qx + 2.0 * ixy * qx * qy + iyy * qy * qy));
+  };
+  double part = 0.0;
+  for (int q = threadIdx.x; q < nqd; q += blockDim.x) part += weight(q);
+  const double tot = block_sum(part, sh);
+  for (int q = threadIdx.x; q < nqd; q += blockDim.x) {
+    const double psi = c.rhoP0 * weight(q) / tot;
+    const double J[4] = {psi * ux, 0.0, psi * (Kxy * qtab[q].qy - c.DQ * qtab[q].fx),
+                         -psi * c.DQ * qtab[q].fy};
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+      double t = psi;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (PV[k][a]) t += 3.0 * PV[k][a] * J[a];
+      col.XP[((size_t)k * nqd + q) * ny + y] = (k == 0 ? 1.0 / 3.0 : 1.0 / 36.0) * t;
+    }
+    col.PSI[(size_t)q * ny + y] = psi;
+  }
+  if (threadIdx.x == 0) {
+    const double uu = ux * ux;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+      const double cu = C9X[d] * ux;
+      col.XS[(size_t)d * ny + y] = W9[d] * c.rhoS0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    }
+    col.FLD[(size_t)F_UX * ny + y] = ux;
+    col.FLD[(size_t)F_UY * ny + y] = 0.0;
+  }
+}
+
+hipError_t launch_analytic_column(int ny, int nqd, const QNode *qtab, AnalyticColumn c,
+                                  StateView col, hipStream_t s) {
+  hipLaunchKernelGGL(k_analytic_column, dim3((unsigned)ny), dim3(256), 0, s, ny, nqd, qtab, c,
+                     col);
+  return hipGetLastError();
+}
+
 // Gather a w x h window (periodic wrap) of XS, XP, PSI and U into
 // dst[plane][h][w] with planes 9 | 25 nqd | nqd | 2, as full FP64 values.
 template <typename T>

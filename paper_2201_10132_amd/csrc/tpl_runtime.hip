@@ -48,6 +48,7 @@ struct Config {
   int inplace = 0;  // one population array, streamed in place
   int gradients = 0;  // 0: lagged (previous step's) gradients; 1: same-step
   int spring_shift = 0;  // spring term: 0 Taylor form, 1 psi at r +- Q/2
+  int init_mode = 0;         // 0: base state by a column pre-run; 1: closed form (Hookean)
   long long diag_every = 0;  // health check every k steps of tpl_step (0: at its end)
   double psi_floor = 0.1;    // unstable if min psi < -psi_floor max psi
 };
@@ -790,6 +791,25 @@ int column_rest(tpl_ctx *x, ColumnBuf &C) {
   return TPL_OK;
 }
 
+// Closed-form Hookean laminar state of the column (init_mode 1): U_L from the
+// momentum balance of the Oldroyd-B profile with stress diffusion,
+// F0 = k^2 U_L [eta_s + eta_pk + G lambda / (1 + lambda D k^2)], eta_s =
+// rho_S c_s^2 tau1_S, eta_pk = rho_P c_s^2 tau1_P, D = c_s^2 tau2_P; the
+// kernel sets populations, psi and U, the refresh the other fields.
+int column_analytic(tpl_ctx *x, ColumnBuf &C) {
+  const Derived &d = x->d;
+  const int ny = x->c.ny;
+  const double k = d.kf, D = kCs2 * d.tau2P;
+  const double Dk2 = d.lambda * D * k * k;
+  const double eta = d.rhoS0 * kCs2 * d.tau1S + d.rhoP0 * kCs2 * d.tau1P + d.G * d.lambda / (1.0 + Dk2);
+  AnalyticColumn a{d.F0 / (k * k * eta), k, d.lambda, Dk2, d.sigma * d.sigma, d.rhoS0, d.rhoP0,
+                   d.DQ};
+  const RefView none{nullptr, nullptr, nullptr, ny};
+  HIPCHK(launch_analytic_column(ny, d.nqd, x->qtab_d, a, C.B.half64(0), x->stream));
+  HIPCHK(launch_refresh<double>(d.nqd, 1, ny, x->qtab_d, C.B.half64(0), none, x->stream));
+  return TPL_OK;
+}
+
 // Copy the converged column to every column of the lattice (half 0).  FP32
 // form: the column rounded to FP32 becomes the reference and the stored
 // deviations start as the rounding residual.
@@ -889,6 +909,7 @@ const Key kKeys[] = {
     {"autotune", nullptr, &Config::autotune, nullptr},
     {"u0", &Config::u0, nullptr, nullptr},
     {"periods", nullptr, &Config::periods, nullptr},
+    {"init_mode", nullptr, &Config::init_mode, nullptr},
     {"diag_every", nullptr, nullptr, &Config::diag_every},
     {"psi_floor", &Config::psi_floor, nullptr, nullptr},
 };
@@ -1124,6 +1145,7 @@ int tpl_set_param(tpl_ctx *x, const char *key, double v) {
   if (!(c.drift_cap >= 0)) return fail(TPL_EINVAL, "drift_cap must be >= 0");
   if (!(c.drift_relax >= 0)) return fail(TPL_EINVAL, "drift_relax must be >= 0");
   if (c.diag_every < 0) return fail(TPL_EINVAL, "diag_every must be >= 0");
+  if (c.init_mode != 0 && c.init_mode != 1) return fail(TPL_EINVAL, "init_mode must be 0 or 1");
   if (!(c.psi_floor >= 0)) return fail(TPL_EINVAL, "psi_floor must be >= 0");
   if (runtime_knob) {
     x->c = c;
@@ -1238,6 +1260,9 @@ int tpl_adopt_buffers(tpl_ctx *x, void *const *dptrs, const size_t *bytes, int n
 int tpl_init(tpl_ctx *x, uint64_t seed, double perturbation) {
   if (!x) return fail(TPL_EINVAL, "null context");
   if (!(perturbation >= 0)) return fail(TPL_EINVAL, "perturbation must be >= 0");
+  if (x->c.init_mode == 1 && (x->c.spring != 1 || x->c.qe_model != 1 || !(x->d.G > 0.0)))
+    return fail(TPL_EINVAL, "init_mode 1 (closed-form state) needs Hookean springs (spring 1), "
+                            "qe_model 1 and Wi > 0");
   int rc = prepare_state(x);
   if (rc) return rc;
   const Derived &d = x->d;
@@ -1247,8 +1272,12 @@ int tpl_init(tpl_ctx *x, uint64_t seed, double perturbation) {
   rc = C.alloc(ny, d.nqd);
   if (rc) return rc;
   int ccur = 0;
-  rc = column_rest(x, C);
-  if (!rc) rc = run_steps(x, C.B, 1, ny, &ccur, pre_steps_of(x), false, kColumnQs);
+  if (x->c.init_mode == 1) {
+    rc = column_analytic(x, C);
+  } else {
+    rc = column_rest(x, C);
+    if (!rc) rc = run_steps(x, C.B, 1, ny, &ccur, pre_steps_of(x), false, kColumnQs);
+  }
   if (!rc) rc = seed_from_column(x, C.B.half64(ccur));
   C.release();
   if (rc) return rc;
@@ -2155,6 +2184,9 @@ int tpl_batch_init(tpl_batch *b) {
         x->c.gradients != b->gradients)
       return fail(TPL_EINVAL, "inplace, spring_shift and gradients are set for the whole batch "
                               "(tpl_batch_set_param)");
+    if (x->c.init_mode != 0)
+      return fail(TPL_EINVAL, "a batch starts every instance from its column pre-run "
+                              "(init_mode 0)");
   }
   b->qe2 = !b->inst.empty() && b->inst[0]->c.qe_model == 2;
   b->inited = false;

@@ -326,3 +326,18 @@ def test_health_check_knobs():
         with pytest.raises(P.TplError):
             t.set_param(k, v)
     t.close()
+
+
+def test_init_mode_knob():
+    t = P.Tpl(16, 16, 20.0, 0.5, 0.8, spring=1)
+    assert t.query("init_mode") == 0
+    t.set_param("init_mode", 1)
+    with pytest.raises(P.TplError):
+        t.set_param("init_mode", 2)
+    t.close()
+    for kw in (dict(spring=0), dict(spring=1, qe_model=2), dict(spring=1, Wi=0.0)):
+        Wi = kw.pop("Wi", 0.5)
+        t = P.Tpl(16, 16, 20.0, Wi, 0.8, init_mode=1, **kw)
+        with pytest.raises(P.TplError, match="init_mode 1"):  # refused before any device call
+            t.init(seed=0, perturbation=0.0)
+        t.close()
