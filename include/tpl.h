@@ -195,11 +195,13 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *   diag_every 0  tpl_step checks the state's health every diag_every steps
  *                 (0: once, after its last step) and stops at the first
  *                 failed check (see tpl_step)
- *   psi_floor 0.1 tolerance of that check on the polymer density: the state
+ *   psi_floor 1   tolerance of that check on the polymer density: the state
  *                 fails if min psi < -psi_floor max psi over all (r, Q)-nodes.
  *                 The linear Q-space equilibrium does not keep psi positive:
- *                 in healthy FENE runs the outermost Q-nodes hold psi down to
- *                 about -1e-2 max psi; a diverging run goes far below
+ *                 in healthy runs the outermost Q-nodes hold psi down to
+ *                 about -1e-2 max psi (the 64^2 workload) and, with strongly
+ *                 stretched FENE dumbbells (Wi 5 on a 16-point Q-grid),
+ *                 -0.3 max psi; a diverging run goes far below
  * Any parameter also fixes the derived values read by tpl_query. */
 int tpl_set_param(tpl_ctx *ctx, const char *key, double value);
 

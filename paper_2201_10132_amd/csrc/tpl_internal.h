@@ -56,6 +56,7 @@ struct StepParams {
   double c1P, c2P, rP;
   double kappa, DQ, F0, kf;
   const double *src;  // extra body force [2][N] added to the forcing (null: none)
+  const int *gate;    // non-null: the launch does nothing once *gate != 0 (drift gate)
 };
 
 // One half of the double-buffered state.  Populations and the lagged psi are
@@ -250,9 +251,76 @@ hipError_t launch_source(const float *corr, int nx, int ny, double *F, hipStream
 hipError_t launch_source_center(double *F, long long N, double *scratch, hipStream_t s);
 hipError_t launch_source_drift(const double *F, const double *FLD, long long N, double *partial,
                                int *nblocks, hipStream_t s);
+// The attached correction of one coarse step in two launches, on the
+// context's stream with no host synchronisation:
+//   launch_correct: per 16-node tile the 54 stencil features straight from
+//     the observables obs[10][N] (standardised, BF16), the network, the
+//     correction corr [N][5] in physical units, and per wave the sums of its
+//     momentum components into partial [waves][2] (waves = correct_waves(N));
+//   launch_source_gate: F [2][N] = (dJ - lattice mean of dJ) + div_h(dtau),
+//     the mean from those sums in a fixed order; if max |F| / rho exceeds
+//     bound (NaN included), gate := tag unless already set; drift holds the
+//     largest |F| / rho seen (as the bits of a non-negative double).
+// Both do nothing once *gate != 0.
+long long correct_waves(long long N);
+hipError_t launch_correct(const MlpDev &w, const double *obs, int nx, int ny, const float *mean,
+                          const float *stdv, float *corr, double *partial, const int *gate,
+                          hipStream_t s);
+hipError_t launch_source_gate(const float *corr, int nx, int ny, const double *partial,
+                              long long nparts, const double *FLD, double bound, int tag,
+                              double *F, int *gate, unsigned long long *drift, hipStream_t s);
 template <typename T>
 hipError_t launch_restrict(int planes, int nxf, int nyf, int m, const T *src, double *dst,
                            hipStream_t s);
+
+// Workgroup reductions of one double per thread.  Each wavefront folds its
+// 64 lanes with cross-lane exchanges in a fixed butterfly order (every lane
+// ends with bitwise the same value, since a + b == b + a), then the
+// wavefront results are combined in wavefront order.  Deterministic; the
+// result is returned to every thread.  sh holds at least blockDim.x / 64
+// doubles.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ inline double block_sum(double v, double *sh) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double out = sh[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) out += sh[w];
+  __syncthreads();
+  return out;
+}
+__device__ inline double block_min(double v, double *sh) {
+  v = wave_min(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double out = sh[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) out = fmin(out, sh[w]);
+  __syncthreads();
+  return out;
+}
+__device__ inline double block_max(double v, double *sh) {
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double out = sh[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) out = fmax(out, sh[w]);
+  __syncthreads();
+  return out;
+}
 
 constexpr int kDiagComp = 8;  // massS massP momx momy enstrophy psiQ2 psi minpsi
 constexpr int kDiagBlocks = 1024;   // workgroups of the diagnostics reduction

@@ -602,6 +602,7 @@ __global__ void __launch_bounds__(MAXT)
            const float *__restrict__ rspull, const float *__restrict__ rsstore,
            const QNode *__restrict__ qtab) {
   extern __shared__ double red[];  // [qs][12][64]
+  if (p.gate && *p.gate) return;  // a learned correction's drift gate closed
   int tile;
   if (p.wg == 0) {
     tile = xcd_tile(blockIdx.x, p.tiles_per_xcd);
@@ -662,6 +663,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(3, 8)
     TPL_LD(F0) TPL_LD(kf) TPL_LD(src)
 #undef TPL_LD
     pp.wg = 0;
+    pp.gate = nullptr;
     pp.qe = QE2 ? 2 : 1;
     pp.shift = 0;
     if constexpr (QE2) {
@@ -1485,55 +1487,6 @@ hipError_t launch_from_f64(int nx, int ny, int planes, const double *src,
   hipLaunchKernelGGL(k_from_f64, dim3((unsigned)((N + 255) / 256), planes), dim3(256),
                      0, s, nx, ny, src, ref, dst);
   return hipGetLastError();
-}
-
-// Workgroup reductions of one double per thread.  Each wavefront folds its
-// 64 lanes with cross-lane exchanges in a fixed butterfly order (every lane
-// ends with bitwise the same value, since a + b == b + a), then the
-// wavefront results are combined in wavefront order.  Deterministic; the
-// result is returned to every thread.  sh holds at least blockDim.x / 64
-// doubles.
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-__device__ inline double wave_min(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
-  return v;
-}
-__device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
-}
-__device__ double block_sum(double v, double *sh) {
-  v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double out = sh[0];
-  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) out += sh[w];
-  __syncthreads();
-  return out;
-}
-__device__ double block_min(double v, double *sh) {
-  v = wave_min(v);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double out = sh[0];
-  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) out = fmin(out, sh[w]);
-  __syncthreads();
-  return out;
-}
-__device__ double block_max(double v, double *sh) {
-  v = wave_max(v);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double out = sh[0];
-  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) out = fmax(out, sh[w]);
-  __syncthreads();
-  return out;
 }
 
 // Divergence-free perturbation velocity.  modes[m] = (kx, ky, a, phase).

@@ -66,13 +66,8 @@ struct Tile {
   v4f z3;
 };
 
-__device__ __forceinline__ void tile_forward(const MlpDev &w, const uint16_t *__restrict__ Xb,
-                                             long long n, long long n0, int c, int g, Tile &t) {
-  const long long node = n0 + c;
-  const bool valid = node < n;
-#pragma unroll
-  for (int kb = 0; kb < 4; ++kb)
-    t.x[kb] = valid ? ld4(Xb + node * 64 + 16 * kb + 4 * g) : v4s{0, 0, 0, 0};
+// The three layers from the input operands already in t.x.
+__device__ __forceinline__ void tile_layers(const MlpDev &w, int c, int g, Tile &t) {
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) {
     v4f acc;
@@ -107,6 +102,16 @@ __device__ __forceinline__ void tile_forward(const MlpDev &w, const uint16_t *__
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb) acc = mfma(ld4(w.W3b + c * 64 + 16 * kb + 4 * g), t.h2[kb], acc);
   t.z3 = acc;
+}
+
+__device__ __forceinline__ void tile_forward(const MlpDev &w, const uint16_t *__restrict__ Xb,
+                                             long long n, long long n0, int c, int g, Tile &t) {
+  const long long node = n0 + c;
+  const bool valid = node < n;
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb)
+    t.x[kb] = valid ? ld4(Xb + node * 64 + 16 * kb + 4 * g) : v4s{0, 0, 0, 0};
+  tile_layers(w, c, g, t);
 }
 
 }  // namespace
@@ -512,6 +517,113 @@ __global__ void k_restrict(int planes, int nxf, int nyf, int m, const T *__restr
 }
 
 // ---------------------------------------------------------------------------
+// The attached correction of a coarse step, fused.
+
+// Feature k of node (x, y) from the observables, as k_features computes it:
+// field f = k % 6 of (rho, Ux, Uy, Cxx, Cxy, Cyy) at stencil position
+// s = k / 6 = 3 (dy + 1) + (dx + 1), periodic.
+__device__ __forceinline__ float stencil_feature(const double *__restrict__ obs, int nx, int ny,
+                                                 int x, int y, int k) {
+  const int s = k / 6, f = k - 6 * s;
+  const int fld = f < 3 ? f : f + 1;
+  const int yy = (y + s / 3 - 1 + ny) % ny, xx = (x + s % 3 - 1 + nx) % nx;
+  return (float)obs[(size_t)fld * nx * ny + (size_t)yy * nx + xx];
+}
+
+// One wave per 16-node tile: features, network, correction in physical
+// units, and the wave's sums of the two momentum corrections.
+__global__ void __launch_bounds__(256) k_correct(MlpDev w, const double *__restrict__ obs, int nx,
+                                                 int ny, const float *__restrict__ mean,
+                                                 const float *__restrict__ stdv,
+                                                 float *__restrict__ corr,
+                                                 double *__restrict__ partial,
+                                                 const int *__restrict__ gate) {
+  if (*gate) return;  // uniform: the drift gate stopped an earlier step
+  const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+  const long long N = (long long)nx * ny;
+  const long long wid = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const long long n0 = wid * 16, node = n0 + c;
+  const bool valid = node < N;
+  double jx = 0.0, jy = 0.0;
+  if (n0 < N) {  // whole wave
+    Tile t;
+    const int y = valid ? (int)(node / nx) : 0, x = valid ? (int)(node - (long long)y * nx) : 0;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      v4s v = {0, 0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = 16 * kb + 4 * g + i;
+        if (valid && k < w.nin)
+          v[i] = bf16_bits((stencil_feature(obs, nx, ny, x, y, k) - mean[k]) / stdv[k]);
+      }
+      t.x[kb] = v;
+    }
+    tile_layers(w, c, g, t);
+    if (valid)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int o = 4 * g + i;
+        if (o < w.nout) {
+          const float v = t.z3[i] * w.out_std[o] + w.out_mean[o];
+          corr[node * w.nout + o] = v;
+          if (o == 0) jx = (double)v;
+          if (o == 1) jy = (double)v;
+        }
+      }
+  }
+  jx = wave_sum(jx);
+  jy = wave_sum(jy);
+  if (lane == 0 && n0 < N) {  // one record per wave of correct_waves(N)
+    partial[2 * wid] = jx;
+    partial[2 * wid + 1] = jy;
+  }
+}
+
+// F = (dJ - <dJ>) + div_h(dtau) and the drift gate (grid-stride; every
+// workgroup forms the lattice mean from the per-wave sums in one fixed
+// order).
+__global__ void __launch_bounds__(256) k_source_gate(const float *__restrict__ corr, int nx,
+                                                     int ny, const double *__restrict__ partial,
+                                                     long long nparts,
+                                                     const double *__restrict__ FLD, double bound,
+                                                     int tag, double *__restrict__ F,
+                                                     int *__restrict__ gate,
+                                                     unsigned long long *__restrict__ drift) {
+  __shared__ double sh[16];
+  if (*gate) return;  // uniform
+  const long long N = (long long)nx * ny;
+  double sx = 0.0, sy = 0.0;
+  for (long long i = threadIdx.x; i < nparts; i += blockDim.x) {
+    sx += partial[2 * i];
+    sy += partial[2 * i + 1];
+  }
+  const double mx = block_sum(sx, sh) / (double)N, my = block_sum(sy, sh) / (double)N;
+  double dmax = 0.0;
+  for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N;
+       r += (long long)gridDim.x * blockDim.x) {
+    const int y = (int)(r / nx), x = (int)(r - (long long)y * nx);
+    const long long e = (long long)y * nx + (x + 1) % nx, wv = (long long)y * nx + (x - 1 + nx) % nx;
+    const long long nn = (long long)((y + 1) % ny) * nx + x, s = (long long)((y - 1 + ny) % ny) * nx + x;
+    auto cc = [&](long long i, int j) -> double { return (double)corr[i * 5 + j]; };
+    const double fx = cc(r, 0) - mx + 0.5 * (cc(e, 2) - cc(wv, 2)) + 0.5 * (cc(nn, 3) - cc(s, 3));
+    const double fy = cc(r, 1) - my + 0.5 * (cc(e, 3) - cc(wv, 3)) + 0.5 * (cc(nn, 4) - cc(s, 4));
+    F[r] = fx;
+    F[N + r] = fy;
+    const double rho = FLD[(size_t)F_RHOS * N + r] + FLD[(size_t)F_RHOP * N + r];
+    const double d = sqrt(fx * fx + fy * fy) / rho;
+    dmax = (d > dmax || !(d == d)) ? d : dmax;  // NaN wins
+  }
+  // a NaN anywhere in the workgroup makes its maximum infinite
+  const double bad = block_sum(dmax == dmax ? 0.0 : 1.0, sh);
+  dmax = bad > 0.0 ? INFINITY : block_max(dmax, sh);
+  if (threadIdx.x == 0) {
+    atomicMax(drift, (unsigned long long)__double_as_longlong(dmax));
+    if (!(dmax <= bound)) atomicCAS(gate, 0, tag);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 
 hipError_t launch_mlp_forward(const MlpDev &w, const uint16_t *Xb, long long n, float *Y,
@@ -603,6 +715,28 @@ hipError_t launch_source_drift(const double *F, const double *FLD, long long N, 
   const long long nb = std::min<long long>(1024, (N + 255) / 256);
   *nblocks = (int)nb;
   hipLaunchKernelGGL(k_source_drift, dim3((unsigned)nb), dim3(256), 0, s, F, FLD, N, partial);
+  return hipGetLastError();
+}
+
+long long correct_waves(long long N) { return (N + 15) / 16; }
+
+hipError_t launch_correct(const MlpDev &w, const double *obs, int nx, int ny, const float *mean,
+                          const float *stdv, float *corr, double *partial, const int *gate,
+                          hipStream_t s) {
+  const long long waves = correct_waves((long long)nx * ny);
+  hipLaunchKernelGGL(k_correct, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, w, obs, nx,
+                     ny, mean, stdv, corr, partial, gate);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_gate(const float *corr, int nx, int ny, const double *partial,
+                              long long nparts, const double *FLD, double bound, int tag,
+                              double *F, int *gate, unsigned long long *drift, hipStream_t s) {
+  const long long N = (long long)nx * ny;
+  long long nb = (N + 255) / 256;
+  if (nb > 128) nb = 128;
+  hipLaunchKernelGGL(k_source_gate, dim3((unsigned)nb), dim3(256), 0, s, corr, nx, ny, partial,
+                     nparts, FLD, bound, tag, F, gate, drift);
   return hipGetLastError();
 }
 

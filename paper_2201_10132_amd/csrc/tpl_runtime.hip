@@ -50,7 +50,7 @@ struct Config {
   int spring_shift = 0;  // spring term: 0 Taylor form, 1 psi at r +- Q/2
   int init_mode = 0;         // 0: base state by a column pre-run; 1: closed form (Hookean)
   long long diag_every = 0;  // health check every k steps of tpl_step (0: at its end)
-  double psi_floor = 0.1;    // unstable if min psi < -psi_floor max psi
+  double psi_floor = 1.0;    // unstable if min psi < -psi_floor max psi
 };
 
 struct Derived {
@@ -265,8 +265,10 @@ struct tpl_ctx {
   tpl_mlp *mlp = nullptr;
   double drift_bound = 0.0, last_drift = 0.0;
   double *obs_d = nullptr;    // [10][N] observables
-  uint16_t *xb_d = nullptr;   // [N][64] standardised features (BF16)
   float *corr_d = nullptr;    // [N][5] correction
+  double *part_d = nullptr;   // [waves][2] per-wave sums of the momentum correction
+  int *gate_d = nullptr;      // drift gate: 0 open, else the step of the call it stopped
+  unsigned long long *drift_d = nullptr;  // largest |F| / rho of the call (double bits)
 };
 
 namespace {
@@ -341,6 +343,7 @@ StepParams make_step_params(const tpl_ctx *x, int nx, int ny, int qs_req) {
   p.F0 = d.F0;
   p.kf = d.kf;
   p.src = (x->src_on && nx == x->c.nx && ny == x->c.ny) ? x->src_d : nullptr;
+  p.gate = (x->mlp && nx == x->c.nx && ny == x->c.ny) ? x->gate_d : nullptr;
   return p;
 }
 
@@ -916,7 +919,8 @@ const Key kKeys[] = {
 
 }  // namespace
 
-int learned_source(tpl_ctx *x);  // attached correction -> x->src_d (below)
+int learned_begin(tpl_ctx *x);  // attached correction: working arrays, gate opened
+int learned_source(tpl_ctx *x, int tag);  // its source for the current state (below)
 
 namespace {
 
@@ -1017,19 +1021,36 @@ namespace {
 int advance(tpl_ctx *x, int64_t n) {
   int rc;
   if (x->mlp) {
+    // every step: the correction's source from the current state, then the
+    // step; the drift gate is checked on the device, and the host learns once
+    // at the end how many steps ran
+    rc = learned_begin(x);
+    if (rc) return rc;
+    const int cur0 = x->cur;
     for (int64_t i = 0; i < n; ++i) {
-      rc = learned_source(x);
+      rc = learned_source(x, (int)(i + 1));
+      if (!rc)
+        rc = run_steps(x, x->buf, x->c.nx, x->c.ny, &x->cur, 1, x->c.time_kernels != 0,
+                       x->c.qsplit);
       if (rc) return rc;
-      if (!(x->last_drift <= x->drift_bound)) {
-        char msg[160];
-        snprintf(msg, sizeof msg, "correction rejected before step %lld: max |F|/rho = %.3e u0 "
-                 "exceeds the drift bound %.3e u0", x->step + 1, x->last_drift, x->drift_bound);
-        return fail(TPL_EREJECTED, msg);
-      }
-      rc = run_steps(x, x->buf, x->c.nx, x->c.ny, &x->cur, 1, x->c.time_kernels != 0,
-                     x->c.qsplit);
-      if (rc) return rc;
-      x->step += 1;
+    }
+    int gate = 0;
+    unsigned long long bits = 0;
+    HIPCHK(hipMemcpyAsync(&gate, x->gate_d, sizeof gate, hipMemcpyDeviceToHost, x->stream));
+    HIPCHK(hipMemcpyAsync(&bits, x->drift_d, sizeof bits, hipMemcpyDeviceToHost, x->stream));
+    HIPCHK(hipStreamSynchronize(x->stream));
+    double dmax;
+    std::memcpy(&dmax, &bits, sizeof dmax);
+    x->last_drift = dmax / x->c.u0;
+    const int64_t ran = gate ? (int64_t)gate - 1 : n;
+    x->cur = cur0 ^ (int)(ran & 1);
+    x->step += ran;
+    if (gate) {
+      char msg[200];
+      snprintf(msg, sizeof msg, "correction rejected before step %lld: max |F|/rho reached "
+               "%.3e u0, above the drift bound %.3e u0", x->step + 1, x->last_drift,
+               x->drift_bound);
+      return fail(TPL_EREJECTED, msg);
     }
     return TPL_OK;
   }
@@ -1640,7 +1661,8 @@ void tpl_destroy(tpl_ctx *x) {
   (void)hipFree(x->scratch);
   (void)hipFree(x->src_d);
   (void)hipFree(x->obs_d);
-  (void)hipFree(x->xb_d);
+  (void)hipFree(x->part_d);
+  (void)hipFree(x->gate_d);
   (void)hipFree(x->corr_d);
   delete x;
 }
@@ -2450,46 +2472,51 @@ int ctx_observables(tpl_ctx *x) {
 
 }  // namespace
 
-// Source of the attached network for the current state; sets last_drift.
-int learned_source(tpl_ctx *x) {
-  tpl_mlp *m = x->mlp;
+// Working arrays of an attached network (on first use) and the drift gate
+// opened, before a run of corrected steps.
+int learned_begin(tpl_ctx *x) {
   const long long N = (long long)x->c.nx * x->c.ny;
-  int rc = mlp_ready(m);
-  if (!rc) rc = ctx_observables(x);
+  int rc = mlp_ready(x->mlp);
   if (!rc) rc = ensure_dev(&x->src_d, 2 * (size_t)N);
+  if (!rc) rc = ensure_dev(&x->part_d, 2 * (size_t)correct_waves(N));
+  if (!rc) rc = ensure_dev(&x->obs_d, (size_t)TPL_NFIELDS * N);
   if (rc) return rc;
-  if (!x->xb_d && hipMalloc(&x->xb_d, (size_t)N * 64 * 2) != hipSuccess) {
-    (void)hipGetLastError();
-    x->xb_d = nullptr;
-    return fail(TPL_ENOMEM, "feature allocation failed");
-  }
   if (!x->corr_d && hipMalloc(&x->corr_d, (size_t)N * 5 * 4) != hipSuccess) {
     (void)hipGetLastError();
     x->corr_d = nullptr;
     return fail(TPL_ENOMEM, "correction allocation failed");
   }
-  // the network's work goes on the context's stream
-  HIPCHK(launch_features(x->obs_d, x->c.nx, x->c.ny, mlp_in_mean(m), mlp_in_std(m), nullptr,
-                         x->xb_d, x->stream));
-  HIPCHK(launch_mlp_forward(mlp_dev(m), x->xb_d, N, x->corr_d, x->stream));
-  HIPCHK(launch_source(x->corr_d, x->c.nx, x->c.ny, x->src_d, x->stream));
-  // total momentum is conserved on both lattices and by the restriction, so
-  // the exact correction has zero lattice mean: remove the predicted mean
-  // (the uniform momentum mode is undamped, a bias there would accumulate)
-  rc = ensure_scratch(x, 2048 + 2);
-  if (rc) return rc;
-  HIPCHK(launch_source_center(x->src_d, N, x->scratch, x->stream));
+  if (!x->gate_d) {
+    void *g = nullptr;
+    if (hipMalloc(&g, 16) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(TPL_ENOMEM, "gate allocation failed");
+    }
+    x->gate_d = static_cast<int *>(g);
+    x->drift_d = reinterpret_cast<unsigned long long *>(static_cast<char *>(g) + 8);
+  }
+  HIPCHK(hipMemsetAsync(x->gate_d, 0, 16, x->stream));  // gate open, largest drift 0
   x->src_on = true;
-  int nb = 0;
-  HIPCHK(launch_source_drift(x->src_d, x->buf.half64(x->cur).FLD, N, x->scratch, &nb,
-                             x->stream));
-  std::vector<double> part(nb);
-  HIPCHK(hipMemcpyAsync(part.data(), x->scratch, sizeof(double) * nb, hipMemcpyDeviceToHost,
-                        x->stream));
-  HIPCHK(hipStreamSynchronize(x->stream));
-  double mx = 0.0;
-  for (double v : part) mx = (v > mx || !(v == v)) ? v : mx;
-  x->last_drift = mx / x->c.u0;
+  return TPL_OK;
+}
+
+// Source of the attached network for the current state, enqueued (no host
+// synchronisation): observables, the fused features + network + sums
+// (k_correct), the centred source with its divergence and the drift gate
+// (k_source_gate; tag = the step of the call it would stop).  Total
+// momentum is conserved on both lattices and by the restriction, so the
+// exact correction has zero lattice mean: the predicted mean is removed (the
+// uniform momentum mode is undamped, a bias there would accumulate).
+int learned_source(tpl_ctx *x, int tag) {
+  tpl_mlp *m = x->mlp;
+  const long long N = (long long)x->c.nx * x->c.ny;
+  int rc = tpl_moments_device(x, x->obs_d, (size_t)TPL_NFIELDS * N);
+  if (rc) return rc;
+  HIPCHK(launch_correct(mlp_dev(m), x->obs_d, x->c.nx, x->c.ny, mlp_in_mean(m), mlp_in_std(m),
+                        x->corr_d, x->part_d, x->gate_d, x->stream));
+  HIPCHK(launch_source_gate(x->corr_d, x->c.nx, x->c.ny, x->part_d, correct_waves(N),
+                            x->buf.half64(x->cur).FLD, x->drift_bound * x->c.u0, tag, x->src_d,
+                            x->gate_d, x->drift_d, x->stream));
   return TPL_OK;
 }
 
@@ -2738,6 +2765,9 @@ int tpl_attach_mlp(tpl_ctx *x, tpl_mlp *m, double drift_bound) {
   }
   if (m->nin != 54 || m->nout != 5)
     return fail(TPL_EINVAL, "a correction network maps 54 features to 5 outputs");
+  if (x->c.inplace || x->c.gradients || x->c.spring_shift)
+    return fail(TPL_EINVAL, "a correction network runs on the two-array step with lagged "
+                            "gradients and the Taylor spring term");
   if (!(drift_bound > 0)) return fail(TPL_EINVAL, "drift bound must be > 0");
   x->mlp = m;
   x->drift_bound = drift_bound;

@@ -159,9 +159,9 @@ def evaluate(torch, mlp, cfg, factor=4, nq=8, fine_steps=400, every=40, pre_step
     """Fine judge vs plain and corrected coarse runs from the same restricted
     initial state.  Errors: relative L2 norm of the coarse mixture velocity
     against the restricted fine one, at every `every` fine steps.  Gate: the
-    correction is rejected if its error exceeds twice the plain error at any
-    evaluation time, or 5 % at the end, or if the runtime drift gate stops a
-    step."""
+    correction is accepted only if it ends below the plain run's error (a
+    gain above 1) and below 5 %, never exceeds twice the plain error at an
+    evaluation time, and the runtime drift gate stops no step."""
     fine = Tpl(cfg["nx"], cfg["ny"], cfg["Re"], cfg["Wi"], cfg["beta"], periods=cfg["periods"],
                nq=nq, pre_steps=pre_steps)
     fine.init(seed=cfg["seed"], perturbation=perturbation)
@@ -197,7 +197,8 @@ def evaluate(torch, mlp, cfg, factor=4, nq=8, fine_steps=400, every=40, pre_step
         times.append(n)
         e_plain.append(uerr(plain))
         e_corr.append(uerr(corr) if rejected is None else float("nan"))
-    ok = rejected is None and all(c <= 2 * p for c, p in zip(e_corr, e_plain)) and e_corr[-1] <= 0.05
+    ok = (rejected is None and all(c <= 2 * p for c, p in zip(e_corr, e_plain))
+          and e_corr[-1] <= 0.05 and e_corr[-1] < e_plain[-1])
     out = dict(times=times, err_plain=e_plain, err_corrected=e_corr,
                gain=(e_plain[-1] / e_corr[-1]) if rejected is None and e_corr[-1] > 0 else 0.0,
                accepted=bool(ok), rejected_by_drift_gate=rejected, coarse_unstable=None)

@@ -318,7 +318,7 @@ def test_batch_model2_rules():
 
 def test_health_check_knobs():
     t = P.Tpl(16, 16, 20.0, 0.5, 0.8)
-    assert t.query("diag_every") == 0 and t.query("psi_floor") == 0.1
+    assert t.query("diag_every") == 0 and t.query("psi_floor") == 1.0
     t.set_param("diag_every", 5)
     t.set_param("psi_floor", 0.0)
     assert t.query("diag_every") == 5 and t.query("psi_floor") == 0.0
