@@ -130,7 +130,8 @@ def main():
                    "nq": w["nq"], "nqd": main64["nqd"], "periods": w["periods"], "Re": w["Re"],
                    "Wi": w["Wi"], "beta": w["beta"], "perturbation": w["perturbation"],
                    "base_state_pre_steps": args.pre_steps, "parallelism": "single GPU"},
-        "roofline": roofline(main64, traffic_bytes(args.traffic_file)),
+        "roofline": dict(roofline(main64, traffic_bytes(args.traffic_file)),
+                         **copy_ceiling(torch, main64)),
         "mqlups": round(main64["mlups"] * main64["nqd"], 1),
         "kernel_ms": round(main64["kernel_ms"], 4),
         "launch": {"qsplit": int(main64["qsplit"]), "group": main64["group"],
@@ -201,8 +202,9 @@ def main():
             e.pop("amplitude_rel_err_vs_fp64")  # another model: not comparable
             e["speed_vs_model1_fp64"] = e.pop("speedup_vs_fp64")
     if not args.no_growth:
-        out["growth_rate"] = measure_growth(torch, dict(w, nq=BATCH["nq"]), args.pre_steps,
-                                            args.growth_steps)
+        # from the converged base state (the library's default column
+        # pre-run): the deviations from it are then the perturbation's
+        out["growth_rate"] = measure_growth(torch, dict(w, nq=BATCH["nq"]), -1, args.growth_steps)
     if not args.no_batch:
         out["batched"] = measure_batch(torch, args.batch_instances, max(5, args.steps // 2),
                                        args.warmup, args.pre_steps, args.one_by_one_steps)
@@ -275,8 +277,6 @@ def measure(torch, w, precision, steps, warmup, pre_steps, **params) -> dict:
 def measure_batch(torch, n, steps, warmup, pre_steps, obo_steps) -> dict:
     """The batched sweep: all instances advanced together (graph replays of
     the batched step), then the same instances stepped one by one."""
-    import math
-
     import paper_2201_10132_amd as P
     from paper_2201_10132_amd import inputs
 
@@ -289,13 +289,11 @@ def measure_batch(torch, n, steps, warmup, pre_steps, obo_steps) -> dict:
     b.init()
     init_s = time.perf_counter() - t0
     b.step(warmup)
-    a0 = b.amplitudes()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(steps)  # synchronises before returning
     wall = time.perf_counter() - t0
     kernel_ms = b.query("kernel_ms")  # HIP events around the step launches only
-    a1 = b.amplitudes()
     nodes = b.query("nodes")
     bytes_all = sum(b.instance(i).query("bytes_per_step") for i in range(n))
     res = {
@@ -312,11 +310,6 @@ def measure_batch(torch, n, steps, warmup, pre_steps, obo_steps) -> dict:
         "pre_steps": pre_steps, "unstable": int(b.query("unstable")),
         "bytes_active_fraction": b.query("bytes_per_step") / bytes_all,
     }
-    g = [math.log(y / x) / steps for x, y in zip(a0, a1) if x > 0 and y > 0]
-    if g:
-        g.sort()
-        res["growth_rate_median"] = g[len(g) // 2]
-        res["growth_rate_range"] = [g[0], g[-1]]
     # the same instances one after another, each with its own launches
     status = b.status()
     res["unstable_instances"] = [i for i, u in enumerate(status) if u]
@@ -410,6 +403,10 @@ def measure_learned(torch, pre_steps) -> dict:
     held = inputs.c5_trajectories(c["held_out_seeds"])
     evals = [LL.evaluate(torch, mlp, cfg, pre_steps=pre_steps) for cfg in held]
     plain_ms, corr_ms = LL.coarse_step_ms(torch, mlp, trs[0])
+    # the plain fine FP64 step of the same workload (1024^2, NQ 8): what a
+    # corrected coarse step stands in for
+    fine = measure(torch, dict(WORKLOAD, nq=8, Re=trs[0]["Re"], Wi=trs[0]["Wi"]), 0, 10, 3,
+                   pre_steps)
     nc = 256 * 256
     res = {
         "workload": "kolmogorov_learned_coarse256_from_fine1024_nq8",
@@ -431,6 +428,9 @@ def measure_learned(torch, pre_steps) -> dict:
         # fine-lattice node updates the corrected coarse step stands for:
         # 16 fine nodes per coarse node, 4 fine steps per coarse step
         "mlups_equivalent": round(nc * 64 / (corr_ms * 1e-3) / 1e6, 1),
+        "fine_fp64_nq8_mlups": round(fine["mlups"], 1),
+        "speedup_vs_fine_fp64": round(nc * 64 / (corr_ms * 1e-3) / 1e6 / fine["mlups"], 2),
+        "corrected_over_plain_coarse": round(corr_ms / plain_ms, 3),
     }
     print(f"# learned: generate {res['generate_s']} s, train {res['train_s']} s, loss "
           f"{l0:.3f} -> {l1:.3f}, accepted {res['accepted']}/{len(evals)}, gains "
@@ -438,6 +438,29 @@ def measure_learned(torch, pre_steps) -> dict:
           file=sys.stderr, flush=True)
     mlp.close()
     return res
+
+
+def copy_ceiling(torch, m, gib=4, reps=10):
+    """A plain device-to-device copy of `gib` GiB on the same GPU (read +
+    write bytes over its time): the bandwidth a streaming kernel reaches
+    here, for context beside the 8 TB/s peak."""
+    n = gib << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    achieved = m["bytes_step"] / (m["kernel_ms"] * 1e-3) / 1e9
+    return {"copy_ceiling_gbs": round(gbs, 1), "frac_of_copy": round(achieved / gbs, 4)}
 
 
 def roofline(m, traffic):

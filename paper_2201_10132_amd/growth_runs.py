@@ -13,8 +13,13 @@ decay rate gamma = d ln A / dn, driven through the C ABI.
               run stored in FP64, FP32 and BF16; gamma and A(n) of the two
               reduced forms against FP64 (NQ 6: the largest Q-grid at which
               the FP64 state, two halves of 230 GB, fits one GPU).
+  c4          the batched sweep: 256 seeded instances (sizes from
+              {128, ..., 512}^2, Re, Wi, beta drawn per instance), FP32, NQ 6,
+              one batch: A(n) of every instance every `every` steps, its
+              growth rate fitted from step 1000 (to the first step with
+              A > 1e-2), and the instances flagged unstable.
 
-Usage: python -m paper_2201_10132_amd.growth_runs {stability,c2,c3} [--steps N] [--nq Q]
+Usage: python -m paper_2201_10132_amd.growth_runs {stability,c2,c3,c4} [--steps N] [--nq Q]
 """
 from __future__ import annotations
 
@@ -25,7 +30,8 @@ import time
 
 import numpy as np
 
-from .tpl import TPL_BF16, TPL_FP32, TPL_FP64, Tpl, TplError
+from . import inputs
+from .tpl import TPL_BF16, TPL_FP32, TPL_FP64, Batch, Tpl, TplError
 
 
 def track(nx, ny, periods, Wi, nq, precision, steps, every, pre_steps=3000, perturbation=1e-4,
@@ -75,7 +81,7 @@ def fit_gamma(n, A, start, stop_amp=1e-2):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["stability", "c2", "c3"])
+    ap.add_argument("what", choices=["stability", "c2", "c3", "c4"])
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--every", type=int, default=None)
@@ -101,6 +107,39 @@ def main():
                                      mass_S=r["mass_S"], mass_P=r["mass_P"],
                                      ms_per_step=round(r["wall_s"] / max(1, steps) * 1e3, 3),
                                      n=r["n"][::8], A=r["A"][::8]))
+    elif args.what == "c4":
+        steps, nq, every = args.steps or 5000, args.nq or 6, args.every or 250
+        insts = inputs.c4_instances(256)
+        b = Batch(insts, precision=TPL_FP32, nq=nq, pre_steps=args.pre_steps)
+        t0 = time.perf_counter()
+        b.init()
+        ns, A = [0], [list(b.amplitudes())]
+        n = 0
+        while n < steps:
+            k = min(every, steps - n)
+            b.step(k)
+            n += k
+            ns.append(n)
+            A.append(list(b.amplitudes()))
+            print(f"# c4 step {n}: {int(b.query('unstable'))} unstable ({time.perf_counter() - t0:.0f} s)",
+                  file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        status = list(b.status())
+        A = np.array(A)  # [samples][instances]
+        cases = []
+        for i, d in enumerate(insts):
+            g, win = fit_gamma(ns, A[:, i], 1000) if not status[i] else (None, None)
+            cases.append(dict(i=i, nx=d["nx"], ny=d["ny"], Re=round(d["Re"], 3), Wi=round(d["Wi"], 4),
+                              beta=round(d["beta"], 4), unstable=bool(status[i]), gamma=g,
+                              fit_window=win, A_end=None if status[i] else float(A[-1, i])))
+        gs = sorted(c["gamma"] for c in cases if c["gamma"] is not None)
+        res.update(nq=nq, steps=steps, pre_steps=args.pre_steps, every=every,
+                   nodes=int(b.query("nodes")), wall_s=round(wall, 1),
+                   unstable=[c["i"] for c in cases if c["unstable"]],
+                   growing=sum(1 for g in gs if g > 0), decaying=sum(1 for g in gs if g <= 0),
+                   gamma_quartiles=[gs[len(gs) // 4], gs[len(gs) // 2], gs[3 * len(gs) // 4]] if gs else None,
+                   cases=cases)
+        b.close()
     else:
         steps, nq, every = args.steps or 2000, args.nq or 6, args.every or 100
         res.update(nq=nq, steps=steps, forms={})

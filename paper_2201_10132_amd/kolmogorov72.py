@@ -13,13 +13,20 @@ extension stays near the equilibrium value for Wi = 0.1 and reaches about
 twice that for Wi = 5.  The paper's figures are not part of its text, so
 these are qualitative checks.
 
+Each cell is forced so that its laminar profile has amplitude u0
+(calibrate_force): Re = U l / nu is defined with the amplitude U of the
+laminar flow.  With F0 = nu u0 k^2 instead (--force-from-nu) the lattice
+polymer's stress diffusion and the FENE shear thinning drive the elastic
+cells faster than u0, which raises their effective Re with Wi.
+
 With --spring-shift the spring term is the shift itself, psi at the two
 beads r +- Q/2, instead of its first-order Taylor form: the dumbbells here
 span a sizeable part of the forcing wavelength (sigma k = 1.1), where the
 two differ.  Options the batched step does not take (the component-stress
 quasi-equilibria, qe_model 2) run the three cells as separate contexts.
 
-Usage: python -m paper_2201_10132_amd.kolmogorov72 [--t-end 2000] [--spring-shift] [--out file.json]
+Usage: python -m paper_2201_10132_amd.kolmogorov72 [--t-end 2000] [--spring-shift]
+       [--force-from-nu] [--out file.json]
 """
 from __future__ import annotations
 
@@ -88,19 +95,56 @@ def convective_steps(u0=CELL["u0"]):
     return l / u0
 
 
+def laminar_amplitude(t):
+    """Amplitude of the sin(k y) component of the x-averaged U_x over u0."""
+    m = t.moments()
+    ny = m.shape[1]
+    y = np.arange(ny)
+    k = 2.0 * math.pi * CELL["periods"] / ny
+    return 2.0 / ny * float(np.sum(m[1].mean(axis=1) * np.sin(k * y))) / CELL["u0"]
+
+
+def calibrate_force(Wi, nq=32, iters=4, **params):
+    """Force scale at which the laminar profile's amplitude is u0.
+
+    Sec. VII defines Re = U l / nu with U the amplitude of the laminar flow
+    the force induces, and F = eta U / l^2 as that force for a fluid of
+    viscosity eta.  On the lattice the polymer's stress also diffuses in r
+    (its r- and Q-diffusivities are tied), and FENE dumbbells thin in shear,
+    so F0 = nu u0 k^2 drives a laminar flow faster than u0 (1.3 u0 at
+    Wi = 5 on a 16-point Q-grid): the effective Re grows with Wi.  This
+    scales F0 until the forced x-invariant state (the column pre-run,
+    5 max(l^2/nu, lambda) steps, through the C ABI) has amplitude u0."""
+    fs = 1.0
+    for _ in range(iters):
+        t = Tpl(1, CELL["ny"], CELL["Re"], Wi, CELL["beta"], periods=CELL["periods"],
+                u0=CELL["u0"], nq=nq, pre_steps=-1, force_scale=fs,
+                **{"drift_cap": DRIFT_CAP, **params})
+        t.init(seed=0, perturbation=0.0)
+        a = laminar_amplitude(t)
+        t.close()
+        fs /= a
+    return fs
+
+
 def run(t_end=2000.0, every=1.0, wis=WIS, nq=32, seed=0, perturbation=1e-3,
-        precision=TPL_FP64, progress=True, **params):
+        precision=TPL_FP64, progress=True, laminar_u0=True, **params):
     """Advance the three cells together; sample the diagnostics every
-    `every` convective times.  Returns dict(t, enstrophy[w], qrms[w],
-    amplitude[w], unstable[w])."""
+    `every` convective times.  laminar_u0: force each cell so that its
+    laminar amplitude is u0 (calibrate_force); else F0 = nu u0 k^2.  Returns
+    dict(t, enstrophy[w], qrms[w], amplitude[w], unstable[w],
+    force_scale[w])."""
     insts = [dict(CELL, Wi=w, seed=seed, perturbation=perturbation) for w in wis]
     cls = _Cells if params.get("qe_model", 1) != 1 else Batch
     params = {"drift_cap": DRIFT_CAP, **params}
+    fscale = [calibrate_force(w, nq=nq, **params) if laminar_u0 else 1.0 for w in wis]
     b = cls(insts, precision=precision, nq=nq, pre_steps=0, **params)
+    for i, f in enumerate(fscale):
+        b.instance(i).set_param("force_scale", f)
     b.init()
     tc = convective_steps()
     out = dict(t=[], enstrophy=[[] for _ in wis], qrms=[[] for _ in wis],
-               amplitude=[[] for _ in wis], steps_per_convective_time=tc)
+               amplitude=[[] for _ in wis], steps_per_convective_time=tc, force_scale=fscale)
     n_done = 0
     t0 = last = time.perf_counter()
     k = 0
@@ -169,15 +213,19 @@ def main():
                     help="psi at the beads instead of the Taylor form of the spring term")
     ap.add_argument("--drift-cap", type=float, default=DRIFT_CAP,
                     help="cap on the Q-drift per step (0: none)")
+    ap.add_argument("--force-from-nu", action="store_true",
+                    help="F0 = nu u0 k^2 for every cell instead of the force that makes the "
+                         "laminar amplitude u0")
     args = ap.parse_args()
     extra = dict(spring_shift=1) if args.spring_shift else {}
     extra["drift_cap"] = args.drift_cap
     res = run(t_end=args.t_end, every=args.every, nq=args.nq, perturbation=args.perturbation,
-              **extra)
+              laminar_u0=not args.force_from_nu, **extra)
     rows = summary(res)
-    line = dict(experiment="kolmogorov_72x72_re3.5_beta0.5_fene_nq%d%s"
-                % (args.nq, "_shifted_spring" if args.spring_shift else ""), u0=CELL["u0"],
-                drift_cap=args.drift_cap,
+    line = dict(experiment="kolmogorov_72x72_re3.5_beta0.5_fene_nq%d%s%s"
+                % (args.nq, "_shifted_spring" if args.spring_shift else "",
+                   "_force_from_nu" if args.force_from_nu else ""), u0=CELL["u0"],
+                drift_cap=args.drift_cap, force_scale=res["force_scale"],
                 steps=res["steps"], wall_s=round(res["wall_s"], 1),
                 lattice_updates_per_s=res["lattice_updates_per_s"], summary=rows)
     print(json.dumps(line), flush=True)
