@@ -151,7 +151,7 @@ def main():
         forms[f"fp64_1024x1024_nq{nq}"] = form_entry(f64q, None)
         f32q = measure(torch, wq, 1, args.steps, args.warmup, args.pre_steps)
         forms[f"fp32_1024x1024_nq{nq}"] = form_entry(f32q, f64q)
-        # BF16 non-equilibrium form (precision 2)
+        # BF16 form (precision 2)
         b16 = measure(torch, w, 2, args.steps, args.warmup, args.pre_steps)
         forms["bf16_1024x1024_nq16"] = form_entry(b16, main64)
         forms["bf16_1024x1024_nq16"]["speedup_vs_fp32"] = round(b16["mlups"] / f32["mlups"], 3)
@@ -472,7 +472,7 @@ def roofline(m, traffic):
 def measure_growth(torch, w, pre_steps, steps, every=100):
     """Growth rate of the perturbation amplitude, gamma = d ln A / dn (least
     squares over samples every `every` steps from steps/4 on), of the same
-    seeded run stored in FP64, FP32 and BF16 non-equilibrium form; the
+    seeded run stored in FP64, FP32 and BF16 form; the
     storage forms' error is stated against the FP64 run.  The same FP64 run
     with same-step gradients, and with the shifted spring term, shows what
     those readings change."""

@@ -60,8 +60,12 @@ enum {
  *                base state), FP64 per-node fields
  *   TPL_BF16     solvent and psi as TPL_FP32; the polymer populations as the
  *                BF16 rounding (nearest even, 8 significant bits) of their
- *                deviation from the same reference (54 bytes per (r, Q)-node
- *                against 104 for FP32 and 208 for FP64).  Its error is set by
+ *                deviation from the same reference, except the rest
+ *                population (it never leaves its node), kept in FP32 and
+ *                carrying the rounding residual of the other 24, so that the
+ *                stored density of every (r, Q)-node, and the mass, are exact
+ *                to FP32 (56 bytes per (r, Q)-node against 104 for FP32 and
+ *                208 for FP64).  Its error is set by
  *                the size of the deviations: small near the reference (a
  *                perturbed, converged base state), large where the state has
  *                moved far from it (a base state still spinning up)
@@ -106,8 +110,8 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
 
 /* Set a parameter before tpl_init (TPL_ESTATE afterwards, except for the
  * launch/timing knobs qsplit, group_x, group_y, group_sync, autotune and
- * time_kernels and the health-check knobs diag_every and psi_floor, which
- * may be set at any time and change no result;
+ * time_kernels and the health-check knobs diag_every, psi_floor and
+ * keep_good, which may be set at any time and change no result;
  * TPL_EINVAL for an unknown key or a value out of range).  Keys and defaults:
  *   nq 16         Q points per axis (even, 4..48)
  *   spring 0      0 = FENE (Warner), 1 = Hookean
@@ -202,6 +206,10 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
  *                 about -1e-2 max psi (the 64^2 workload) and, with strongly
  *                 stretched FENE dumbbells (Wi 5 on a 16-point Q-grid),
  *                 -0.3 max psi; a diverging run goes far below
+ *   keep_good 0   1 = a failed check puts back the state of the last passed
+ *                 check (see tpl_step); costs a device copy of the state
+ *                 (bytes_state / 2, allocated on the first such tpl_step)
+ *                 and one device-to-device copy of it per check
  * Any parameter also fixes the derived values read by tpl_query. */
 int tpl_set_param(tpl_ctx *ctx, const char *key, double value);
 
@@ -241,9 +249,11 @@ int tpl_init(tpl_ctx *ctx, uint64_t seed, double perturbation);
  * diag_every is 0) a health check reads the mixture velocity and psi of
  * every (r, Q)-node: if any is NaN or Inf, or min psi < -psi_floor max psi
  * (psi is a density of dumbbell configurations, Sec. VI.B), the call returns
- * TPL_EUNSTABLE at once, with the state and the step counter (tpl_query key
- * step) of that check and the cause in tpl_last_error; the state is not
- * rolled back (tpl_save / tpl_load restore a checkpoint). */
+ * TPL_EUNSTABLE at once, with the cause in tpl_last_error.  With keep_good 0
+ * the state and the step counter (tpl_query key step) are those of the
+ * failed check; with keep_good 1 they are put back to the last check that
+ * passed in this call, or to the call's start if none did (the message
+ * names that step).  TPL_ENOMEM if keep_good cannot allocate its copy. */
 int tpl_step(tpl_ctx *ctx, int64_t n);
 
 /* Observables of the last completed step (step 0 = the initial state), SoA
@@ -294,7 +304,8 @@ int tpl_set_populations(tpl_ctx *ctx, int species, const void *host,
 
 /* Checkpoint: parameters, step counter and the full state in storage
  * precision.  tpl_load requires a context created with the same lattice
- * size and parameters and resumes bitwise. */
+ * size and parameters (the launch, timing and health knobs may differ) and
+ * resumes bitwise. */
 int tpl_save(tpl_ctx *ctx, const char *path);
 int tpl_load(tpl_ctx *ctx, const char *path);
 

@@ -109,7 +109,7 @@ struct InstDev {
 // BF16 form), 0: read a, write b.
 template <typename T>
 hipError_t launch_step(const StepParams &p, StateT<T> a, StateT<T> b,
-                       StepRef ref, const QNode *qtab, hipStream_t s, bool neq = false,
+                       StepRef ref, const QNode *qtab, hipStream_t s, bool b16 = false,
                        int ip = 0);
 // Non-local spring term: S = kappa sum_Q Fhat [psi(r + Q/2) - psi(r - Q/2)]
 // of the read half's psi (bilinear interpolation, periodic) into its FLD

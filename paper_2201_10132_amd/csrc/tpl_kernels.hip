@@ -398,6 +398,7 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
     // the store reference), which halves the registers they hold
     using GT = std::conditional_t<B16, float, double>;
     GT g[25];
+    float rest_res = 0.0f;  // BF16 form: rounding residual of velocities 1..24
     auto G = [&](int k) -> double {
       if constexpr (B16) return rq(rpull, y, q, k) + (double)g[k];
       else return g[k];
@@ -419,12 +420,16 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
       for (int k = 0; k < 25; ++k)
         g[k] = full(ldo(plane(a.XP, qn.plane[k]), osrc[pdir(k)]), rq(rpull, y, q, k));
     } else {
-      // BF16 form: the 25 pulled deviations, 16 bits each, at half the byte
-      // offsets of the FP32 planes
+      // BF16 form: the 24 pulled deviations, 16 bits each, at half the byte
+      // offsets of the FP32 planes; the node's own rest population in FP32
+      // from its two 16-bit halves (planes 0 and 25)
       const uint16_t *xp = reinterpret_cast<const uint16_t *>(a.XP);
 #pragma unroll
-      for (int k = 0; k < 25; ++k)
+      for (int k = 1; k < 25; ++k)
         g[k] = (float)from_bf16(ldo(uni(xp + (size_t)qn.plane[k] * N), osrc[pdir(k)] >> 1));
+      const uint32_t hi = ldo(uni(xp + (size_t)q * N), oR >> 1);
+      const uint32_t lo = ldo(uni(xp + (size_t)(25 * nqd + q) * N), oR >> 1);
+      g[0] = __uint_as_float((hi << 16) | lo);
     }
     double psi = 0.0, Jrx = 0.0, Jry = 0.0, JQx = 0.0, JQy = 0.0;
     double P2[4][4] = {};  // model 2: second moments sum xi_a xi_b g (a <= b)
@@ -516,9 +521,18 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
       }
       const double go = p.c1P * G(k) + t;  // post-collision population
       mg[pdir(k)] += go;
-      if constexpr (B16) g[k] = (float)(go - rq(rstore, y, q, k));
-      else g[k] = go;
+      if constexpr (B16) {
+        // the deviation from the store reference; the rest population (k = 0)
+        // collects what BF16 rounding takes from the other 24 (each such
+        // residual is exact in FP32)
+        const float dv = (float)(go - rq(rstore, y, q, k));
+        g[k] = dv;
+        if (k > 0) rest_res += dv - (float)from_bf16(to_bf16(dv));
+      } else {
+        g[k] = go;
+      }
     }
+    if constexpr (B16) g[0] += rest_res;
     if (active) {
       if constexpr (IP == 1) {
         // the source planes are read again here rather than held across the
@@ -544,15 +558,20 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const StateT<T> &
               stored<T>(g[k], rq(rstore, y, q, k)));
         sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
       } else {
-        // BF16 form: the 25 deviations (from the store reference) rounded to
-        // 16 bits, plane stride opaque as above
+        // BF16 form: the 24 deviations (from the store reference) rounded to
+        // 16 bits, the rest population's FP32 bits split over planes 0 and
+        // 25; plane stride opaque as above
         sto(wplane(b.PSI, q), oR, stored<T>(psi, rpq(y, q)));
         uint64_t stride = (uint64_t)nqd * (uint64_t)N * 2u;
         asm volatile("" : "+s"(stride));
         char *pw = reinterpret_cast<char *>(uni(reinterpret_cast<uint16_t *>(b.XP) + (size_t)q * N));
+        const uint32_t u0 = __float_as_uint(g[0]);
+        sto(reinterpret_cast<uint16_t *>(pw), oR >> 1, (uint16_t)(u0 >> 16));
 #pragma unroll
-        for (int k = 0; k < 25; ++k)
+        for (int k = 1; k < 25; ++k)
           sto(reinterpret_cast<uint16_t *>(pw + (size_t)k * stride), oR >> 1, to_bf16(g[k]));
+        sto(reinterpret_cast<uint16_t *>(pw + (size_t)25 * stride), oR >> 1,
+            (uint16_t)(u0 & 0xffffu));
       }
     }
     Mxx += psi * qn.qx * qn.fx;
@@ -1235,29 +1254,53 @@ template hipError_t launch_same_step_fields<float>(const StepParams &, StateT<fl
                                                    const QNode *, hipStream_t, int);
 
 // BF16 form: conversions of the polymer populations to and from FP32
-// deviations, elementwise over [25][nqd][N] (auxiliary paths: initialisation,
-// state exchange, diagnostics).
-__global__ void k_bf16_decode(long long n, const uint16_t *__restrict__ src,
-                              float *__restrict__ dev) {
-  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) dev[j] = (float)from_bf16(src[j]);
+// deviations ([25][nqd][N] floats).  Velocities 1..24 are BF16 planes; the
+// rest population (velocity 0, which never leaves its node) is kept in full
+// FP32, its upper 16 bits in plane 0 and its lower 16 in plane 25, and
+// carries the node's rounding residual: the 24 deviations lost to BF16
+// rounding are added to it, so the node's density (and the lattice's mass)
+// is stored to FP32 accuracy.
+__device__ __forceinline__ double rest_with_residual(double rest, const double *d) {
+  double e = 0.0;
+#pragma unroll
+  for (int k = 1; k < 25; ++k) e += d[k] - from_bf16(to_bf16(d[k]));
+  return rest + e;
 }
-__global__ void k_bf16_encode(long long n, const float *__restrict__ dev,
+
+__global__ void k_bf16_decode(long long nq, const uint16_t *__restrict__ src,
+                              float *__restrict__ dev) {
+  // one thread per (Q-node, r) pair; nq = nqd N
+  const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (j >= nq) return;
+  dev[j] = __uint_as_float(((uint32_t)src[j] << 16) | (uint32_t)src[25 * nq + j]);
+#pragma unroll 4
+  for (int k = 1; k < 25; ++k) dev[k * nq + j] = (float)from_bf16(src[k * nq + j]);
+}
+
+__global__ void k_bf16_encode(long long nq, const float *__restrict__ dev,
                               uint16_t *__restrict__ dst) {
-  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) dst[j] = to_bf16(dev[j]);
+  const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (j >= nq) return;
+  double d[25];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) d[k] = dev[k * nq + j];
+#pragma unroll
+  for (int k = 1; k < 25; ++k) dst[k * nq + j] = to_bf16(d[k]);
+  const uint32_t u = __float_as_uint((float)rest_with_residual(d[0], d));
+  dst[j] = (uint16_t)(u >> 16);
+  dst[25 * nq + j] = (uint16_t)(u & 0xffffu);
 }
 
 hipError_t launch_bf16_decode(int nqd, long long N, StateT<float> a, float *dev, hipStream_t s) {
-  const long long n = 25 * N * nqd;
-  hipLaunchKernelGGL(k_bf16_decode, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+  const long long nq = N * nqd;
+  hipLaunchKernelGGL(k_bf16_decode, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq,
                      reinterpret_cast<const uint16_t *>(a.XP), dev);
   return hipGetLastError();
 }
 hipError_t launch_bf16_encode(int nqd, long long N, const float *dev, StateT<float> a,
                               hipStream_t s) {
-  const long long n = 25 * N * nqd;
-  hipLaunchKernelGGL(k_bf16_encode, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, dev,
+  const long long nq = N * nqd;
+  hipLaunchKernelGGL(k_bf16_encode, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, dev,
                      reinterpret_cast<uint16_t *>(a.XP));
   return hipGetLastError();
 }

@@ -51,6 +51,7 @@ struct Config {
   int init_mode = 0;         // 0: base state by a column pre-run; 1: closed form (Hookean)
   long long diag_every = 0;  // health check every k steps of tpl_step (0: at its end)
   double psi_floor = 1.0;    // unstable if min psi < -psi_floor max psi
+  int keep_good = 0;         // 1: a failed check restores the last checked state
 };
 
 struct Derived {
@@ -269,6 +270,11 @@ struct tpl_ctx {
   double *part_d = nullptr;   // [waves][2] per-wave sums of the momentum correction
   int *gate_d = nullptr;      // drift gate: 0 open, else the step of the call it stopped
   unsigned long long *drift_d = nullptr;  // largest |F| / rho of the call (double bits)
+  // keep_good: copy of the last state that passed a health check
+  char *good_d = nullptr;
+  size_t good_bytes = 0;
+  long long good_step = 0;
+  int good_cur = 0, good_ip_odd = 0;
 };
 
 namespace {
@@ -277,7 +283,9 @@ size_t state_elems(const tpl_ctx *x, int which) {
   const size_t N = (size_t)x->c.nx * x->c.ny, nqd = x->d.nqd;
   switch (which) {
     case 0: return 9 * N;
-    case 1: return 25 * nqd * N;
+    // the BF16 form holds a 26th 16-bit plane per Q-node: the lower half of
+    // the rest population's FP32 deviation
+    case 1: return (x->c.precision == TPL_BF16 ? 26 : 25) * nqd * N;
     case 2: return nqd * N;
     default: return (size_t)NF * N;
   }
@@ -364,7 +372,7 @@ size_t elem_size(const tpl_ctx *x) { return x->c.precision == TPL_FP64 ? 8 : 4; 
 size_t xp_size(const tpl_ctx *x) {
   return x->c.precision == TPL_FP64 ? 8 : x->c.precision == TPL_FP32 ? 4 : 2;
 }
-// FP32 reference forms (FP32 storage and the BF16 non-equilibrium form)
+// FP32 reference forms (FP32 storage and the BF16 form)
 bool fp32(const tpl_ctx *x) { return x->c.precision != TPL_FP64; }
 bool bf16(const tpl_ctx *x) { return x->c.precision == TPL_BF16; }
 
@@ -427,7 +435,7 @@ int build_step_ref(tpl_ctx *x) {
   return TPL_OK;
 }
 
-// BF16 non-equilibrium form: an FP32 view of one half whose polymer
+// BF16 form: an FP32 view of one half whose polymer
 // populations are decoded into a temporary (FP32 deviations), for the
 // auxiliary kernels; write-back re-encodes them.
 // For the other forms the view is the stored half itself.
@@ -915,7 +923,31 @@ const Key kKeys[] = {
     {"init_mode", nullptr, &Config::init_mode, nullptr},
     {"diag_every", nullptr, nullptr, &Config::diag_every},
     {"psi_floor", &Config::psi_floor, nullptr, nullptr},
+    {"keep_good", nullptr, &Config::keep_good, nullptr},
 };
+
+// Knobs that change no state (launch shape, timing, health checks): they may
+// be set at any time and do not take part in matching a checkpoint.
+bool is_runtime_knob(const char *key) {
+  return !std::strcmp(key, "qsplit") || !std::strcmp(key, "time_kernels") ||
+         !std::strncmp(key, "group_", 6) || !std::strcmp(key, "autotune") ||
+         !std::strcmp(key, "diag_every") || !std::strcmp(key, "psi_floor") ||
+         !std::strcmp(key, "keep_good");
+}
+
+// Whether two configurations describe the same lattice and scheme (every
+// field but the runtime knobs).
+bool same_state_config(const Config &a, const Config &b) {
+  if (a.nx != b.nx || a.ny != b.ny || a.Re != b.Re || a.Wi != b.Wi || a.beta != b.beta)
+    return false;
+  for (const Key &k : kKeys) {
+    if (is_runtime_knob(k.name)) continue;
+    if (k.dbl && !(a.*(k.dbl) == b.*(k.dbl))) return false;
+    if (k.in && a.*(k.in) != b.*(k.in)) return false;
+    if (k.ll && a.*(k.ll) != b.*(k.ll)) return false;
+  }
+  return true;
+}
 
 }  // namespace
 
@@ -1103,6 +1135,69 @@ int check_health(tpl_ctx *x) {
   return judge_health(x, h);
 }
 
+// The parts of state half h that a step reads (populations: the single array
+// when streamed in place; lagged psi; per-node fields; stored moments):
+// device addresses and byte counts.
+void half_parts(const tpl_ctx *x, int h, char *ptr[5], size_t nb[5]) {
+  const Buffers &B = x->buf;
+  const size_t hp = B.pop_half(h);
+  ptr[0] = static_cast<char *>(B.XS) + hp * B.nXS * B.esize;
+  ptr[1] = static_cast<char *>(B.XP) + hp * B.nXP * B.xsize;
+  ptr[2] = static_cast<char *>(B.PSI) + (size_t)h * B.nPSI * B.esize;
+  ptr[3] = reinterpret_cast<char *>(B.FLD + (size_t)h * B.nFLD);
+  ptr[4] = B.MOM ? reinterpret_cast<char *>(B.MOM + (size_t)h * B.nMOM) : nullptr;
+  nb[0] = B.nXS * B.esize;
+  nb[1] = B.nXP * B.xsize;
+  nb[2] = B.nPSI * B.esize;
+  nb[3] = B.nFLD * sizeof(double);
+  nb[4] = B.MOM ? B.nMOM * sizeof(float) : 0;
+}
+
+// keep_good: copy the current state (one half) into the context's spare
+// array, allocated on first use, and remember its step.
+int keep_state(tpl_ctx *x) {
+  char *ptr[5];
+  size_t nb[5], total = 0;
+  half_parts(x, x->cur, ptr, nb);
+  for (size_t b : nb) total += b;
+  if (!x->good_d) {
+    if (hipMalloc(&x->good_d, total) != hipSuccess) {
+      (void)hipGetLastError();
+      x->good_d = nullptr;
+      return fail(TPL_ENOMEM, "keep_good: no device memory for a copy of the state (" +
+                                  std::to_string(total) + " bytes)");
+    }
+    x->good_bytes = total;
+  }
+  size_t off = 0;
+  for (int i = 0; i < 5; ++i) {
+    if (!nb[i]) continue;
+    HIPCHK(hipMemcpyAsync(x->good_d + off, ptr[i], nb[i], hipMemcpyDeviceToDevice, x->stream));
+    off += nb[i];
+  }
+  x->good_step = x->step;
+  x->good_cur = x->cur;
+  x->good_ip_odd = x->ip_odd;
+  return TPL_OK;
+}
+
+// keep_good: put the kept state back (into the half it came from).
+int restore_state(tpl_ctx *x) {
+  char *ptr[5];
+  size_t nb[5], off = 0;
+  half_parts(x, x->good_cur, ptr, nb);
+  for (int i = 0; i < 5; ++i) {
+    if (!nb[i]) continue;
+    HIPCHK(hipMemcpyAsync(ptr[i], x->good_d + off, nb[i], hipMemcpyDeviceToDevice, x->stream));
+    off += nb[i];
+  }
+  HIPCHK(hipStreamSynchronize(x->stream));
+  x->step = x->good_step;
+  x->cur = x->good_cur;
+  x->ip_odd = x->good_ip_odd;
+  return TPL_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1135,10 +1230,8 @@ tpl_ctx *tpl_create(int nx, int ny, double Re, double Wi, double beta,
 
 int tpl_set_param(tpl_ctx *x, const char *key, double v) {
   if (!x || !key) return fail(TPL_EINVAL, "null argument");
-  // launch and timing knobs change no state and may be set at any time
-  const bool runtime_knob = !std::strcmp(key, "qsplit") || !std::strcmp(key, "time_kernels") ||
-                            !std::strncmp(key, "group_", 6) || !std::strcmp(key, "autotune") ||
-                            !std::strcmp(key, "diag_every") || !std::strcmp(key, "psi_floor");
+  // launch, timing and health knobs change no state and may be set at any time
+  const bool runtime_knob = is_runtime_knob(key);
   if (x->inited && !runtime_knob)
     return fail(TPL_ESTATE, "parameters are fixed after tpl_init");
   Config c = x->c;
@@ -1168,6 +1261,7 @@ int tpl_set_param(tpl_ctx *x, const char *key, double v) {
   if (c.diag_every < 0) return fail(TPL_EINVAL, "diag_every must be >= 0");
   if (c.init_mode != 0 && c.init_mode != 1) return fail(TPL_EINVAL, "init_mode must be 0 or 1");
   if (!(c.psi_floor >= 0)) return fail(TPL_EINVAL, "psi_floor must be >= 0");
+  if (c.keep_good != 0 && c.keep_good != 1) return fail(TPL_EINVAL, "keep_good must be 0 or 1");
   if (runtime_knob) {
     x->c = c;
     return TPL_OK;
@@ -1192,7 +1286,7 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
   const double es = x->c.precision == TPL_FP64 ? 8.0 : 4.0;
   const double xs = x->c.precision == TPL_FP64 ? 8.0 : x->c.precision == TPL_FP32 ? 4.0 : 2.0;
   const double ms = 0.0;
-  const double xq = 25.0 * xs;  // XP bytes per (r, Q)
+  const double xq = (bf16(x) ? 26.0 : 25.0) * xs;  // XP bytes per (r, Q)
   const double pc = x->c.inplace ? 1.0 : 2.0;  // population arrays
   struct {
     const char *n;
@@ -1213,7 +1307,7 @@ int tpl_query(const tpl_ctx *x, const char *key, double *out) {
        N * (pc * (es * 9 + xq * d.nqd) + 2.0 * (es * d.nqd + ms * d.nqd + 8.0 * NF))},
       // algorithmic HBM bytes of one step: populations read + written,
       // lagged psi written + read, lagged per-node fields written + read
-      // (BF16 form: remainders and FP32 fluxes read + written once); same-step
+      // (BF16 form: 26 16-bit values per (r, Q)-node); same-step
       // gradients add a second read of the polymer populations, psi written
       // and read, the solvent read and 17 FP64 field values per node; the
       // shifted spring term a second read of psi and its Q-sum written (the
@@ -1326,7 +1420,11 @@ int tpl_step(tpl_ctx *x, int64_t n) {
     x->wg_used = p.wg;
   }
   // advance in chunks of diag_every steps (all n if 0), checking the state's
-  // health after each chunk; a failed check stops the call there
+  // health after each chunk; a failed check stops the call there (and with
+  // keep_good puts back the state of the last passed check, or of the call's
+  // start)
+  const bool keep = x->c.keep_good != 0;
+  if (keep && (rc = keep_state(x))) return rc;
   int64_t done = 0;
   do {
     const int64_t chunk = x->c.diag_every > 0 ? std::min<int64_t>(x->c.diag_every, n - done)
@@ -1335,7 +1433,14 @@ int tpl_step(tpl_ctx *x, int64_t n) {
     if (rc) return rc;
     done += chunk;
     rc = check_health(x);
+    if (rc == TPL_EUNSTABLE && keep) {
+      const std::string why = g_err;
+      const int rr = restore_state(x);
+      if (rr) return rr;
+      return fail(TPL_EUNSTABLE, why + "; state restored to step " + std::to_string(x->step));
+    }
     if (rc) return rc;
+    if (keep && done < n && (rc = keep_state(x))) return rc;
   } while (done < n);
   return TPL_OK;
 }
@@ -1610,7 +1715,7 @@ int tpl_load(tpl_ctx *x, const char *path) {
   long long step = 0;
   bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
             std::fread(&c, sizeof c, 1, f) == 1 && std::fread(&step, sizeof step, 1, f) == 1;
-  if (!ok || std::memcmp(&c, &x->c, sizeof c) != 0) {
+  if (!ok || !same_state_config(c, x->c)) {
     std::fclose(f);
     return fail(TPL_EINVAL, "checkpoint does not match this context");
   }
@@ -1664,6 +1769,7 @@ void tpl_destroy(tpl_ctx *x) {
   (void)hipFree(x->part_d);
   (void)hipFree(x->gate_d);
   (void)hipFree(x->corr_d);
+  (void)hipFree(x->good_d);
   delete x;
 }
 
@@ -1910,7 +2016,56 @@ int time_shape(tpl_batch *b, int qs, int grid, int reps, double *ms, int group =
 // Units of `group` consecutive items: what a grouped launch's grid counts.
 int batch_units(const tpl_batch *b, int group) { return (b->nitems + group - 1) / group; }
 
+int choose_shape_timed(tpl_batch *b);
+
+// The launch shape, chosen by timing repeated launches on the current half.
+// Those launches leave the populations unchanged, but the passes that same-step
+// gradients and the shifted spring term run before each step rewrite the
+// current half's psi and per-node fields (M, U): those are kept and put back.
 int choose_shape(tpl_batch *b) {
+  if (!b->autotune || b->inplace || !(b->gradients || b->spring_shift) || !b->inited)
+    return choose_shape_timed(b);
+  size_t total = 0;
+  for (tpl_ctx *x : b->inst) {
+    char *ptr[5];
+    size_t nb[5];
+    half_parts(x, x->cur, ptr, nb);
+    total += nb[2] + nb[3];
+  }
+  char *keep = nullptr;
+  if (hipMalloc(&keep, total) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TPL_ENOMEM, "autotune: no device memory to keep psi and the per-node fields");
+  }
+  int rc = TPL_OK;
+  auto copy = [&](bool save) -> int {
+    size_t off = 0;
+    for (tpl_ctx *x : b->inst) {
+      char *ptr[5];
+      size_t nb[5];
+      half_parts(x, x->cur, ptr, nb);
+      for (int i = 2; i <= 3; ++i) {
+        const hipError_t e = save ? hipMemcpyAsync(keep + off, ptr[i], nb[i],
+                                                   hipMemcpyDeviceToDevice, b->stream)
+                                  : hipMemcpyAsync(ptr[i], keep + off, nb[i],
+                                                   hipMemcpyDeviceToDevice, b->stream);
+        if (e != hipSuccess) return fail(TPL_EHIP, std::string("autotune keep: ") + hipGetErrorString(e));
+        off += nb[i];
+      }
+    }
+    return TPL_OK;
+  };
+  rc = copy(true);
+  if (!rc) rc = choose_shape_timed(b);
+  const int rr = copy(false);
+  if (!rc) rc = rr;
+  const hipError_t e = hipStreamSynchronize(b->stream);
+  if (!rc && e != hipSuccess) rc = fail(TPL_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+  (void)hipFree(keep);
+  return rc;
+}
+
+int choose_shape_timed(tpl_batch *b) {
   int qs_list[4] = {1, 2, 4, 8}, nqs = 4;
   if (b->qsplit > 0) {
     const int q = b->qsplit >= 8 ? 8 : b->qsplit >= 4 ? 4 : b->qsplit >= 2 ? 2 : 1;

@@ -51,7 +51,7 @@ def main():
     del src, dst
     torch.cuda.empty_cache()
     if args.batch:
-        from . import inputs
+        from paper_2201_10132_amd import inputs
 
         b = P.Batch(inputs.c4_instances(args.batch), precision=1, nq=args.batch_nq, pre_steps=100,
                     autotune=0, qsplit=args.qsplit, group=args.group, graph_steps=0)

@@ -1,10 +1,11 @@
 """Summarise rocprofv3 result databases into short text files under profiles/.
 
-  python paper_2201_10132_amd/profile_summary.py stats <run_results.db> <out.md> [--bench-log <log>] <command>
+  python paper_2201_10132_amd/profile_summary.py stats <run_results.db> <out.md> [--bench-log <log>] [--also a,b,...] <command>
   python paper_2201_10132_amd/profile_summary.py traffic <fetch.db> <write.db> <kernel-substring> <out.md> [--last N] <command...>
 
 --bench-log: the log of the profiled bench.py run; its HIP-event kernel time
-is quoted beside the trace's average.  --last N: only the last N matching
+is quoted beside the trace's average.  --also: kernels outside the 15
+longest that are listed too (substrings of their names).  --last N: only the last N matching
 dispatches (the steps after the launch-shape tuning of the first step).
 
 The traffic summary calibrates FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
@@ -31,10 +32,12 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def stats(db, out, command, bench_log=None):
+def stats(db, out, command, bench_log=None, also=None):
     c = sqlite3.connect(db)
     rows = list(c.execute("select name, total_calls, total_duration, average, percentage "
-                          "from top_kernels order by total_duration desc limit 15"))
+                          "from top_kernels order by total_duration desc"))
+    # the 15 longest, then any other kernel whose name holds one of `also`
+    rows = rows[:15] + [r for r in rows[15:] if any(a in r[0] for a in (also or []))]
     lines = ["# Kernel trace summary", "", f"Command: `{command}`", "",
              "| kernel | calls | total (ms) | average (ms) | % |", "|---|---|---|---|---|"]
     for n, calls, tot, avg, pct in rows:
@@ -106,9 +109,12 @@ def _option(args, name):
 
 if __name__ == "__main__":
     a = sys.argv[1:]
+    if not a:
+        raise SystemExit(__doc__)
     if a[0] == "stats":
         log = _option(a, "--bench-log")
-        stats(a[1], a[2], " ".join(a[3:]), bench_log=log)
+        also = _option(a, "--also")
+        stats(a[1], a[2], " ".join(a[3:]), bench_log=log, also=also.split(",") if also else None)
     elif a[0] == "traffic":
         last = _option(a, "--last")
         traffic(a[1], a[2], a[3], a[4], " ".join(a[5:]), last=int(last) if last else None)

@@ -147,9 +147,10 @@ def test_batched_sweep_draw():
 def test_bf16_form_bytes_and_rejections():
     t = P.Tpl(64, 64, 20.0, 0.5, 0.8, nq=8, precision=P.TPL_BF16)
     N, nqd = 64 * 64, t.nqd
-    # FP32 solvent and psi, BF16 polymer deviations (54 bytes per (r, Q))
-    assert t.query("bytes_per_step") == N * (2 * 4 * (9 + nqd) + 2 * (2 * 25) * nqd + 16 * 18)
-    assert t.query("bytes_XP") == 2 * 2 * 25 * nqd * N
+    # FP32 solvent and psi, BF16 polymer deviations and the rest population's
+    # lower 16 bits (56 bytes per (r, Q))
+    assert t.query("bytes_per_step") == N * (2 * 4 * (9 + nqd) + 2 * (2 * 26) * nqd + 16 * 18)
+    assert t.query("bytes_XP") == 2 * 2 * 26 * nqd * N
     with pytest.raises(P.TplError):  # null device pointers
         t.adopt_buffers([0, 0, 0, 0], [1, 1, 1, 1])
     with pytest.raises(P.TplError):
@@ -319,10 +320,14 @@ def test_batch_model2_rules():
 def test_health_check_knobs():
     t = P.Tpl(16, 16, 20.0, 0.5, 0.8)
     assert t.query("diag_every") == 0 and t.query("psi_floor") == 1.0
+    assert t.query("keep_good") == 0
     t.set_param("diag_every", 5)
     t.set_param("psi_floor", 0.0)
+    t.set_param("keep_good", 1)
     assert t.query("diag_every") == 5 and t.query("psi_floor") == 0.0
-    for k, v in (("diag_every", -1), ("psi_floor", -0.5), ("diag_every", 1.5)):
+    assert t.query("keep_good") == 1
+    for k, v in (("diag_every", -1), ("psi_floor", -0.5), ("diag_every", 1.5),
+                 ("keep_good", 2), ("keep_good", 0.5)):
         with pytest.raises(P.TplError):
             t.set_param(k, v)
     t.close()

@@ -3,6 +3,10 @@ base state (as the FP32 form), the polymer populations as the BF16 rounding
 (nearest even: relative error at most 2^-9) of their deviation from it.
 Arithmetic in FP64.
 
+The rest population (velocity 0, which never leaves its node) is stored in
+FP32 and takes up the BF16 rounding residual of the node's other 24, so the
+stored density of every (r, Q)-node, and the polymer mass, are exact to FP32.
+
 Error model: every step rounds each polymer deviation to BF16 (2^-9 of its
 size) and the solvent's and psi to FP32 (2^-24); the scheme is dissipative,
 so after n steps the difference from the FP64 oracle is bounded by about
@@ -22,6 +26,10 @@ from tests.gpu_common import make_pair
 pytestmark = pytest.mark.gpu
 
 EPS32, EPS_BF16 = 2.0 ** -24, 2.0 ** -9
+# polymer mass error allowed over ~100 steps: FP32 rounding of the
+# deviations gives ~1e-11, BF16 rounding without the rest population's
+# residual ~2^15 times that
+MASS_BAR = 1e-9
 
 
 def _dev(st, base):
@@ -52,10 +60,21 @@ def test_bf16_parity_with_oracle(nx, ny, nq, spring):
     o.step(n)
     got, want = t.get_state(), o.get_state()
     bound = _bound(n + 1, [want0, want], base)
-    errs = {k: float(np.abs(got[k] - want[k]).max()) for k in ("XS", "XP", "psi")}
+    errs = {k: float(np.abs(got[k] - want[k]).max()) for k in ("XS", "psi")}
+    errs["XP moving"] = float(np.abs(got["XP"][1:] - want["XP"][1:]).max())
+    # the rest population carries the rounding residual of the node's other
+    # 24 populations (a sum of 24 roundings: about sqrt(24) of one), bound 6x
+    errs["XP rest"] = float(np.abs(got["XP"][0] - want["XP"][0]).max()) / 6
     print("errors", errs, "bound", bound, flush=True)
     for k, e in errs.items():
         assert e <= bound, (k, e, bound)
+    # the node densities, and the lattice's polymer mass, are kept to FP32:
+    # about 1e-11 after these 100 steps (measured 1.3e-11 on the smallest
+    # lattice), where BF16 rounding of every deviation would move it 2^15
+    # times as far; the bar sits between the two
+    dm = abs(got["XP"].sum() / want["XP"].sum() - 1)
+    print("polymer mass against the oracle", dm, flush=True)
+    assert dm < MASS_BAR
 
 
 def _rate(amps, steps):
@@ -101,11 +120,12 @@ def test_bf16_checkpoint_conservation_and_state_exchange(tmp_path):
     for k in a:
         assert np.array_equal(a[k], b[k]), k
     d1 = t.diagnostics()
-    # mass: the solvent as in the FP32 form; the polymer's rounding is not
-    # conservative, of order 2^-9 of its deviations per step
+    # mass: the solvent as in the FP32 form; the polymer's too, since the
+    # rest population stored in FP32 takes up every node's BF16 rounding
+    # residual (35 steps of FP32 rounding of the deviations)
     print("mass drift", d1["mass_S"] / d0["mass_S"] - 1, d1["mass_P"] / d0["mass_P"] - 1, flush=True)
     assert abs(d1["mass_S"] / d0["mass_S"] - 1) < 1e-8
-    assert abs(d1["mass_P"] / d0["mass_P"] - 1) < 35 * EPS_BF16 * 1e-2
+    assert abs(d1["mass_P"] / d0["mass_P"] - 1) < MASS_BAR
     # state exchange: writing back what was read re-rounds nothing (the
     # stored values are exactly representable)
     st = t.get_state()

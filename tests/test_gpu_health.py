@@ -15,11 +15,12 @@ def _ctx(**kw):
     return t
 
 
-def _plant_negative_psi(t, x=5, y=5, q=3):
-    """Flip the populations of one (r, Q)-node to -1000 times their value:
-    after one step their pull makes psi strongly negative at the nodes they
-    stream to."""
+def _plant_negative_psi(t, x=5, y=5):
+    """Flip the populations of one (r, Q)-node, the most populated Q-node of
+    r-node (x, y), to -1000 times their value: after one step their pull
+    makes psi at the nodes they stream to about -100 max psi."""
     st = t.get_state()
+    q = int(np.argmax(st["psi"][:, y, x]))
     st["XP"][:, q, y, x] *= -1000.0
     t.set_state(XS=st["XS"], XP=st["XP"], psi=st["psi"], U=st["U"])
 
@@ -100,3 +101,96 @@ def test_batch_flags_an_instance_with_negative_psi():
     b.step(2)
     assert list(b.status()) == [0, 1, 0]
     b.close()
+
+
+def _psi_ratio(t):
+    psi = t.get_state(populations=False)["psi"]
+    return float(psi.min() / psi.max())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [P.TPL_FP64, P.TPL_FP32])
+def test_keep_good_puts_back_the_last_passed_check(precision):
+    """A healthy FENE run whose min psi / max psi first falls below its
+    earlier minimum at step k >= 2: a psi floor between the two makes the
+    check after step k fail while those after steps 1 .. k-1 pass.  With
+    keep_good the failed call leaves the state of step k-1, bitwise; without
+    it, the state of step k."""
+    ref = _ctx(precision=precision)
+    ratios, states = [], []
+    for _ in range(8):
+        ref.step(1)
+        ratios.append(_psi_ratio(ref))
+        states.append(ref.get_state())
+    ref.close()
+    k = next(n for n in range(1, len(ratios)) if ratios[n] < min(ratios[:n])) + 1  # 1-based step
+    floor = -0.5 * (ratios[k - 1] + min(ratios[:k - 1]))
+    print(f"psi ratios {ratios}; first new minimum after step {k}; floor {floor:.4e}", flush=True)
+    for keep, expect in ((1, k - 1), (0, k)):
+        t = _ctx(precision=precision, diag_every=1, psi_floor=floor, keep_good=keep)
+        with pytest.raises(P.TplError, match="polymer density negative after step %d" % k) as e:
+            t.step(8)
+        assert e.value.code == P.tpl.TPL_EUNSTABLE
+        assert t.query("step") == expect
+        if keep:
+            assert "state restored to step %d" % expect in str(e.value)
+        st = t.get_state()
+        for name, a in states[expect - 1].items():
+            assert np.array_equal(st[name], a), (keep, name)
+        # the run goes on from there once the floor is relaxed
+        t.set_param("psi_floor", 1.0)
+        t.step(2)
+        assert t.query("step") == expect + 2
+        t.close()
+
+
+@pytest.mark.gpu
+def test_keep_good_puts_back_the_call_start_when_no_check_passed():
+    t = _ctx(keep_good=1, diag_every=3)
+    t.step(2)
+    before = t.get_state()
+    _plant_negative_psi(t)
+    planted = t.get_state()
+    with pytest.raises(P.TplError, match="state restored to step 2") as e:
+        t.step(9)
+    assert e.value.code == P.tpl.TPL_EUNSTABLE
+    assert t.query("step") == 2
+    st = t.get_state()
+    for name in st:
+        assert np.array_equal(st[name], planted[name]), name
+    assert not np.array_equal(planted["XP"], before["XP"])
+    t.close()
+
+
+@pytest.mark.gpu
+def test_keep_good_changes_no_result():
+    a, b = _ctx(), _ctx(keep_good=1, diag_every=2)
+    a.step(7)
+    b.step(7)
+    sa, sb = a.get_state(), b.get_state()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    a.close()
+    b.close()
+
+
+@pytest.mark.gpu
+def test_checkpoint_loads_into_a_context_with_other_health_knobs(tmp_path):
+    a = _ctx()
+    a.step(3)
+    path = str(tmp_path / "ck.tpl")
+    a.save(path)
+    b = _ctx(diag_every=2, keep_good=1, psi_floor=0.5)
+    b.load(path)
+    assert b.query("step") == 3
+    a.step(4)
+    b.step(4)
+    sa, sb = a.get_state(), b.get_state()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    c = P.Tpl(16, 16, 20.0, 0.5, 0.8, periods=1, nq=8, pre_steps=20)
+    c.init(seed=0, perturbation=1e-3)
+    with pytest.raises(P.TplError, match="does not match"):
+        c.load(path)
+    for t in (a, b, c):
+        t.close()
