@@ -127,8 +127,23 @@ def calibrate_force(Wi, nq=32, iters=4, **params):
     return fs
 
 
+def shared_drag_time(Wi, nq=32, **params):
+    """The solvent's drag time under the reading that both components share
+    one drag time (Sec. V writes the momentum exchange between solvent and
+    polymer with a single tau_2): the polymer's tau2_P, raised to the
+    solvent's viscous time tau1_S where the ordering tau_1 <= tau_2 (needed
+    for the H-theorem) requires it.  The library's own default is 1, which
+    with phi = 0.01 adds phi c_s^2 to the polymer's r-diffusivity (about as
+    much again as its own c_s^2 tau2_P in the elastic cells)."""
+    t = Tpl(1, CELL["ny"], CELL["Re"], Wi, CELL["beta"], periods=CELL["periods"],
+            u0=CELL["u0"], nq=nq, **params)
+    v = max(t.query("tau1S"), t.query("tau2P"))
+    t.close()
+    return v
+
+
 def run(t_end=2000.0, every=1.0, wis=WIS, nq=32, seed=0, perturbation=1e-3,
-        precision=TPL_FP64, progress=True, laminar_u0=True, **params):
+        precision=TPL_FP64, progress=True, laminar_u0=True, shared_drag=False, **params):
     """Advance the three cells together; sample the diagnostics every
     `every` convective times.  laminar_u0: force each cell so that its
     laminar amplitude is u0 (calibrate_force); else F0 = nu u0 k^2.  Returns
@@ -137,14 +152,19 @@ def run(t_end=2000.0, every=1.0, wis=WIS, nq=32, seed=0, perturbation=1e-3,
     insts = [dict(CELL, Wi=w, seed=seed, perturbation=perturbation) for w in wis]
     cls = _Cells if params.get("qe_model", 1) != 1 else Batch
     params = {"drift_cap": DRIFT_CAP, **params}
-    fscale = [calibrate_force(w, nq=nq, **params) if laminar_u0 else 1.0 for w in wis]
+    drag = [shared_drag_time(w, nq=nq, **params) if shared_drag else None for w in wis]
+    fscale = [calibrate_force(w, nq=nq, **params, **({"tau_drag": d} if d else {}))
+              if laminar_u0 else 1.0 for w, d in zip(wis, drag)]
     b = cls(insts, precision=precision, nq=nq, pre_steps=0, **params)
     for i, f in enumerate(fscale):
         b.instance(i).set_param("force_scale", f)
+        if drag[i]:
+            b.instance(i).set_param("tau_drag", drag[i])
     b.init()
     tc = convective_steps()
     out = dict(t=[], enstrophy=[[] for _ in wis], qrms=[[] for _ in wis],
-               amplitude=[[] for _ in wis], steps_per_convective_time=tc, force_scale=fscale)
+               amplitude=[[] for _ in wis], steps_per_convective_time=tc, force_scale=fscale,
+               tau_drag=[d if d else b.instance(i).query("tau2S") for i, d in enumerate(drag)])
     n_done = 0
     t0 = last = time.perf_counter()
     k = 0
@@ -213,6 +233,9 @@ def main():
                     help="psi at the beads instead of the Taylor form of the spring term")
     ap.add_argument("--drift-cap", type=float, default=DRIFT_CAP,
                     help="cap on the Q-drift per step (0: none)")
+    ap.add_argument("--drag", choices=["library", "shared"], default="library",
+                    help="solvent drag time: the library's (1) or the polymer's tau2_P "
+                         "(at least tau1_S): one drag time for both components")
     ap.add_argument("--force-from-nu", action="store_true",
                     help="F0 = nu u0 k^2 for every cell instead of the force that makes the "
                          "laminar amplitude u0")
@@ -220,12 +243,14 @@ def main():
     extra = dict(spring_shift=1) if args.spring_shift else {}
     extra["drift_cap"] = args.drift_cap
     res = run(t_end=args.t_end, every=args.every, nq=args.nq, perturbation=args.perturbation,
-              laminar_u0=not args.force_from_nu, **extra)
+              laminar_u0=not args.force_from_nu, shared_drag=args.drag == "shared", **extra)
     rows = summary(res)
-    line = dict(experiment="kolmogorov_72x72_re3.5_beta0.5_fene_nq%d%s%s"
+    line = dict(experiment="kolmogorov_72x72_re3.5_beta0.5_fene_nq%d%s%s%s"
                 % (args.nq, "_shifted_spring" if args.spring_shift else "",
-                   "_force_from_nu" if args.force_from_nu else ""), u0=CELL["u0"],
+                   "_force_from_nu" if args.force_from_nu else "",
+                   "_shared_drag" if args.drag == "shared" else ""), u0=CELL["u0"],
                 drift_cap=args.drift_cap, force_scale=res["force_scale"],
+                tau_drag=res["tau_drag"],
                 steps=res["steps"], wall_s=round(res["wall_s"], 1),
                 lattice_updates_per_s=res["lattice_updates_per_s"], summary=rows)
     print(json.dumps(line), flush=True)
