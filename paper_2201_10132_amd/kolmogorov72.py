@@ -25,8 +25,13 @@ span a sizeable part of the forcing wavelength (sigma k = 1.1), where the
 two differ.  Options the batched step does not take (the component-stress
 quasi-equilibria, qe_model 2) run the three cells as separate contexts.
 
+With --n N the cell has N x N nodes instead of 72 x 72, with the same four
+periods and parameters: the dumbbells (sigma = 3.2 nodes on the 32-point
+Q-grid) then span less of the forcing wavelength, sigma k = 1.1 x 72 / N,
+as if the Q-grid spacing were 72 / N of the r-spacing.
+
 Usage: python -m paper_2201_10132_amd.kolmogorov72 [--t-end 2000] [--spring-shift]
-       [--force-from-nu] [--out file.json]
+       [--force-from-nu] [--drag shared] [--n 72] [--out file.json]
 """
 from __future__ import annotations
 
@@ -233,6 +238,7 @@ def main():
                     help="psi at the beads instead of the Taylor form of the spring term")
     ap.add_argument("--drift-cap", type=float, default=DRIFT_CAP,
                     help="cap on the Q-drift per step (0: none)")
+    ap.add_argument("--n", type=int, default=CELL["nx"], help="nodes per side of the cell")
     ap.add_argument("--drag", choices=["library", "shared"], default="library",
                     help="solvent drag time: the library's (1) or the polymer's tau2_P "
                          "(at least tau1_S): one drag time for both components")
@@ -240,13 +246,14 @@ def main():
                     help="F0 = nu u0 k^2 for every cell instead of the force that makes the "
                          "laminar amplitude u0")
     args = ap.parse_args()
+    CELL["nx"] = CELL["ny"] = args.n
     extra = dict(spring_shift=1) if args.spring_shift else {}
     extra["drift_cap"] = args.drift_cap
     res = run(t_end=args.t_end, every=args.every, nq=args.nq, perturbation=args.perturbation,
               laminar_u0=not args.force_from_nu, shared_drag=args.drag == "shared", **extra)
     rows = summary(res)
-    line = dict(experiment="kolmogorov_72x72_re3.5_beta0.5_fene_nq%d%s%s%s"
-                % (args.nq, "_shifted_spring" if args.spring_shift else "",
+    line = dict(experiment="kolmogorov_%dx%d_re3.5_beta0.5_fene_nq%d%s%s%s"
+                % (args.n, args.n, args.nq, "_shifted_spring" if args.spring_shift else "",
                    "_force_from_nu" if args.force_from_nu else "",
                    "_shared_drag" if args.drag == "shared" else ""), u0=CELL["u0"],
                 drift_cap=args.drift_cap, force_scale=res["force_scale"],
