@@ -109,7 +109,7 @@ def _psi_ratio(t):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("precision", [P.TPL_FP64, P.TPL_FP32])
+@pytest.mark.parametrize("precision", [P.TPL_FP64, P.TPL_FP32, P.TPL_BF16])
 def test_keep_good_puts_back_the_last_passed_check(precision):
     """A healthy FENE run whose min psi / max psi first falls below its
     earlier minimum at step k >= 2: a psi floor between the two makes the
@@ -194,3 +194,37 @@ def test_checkpoint_loads_into_a_context_with_other_health_knobs(tmp_path):
         c.load(path)
     for t in (a, b, c):
         t.close()
+
+
+@pytest.mark.gpu
+def test_keep_good_in_place_restores_the_streaming_parity():
+    """In-place streaming holds the populations in streamed order after an
+    odd step count: a restored state must come back with its step count's
+    parity, so that the run goes on exactly as an unchecked one."""
+    def ctx(**kw):
+        t = P.Tpl(64, 16, 20.0, 0.5, 0.8, periods=1, nq=6, pre_steps=20, inplace=1, **kw)
+        t.init(seed=0, perturbation=1e-3)
+        return t
+
+    ref = ctx()
+    ratios = []
+    for _ in range(8):
+        ref.step(1)
+        ratios.append(_psi_ratio(ref))
+    ref.close()
+    k = next(n for n in range(1, len(ratios)) if ratios[n] < min(ratios[:n])) + 1
+    floor = -0.5 * (ratios[k - 1] + min(ratios[:k - 1]))
+    t = ctx(diag_every=1, psi_floor=floor, keep_good=1)
+    with pytest.raises(P.TplError, match="state restored to step %d" % (k - 1)):
+        t.step(8)
+    assert t.query("step") == k - 1
+    assert t.query("inplace_odd") == (k - 1) % 2
+    t.set_param("psi_floor", 1.0)
+    t.step(12 - (k - 1))  # to step 12 (even: populations in plain order)
+    u = ctx()
+    u.step(12)
+    st, su = t.get_state(), u.get_state()
+    for name in st:
+        assert np.array_equal(st[name], su[name]), name
+    t.close()
+    u.close()
