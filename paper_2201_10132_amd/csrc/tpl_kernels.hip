@@ -84,10 +84,12 @@ __device__ __forceinline__ int xcd_tile(int bid, int tiles_per_xcd) {
 
 // ---------------------------------------------------------------------------
 // Storage access.  Loads and stores at a wave-uniform plane base plus a 32-bit
-// byte offset (global_load/store with an SGPR base; every offset is
-// < sizeof(T) N < 2^32).  The base goes through readfirstlane so that the
-// compiler cannot fold the per-lane offset into hoisted 64-bit per-lane
-// pointers.
+// byte offset (every offset is < sizeof(T) N < 2^32).  The base goes through
+// readfirstlane so that it stays in scalar registers; the compiler hoists the
+// zero-extended offsets out of the Q-loop and issues the accesses with 64-bit
+// per-lane addresses (SGPR base plus offset, one VALU add each).  Forcing the
+// SGPR-base instruction form instead (an opaque 32-bit offset per access)
+// saves 8-15 VGPRs but measured no faster: the step is bound by DRAM.
 template <typename T>
 __device__ __forceinline__ T *uni(T *p) {
   const uint64_t v = reinterpret_cast<uint64_t>(p);

@@ -1,16 +1,17 @@
 """The BF16 form: solvent and psi as FP32 deviations from the FP32-rounded
 base state (as the FP32 form), the polymer populations as the BF16 rounding
-(nearest even: relative error at most 2^-9) of their deviation from it.
+(nearest even, 8 significant bits: relative error at most 2^-8) of their
+deviation from it.
 Arithmetic in FP64.
 
 The rest population (velocity 0, which never leaves its node) is stored in
 FP32 and takes up the BF16 rounding residual of the node's other 24, so the
 stored density of every (r, Q)-node, and the polymer mass, are exact to FP32.
 
-Error model: every step rounds each polymer deviation to BF16 (2^-9 of its
+Error model: every step rounds each polymer deviation to BF16 (2^-8 of its
 size) and the solvent's and psi to FP32 (2^-24); the scheme is dissipative,
 so after n steps the difference from the FP64 oracle is bounded by about
-n (2^-9 max|delta_P| + 2^-24 max|delta|), tested with a factor 4 margin.
+n (2^-8 max|delta_P| + 2^-24 max|delta|), tested with a factor 4 margin.
 The deviations delta are evaluated from the oracle's own states against the
 FP32 rounding of its base state (the library's reference is the FP32
 rounding of its own base state, which agrees with the oracle's to ~1e-13).
@@ -25,10 +26,10 @@ from tests.gpu_common import make_pair
 
 pytestmark = pytest.mark.gpu
 
-EPS32, EPS_BF16 = 2.0 ** -24, 2.0 ** -9
+EPS32, EPS_BF16 = 2.0 ** -24, 2.0 ** -8  # unit roundoffs: 24 and 8 significant bits
 # polymer mass error allowed over ~100 steps: FP32 rounding of the
 # deviations gives ~1e-11, BF16 rounding without the rest population's
-# residual ~2^15 times that
+# residual ~2^16 times that
 MASS_BAR = 1e-9
 
 
@@ -70,7 +71,7 @@ def test_bf16_parity_with_oracle(nx, ny, nq, spring):
         assert e <= bound, (k, e, bound)
     # the node densities, and the lattice's polymer mass, are kept to FP32:
     # about 1e-11 after these 100 steps (measured 1.3e-11 on the smallest
-    # lattice), where BF16 rounding of every deviation would move it 2^15
+    # lattice), where BF16 rounding of every deviation would move it 2^16
     # times as far; the bar sits between the two
     dm = abs(got["XP"].sum() / want["XP"].sum() - 1)
     print("polymer mass against the oracle", dm, flush=True)

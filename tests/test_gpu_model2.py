@@ -3,7 +3,7 @@
 
 Tolerances as for model (i): FP64 1e-14 for one step from a random state,
 1e-13 after 100 steps and through init; FP32 within n 2^-24 max|deviation|
-of the oracle (factor 4 margin); BF16 within n (2^-9 max|polymer deviation|
+of the oracle (factor 4 margin); BF16 within n (2^-8 max|polymer deviation|
 + 4 2^-24 max|deviation|) (factor 4).  The drag time tau1_S = tau_drag must
 not exceed the viscous tau2_S = nu_S / c_s^2, so each case takes half of it.
 """
