@@ -74,3 +74,76 @@ def test_fullsize_nq4_whole_lattice_parity():
     print("fullsize nq4 errors", errs, flush=True)
     assert max_rel(t.moments(), o.observables()) < 1e-13
     t.close()
+
+
+def test_fullsize_bf16_sampled_node_parity():
+    """The BF16 form at the same size and launch configuration.  The oracle
+    steps the decoded 3 x 3 window exactly in FP64; the GPU's stored result
+    differs from it by the storage rounding of the outputs: at most 2^-8 of
+    a polymer population's deviation from the base state (the rest
+    population 24 such roundings, the residual it takes up), 2^-24 of the
+    solvent's and psi's; the mixture velocity by the rounding of the ~25 nqd
+    / 9 stored polymer populations behind each of its Q-marginals (the kernel
+    takes the marginals before rounding), and every population's
+    equilibrium by that velocity difference.  Tested with a factor 4 margin;
+    the deviations are measured against the base state of a one-column
+    context with the same parameters."""
+    eps16, eps32 = 2.0 ** -8, 2.0 ** -24
+    print("fullsize bf16: init 1024x1024 nq=16", flush=True)
+    t = P.Tpl(NX, NY, PARAMS["Re"], PARAMS["Wi"], PARAMS["beta"], periods=PARAMS["periods"],
+              nq=16, pre_steps=200, pert_modes=1, precision=P.TPL_BF16)
+    t.init(seed=0, perturbation=1e-4)
+    t.step(2)
+    base = P.Tpl(1, NY, PARAMS["Re"], PARAMS["Wi"], PARAMS["beta"], periods=PARAMS["periods"],
+                 nq=16, pre_steps=200, pert_modes=1)
+    base.init(seed=0, perturbation=0.0)
+    nqd = t.nqd
+    dP_seen = []
+    d0 = t.diagnostics()
+    wins = {s: t.get_window(s[0] - 1, s[1] - 1, 3, 3) for s in SAMPLES}
+    t.step(1)
+    d1 = t.diagnostics()
+    for (x, y), w in wins.items():
+        print(f"fullsize bf16: node ({x},{y})", flush=True)
+        ref = base.get_window(0, y - 1, 1, 3)  # the base state of the window's rows
+        dP = max(float(np.abs(w["XP"][..., j, :] - ref["XP"][..., j, :1]).max()) for j in range(3))
+        dS = max(float(np.abs(w[k][..., j, :] - ref[k][..., j, :1]).max())
+                 for k in ("XS", "psi") for j in range(3))
+        dP_seen.append(dP)
+        o = oracle.OracleSim(3, 3, nq=16, ny_param=NY, y_offset=y - 1, **PARAMS)
+        o.set_state(XS=w["XS"], XP=w["XP"], psi=w["psi"], U=w["U"])
+        o.step(1)
+        want = o.get_state()
+        got = t.get_window(x, y, 1, 1)
+        g, v = (lambda k: got[k][..., 0, 0]), (lambda k: want[k][..., 1, 1])
+        fp64 = lambda k: 1e-13 * float(np.abs(v(k)).max())
+        # the mixture velocity, and through the equilibria every population
+        # (d f_eq / d U is at most about 3 rho w |c| < 2 rho); psi is the
+        # node's pulled density, which no equilibrium changes
+        dU = 4 * (25 * nqd / 9) * eps16 * dP + 1e-14
+        psi_max = float(np.abs(v("psi")).max())
+        bounds = {"XS": 4 * eps32 * dS + 2 * dU + fp64("XS"),
+                  "psi": 4 * eps32 * dS + fp64("psi"),
+                  "XP moving": 4 * eps16 * dP + 2 * psi_max * dU + fp64("XP"),
+                  "XP rest": 4 * 24 * eps16 * dP + 2 * psi_max * dU + fp64("XP"),
+                  "U": dU}
+        errs = {"XS": float(np.abs(g("XS") - v("XS")).max()),
+                "psi": float(np.abs(g("psi") - v("psi")).max()),
+                "XP moving": float(np.abs(g("XP")[1:] - v("XP")[1:]).max()),
+                "XP rest": float(np.abs(g("XP")[0] - v("XP")[0]).max()),
+                "U": float(np.abs(g("U") - v("U")).max())}
+        print(f"  dP {dP:.3e} dS {dS:.3e} errors {errs}", flush=True)
+        for k, e in errs.items():
+            assert e <= bounds[k], (k, e, bounds[k], x, y)
+    # mass to FP32: the rest population takes up the node's BF16 rounding
+    # residual, so one step moves the polymer mass by at most one FP32
+    # rounding of every rest population (BF16 rounding of all 25 populations
+    # would allow 25 * 2^16 times as much)
+    dP_all = max(dP_seen)
+    mass_bound = NX * NY * nqd * eps32 * dP_all / d0["mass_P"]
+    print(f"mass drift S {d1['mass_S'] / d0['mass_S'] - 1:.3e} P "
+          f"{d1['mass_P'] / d0['mass_P'] - 1:.3e} (bound {mass_bound:.3e})", flush=True)
+    assert abs(d1["mass_S"] / d0["mass_S"] - 1) < 1e-12
+    assert abs(d1["mass_P"] / d0["mass_P"] - 1) <= mass_bound
+    base.close()
+    t.close()
