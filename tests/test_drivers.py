@@ -41,3 +41,32 @@ def test_kolmogorov72_summary_on_a_synthetic_history():
 def test_convective_time_of_the_cell():
     # l = 72 / (8 pi) lattice units at u0 = 0.01
     assert abs(kolmogorov72.convective_steps() - 72 / (8 * math.pi) / 0.01) < 1e-12
+
+
+def test_shared_drag_time_is_the_polymer_one_bounded_by_the_solvent_viscous_time():
+    """The shared drag-time reading (one tau_2 for both components): tau2_P,
+    raised to tau1_S where the ordering tau_1 <= tau_2 requires it.  Host
+    only: the derived parameters need no GPU."""
+    import paper_2201_10132_amd as P
+
+    C = kolmogorov72.CELL
+    binds = {}
+    for Wi in kolmogorov72.WIS:
+        t = P.Tpl(1, C["ny"], C["Re"], Wi, C["beta"], periods=C["periods"], u0=C["u0"], nq=32)
+        t1S, t2P = t.query("tau1S"), t.query("tau2P")
+        t.close()
+        v = kolmogorov72.shared_drag_time(Wi)
+        assert v == max(t1S, t2P)
+        binds[Wi] = t1S > t2P
+    # the solvent's viscous time binds only in the most elastic cell
+    assert binds == {0.1: False, 2.5: False, 5.0: True}
+
+
+def test_cell_size_option_scales_the_convective_time():
+    C = kolmogorov72.CELL
+    old = (C["nx"], C["ny"])
+    try:
+        C["nx"] = C["ny"] = 144
+        assert abs(kolmogorov72.convective_steps() - 144 / (8 * math.pi) / 0.01) < 1e-12
+    finally:
+        C["nx"], C["ny"] = old
