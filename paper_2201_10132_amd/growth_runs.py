@@ -6,9 +6,9 @@ decay rate gamma = d ln A / dn, driven through the C ABI.
               workloads (Re 60, Wi 1, beta 0.7): does the scheme stay finite
               for `steps` steps at a given NQ?
   c2          1024^2, four periods, Re 60, beta 0.7, Wi in {0, 1}, FP64,
-              multimode perturbation 1e-4 u0: A(n) over `steps` steps; gamma
-              fitted from step 1000 to the first step with A > 1e-2 (or the
-              end).
+              multimode perturbation 1e-4 u0 (seed 0, or --seeds), A(n) over
+              `steps` steps; gamma fitted from step 1000 to the first step
+              with A > 1e-2 (or the end).
   c3          4096^2, sixteen periods, Re 60, Wi 1, beta 0.7: the same seeded
               run stored in FP64, FP32 and BF16; gamma and A(n) of the two
               reduced forms against FP64 (NQ 6: the largest Q-grid at which
@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--every", type=int, default=None)
     ap.add_argument("--pre-steps", type=int, default=3000,
                     help="base-state column steps (-1: the library's 5 max(l^2/nu, lambda))")
+    ap.add_argument("--seeds", type=int, nargs="+", default=[0],
+                    help="c2: perturbation seeds (one run per seed and Wi)")
+    ap.add_argument("--wis", type=float, nargs="+", default=[0.0, 1.0], help="c2: Weissenberg numbers")
     args = ap.parse_args()
     res = dict(run=args.what)
     if args.what == "stability":
@@ -98,11 +101,11 @@ def main():
     elif args.what == "c2":
         steps, nq, every = args.steps or 20000, args.nq or 16, args.every or 250
         res.update(nq=nq, steps=steps, pre_steps=args.pre_steps, cases=[])
-        for Wi in (0.0, 1.0):
+        for seed, Wi in [(s, w) for s in args.seeds for w in args.wis]:
             r = track(1024, 1024, 4, Wi, nq, TPL_FP64, steps, every, pre_steps=args.pre_steps,
-                      tag=f"c2 Wi {Wi}")
+                      seed=seed, tag=f"c2 Wi {Wi} seed {seed}")
             g, win = fit_gamma(r["n"], r["A"], 1000)
-            res["cases"].append(dict(Wi=Wi, gamma=g, fit_window=win, A_end=r["A"][-1],
+            res["cases"].append(dict(Wi=Wi, seed=seed, gamma=g, fit_window=win, A_end=r["A"][-1],
                                      A_max=float(np.nanmax(r["A"])), failed=r["failed"],
                                      mass_S=r["mass_S"], mass_P=r["mass_P"],
                                      ms_per_step=round(r["wall_s"] / max(1, steps) * 1e3, 3),

@@ -11,6 +11,9 @@ P9     forced laminar Kolmogorov state with Hookean dumbbells against the
        Oldroyd-B closed form (Sec. VII forcing; Sec. III elastic stress).
 P12    x-invariance: with no perturbation the amplitude stays at round-off.
 P14    the parameter mapping gives the paper's Schmidt-number range (Sec. VII).
+Rest distributions: the sampled FENE and Hookean equilibria on the Q-disk
+       give the closed-form RMS extensions (sqrt(2 / (b + 4)) and the
+       truncated Gaussian's) of the spring laws (Sec. VI.C, VII).
 Same-step gradients (the reading of the gradients' time level that takes
 this step's observables): the invariants and the laminar closed form as
 above, and a step that ignores the recorded fields.
@@ -442,3 +445,36 @@ def test_analytic_hookean_state_is_the_laminar_steady_state():
     assert abs(_sin_amp(b.observables()[1, :, 0], k, y) / U0 - 1) < 3e-3
     with pytest.raises(ValueError):
         oracle.OracleSim(1, ny, **dict(kw, spring=0)).analytic_state()
+
+
+def _rest_extension(nq, spring):
+    """RMS extension over R = sqrt(b) sigma of the oracle's sampled rest
+    distribution (its Q-node table), at the 72^2 cell's parameters."""
+    o = oracle.OracleSim(1, 8, nq=nq, Re=3.5, Wi=0.1, beta=0.5, periods=2, u0=0.01,
+                         force_scale=0.0, lambda_set=28.6479, spring=spring)
+    d, t = o.derived(), o.tables()
+    q2 = (t["Q"] ** 2).sum(1)
+    return np.sqrt((t["peq"] * q2).sum() / t["peq"].sum()) / (np.sqrt(25.0) * d["sigma"])
+
+
+@pytest.mark.parametrize("nq,tol", [(8, 1e-4), (16, 1e-7), (32, 1e-10)])
+def test_fene_rest_extension_is_the_closed_form(nq, tol):
+    """FENE rest distribution (1 - Q^2/(b sigma^2))^(b/2) in two dimensions:
+    with u = Q^2/(b sigma^2), <Q^2> = b sigma^2 B(2, b/2 + 1) / B(1, b/2 + 1)
+    = 2 b sigma^2 / (b + 4), so Q_rms / (sqrt(b) sigma) = sqrt(2 / (b + 4))
+    = 0.26261 for b = 25 (Sec. VII's equilibrium extension).  The sampled
+    distribution on the half-integer nodes of the open Q-disk converges to
+    it spectrally (the density vanishes at the rim with all its low
+    derivatives)."""
+    assert abs(_rest_extension(nq, 0) / np.sqrt(2.0 / 29.0) - 1) < tol
+
+
+@pytest.mark.parametrize("nq,tol", [(16, 3e-5), (32, 1e-5)])
+def test_hookean_rest_extension_is_the_truncated_gaussian(nq, tol):
+    """Hookean rest distribution exp(-Q^2/(2 sigma^2)) on the disk |Q| < R =
+    sqrt(b) sigma: <Q^2>/sigma^2 = 2 - a e^-a / (1 - e^-a) with
+    a = R^2 / (2 sigma^2) = b/2, the Gaussian's 2 sigma^2 less the part cut
+    off beyond R (about 3e-4 of it here)."""
+    a = 12.5
+    want = np.sqrt((2.0 - 2.0 * a * np.exp(-a) / (1.0 - np.exp(-a))) / 25.0)
+    assert abs(_rest_extension(nq, 1) / want - 1) < tol
