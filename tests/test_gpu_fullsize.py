@@ -76,8 +76,9 @@ def test_fullsize_nq4_whole_lattice_parity():
     t.close()
 
 
-def test_fullsize_bf16_sampled_node_parity():
-    """The BF16 form at the same size and launch configuration.  The oracle
+@pytest.mark.parametrize("precision", [P.TPL_BF16, P.TPL_FP32], ids=["bf16", "fp32"])
+def test_fullsize_reduced_precision_sampled_node_parity(precision):
+    """The BF16 and FP32 forms at the same size and launch configuration.  The oracle
     steps the decoded 3 x 3 window exactly in FP64; the GPU's stored result
     differs from it by the storage rounding of the outputs: at most 2^-8 of
     a polymer population's deviation from the base state (the rest
@@ -85,13 +86,18 @@ def test_fullsize_bf16_sampled_node_parity():
     solvent's and psi's; the mixture velocity by the rounding of the ~25 nqd
     / 9 stored polymer populations behind each of its Q-marginals (the kernel
     takes the marginals before rounding), and every population's
-    equilibrium by that velocity difference.  Tested with a factor 4 margin;
-    the deviations are measured against the base state of a one-column
-    context with the same parameters."""
-    eps16, eps32 = 2.0 ** -8, 2.0 ** -24
-    print("fullsize bf16: init 1024x1024 nq=16", flush=True)
+    equilibrium by that velocity difference.  The FP32 form rounds every
+    population to 2^-24 of its deviation and has no residual to carry.
+    Tested with a factor 4 margin; the deviations are measured against the
+    base state of a one-column context with the same parameters."""
+    bf16 = precision == P.TPL_BF16
+    eps32 = 2.0 ** -24
+    eps16 = 2.0 ** -8 if bf16 else eps32  # the polymer populations' unit roundoff
+    rest_terms = 24 if bf16 else 1
+    tag = "bf16" if bf16 else "fp32"
+    print(f"fullsize {tag}: init 1024x1024 nq=16", flush=True)
     t = P.Tpl(NX, NY, PARAMS["Re"], PARAMS["Wi"], PARAMS["beta"], periods=PARAMS["periods"],
-              nq=16, pre_steps=200, pert_modes=1, precision=P.TPL_BF16)
+              nq=16, pre_steps=200, pert_modes=1, precision=precision)
     t.init(seed=0, perturbation=1e-4)
     t.step(2)
     base = P.Tpl(1, NY, PARAMS["Re"], PARAMS["Wi"], PARAMS["beta"], periods=PARAMS["periods"],
@@ -104,7 +110,7 @@ def test_fullsize_bf16_sampled_node_parity():
     t.step(1)
     d1 = t.diagnostics()
     for (x, y), w in wins.items():
-        print(f"fullsize bf16: node ({x},{y})", flush=True)
+        print(f"fullsize {tag}: node ({x},{y})", flush=True)
         ref = base.get_window(0, y - 1, 1, 3)  # the base state of the window's rows
         dP = max(float(np.abs(w["XP"][..., j, :] - ref["XP"][..., j, :1]).max()) for j in range(3))
         dS = max(float(np.abs(w[k][..., j, :] - ref[k][..., j, :1]).max())
@@ -125,7 +131,7 @@ def test_fullsize_bf16_sampled_node_parity():
         bounds = {"XS": 4 * eps32 * dS + 2 * dU + fp64("XS"),
                   "psi": 4 * eps32 * dS + fp64("psi"),
                   "XP moving": 4 * eps16 * dP + 2 * psi_max * dU + fp64("XP"),
-                  "XP rest": 4 * 24 * eps16 * dP + 2 * psi_max * dU + fp64("XP"),
+                  "XP rest": 4 * rest_terms * eps16 * dP + 2 * psi_max * dU + fp64("XP"),
                   "U": dU}
         errs = {"XS": float(np.abs(g("XS") - v("XS")).max()),
                 "psi": float(np.abs(g("psi") - v("psi")).max()),
@@ -135,12 +141,13 @@ def test_fullsize_bf16_sampled_node_parity():
         print(f"  dP {dP:.3e} dS {dS:.3e} errors {errs}", flush=True)
         for k, e in errs.items():
             assert e <= bounds[k], (k, e, bounds[k], x, y)
-    # mass to FP32: the rest population takes up the node's BF16 rounding
-    # residual, so one step moves the polymer mass by at most one FP32
-    # rounding of every rest population (BF16 rounding of all 25 populations
-    # would allow 25 * 2^16 times as much)
+    # mass to FP32: in the BF16 form the rest population takes up the node's
+    # rounding residual, so one step moves the polymer mass by at most one
+    # FP32 rounding of every rest population (BF16 rounding of all 25
+    # populations would allow 25 * 2^16 times as much); the FP32 form rounds
+    # all 25
     dP_all = max(dP_seen)
-    mass_bound = NX * NY * nqd * eps32 * dP_all / d0["mass_P"]
+    mass_bound = (1 if bf16 else 25) * NX * NY * nqd * eps32 * dP_all / d0["mass_P"]
     print(f"mass drift S {d1['mass_S'] / d0['mass_S'] - 1:.3e} P "
           f"{d1['mass_P'] / d0['mass_P'] - 1:.3e} (bound {mass_bound:.3e})", flush=True)
     assert abs(d1["mass_S"] / d0["mass_S"] - 1) < 1e-12
