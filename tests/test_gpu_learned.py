@@ -262,9 +262,9 @@ def test_attached_network_source_and_step():
 
 
 def test_pipeline_small():
-    """The training and judging workflow end to end on a small lattice:
-    targets are finite, training lowers the loss, and the judge's verdict
-    follows its stated rule."""
+    """The training and evaluation workflow end to end on a small lattice:
+    targets are finite, training lowers the loss, and the acceptance
+    decision follows its stated rule."""
     from paper_2201_10132_amd import learned as LL
 
     kw = dict(nx=128, ny=128, periods=1, Re=(15.0, 25.0), Wi=(0.1, 0.3))
@@ -290,8 +290,8 @@ def test_trained_network_gains_on_a_held_out_seed():
     trajectories of 960 fine steps (seeds 1000-1007), pairs settled 10
     coarse steps, horizon 20; on the held-out seed 2003 (Re 21.1, Wi 0.63)
     the corrected 64^2 coarse run ends with a smaller velocity error against
-    the restricted fine run than the plain coarse run, and the judge accepts
-    it.  (Training is deterministic: seeded order, fixed-order reductions.)"""
+    the restricted fine run than the plain coarse run, and the acceptance
+    rule accepts it.  (Training is deterministic: seeded order, fixed-order reductions.)"""
     from paper_2201_10132_amd import learned as LL
 
     kw = dict(nx=256, ny=256, periods=1)
