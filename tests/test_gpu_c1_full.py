@@ -10,8 +10,9 @@ conformation, G for the polymer stress, which cancels against G).  The two
 sides sum in different orders, so their difference grows with the step
 count (about 7e-16 per step in rho_P, linearly; the stress, a product of
 rho_P with the conformation, carries 1.5 times that): 2e-15 per step, 4e-12
-over 2000 steps.  Masses conserved to 1e-12.  FP32 storage: the growth rate fitted over steps
-500-2000 within 1e-3 of the oracle's."""
+over 2000 steps.  Masses conserved to 1e-12.  FP32 and BF16 storage: the
+growth rate fitted over steps 500-2000 within 1e-3 of the oracle's (BF16
+also conserving the polymer mass to 1e-9)."""
 import numpy as np
 import pytest
 
@@ -91,4 +92,22 @@ def test_c1_fp32_growth_rate_within_1e3_of_oracle(reference):
     g, g0 = _gamma(ns, a), _gamma(reference["ns"], reference["a"])
     print(f"C1 growth rate: oracle {g0:.6e}, FP32 {g:.6e}, rel {abs(g / g0 - 1):.2e}", flush=True)
     assert abs(g / g0 - 1) < 1e-3
+    t.close()
+
+
+def test_c1_bf16_growth_rate_and_mass_over_2000_steps(reference):
+    """The BF16 form over the same 2000 steps: growth rate within 1e-3 of the
+    oracle's (the FP32 form's bar), and the polymer mass kept to FP32 (the
+    rest population takes up each node's rounding residual; BF16 rounding of
+    every population would drift it by orders of magnitude more)."""
+    t = _gpu(P.TPL_BF16)
+    d0 = t.diagnostics()
+    ns, a = _series(t.step, t.amplitude)
+    d1 = t.diagnostics()
+    g, g0 = _gamma(ns, a), _gamma(reference["ns"], reference["a"])
+    dm = d1["mass_P"] / d0["mass_P"] - 1
+    print(f"C1 BF16: growth rate oracle {g0:.6e}, BF16 {g:.6e}, rel {abs(g / g0 - 1):.2e}; "
+          f"polymer mass drift {dm:.2e}", flush=True)
+    assert abs(g / g0 - 1) < 1e-3
+    assert abs(dm) < 1e-9
     t.close()
