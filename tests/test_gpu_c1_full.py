@@ -111,3 +111,38 @@ def test_c1_bf16_growth_rate_and_mass_over_2000_steps(reference):
     assert abs(g / g0 - 1) < 1e-3
     assert abs(dm) < 1e-9
     t.close()
+
+
+def test_c1_model2_matches_oracle_over_2000_steps():
+    """The stress-tensor quasi-equilibrium model (Sec. V model (ii)) on the
+    same workload and length: drag time tau1_S half the viscous tau2_S,
+    polymer stresses relaxing at half the flux rate; amplitude and the ten
+    observables within the same 4e-12 of the oracle, masses to 1e-12."""
+    c = C1
+    print("C1 model (ii): oracle default base state + 2000 steps", flush=True)
+    nuS = oracle.OracleSim(c["nx"], c["ny"], nq=c["nq"], Re=c["Re"], Wi=c["Wi"], beta=c["beta"],
+                           periods=c["periods"]).derived()["nuS"]
+    m2 = dict(qe_model=2, tau_drag=0.5 * nuS * 3.0, tau_ratio_p=0.5)
+    o = oracle.OracleSim(c["nx"], c["ny"], nq=c["nq"], Re=c["Re"], Wi=c["Wi"], beta=c["beta"],
+                         periods=c["periods"], **m2)
+    o.base_state(-1)
+    o.perturb(c["seed"], c["amp"], False)
+    ns_o, a_o = _series(o.step, o.amplitude)
+    t = P.Tpl(c["nx"], c["ny"], c["Re"], c["Wi"], c["beta"], periods=c["periods"], nq=c["nq"],
+              pre_steps=-1, pert_modes=0, **m2)
+    t.init(seed=c["seed"], perturbation=c["amp"])
+    d0 = t.diagnostics()
+    ns, a = _series(t.step, t.amplitude)
+    assert np.abs(a - a_o).max() < TOL
+    got, want = t.moments(), o.observables()
+    G = t.query("G")
+    floors = [0.0, 0.05, 0.05, 0.0, 1.0, 1.0, 1.0, G, G, G]
+    errs = [np.abs(got[f] - want[f]).max() / max(np.abs(want[f]).max(), floors[f])
+            for f in range(10)]
+    print("C1 model (ii) observables, relative errors:", " ".join(f"{e:.1e}" for e in errs),
+          flush=True)
+    assert max(errs) <= TOL, errs
+    d1 = t.diagnostics()
+    for k in ("mass_S", "mass_P"):
+        assert abs(d1[k] / d0[k] - 1) < 1e-12, k
+    t.close()
